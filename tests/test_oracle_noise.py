@@ -1,0 +1,150 @@
+"""Pins of the oracle's noise stream (Alg. 1, Sampling: theta_k ~ N(theta, C)).
+
+* Philox4x32-10 against PyTorch's header-only ATen engine (an independent
+  implementation of Salmon et al., SC'11).
+* The FP32 Box-Muller transform against FP64 libm Box-Muller, and the
+  resulting draws against the standard normal (moments, KS test).
+* The counter map (which word feeds which GRF dimension) and the frequency
+  draws against their definitions.
+"""
+import ctypes as C
+import math
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import stats
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def aten_philox():
+    import torch  # only for its include directory
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    out = os.path.join(tempfile.mkdtemp(prefix="aten_philox_"), "libatenphilox.so")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-I", inc,
+                    os.path.join(HERE, "aten_philox_ref.cpp"), "-o", out], check=True)
+    L = C.CDLL(out)
+    p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+    L.aten_philox_block.argtypes = [p, p, p]
+
+    def block(ctr, key):
+        o = np.zeros(4, np.uint32)
+        L.aten_philox_block(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), o)
+        return o
+    return block
+
+
+def test_philox_matches_aten(orc, aten_philox):
+    rng = np.random.default_rng(11)
+    cases = [([0, 0, 0, 0], [0, 0]),
+             ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2),
+             ([1, 2, 3, 4], [5, 6])]
+    cases += [(rng.integers(0, 2**32, 4, dtype=np.uint64).astype(np.uint32),
+               rng.integers(0, 2**32, 2, dtype=np.uint64).astype(np.uint32))
+              for _ in range(2000)]
+    for ctr, key in cases:
+        np.testing.assert_array_equal(orc.philox(ctr, key), aten_philox(ctr, key))
+
+
+def _libm_box_muller(w0, w1):
+    u1 = ((w0 >> 8) + 1) * 2.0**-24
+    u2 = (w1 >> 8) * 2.0**-24
+    r = math.sqrt(-2.0 * math.log(u1))
+    return r * math.cos(2 * math.pi * u2), r * math.sin(2 * math.pi * u2)
+
+
+def test_gauss_pair_close_to_libm_box_muller(orc):
+    rng = np.random.default_rng(12)
+    w = rng.integers(0, 2**32, size=(20000, 2), dtype=np.uint64)
+    edge = [(0, 0), (0xFFFFFFFF, 0), (0, 0xFFFFFFFF), (0xFFFFFFFF, 0xFFFFFFFF),
+            (0x7FFFFFFF, 1 << 30), (12345, 1 << 30), (99, 1 << 31), (5, 3 << 30),
+            (0x00000100, 0x00400000), (0xFFFFFF00, 0x00200000)]
+    worst = 0.0
+    for w0, w1 in list(map(tuple, w.tolist())) + edge:
+        got = orc.gauss_pair(int(w0), int(w1))
+        ref = _libm_box_muller(int(w0), int(w1))
+        for g, r in zip(got, ref):
+            err = abs(float(g) - r)
+            # FP32 transform: within 4 ulp of max(|z|, 1) (measured worst 2.6)
+            assert err <= 4 * float(np.spacing(np.float32(max(1.0, abs(r))))), (w0, w1, got, ref)
+            worst = max(worst, err / (1.0 + abs(r)))
+    assert worst > 0.0
+
+
+def test_gauss_pair_edges(orc):
+    # u1 = 1 gives a zero radius; u1 = 2^-24 gives the truncation radius.
+    assert np.all(orc.gauss_pair(0xFFFFFFFF, 12345) == 0.0)
+    z = orc.gauss_pair(0, 0)
+    assert abs(float(z[0]) - math.sqrt(48 * math.log(2))) < 2e-6
+    assert float(z[1]) == 0.0
+    # a quarter turn: cos -> 0 exactly, sin -> the radius
+    z = orc.gauss_pair(0, 1 << 30)
+    assert float(z[0]) == 0.0 and abs(float(z[1]) - math.sqrt(48 * math.log(2))) < 2e-6
+
+
+def test_noise_is_standard_normal(orc):
+    z = orc.noise_block(seed=7, tick=3, r=0, n=2048, h=10).reshape(-1).astype(np.float64)
+    n = z.size
+    assert abs(z.mean()) < 5.0 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+    assert np.abs(z).max() <= math.sqrt(48 * math.log(2)) + 1e-5
+    ks = stats.kstest(z, "norm")
+    assert ks.pvalue > 1e-4
+    # every GRF dimension on its own is standard normal too
+    zz = z.reshape(-1, 12)
+    for d in range(12):
+        assert abs(zz[:, d].mean()) < 5.0 / math.sqrt(zz.shape[0])
+
+
+def test_noise_counter_map(orc):
+    seed, tick, r, k, j = 0x123456789ABCDEF0, 17, 2, 333, 41
+    z = orc.noise_step(seed, tick, r, k, j)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for c in range(3):
+        w = orc.philox([k, j, tick, (r << 8) | c], key)
+        np.testing.assert_array_equal(z[4 * c:4 * c + 2], orc.gauss_pair(int(w[0]), int(w[1])))
+        np.testing.assert_array_equal(z[4 * c + 2:4 * c + 4], orc.gauss_pair(int(w[2]), int(w[3])))
+
+
+def test_noise_streams_are_distinct(orc):
+    base = orc.noise_step(1, 2, 0, 5, 6)
+    for args in [(2, 2, 0, 5, 6), (1, 3, 0, 5, 6), (1, 2, 1, 5, 6), (1, 2, 0, 6, 6),
+                 (1, 2, 0, 5, 7)]:
+        assert not np.array_equal(base, orc.noise_step(*args))
+
+
+def test_frequency_quantisation(orc):
+    # q = round(f dt 2^32): one gait cycle is 2^32 phase units.
+    assert orc.q_of_freq(1.4, 0.02) == 120259084
+    assert orc.q_of_freq(1.0, 0.02) == 85899346
+    assert orc.q_of_freq(2.5, 0.02) == 214748365
+    for f in (1.0, 1.3, 1.4, 2.0, 2.4, 2.5):
+        q = orc.q_of_freq(f, 0.02)
+        assert abs(orc.freq_of_q(q, 0.02) - f) <= 0.5 / (0.02 * 2**32) + 1e-15
+
+
+def test_uniform_frequency_draws(orc):
+    from paper_2403_11383_amd import workloads
+    cfg = workloads.config("c1", N=4000)
+    qlo, qhi = orc.q_of_freq(1.0, 0.02), orc.q_of_freq(2.5, 0.02)
+    qs = np.array([orc.freq_q(cfg, 1.4, 0.0, 9, 0, k) for k in range(4000)], np.int64)
+    assert qs.min() >= qlo and qs.max() <= qhi
+    f = qs / (0.02 * 2**32)
+    assert stats.kstest(f, stats.uniform(loc=1.0, scale=1.5).cdf).pvalue > 1e-4
+
+
+def test_gaussian_frequency_draws(orc):
+    from paper_2403_11383_amd import workloads
+    cfg = workloads.config("c2", f_min=-100.0, f_max=100.0)
+    qs = np.array([orc.freq_q(cfg, 1.7, 0.1, 4, 1, k) for k in range(4000)], np.float64)
+    f = qs / (0.02 * 2**32)
+    assert abs(f.mean() - 1.7) < 5 * 0.1 / math.sqrt(4000)
+    assert abs(f.std() - 0.1) < 0.01
+    # clamped to the admissible range when the range is active
+    cfg = workloads.config("c2")
+    qs = np.array([orc.freq_q(cfg, 1.4, 5.0, 4, 1, k) for k in range(2000)])
+    assert qs.min() == orc.q_of_freq(1.0, 0.02) and qs.max() == orc.q_of_freq(2.5, 0.02)
