@@ -1,0 +1,209 @@
+/*
+ * sbs.h -- C ABI of the MI355X (gfx950) sample-based stochastic (SBS)
+ * predictive controller for quadruped locomotion.
+ *
+ * Method (Turrisi et al., "On the Benefits of GPU Sample-Based Stochastic
+ * Predictive Controllers for Legged Locomotion", IROS 2024): every control
+ * step samples N decision vectors theta_k = [gait frequency, per-step GRFs]
+ * from N(theta, C) (Alg. 1, Sampling), rolls each out over H steps of the
+ * single-rigid-body model of Eq. (1) with explicit Euler (Alg. 2), evaluates
+ * the quadratic tracking cost of Sec. V plus the frequency regulariser, and
+ * updates the sampling mean: MPPI weights (Sec. III-C, Alg. 4), the top-K_e
+ * elite mean and covariance (Alg. 1), or the best sample (Sec. III-B, Alg. 3).
+ * The mean is warm-started across steps (Sec. III-A) and its first step is the
+ * action handed to the low-level controller (Sec. IV, Fig. 2).
+ *
+ * Ownership and threading
+ *   - The caller lends device memory (an "arena", e.g. a torch uint8 tensor)
+ *     and a HIP stream; the arena must outlive the runtime.  Every device
+ *     buffer of the library is carved from the arena; nothing else is
+ *     allocated on the device.  Pinned host staging is allocated with
+ *     hipHostMalloc at runtime creation.
+ *   - Structs passed by pointer are read (or written) during the call only.
+ *   - All functions are thread-safe for one runtime.  Ticks of one controller
+ *     execute in submission order.  No exception crosses the ABI.
+ *   - Every function returns an sbs_status; on failure a message is kept per
+ *     thread and returned by sbs_last_error().
+ *
+ * Layouts: states are x = [p(3) world, Phi(3) roll/pitch/yaw, v(3) world,
+ * omega(3) body]; GRFs are world-frame, leg-major [FL, FR, RL, RR][x, y, z];
+ * means are [H][12] row-major.
+ */
+#ifndef SBS_H
+#define SBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBS_ABI_VERSION 1
+
+typedef enum {
+  SBS_OK = 0,
+  SBS_EINVAL = -1,    /* bad argument, non-finite state, unknown id        */
+  SBS_ENOMEM = -2,    /* arena or staging exhausted                        */
+  SBS_EAGAIN = -3,    /* result not ready yet (fetch with timeout 0)       */
+  SBS_ETIMEDOUT = -4, /* fetch timed out                                   */
+  SBS_EDEVICE = -5,   /* a HIP call failed                                 */
+  SBS_ECANCELED = -6, /* controller destroyed before the tick ran          */
+  SBS_ENOENT = -7     /* unknown or already fetched ticket                 */
+} sbs_status;
+
+enum { SBS_MPPI = 0, SBS_ELITE = 1, SBS_NAIVE = 2 };
+enum { SBS_FREQ_FIXED = 0, SBS_FREQ_UNIFORM = 1, SBS_FREQ_GAUSSIAN = 2 };
+enum { SBS_FP32 = 0, SBS_FP64 = 1 };
+enum { SBS_FLAG_NONFINITE = 1 };
+enum { SBS_MODE_DIRECT = 0, SBS_MODE_SERVING = 1 };
+
+/* Controller configuration.  N samples per iteration (the paper's K), H
+ * horizon steps (the paper's N), `iterations` SBS iterations per control step
+ * (Alg. 1 repeated from the same state), method SBS_MPPI / SBS_ELITE /
+ * SBS_NAIVE, gait-frequency mode SBS_FREQ_* (Sec. IV-C: fixed, uniform on
+ * [f_min, f_max], or Gaussian around the frequency mean), precision of the
+ * rollouts and costs (SBS_FP32 or SBS_FP64).  The frequency is carried as a
+ * phase increment per step q = round-half-even(f dt 2^32). */
+typedef struct sbs_controller_cfg {
+  int32_t N, H, iterations, method, freq_mode, friction_on, precision, reserved0;
+  double dt;            /* step of the discretised dynamics [s]             */
+  double lambda;        /* MPPI temperature                                 */
+  double elite_frac;    /* K_e = max(1, floor(elite_frac N))                */
+  double mu_fric;       /* friction coefficient of the cone clip            */
+  double rho;           /* weight of (f_k - f_nominal)^2                    */
+  double f_nominal;     /* nominal stepping frequency [Hz]                  */
+  double sigma_grf;     /* GRF noise std [N], reset every control step      */
+  double sigma_f;       /* frequency noise std [Hz] (Gaussian mode)         */
+  double sigma_min_grf, sigma_min_f; /* elite covariance floors           */
+  double f_min, f_max;  /* admissible frequency range [Hz]                  */
+  double f_fixed;       /* frequency of the fixed mode [Hz]                 */
+  double duty;          /* duty factor D_f: stance time D_f / f_s           */
+  double mu_f0;         /* initial frequency mean [Hz]                      */
+  double mass, gravity;
+  double inertia[3];    /* diagonal body inertia [kg m^2]                   */
+  double hip[12];       /* body-frame hip offsets [leg][xyz] [m]            */
+  double Q[12];         /* diagonal state weights                           */
+  double R[12];         /* diagonal GRF weights                             */
+  uint32_t phase_offset[4]; /* leg phase offsets, 2^32 = one gait cycle     */
+  uint64_t seed;        /* key of the counter-based noise stream            */
+} sbs_controller_cfg;
+
+/* One control-step request ("Given x0", Alg. 5). */
+typedef struct sbs_tick_input {
+  double x0[12];        /* current state estimate                           */
+  double foot_pos[12];  /* world footholds [leg][xyz] of the stance legs    */
+  double p_ref0[3];     /* reference position at the first step             */
+  double v_ref[3];      /* reference (desired) velocity                     */
+  double yaw_ref;
+  uint32_t phase_robot; /* gait phase of the robot, 2^32 = one cycle        */
+  uint32_t reserved0;
+} sbs_tick_input;
+
+/* Result of one control step. */
+typedef struct sbs_action {
+  double grf[12];       /* first-step GRFs of the updated mean, masked by the
+                           contact flags and clipped to the friction cone   */
+  int32_t contact[4];   /* stance flags at the robot's current phase        */
+  double freq_hz;       /* updated gait frequency                           */
+  double best_cost;     /* lowest cost of the last iteration                */
+  uint32_t q;           /* phase increment per step of freq_hz              */
+  int32_t flags;        /* SBS_FLAG_*                                        */
+  uint32_t tick;        /* control-step counter of the controller           */
+  int32_t controller;
+  int64_t t_submit_ns, t_launch_ns, t_done_ns; /* CLOCK_MONOTONIC           */
+} sbs_action;
+
+typedef struct sbs_runtime sbs_runtime;
+
+/* Create a runtime on the current HIP device.  arena: device pointer of
+ * arena_bytes bytes (256-byte aligned); stream: hipStream_t the library
+ * enqueues on; mode SBS_MODE_DIRECT launches each submission immediately on
+ * the caller's thread, SBS_MODE_SERVING queues submissions for a scheduler
+ * thread that admits them by arena memory and batches them (continuous
+ * batching).  stream2 (may be NULL) is a second stream the serving scheduler
+ * alternates batches on so that consecutive batches overlap. */
+int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *stream2,
+                       int32_t mode, sbs_runtime **out);
+/* Waits for all work, then frees host resources.  Pending tickets are
+ * cancelled. */
+int sbs_runtime_destroy(sbs_runtime *rt);
+
+/* Validate cfg, reserve the controller's persistent device state (mean [H][12]
+ * in the controller precision, frequency mean, counters), set the mean to the
+ * hover forces (0, 0, m g / 2) on every leg and step (first warm start,
+ * Sec. III-A) and return its id.  SBS_ENOMEM if the arena cannot hold it. */
+int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t *id);
+int sbs_destroy_controller(sbs_runtime *rt, int32_t id);
+
+/* Queue one control step of controller id.  Never blocks.  Returns a ticket
+ * for sbs_fetch_action.  SBS_EINVAL for a non-finite state; SBS_ENOMEM
+ * (direct mode) if the arena cannot hold the step's workspace now. */
+int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint64_t *ticket);
+
+/* Queue one control step for each of n distinct controllers as one fused
+ * launch sequence (one kernel per stage for all of them). */
+int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_tick_input *in,
+                     uint64_t *tickets);
+
+/* Wait up to timeout_us (0: poll, <0: forever) for a ticket.  SBS_EAGAIN or
+ * SBS_ETIMEDOUT if not done; on SBS_OK the ticket is consumed. */
+int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us);
+
+/* Fixed-membership batch for repeated fused ticks: reserves the workspace of
+ * the n controllers once and records the whole tick (all stages and
+ * iterations) as a HIP graph that sbs_plan_submit replays with new inputs. */
+int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_graph,
+                    int32_t *plan);
+int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uint64_t *tickets);
+int sbs_plan_destroy(sbs_runtime *rt, int32_t plan);
+
+/* Synchronous state access (waits for the controller's pending work):
+ * mean [H][12], frequency mean and next tick number.  Used for checkpoint
+ * and resume: export, then import into a fresh controller, reproduces the
+ * following ticks bit for bit (the noise is counter-based). */
+int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick);
+int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick);
+
+/* Debug taps.  sbs_set_debug(1) makes every later tick of the controller
+ * keep its per-iteration costs [iterations][N], sampled phase increments
+ * [iterations][N] and the updated mean before the warm-start shift [H][12];
+ * sbs_debug_fetch returns those of the last completed tick.
+ * sbs_debug_noise runs the noise stage alone for (tick, iteration r) with the
+ * controller's current frequency mean and returns z [N][H][12] and q [N]. */
+int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable);
+int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean);
+int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q);
+
+/* Serving statistics: ticks completed, batches launched, admission waits. */
+int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *admit_waits);
+
+/* Kernel timing: average device time [ns] of each stage's launches since the
+ * last call (0 noise, 1 rollout, 2 select, 3 update), measured with HIP
+ * events on the runtime stream when enabled. */
+int sbs_set_timing(sbs_runtime *rt, int32_t enable);
+int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
+
+/* Simulated robot for closed-loop runs (host, FP64, not part of the control
+ * step): advances the single-rigid-body plant of Eq. (1) by one step dt
+ * under the action's GRFs on the stance legs, an external world-frame force
+ * ext_force [N] on the CoM, and world-fixed feet; a leg that touches down is
+ * placed by the foothold rule of Eq. (2) with the executed frequency and
+ * v_ref.  state (x[12], foot_pos[12], phase) is updated in place; the phase
+ * advances by action->q.  Uses cfg for the model constants. */
+typedef struct sbs_plant_state {
+  double x[12];
+  double foot_pos[12];
+  int32_t contact[4];   /* stance flags of the previous step                */
+  uint32_t phase;
+  uint32_t reserved0;
+} sbs_plant_state;
+int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st, const sbs_action *act,
+                   const double ext_force[3], const double v_ref[3]);
+
+const char *sbs_last_error(void);
+int32_t sbs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,355 @@
+"""ctypes binding of libsbs.so (include/sbs.h), argument marshalling only.
+
+Every step of a control tick runs in the HIP kernels of the library; this
+module converts dicts and numpy arrays to the C structs, lends the library a
+torch-allocated device arena and torch streams, and turns status codes into
+exceptions.  If the library is not built, loading fails loudly: there is no
+other execution path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbs.so")
+
+MPPI, ELITE, NAIVE = 0, 1, 2
+METHODS = {"mppi": MPPI, "elite": ELITE, "naive": NAIVE}
+FREQ_MODES = {"fixed": 0, "uniform": 1, "gaussian": 2}
+PRECISIONS = {"fp32": 0, "fp64": 1}
+MODES = {"direct": 0, "serving": 1}
+FLAG_NONFINITE = 1
+
+OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EDEVICE, ECANCELED, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
+
+EXPORTED = [
+    "sbs_runtime_create", "sbs_runtime_destroy", "sbs_init_controller",
+    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action",
+    "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_get_state",
+    "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
+    "sbs_set_timing", "sbs_timing", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
+]
+
+
+class SBSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sbs error {code}: {msg}")
+        self.code = code
+
+
+class ControllerCfg(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("H", C.c_int32), ("iterations", C.c_int32), ("method", C.c_int32),
+        ("freq_mode", C.c_int32), ("friction_on", C.c_int32), ("precision", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("dt", C.c_double), ("lam", C.c_double), ("elite_frac", C.c_double),
+        ("mu_fric", C.c_double), ("rho", C.c_double), ("f_nominal", C.c_double),
+        ("sigma_grf", C.c_double), ("sigma_f", C.c_double), ("sigma_min_grf", C.c_double),
+        ("sigma_min_f", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double),
+        ("f_fixed", C.c_double), ("duty", C.c_double), ("mu_f0", C.c_double),
+        ("mass", C.c_double), ("gravity", C.c_double), ("inertia", C.c_double * 3),
+        ("hip", C.c_double * 12), ("Q", C.c_double * 12), ("R", C.c_double * 12),
+        ("phase_offset", C.c_uint32 * 4), ("seed", C.c_uint64),
+    ]
+
+
+class TickInput(C.Structure):
+    _fields_ = [
+        ("x0", C.c_double * 12), ("foot_pos", C.c_double * 12), ("p_ref0", C.c_double * 3),
+        ("v_ref", C.c_double * 3), ("yaw_ref", C.c_double), ("phase_robot", C.c_uint32),
+        ("reserved0", C.c_uint32),
+    ]
+
+
+class Action(C.Structure):
+    _fields_ = [
+        ("grf", C.c_double * 12), ("contact", C.c_int32 * 4), ("freq_hz", C.c_double),
+        ("best_cost", C.c_double), ("q", C.c_uint32), ("flags", C.c_int32),
+        ("tick", C.c_uint32), ("controller", C.c_int32), ("t_submit_ns", C.c_int64),
+        ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64),
+    ]
+
+
+class PlantState(C.Structure):
+    _fields_ = [
+        ("x", C.c_double * 12), ("foot_pos", C.c_double * 12), ("contact", C.c_int32 * 4),
+        ("phase", C.c_uint32), ("reserved0", C.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2403_11383_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, i32, u32 = C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32
+        L.sbs_runtime_create.argtypes = [vp, u64, vp, vp, i32, C.POINTER(vp)]
+        L.sbs_runtime_destroy.argtypes = [vp]
+        L.sbs_init_controller.argtypes = [vp, C.POINTER(ControllerCfg), C.POINTER(i32)]
+        L.sbs_destroy_controller.argtypes = [vp, i32]
+        L.sbs_submit_tick.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
+        L.sbs_submit_batch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(TickInput), C.POINTER(u64)]
+        L.sbs_fetch_action.argtypes = [vp, u64, C.POINTER(Action), C.c_int64]
+        L.sbs_plan_create.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
+        L.sbs_plan_submit.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
+        L.sbs_plan_destroy.argtypes = [vp, i32]
+        L.sbs_get_state.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.POINTER(u32)]
+        L.sbs_set_state.argtypes = [vp, i32, vp, C.c_double, u32]
+        L.sbs_set_debug.argtypes = [vp, i32, i32]
+        L.sbs_debug_fetch.argtypes = [vp, i32, vp, vp, vp]
+        L.sbs_debug_noise.argtypes = [vp, i32, u32, u32, vp, vp]
+        L.sbs_stats.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
+        L.sbs_set_timing.argtypes = [vp, i32]
+        L.sbs_timing.argtypes = [vp, vp, vp]
+        L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
+                                     C.POINTER(Action), vp, vp]
+        L.sbs_last_error.restype = C.c_char_p
+        L.sbs_abi_version.restype = i32
+        for name in EXPORTED:
+            if name not in ("sbs_last_error", "sbs_abi_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise SBSError(rc, lib().sbs_last_error().decode(errors="replace"))
+
+
+def make_cfg(d: dict) -> ControllerCfg:
+    c = ControllerCfg()
+    c.N, c.H, c.iterations = int(d["N"]), int(d["H"]), int(d.get("iterations", 1))
+    c.method = METHODS[d.get("method", "mppi")]
+    c.freq_mode = FREQ_MODES[d.get("freq_mode", "fixed")]
+    c.friction_on = 1 if d.get("friction_on", False) else 0
+    c.precision = PRECISIONS[d.get("precision", "fp32")]
+    c.dt, c.lam = float(d["dt"]), float(d.get("lambda", 1.0))
+    c.elite_frac, c.mu_fric = float(d.get("elite_frac", 0.1)), float(d.get("mu_fric", 0.5))
+    c.rho, c.f_nominal = float(d.get("rho", 0.0)), float(d.get("f_nominal", 1.4))
+    c.sigma_grf, c.sigma_f = float(d["sigma_grf"]), float(d.get("sigma_f", 0.0))
+    c.sigma_min_grf = float(d.get("sigma_min_grf", 1.0))
+    c.sigma_min_f = float(d.get("sigma_min_f", 0.05))
+    c.f_min, c.f_max = float(d.get("f_min", 1.0)), float(d.get("f_max", 2.5))
+    c.f_fixed, c.duty = float(d.get("f_fixed", 1.4)), float(d.get("duty", 0.5))
+    c.mu_f0 = float(d.get("mu_f0", 1.4))
+    c.mass, c.gravity = float(d["mass"]), float(d["gravity"])
+    c.inertia[:] = [float(v) for v in d["inertia"]]
+    c.hip[:] = [float(v) for v in np.asarray(d["hip"], dtype=np.float64).reshape(12)]
+    c.Q[:] = [float(v) for v in d["Q"]]
+    c.R[:] = [float(v) for v in d["R"]]
+    c.phase_offset[:] = [int(v) & 0xFFFFFFFF for v in d["phase_offset"]]
+    c.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    return c
+
+
+def make_input(d: dict) -> TickInput:
+    i = TickInput()
+    i.x0[:] = [float(v) for v in d["x0"]]
+    i.foot_pos[:] = [float(v) for v in np.asarray(d["foot_pos"], dtype=np.float64).reshape(12)]
+    i.p_ref0[:] = [float(v) for v in d.get("p_ref0", (0.0, 0.0, 0.35))]
+    i.v_ref[:] = [float(v) for v in d.get("v_ref", (0.0, 0.0, 0.0))]
+    i.yaw_ref = float(d.get("yaw_ref", 0.0))
+    i.phase_robot = int(d.get("phase_robot", 0)) & 0xFFFFFFFF
+    return i
+
+
+def action_dict(a: Action) -> dict:
+    return {
+        "grf": np.array(a.grf[:]), "contact": np.array(a.contact[:], np.int32),
+        "freq_hz": a.freq_hz, "best_cost": a.best_cost, "q": int(a.q), "flags": int(a.flags),
+        "tick": int(a.tick), "controller": int(a.controller),
+        "t_submit_ns": int(a.t_submit_ns), "t_launch_ns": int(a.t_launch_ns),
+        "t_done_ns": int(a.t_done_ns),
+    }
+
+
+class Runtime:
+    """A runtime on one GPU.  The device arena is a torch uint8 tensor and
+    the streams are torch streams; both stay alive as long as this object."""
+
+    def __init__(self, arena_bytes: int = 1 << 30, mode: str = "direct", device: str = "cuda:0",
+                 two_streams: bool = False):
+        import torch
+        self._torch = torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.stream2 = torch.cuda.Stream(self.device) if two_streams else None
+        self.cfgs = {}
+        h = C.c_void_p()
+        _check(lib().sbs_runtime_create(
+            C.c_void_p(self.arena.data_ptr()), C.c_uint64(self.arena.numel()),
+            C.c_void_p(self.stream.cuda_stream),
+            C.c_void_p(self.stream2.cuda_stream) if self.stream2 is not None else None,
+            MODES[mode], C.byref(h)))
+        self._h = h
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().sbs_runtime_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- controllers -----------------------------------------------------------
+    def init_controller(self, cfg: dict) -> int:
+        c = make_cfg(cfg)
+        i = C.c_int32()
+        _check(lib().sbs_init_controller(self._h, C.byref(c), C.byref(i)))
+        self.cfgs[i.value] = dict(cfg)
+        return i.value
+
+    def destroy_controller(self, cid: int):
+        _check(lib().sbs_destroy_controller(self._h, cid))
+        self.cfgs.pop(cid, None)
+
+    # -- ticks -----------------------------------------------------------------
+    def submit_tick(self, cid: int, inp: dict) -> int:
+        t = C.c_uint64()
+        i = make_input(inp)
+        _check(lib().sbs_submit_tick(self._h, cid, C.byref(i), C.byref(t)))
+        return t.value
+
+    def submit_batch(self, cids, inputs) -> list:
+        n = len(cids)
+        ids = (C.c_int32 * n)(*cids)
+        ins = (TickInput * n)(*[make_input(x) for x in inputs])
+        tks = (C.c_uint64 * n)()
+        _check(lib().sbs_submit_batch(self._h, n, ids, ins, tks))
+        return list(tks)
+
+    def fetch(self, ticket: int, timeout_us: int = -1):
+        a = Action()
+        rc = lib().sbs_fetch_action(self._h, C.c_uint64(ticket), C.byref(a), timeout_us)
+        if rc in (EAGAIN, ETIMEDOUT):
+            return None
+        _check(rc)
+        return action_dict(a)
+
+    def tick(self, cid: int, inp: dict) -> dict:
+        return self.fetch(self.submit_tick(cid, inp))
+
+    # -- plans -----------------------------------------------------------------
+    def plan_create(self, cids, use_graph: bool = True) -> int:
+        n = len(cids)
+        ids = (C.c_int32 * n)(*cids)
+        p = C.c_int32()
+        _check(lib().sbs_plan_create(self._h, n, ids, 1 if use_graph else 0, C.byref(p)))
+        return p.value
+
+    def plan_submit(self, plan: int, inputs) -> list:
+        n = len(inputs)
+        ins = (TickInput * n)(*[make_input(x) for x in inputs])
+        tks = (C.c_uint64 * n)()
+        _check(lib().sbs_plan_submit(self._h, plan, ins, tks))
+        return list(tks)
+
+    def plan_destroy(self, plan: int):
+        _check(lib().sbs_plan_destroy(self._h, plan))
+
+    # -- state -----------------------------------------------------------------
+    def get_state(self, cid: int):
+        H = int(self.cfgs[cid]["H"])
+        mu = np.zeros((H, 12))
+        mf = C.c_double()
+        tk = C.c_uint32()
+        _check(lib().sbs_get_state(self._h, cid, mu.ctypes.data, C.byref(mf), C.byref(tk)))
+        return mu, mf.value, tk.value
+
+    def set_state(self, cid: int, mu, mu_f: float, tick: int):
+        m = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
+        assert m.size == 12 * int(self.cfgs[cid]["H"])
+        _check(lib().sbs_set_state(self._h, cid, m.ctypes.data, float(mu_f), int(tick) & 0xFFFFFFFF))
+
+    # -- debug taps --------------------------------------------------------------
+    def set_debug(self, cid: int, on: bool = True):
+        _check(lib().sbs_set_debug(self._h, cid, 1 if on else 0))
+
+    def debug_fetch(self, cid: int):
+        c = self.cfgs[cid]
+        R, N, H = int(c.get("iterations", 1)), int(c["N"]), int(c["H"])
+        J = np.zeros((R, N))
+        q = np.zeros((R, N), np.uint32)
+        mean = np.zeros((H, 12))
+        _check(lib().sbs_debug_fetch(self._h, cid, J.ctypes.data, q.ctypes.data, mean.ctypes.data))
+        return J, q, mean
+
+    def debug_noise(self, cid: int, tick: int, r: int = 0):
+        c = self.cfgs[cid]
+        N, H = int(c["N"]), int(c["H"])
+        z = np.zeros((N, H, 12), np.float32)
+        q = np.zeros(N, np.uint32)
+        _check(lib().sbs_debug_noise(self._h, cid, tick, r, z.ctypes.data, q.ctypes.data))
+        return z, q
+
+    # -- statistics ----------------------------------------------------------------
+    def stats(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().sbs_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"ticks": a.value, "batches": b.value, "admit_waits": c.value}
+
+    def set_timing(self, on: bool = True):
+        _check(lib().sbs_set_timing(self._h, 1 if on else 0))
+
+    def timing(self):
+        avg = np.zeros(4)
+        n = np.zeros(4, np.uint64)
+        _check(lib().sbs_timing(self._h, avg.ctypes.data, n.ctypes.data))
+        return {"noise_ns": avg[0], "rollout_ns": avg[1], "select_ns": avg[2],
+                "update_ns": avg[3], "launches": n.tolist()}
+
+
+class Plant:
+    """The simulated robot of closed-loop runs (host FP64, in the library)."""
+
+    def __init__(self, cfg: dict, x0, foot_pos, phase: int = 0):
+        self.cfg = make_cfg(cfg)
+        self.st = PlantState()
+        self.st.x[:] = [float(v) for v in x0]
+        self.st.foot_pos[:] = [float(v) for v in np.asarray(foot_pos, np.float64).reshape(12)]
+        self.st.phase = int(phase) & 0xFFFFFFFF
+        self._ext = np.zeros(3)
+        self._vref = np.zeros(3)
+
+    def step(self, act: dict, ext_force=(0.0, 0.0, 0.0), v_ref=(0.0, 0.0, 0.0)):
+        a = Action()
+        a.grf[:] = [float(v) for v in act["grf"]]
+        a.contact[:] = [int(v) for v in act["contact"]]
+        a.q = int(act["q"]) & 0xFFFFFFFF
+        self._ext[:] = ext_force
+        self._vref[:] = v_ref
+        _check(lib().sbs_plant_step(C.byref(self.cfg), C.byref(self.st), C.byref(a),
+                                    self._ext.ctypes.data, self._vref.ctypes.data))
+
+    @property
+    def x(self):
+        return np.array(self.st.x[:])
+
+    @property
+    def foot_pos(self):
+        return np.array(self.st.foot_pos[:]).reshape(4, 3)
+
+    @property
+    def phase(self):
+        return int(self.st.phase)

@@ -1,0 +1,92 @@
+// sbs_device.h -- descriptors shared by the host runtime and the gfx950
+// kernels.  One TickDesc describes one controller's control step; a LaunchTab
+// maps the flattened block index of each stage onto the descriptors active in
+// one iteration of a fused batch.
+#pragma once
+
+#include <stdint.h>
+
+namespace sbs {
+
+constexpr int kRollBlock = 64;     // rollouts per workgroup (one wave64)
+constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
+constexpr int kUpdBlock = 256;     // threads per update workgroup
+constexpr int kUpdChunk = 1024;    // samples reduced by one update workgroup
+constexpr int kSelBlock = 1024;    // threads of the per-controller select block
+constexpr int kResultDoubles = 24; // action record
+constexpr int kItScalars = 16;     // per-iteration scalars
+constexpr int kMaxH = 256;         // longest horizon the update stage holds in LDS
+
+// result record layout (doubles)
+enum : int {
+  RES_GRF = 0,        // 12
+  RES_CONTACT = 12,   // 4
+  RES_FREQ = 16,
+  RES_Q = 17,
+  RES_BEST = 18,
+  RES_FLAGS = 19,
+};
+
+// per-iteration scalars (doubles)
+enum : int {
+  IT_MUF = 0,      // frequency mean for the next sampling round
+  IT_SIGF = 1,     // frequency std for the next sampling round
+  IT_BETA = 2,     // lowest cost
+  IT_OMEGA = 3,    // normaliser (MPPI), K_e (elite), 1 (naive)
+  IT_BEST = 4,     // index of the lowest cost
+  IT_FNEW = 5,     // updated frequency
+  IT_FLAGS = 6,
+  IT_SKIP = 7,     // 1 when no cost was finite: keep the mean
+};
+
+struct TickDesc {
+  int32_t N, H, R, method, freq_mode, friction_on, precision, Ke;
+  int32_t nchunk;        // update chunks of kUpdChunk samples
+  uint32_t tick;         // control-step counter (noise counter word 2)
+  uint32_t phase_robot;
+  uint32_t q_fixed, q_lo, q_hi;
+  uint32_t phase_offset[4];
+  uint32_t duty_q;       // stance iff phase < duty_q (duty_full: always)
+  int32_t duty_full;
+  int32_t slot;          // index of this descriptor in the batch
+  int32_t pad0;
+  uint64_t seed;
+  double dt, inv_lambda, mu_fric, rho, f_nominal, mass, inv_mass, gravity, inv_g;
+  double inertia[3], inv_inertia[3], hip[12], Q[12], Rw[12];
+  double sigma0, sigma_f0, sigma_min_grf, sigma_min_f, f_min, f_max, f_fixed;
+  double half_duty;      // D_f / 2, so T_st / 2 = half_duty / f
+  double inv_q_scale;    // 1 / (dt 2^32): f = q * inv_q_scale
+  double x0[12], foot[12], p_ref0[3], v_ref[3], yaw_ref;
+  // persistent controller state
+  void *mu;              // [H][12] in the controller precision
+  double *ctl;           // [0] frequency mean
+  uint32_t *counter;     // update-stage arrival counter (self-resetting)
+  // step workspace
+  float *z;              // [H][N][12] noise of the current iteration
+  uint32_t *q;           // [N]
+  void *J;               // [N] costs, controller precision
+  void *w;               // [N] weights, controller precision
+  double *sigma;         // [H][12] elite std of the current iteration
+  double *partial;       // [H][nchunk][24] update partial sums
+  double *it;            // [kItScalars]
+  double *result;        // [kResultDoubles]
+  double *dbg_J;         // optional [R][N]
+  uint32_t *dbg_q;       // optional [R][N]
+  double *dbg_mean;      // optional [H][12]
+};
+
+// Block maps of one (iteration, precision) launch over n active descriptors:
+// start arrays are exclusive prefix sums of each stage's blocks per item.
+struct LaunchTab {
+  int32_t n;
+  int32_t r;             // iteration index
+  int32_t total_noise, total_roll, total_upd;
+  int32_t pad;
+  const TickDesc *desc;  // descriptor array of the batch
+  const int32_t *item;   // [n] descriptor index
+  const int32_t *noise_start;  // [n+1]
+  const int32_t *roll_start;   // [n+1]
+  const int32_t *upd_start;    // [n+1]
+};
+
+}  // namespace sbs

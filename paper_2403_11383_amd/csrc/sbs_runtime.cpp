@@ -1,0 +1,1279 @@
+// sbs_runtime.cpp -- host runtime behind the C ABI of include/sbs.h.
+//
+// Device memory: every buffer is carved from the caller's arena by a
+// first-fit allocator (persistent controller state at init, step workspaces
+// per launched batch, released when the batch completes).  Pinned host
+// staging comes from one hipHostMalloc block carved the same way.
+//
+// A batch is the unit of launch: its descriptors and block maps go to the
+// device in one copy, then per iteration one launch per stage covers every
+// controller of the batch, then one copy brings all actions back and an
+// event marks completion.  Direct mode launches each submission at once;
+// serving mode queues submissions for a scheduler thread that forms batches
+// from whatever is pending whenever a stream slot frees up and the arena can
+// hold the workspace (continuous batching with memory admission).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sbs.h"
+#include "sbs_device.h"
+
+namespace sbs {
+hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s);
+}
+
+using namespace sbs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// First-fit allocator over [0, size) with coalescing frees.
+class Carver {
+ public:
+  void reset(uint64_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    size_ = size;
+    used_ = 0;
+  }
+  bool alloc(uint64_t bytes, uint64_t *off) {
+    bytes = align_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        uint64_t rest = it->second - bytes, roff = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[roff] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = align_up(bytes ? bytes : 1);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t used() const { return used_; }
+  uint64_t size() const { return size_; }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;
+  uint64_t size_ = 0, used_ = 0;
+};
+
+struct Controller {
+  int32_t id = -1;
+  sbs_controller_cfg cfg{};
+  uint64_t st_off = 0, st_bytes = 0;
+  void *mu = nullptr;
+  double *ctl = nullptr;
+  uint32_t *counter = nullptr;
+  uint32_t next_tick = 0;
+  bool debug = false;
+  uint64_t dbg_off = 0, dbg_bytes = 0;
+  double *dbg_J = nullptr;
+  uint32_t *dbg_q = nullptr;
+  double *dbg_mean = nullptr;
+  int inflight = 0;
+  int plan = -1;
+};
+
+struct Request {
+  uint64_t ticket;
+  int32_t id;
+  sbs_tick_input in;
+  int64_t t_submit;
+};
+
+struct TicketRec {
+  int32_t controller = -1;
+  uint32_t tick = 0;
+  int status = 1;  // 1 pending, 0 done, <0 error
+  int64_t t_submit = 0, t_launch = 0, t_done = 0;
+  double res[kResultDoubles];
+};
+
+// Byte layout of one batch (device workspace and host staging share the
+// header part so that one copy uploads it).
+struct Layout {
+  uint64_t desc = 0, tabs = 0, hdr_bytes = 0, results = 0, items = 0, total = 0;
+  std::vector<uint64_t> item_off;  // per item workspace offset
+  uint64_t host_total = 0;         // header + results
+};
+
+struct ItemWs {
+  uint64_t z, q, J, w, sigma, partial, it, bytes;
+};
+
+ItemWs item_ws(const sbs_controller_cfg &c) {
+  ItemWs o{};
+  const uint64_t N = (uint64_t)c.N, H = (uint64_t)c.H;
+  const uint64_t ts = c.precision == SBS_FP64 ? 8 : 4;
+  const uint64_t nchunk = (N + kUpdChunk - 1) / kUpdChunk;
+  uint64_t p = 0;
+  o.z = p; p = align_up(p + H * N * 12 * 4);
+  o.q = p; p = align_up(p + N * 4);
+  o.J = p; p = align_up(p + N * ts);
+  o.w = p; p = align_up(p + N * ts);
+  o.sigma = p; p = align_up(p + H * 12 * 8);
+  o.partial = p; p = align_up(p + H * nchunk * 24 * 8);
+  o.it = p; p = align_up(p + kItScalars * 8);
+  o.bytes = p;
+  return o;
+}
+
+struct Batch {
+  int id = 0;
+  int stream_slot = 0;
+  hipEvent_t done = nullptr;
+  std::vector<uint64_t> tickets;
+  std::vector<int32_t> ctrls;
+  uint64_t ws_off = 0, ws_bytes = 0, host_off = 0, host_bytes = 0;
+  double *host_results = nullptr;
+  int plan = -1;
+  std::vector<hipEvent_t> timing;  // 5 per launched (iteration, precision)
+  bool owns_memory = true;
+};
+
+struct Plan {
+  int id = -1;
+  std::vector<int32_t> ctrls;
+  Layout lay;
+  uint64_t ws_off = 0, host_off = 0;
+  char *host = nullptr;
+  char *dev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = false;
+  bool busy = false;
+  hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct sbs_runtime {
+  std::mutex mu;
+  std::condition_variable cv;
+  int device = 0;
+  char *arena = nullptr;
+  Carver dev_alloc;
+  char *pinned = nullptr;
+  Carver host_alloc;
+  hipStream_t streams[2] = {nullptr, nullptr};
+  int nstreams = 1;
+  int mode = SBS_MODE_DIRECT;
+  int32_t next_id = 0;
+  std::unordered_map<int32_t, Controller> ctrls;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, TicketRec> tickets;
+  std::deque<Request> pending;
+  std::deque<std::unique_ptr<Batch>> inflight;  // launch order
+  int next_batch = 0;
+  std::unordered_map<int, std::unique_ptr<Plan>> plans;
+  int next_plan = 0;
+  std::vector<hipEvent_t> event_pool;
+  // serving
+  std::thread sched;
+  std::atomic<bool> stop{false};
+  uint64_t n_ticks = 0, n_batches = 0, n_admit_waits = 0;
+  // timing
+  bool timing = false;
+  double stage_ns[4] = {0, 0, 0, 0};
+  uint64_t stage_n[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+hipEvent_t take_event(sbs_runtime *rt) {
+  if (!rt->event_pool.empty()) {
+    hipEvent_t e = rt->event_pool.back();
+    rt->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void give_event(sbs_runtime *rt, hipEvent_t e) {
+  if (e) rt->event_pool.push_back(e);
+}
+
+bool finite_vec(const double *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+uint32_t host_q_of_freq(double f, double dt) {
+  double v = std::rint((f * dt) * 4294967296.0);
+  if (!(v > 0.0)) return 0u;
+  if (v > 4294967295.0) return 4294967295u;
+  return (uint32_t)v;
+}
+
+int validate_cfg(const sbs_controller_cfg &c) {
+  if (c.N < 1 || c.N > (1 << 22)) return fail(SBS_EINVAL, "N=%d out of [1, 2^22]", c.N);
+  if (c.H < 1 || c.H > kMaxH) return fail(SBS_EINVAL, "H=%d out of [1, %d]", c.H, kMaxH);
+  if (c.iterations < 1 || c.iterations > 64)
+    return fail(SBS_EINVAL, "iterations=%d out of [1, 64]", c.iterations);
+  if (c.method < 0 || c.method > 2) return fail(SBS_EINVAL, "unknown method %d", c.method);
+  if (c.freq_mode < 0 || c.freq_mode > 2) return fail(SBS_EINVAL, "unknown freq_mode %d", c.freq_mode);
+  if (c.precision != SBS_FP32 && c.precision != SBS_FP64)
+    return fail(SBS_EINVAL, "unknown precision %d", c.precision);
+  if (!(c.dt > 0) || !(c.mass > 0) || !(c.gravity > 0) || !(c.inertia[0] > 0) ||
+      !(c.inertia[1] > 0) || !(c.inertia[2] > 0))
+    return fail(SBS_EINVAL, "dt, mass, gravity and inertia must be positive");
+  if (c.method == SBS_MPPI && !(c.lambda > 0)) return fail(SBS_EINVAL, "lambda must be positive");
+  if (!(c.duty >= 0.0 && c.duty <= 1.0)) return fail(SBS_EINVAL, "duty must be in [0, 1]");
+  if (!(c.sigma_grf >= 0.0)) return fail(SBS_EINVAL, "sigma_grf must be >= 0");
+  if (c.freq_mode != SBS_FREQ_FIXED && !(c.f_min > 0 && c.f_max >= c.f_min))
+    return fail(SBS_EINVAL, "frequency range must satisfy 0 < f_min <= f_max");
+  if (c.freq_mode == SBS_FREQ_FIXED && !(c.f_fixed > 0)) return fail(SBS_EINVAL, "f_fixed must be > 0");
+  return SBS_OK;
+}
+
+void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char *dev_item,
+               double *dev_result, const sbs_tick_input &in, uint32_t tick, int slot,
+               TickDesc *d) {
+  const sbs_controller_cfg &c = C.cfg;
+  std::memset(d, 0, sizeof *d);
+  d->N = c.N;
+  d->H = c.H;
+  d->R = c.iterations;
+  d->method = c.method;
+  d->freq_mode = c.freq_mode;
+  d->friction_on = c.friction_on ? 1 : 0;
+  d->precision = c.precision;
+  double kef = std::floor(c.elite_frac * (double)c.N);
+  int32_t ke = (int32_t)std::min<double>(std::max<double>(kef, 1.0), (double)c.N);
+  d->Ke = c.method == SBS_NAIVE ? 1 : ke;
+  d->nchunk = (c.N + kUpdChunk - 1) / kUpdChunk;
+  d->tick = tick;
+  d->phase_robot = in.phase_robot;
+  d->q_fixed = host_q_of_freq(c.f_fixed, c.dt);
+  d->q_lo = host_q_of_freq(c.f_min, c.dt);
+  d->q_hi = host_q_of_freq(c.f_max, c.dt);
+  for (int l = 0; l < 4; ++l) d->phase_offset[l] = c.phase_offset[l];
+  const double dq = std::rint(c.duty * 4294967296.0);
+  d->duty_full = dq >= 4294967296.0 ? 1 : 0;
+  d->duty_q = d->duty_full ? 0xFFFFFFFFu : (uint32_t)dq;
+  d->slot = slot;
+  d->seed = c.seed;
+  d->dt = c.dt;
+  d->inv_lambda = c.method == SBS_MPPI ? 1.0 / c.lambda : 0.0;
+  d->mu_fric = c.mu_fric;
+  d->rho = c.rho;
+  d->f_nominal = c.f_nominal;
+  d->mass = c.mass;
+  d->inv_mass = 1.0 / c.mass;
+  d->gravity = c.gravity;
+  d->inv_g = 1.0 / c.gravity;
+  for (int i = 0; i < 3; ++i) {
+    d->inertia[i] = c.inertia[i];
+    d->inv_inertia[i] = 1.0 / c.inertia[i];
+  }
+  for (int i = 0; i < 12; ++i) {
+    d->hip[i] = c.hip[i];
+    d->Q[i] = c.Q[i];
+    d->Rw[i] = c.R[i];
+    d->x0[i] = in.x0[i];
+    d->foot[i] = in.foot_pos[i];
+  }
+  d->sigma0 = c.sigma_grf;
+  d->sigma_f0 = c.sigma_f;
+  d->sigma_min_grf = c.sigma_min_grf;
+  d->sigma_min_f = c.sigma_min_f;
+  d->f_min = c.f_min;
+  d->f_max = c.f_max;
+  d->f_fixed = c.f_fixed;
+  d->half_duty = 0.5 * c.duty;
+  d->inv_q_scale = 1.0 / (c.dt * 4294967296.0);
+  for (int i = 0; i < 3; ++i) {
+    d->p_ref0[i] = in.p_ref0[i];
+    d->v_ref[i] = in.v_ref[i];
+  }
+  d->yaw_ref = in.yaw_ref;
+  d->mu = C.mu;
+  d->ctl = C.ctl;
+  d->counter = C.counter;
+  d->z = reinterpret_cast<float *>(dev_item + w.z);
+  d->q = reinterpret_cast<uint32_t *>(dev_item + w.q);
+  d->J = dev_item + w.J;
+  d->w = dev_item + w.w;
+  d->sigma = reinterpret_cast<double *>(dev_item + w.sigma);
+  d->partial = reinterpret_cast<double *>(dev_item + w.partial);
+  d->it = reinterpret_cast<double *>(dev_item + w.it);
+  d->result = dev_result;
+  if (C.debug) {
+    d->dbg_J = C.dbg_J;
+    d->dbg_q = C.dbg_q;
+    d->dbg_mean = C.dbg_mean;
+  }
+  (void)rt;
+}
+
+// Layout of a batch over the given controllers.
+Layout make_layout(const std::vector<const Controller *> &cs) {
+  Layout L;
+  const uint64_t n = cs.size();
+  int rmax = 1;
+  for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
+  L.desc = 0;
+  L.tabs = align_up(n * sizeof(TickDesc));
+  // per (iteration, precision): item[n] + 3 x start[n+1]
+  const uint64_t tab_bytes = align_up((n + 3 * (n + 1)) * 4);
+  L.hdr_bytes = align_up(L.tabs + (uint64_t)rmax * 2 * tab_bytes);
+  L.results = L.hdr_bytes;
+  L.items = align_up(L.results + n * kResultDoubles * 8);
+  uint64_t p = L.items;
+  for (auto *c : cs) {
+    L.item_off.push_back(p);
+    p = align_up(p + item_ws(c->cfg).bytes);
+  }
+  L.total = p;
+  L.host_total = L.items;  // header + results
+  return L;
+}
+
+// Builds descriptors and block maps into host staging `host` for a batch
+// whose device base is `dev`; returns the per-(iteration, precision) tables.
+std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
+                                                   const std::vector<const Controller *> &cs,
+                                                   const std::vector<const sbs_tick_input *> &ins,
+                                                   const std::vector<uint32_t> &ticks,
+                                                   const Layout &L, char *host, char *dev) {
+  const int n = (int)cs.size();
+  int rmax = 1;
+  for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
+  TickDesc *hd = reinterpret_cast<TickDesc *>(host + L.desc);
+  for (int i = 0; i < n; ++i) {
+    fill_desc(rt, *cs[i], item_ws(cs[i]->cfg), dev + L.item_off[i],
+              reinterpret_cast<double *>(dev + L.results) + (size_t)i * kResultDoubles, *ins[i],
+              ticks[i], i, &hd[i]);
+  }
+  std::vector<std::pair<LaunchTab, int>> out;
+  const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
+  for (int r = 0; r < rmax; ++r) {
+    for (int prec = 0; prec < 2; ++prec) {
+      const uint64_t off = L.tabs + ((uint64_t)r * 2 + prec) * tab_bytes;
+      int32_t *item = reinterpret_cast<int32_t *>(host + off);
+      int32_t *ns = item + n, *rs = ns + (n + 1), *us = rs + (n + 1);
+      // longest horizon first: the rollout stage's tail is the longest lanes
+      std::vector<int> idx;
+      for (int i = 0; i < n; ++i)
+        if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec) idx.push_back(i);
+      std::stable_sort(idx.begin(), idx.end(),
+                       [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
+      int m = (int)idx.size();
+      ns[0] = rs[0] = us[0] = 0;
+      for (int t = 0; t < m; ++t) {
+        const sbs_controller_cfg &c = cs[idx[t]]->cfg;
+        item[t] = idx[t];
+        ns[t + 1] = ns[t] + c.H * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
+        rs[t + 1] = rs[t] + (c.N + kRollBlock - 1) / kRollBlock;
+        us[t + 1] = us[t] + c.H * ((c.N + kUpdChunk - 1) / kUpdChunk);
+      }
+      if (m == 0) continue;
+      LaunchTab tab{};
+      tab.n = m;
+      tab.r = r;
+      tab.total_noise = ns[m];
+      tab.total_roll = rs[m];
+      tab.total_upd = us[m];
+      tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
+      tab.item = reinterpret_cast<const int32_t *>(dev + off);
+      tab.noise_start = tab.item + n;
+      tab.roll_start = tab.noise_start + (n + 1);
+      tab.upd_start = tab.roll_start + (n + 1);
+      out.push_back({tab, prec});
+    }
+  }
+  return out;
+}
+
+void record_timing(sbs_runtime *rt, Batch &b) {
+  // events come in groups of 5 around the 4 stages
+  for (size_t g = 0; g + 5 <= b.timing.size(); g += 5) {
+    for (int s = 0; s < 4; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, b.timing[g + s], b.timing[g + s + 1]) == hipSuccess) {
+        rt->stage_ns[s] += (double)ms * 1e6;
+        rt->stage_n[s] += 1;
+      }
+    }
+  }
+  for (auto e : b.timing) give_event(rt, e);
+  b.timing.clear();
+}
+
+// Complete a finished batch: copy the actions into the tickets, free memory.
+void finish_batch(sbs_runtime *rt, Batch &b) {
+  const int64_t t = now_ns();
+  for (size_t i = 0; i < b.tickets.size(); ++i) {
+    auto it = rt->tickets.find(b.tickets[i]);
+    if (it != rt->tickets.end()) {
+      std::memcpy(it->second.res, b.host_results + i * kResultDoubles, sizeof(it->second.res));
+      it->second.status = 0;
+      it->second.t_done = t;
+    }
+    auto c = rt->ctrls.find(b.ctrls[i]);
+    if (c != rt->ctrls.end()) c->second.inflight -= 1;
+  }
+  rt->n_ticks += b.tickets.size();
+  if (rt->timing) record_timing(rt, b);
+  else {
+    for (auto e : b.timing) give_event(rt, e);
+    b.timing.clear();
+  }
+  if (b.owns_memory) {
+    rt->dev_alloc.release(b.ws_off, b.ws_bytes);
+    rt->host_alloc.release(b.host_off, b.host_bytes);
+  }
+  if (b.plan >= 0) {
+    auto p = rt->plans.find(b.plan);
+    if (p != rt->plans.end()) p->second->busy = false;
+  }
+  give_event(rt, b.done);
+  b.done = nullptr;
+}
+
+// Retire completed batches in launch order per stream.  Returns the number
+// retired.  Caller holds rt->mu.
+int reap(sbs_runtime *rt) {
+  int n = 0;
+  for (auto it = rt->inflight.begin(); it != rt->inflight.end();) {
+    hipError_t q = hipEventQuery((*it)->done);
+    if (q == hipSuccess) {
+      finish_batch(rt, **it);
+      it = rt->inflight.erase(it);
+      ++n;
+    } else {
+      if (q != hipErrorNotReady) {
+        (void)hipGetLastError();
+      }
+      ++it;
+    }
+  }
+  return n;
+}
+
+// Launch one batch of (controller, input) pairs on stream slot `slot`.
+// Caller holds rt->mu; returns SBS_ENOMEM when memory is short.
+int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
+           const std::vector<const sbs_tick_input *> &ins, const std::vector<uint64_t> &tks,
+           int slot) {
+  std::vector<const Controller *> cs;
+  for (int32_t id : ids) cs.push_back(&rt->ctrls.at(id));
+  Layout L = make_layout(cs);
+  uint64_t ws_off = 0, host_off = 0;
+  if (!rt->dev_alloc.alloc(L.total, &ws_off))
+    return fail(SBS_ENOMEM, "arena cannot hold %llu bytes of step workspace",
+                (unsigned long long)L.total);
+  if (!rt->host_alloc.alloc(L.host_total, &host_off)) {
+    rt->dev_alloc.release(ws_off, L.total);
+    return fail(SBS_ENOMEM, "pinned staging exhausted");
+  }
+  char *dev = rt->arena + ws_off;
+  char *host = rt->pinned + host_off;
+  std::vector<uint32_t> ticks;
+  for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev);
+  hipStream_t s = rt->streams[slot];
+  auto b = std::make_unique<Batch>();
+  b->id = rt->next_batch++;
+  b->stream_slot = slot;
+  b->ws_off = ws_off;
+  b->ws_bytes = L.total;
+  b->host_off = host_off;
+  b->host_bytes = L.host_total;
+  b->host_results = reinterpret_cast<double *>(host + L.results);
+  b->tickets = tks;
+  b->ctrls = ids;
+  b->done = take_event(rt);
+  hipError_t e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  const int64_t t_launch = now_ns();
+  for (auto &tp : tabs) {
+    if (e != hipSuccess) break;
+    hipEvent_t *ev = nullptr;
+    if (rt->timing) {
+      size_t base = b->timing.size();
+      for (int i = 0; i < 5; ++i) b->timing.push_back(take_event(rt));
+      ev = &b->timing[base];
+    }
+    e = launch_iteration(tp.first, tp.second, s, ev);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host + L.results, dev + L.results, ids.size() * kResultDoubles * 8,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(b->done, s);
+  if (e != hipSuccess) {
+    // the stream may still run what was enqueued: wait before freeing
+    (void)hipStreamSynchronize(s);
+    rt->dev_alloc.release(ws_off, L.total);
+    rt->host_alloc.release(host_off, L.host_total);
+    give_event(rt, b->done);
+    for (auto ev : b->timing) give_event(rt, ev);
+    return fail(SBS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  }
+  for (size_t i = 0; i < ids.size(); ++i) {
+    Controller &c = rt->ctrls.at(ids[i]);
+    c.next_tick += 1;
+    c.inflight += 1;
+    TicketRec &t = rt->tickets[tks[i]];
+    t.t_launch = t_launch;
+    t.tick = ticks[i];
+  }
+  rt->n_batches += 1;
+  rt->inflight.push_back(std::move(b));
+  return SBS_OK;
+}
+
+int slot_busy(sbs_runtime *rt, int slot) {
+  int n = 0;
+  for (auto &b : rt->inflight)
+    if (b->stream_slot == slot) ++n;
+  return n;
+}
+
+// Serving scheduler: continuous batching with memory admission.
+void scheduler_loop(sbs_runtime *rt) {
+  (void)hipSetDevice(rt->device);
+  std::unique_lock<std::mutex> lk(rt->mu);
+  while (!rt->stop.load()) {
+    int retired = reap(rt);
+    if (retired) rt->cv.notify_all();
+    // a free stream slot?
+    int slot = -1;
+    for (int s = 0; s < rt->nstreams; ++s)
+      if (slot_busy(rt, s) == 0) {
+        slot = s;
+        break;
+      }
+    if (slot >= 0 && !rt->pending.empty()) {
+      // admit in arrival order: one tick per controller per batch, skip
+      // controllers with a tick in flight (their next tick needs the warm
+      // start), stop when the arena cannot hold the workspace
+      std::vector<int32_t> ids;
+      std::vector<const sbs_tick_input *> ins;
+      std::vector<uint64_t> tks;
+      std::vector<size_t> taken;
+      std::vector<const Controller *> cs;
+      std::unordered_map<int32_t, bool> seen;
+      uint64_t need = 0;
+      uint64_t avail = rt->dev_alloc.size() - rt->dev_alloc.used();
+      bool waited = false;
+      for (size_t i = 0; i < rt->pending.size() && ids.size() < 1024; ++i) {
+        Request &rq = rt->pending[i];
+        if (seen.count(rq.id)) continue;
+        seen[rq.id] = true;
+        auto cit = rt->ctrls.find(rq.id);
+        if (cit == rt->ctrls.end()) continue;
+        if (cit->second.inflight > 0) continue;
+        cs.push_back(&cit->second);
+        Layout L = make_layout(cs);
+        if (L.total + kAlign > avail) {
+          cs.pop_back();
+          waited = true;
+          break;
+        }
+        need = L.total;
+        ids.push_back(rq.id);
+        ins.push_back(&rq.in);
+        tks.push_back(rq.ticket);
+        taken.push_back(i);
+      }
+      (void)need;
+      if (waited) rt->n_admit_waits += 1;
+      if (!ids.empty()) {
+        std::vector<Request> keep;  // inputs must stay valid during launch
+        int rc = launch(rt, ids, ins, tks, slot);
+        if (rc == SBS_OK) {
+          for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
+        } else if (rc != SBS_ENOMEM) {
+          for (uint64_t tk : tks) rt->tickets[tk].status = rc;
+          for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
+          rt->cv.notify_all();
+        }
+        continue;
+      }
+    }
+    // nothing to launch: poll briefly (completion detection latency)
+    lk.unlock();
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+    lk.lock();
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *sbs_last_error(void) { return g_err.c_str(); }
+int32_t sbs_abi_version(void) { return SBS_ABI_VERSION; }
+
+int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *stream2,
+                       int32_t mode, sbs_runtime **out) {
+  if (!out) return fail(SBS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!arena || arena_bytes < (1u << 20)) return fail(SBS_EINVAL, "arena missing or below 1 MiB");
+  if (((uintptr_t)arena) % kAlign) return fail(SBS_EINVAL, "arena must be 256-byte aligned");
+  if (mode != SBS_MODE_DIRECT && mode != SBS_MODE_SERVING) return fail(SBS_EINVAL, "bad mode");
+  auto rt = std::make_unique<sbs_runtime>();
+  if (hipGetDevice(&rt->device) != hipSuccess) return fail(SBS_EDEVICE, "no HIP device");
+  rt->arena = static_cast<char *>(arena);
+  rt->dev_alloc.reset(arena_bytes);
+  const uint64_t pinned_bytes = 64ull << 20;
+  if (hipHostMalloc((void **)&rt->pinned, pinned_bytes, hipHostMallocDefault) != hipSuccess)
+    return fail(SBS_EDEVICE, "hipHostMalloc of %llu bytes failed", (unsigned long long)pinned_bytes);
+  rt->host_alloc.reset(pinned_bytes);
+  rt->streams[0] = static_cast<hipStream_t>(stream);
+  rt->streams[1] = static_cast<hipStream_t>(stream2);
+  rt->nstreams = stream2 ? 2 : 1;
+  rt->mode = mode;
+  if (mode == SBS_MODE_SERVING) {
+    sbs_runtime *raw = rt.get();
+    rt->sched = std::thread([raw] { scheduler_loop(raw); });
+  }
+  *out = rt.release();
+  return SBS_OK;
+}
+
+int sbs_runtime_destroy(sbs_runtime *rt) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  if (rt->sched.joinable()) {
+    rt->stop.store(true);
+    rt->sched.join();
+  }
+  for (int s = 0; s < rt->nstreams; ++s) (void)hipStreamSynchronize(rt->streams[s]);
+  {
+    std::lock_guard<std::mutex> lk(rt->mu);
+    reap(rt);
+    for (auto &p : rt->plans) {
+      if (p.second->exec) (void)hipGraphExecDestroy(p.second->exec);
+      if (p.second->graph) (void)hipGraphDestroy(p.second->graph);
+      if (p.second->done) (void)hipEventDestroy(p.second->done);
+    }
+    for (auto e : rt->event_pool) (void)hipEventDestroy(e);
+  }
+  (void)hipHostFree(rt->pinned);
+  delete rt;
+  return SBS_OK;
+}
+
+int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t *id) {
+  if (!rt || !cfg || !id) return fail(SBS_EINVAL, "NULL argument");
+  int rc = validate_cfg(*cfg);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(rt->mu);
+  Controller C;
+  C.cfg = *cfg;
+  const uint64_t ts = cfg->precision == SBS_FP64 ? 8 : 4;
+  const uint64_t mu_bytes = align_up((uint64_t)cfg->H * 12 * ts);
+  C.st_bytes = mu_bytes + kAlign + kAlign;
+  if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off)) {
+    reap(rt);
+    if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off))
+      return fail(SBS_ENOMEM, "arena cannot hold the controller state");
+  }
+  char *base = rt->arena + C.st_off;
+  C.mu = base;
+  C.ctl = reinterpret_cast<double *>(base + mu_bytes);
+  C.counter = reinterpret_cast<uint32_t *>(base + mu_bytes + kAlign);
+  // hover mean: (0, 0, m g / 2) on every leg and step
+  std::vector<char> hostbuf(C.st_bytes, 0);
+  const double hover = 0.5 * cfg->mass * cfg->gravity;
+  for (int j = 0; j < cfg->H; ++j)
+    for (int c = 0; c < 12; ++c) {
+      const double v = (c % 3 == 2) ? hover : 0.0;
+      if (ts == 8) reinterpret_cast<double *>(hostbuf.data())[j * 12 + c] = v;
+      else reinterpret_cast<float *>(hostbuf.data())[j * 12 + c] = (float)v;
+    }
+  *reinterpret_cast<double *>(hostbuf.data() + mu_bytes) = cfg->mu_f0;
+  hipStream_t s = rt->streams[0];
+  if (hipMemcpyAsync(base, hostbuf.data(), C.st_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    rt->dev_alloc.release(C.st_off, C.st_bytes);
+    return fail(SBS_EDEVICE, "controller state upload failed");
+  }
+  C.id = rt->next_id++;
+  *id = C.id;
+  rt->ctrls[C.id] = C;
+  return SBS_OK;
+}
+
+int sbs_destroy_controller(sbs_runtime *rt, int32_t id) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  if (it->second.plan >= 0) return fail(SBS_EINVAL, "controller %d belongs to plan %d", id, it->second.plan);
+  // cancel queued requests
+  for (auto r = rt->pending.begin(); r != rt->pending.end();) {
+    if (r->id == id) {
+      rt->tickets[r->ticket].status = SBS_ECANCELED;
+      r = rt->pending.erase(r);
+    } else {
+      ++r;
+    }
+  }
+  while (it->second.inflight > 0) {
+    reap(rt);
+    if (it->second.inflight > 0) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+      lk.lock();
+      it = rt->ctrls.find(id);
+    }
+  }
+  rt->dev_alloc.release(it->second.st_off, it->second.st_bytes);
+  if (it->second.dbg_bytes) rt->dev_alloc.release(it->second.dbg_off, it->second.dbg_bytes);
+  rt->ctrls.erase(it);
+  rt->cv.notify_all();
+  return SBS_OK;
+}
+
+static int check_input(const sbs_tick_input *in) {
+  if (!in) return fail(SBS_EINVAL, "input is NULL");
+  if (!finite_vec(in->x0, 12) || !finite_vec(in->foot_pos, 12) || !finite_vec(in->p_ref0, 3) ||
+      !finite_vec(in->v_ref, 3) || !std::isfinite(in->yaw_ref))
+    return fail(SBS_EINVAL, "non-finite tick input");
+  return SBS_OK;
+}
+
+int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_tick_input *in,
+                     uint64_t *tickets) {
+  if (!rt || n < 1 || !ids || !in || !tickets) return fail(SBS_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    int rc = check_input(&in[i]);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lk(rt->mu);
+  std::vector<int32_t> vid(ids, ids + n);
+  {
+    std::vector<int32_t> sorted = vid;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(SBS_EINVAL, "a batch may hold each controller once");
+  }
+  for (int32_t id : vid)
+    if (!rt->ctrls.count(id)) return fail(SBS_EINVAL, "unknown controller %d", id);
+  const int64_t t = now_ns();
+  std::vector<uint64_t> tks;
+  for (int i = 0; i < n; ++i) {
+    uint64_t tk = rt->next_ticket++;
+    TicketRec rec;
+    rec.controller = vid[i];
+    rec.t_submit = t;
+    rt->tickets[tk] = rec;
+    tks.push_back(tk);
+    tickets[i] = tk;
+  }
+  if (rt->mode == SBS_MODE_SERVING) {
+    for (int i = 0; i < n; ++i) rt->pending.push_back({tks[i], vid[i], in[i], t});
+    return SBS_OK;
+  }
+  std::vector<const sbs_tick_input *> ins;
+  for (int i = 0; i < n; ++i) ins.push_back(&in[i]);
+  int rc = launch(rt, vid, ins, tks, 0);
+  if (rc == SBS_ENOMEM) {
+    reap(rt);
+    rc = launch(rt, vid, ins, tks, 0);
+  }
+  if (rc != SBS_OK) {
+    for (uint64_t tk : tks) rt->tickets.erase(tk);
+    return rc;
+  }
+  return SBS_OK;
+}
+
+int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint64_t *ticket) {
+  return sbs_submit_batch(rt, 1, &id, in, ticket);
+}
+
+int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us) {
+  if (!rt || !out) return fail(SBS_EINVAL, "NULL argument");
+  const int64_t t0 = now_ns();
+  std::unique_lock<std::mutex> lk(rt->mu);
+  for (;;) {
+    auto it = rt->tickets.find(ticket);
+    if (it == rt->tickets.end()) return fail(SBS_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    TicketRec &t = it->second;
+    if (t.status == 1 && rt->mode == SBS_MODE_DIRECT) reap(rt);
+    if (t.status <= 0) {
+      int st = t.status;
+      if (st == 0) {
+        std::memset(out, 0, sizeof *out);
+        for (int i = 0; i < 12; ++i) out->grf[i] = t.res[RES_GRF + i];
+        for (int l = 0; l < 4; ++l) out->contact[l] = (int32_t)t.res[RES_CONTACT + l];
+        out->freq_hz = t.res[RES_FREQ];
+        out->q = (uint32_t)t.res[RES_Q];
+        out->best_cost = t.res[RES_BEST];
+        out->flags = (int32_t)t.res[RES_FLAGS];
+        out->tick = t.tick;
+        out->controller = t.controller;
+        out->t_submit_ns = t.t_submit;
+        out->t_launch_ns = t.t_launch;
+        out->t_done_ns = t.t_done;
+      }
+      rt->tickets.erase(it);
+      if (st < 0) return fail(st, "tick failed or was cancelled");
+      return SBS_OK;
+    }
+    if (timeout_us == 0) return fail(SBS_EAGAIN, "not ready");
+    if (timeout_us > 0 && now_ns() - t0 > timeout_us * 1000) return fail(SBS_ETIMEDOUT, "timed out");
+    lk.unlock();
+    std::this_thread::yield();
+    lk.lock();
+  }
+}
+
+int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  while (it->second.inflight > 0) {
+    reap(rt);
+    if (it->second.inflight > 0) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      it = rt->ctrls.find(id);
+      if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "controller destroyed");
+    }
+  }
+  Controller &C = it->second;
+  const int n = C.cfg.H * 12;
+  const bool f64 = C.cfg.precision == SBS_FP64;
+  std::vector<char> buf((size_t)n * (f64 ? 8 : 4));
+  double mf = 0;
+  hipStream_t s = rt->streams[0];
+  if (hipMemcpyAsync(buf.data(), C.mu, buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&mf, C.ctl, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(SBS_EDEVICE, "state download failed");
+  if (mu)
+    for (int i = 0; i < n; ++i)
+      mu[i] = f64 ? reinterpret_cast<double *>(buf.data())[i] : (double)reinterpret_cast<float *>(buf.data())[i];
+  if (mu_f) *mu_f = mf;
+  if (tick) *tick = C.next_tick;
+  return SBS_OK;
+}
+
+int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick) {
+  if (!rt || !mu) return fail(SBS_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  while (it->second.inflight > 0) {
+    reap(rt);
+    if (it->second.inflight > 0) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      it = rt->ctrls.find(id);
+      if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "controller destroyed");
+    }
+  }
+  Controller &C = it->second;
+  const int n = C.cfg.H * 12;
+  if (!finite_vec(mu, n) || !std::isfinite(mu_f)) return fail(SBS_EINVAL, "non-finite state");
+  const bool f64 = C.cfg.precision == SBS_FP64;
+  std::vector<char> buf((size_t)n * (f64 ? 8 : 4));
+  for (int i = 0; i < n; ++i) {
+    if (f64) reinterpret_cast<double *>(buf.data())[i] = mu[i];
+    else reinterpret_cast<float *>(buf.data())[i] = (float)mu[i];
+  }
+  hipStream_t s = rt->streams[0];
+  if (hipMemcpyAsync(C.mu, buf.data(), buf.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(C.ctl, &mu_f, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(SBS_EDEVICE, "state upload failed");
+  C.next_tick = tick;
+  return SBS_OK;
+}
+
+int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  Controller &C = it->second;
+  if (enable && !C.debug) {
+    const uint64_t RN = (uint64_t)C.cfg.iterations * C.cfg.N;
+    const uint64_t bJ = align_up(RN * 8), bq = align_up(RN * 4), bm = align_up((uint64_t)C.cfg.H * 12 * 8);
+    C.dbg_bytes = bJ + bq + bm;
+    if (!rt->dev_alloc.alloc(C.dbg_bytes, &C.dbg_off)) {
+      C.dbg_bytes = 0;
+      return fail(SBS_ENOMEM, "arena cannot hold the debug buffers");
+    }
+    char *b = rt->arena + C.dbg_off;
+    C.dbg_J = reinterpret_cast<double *>(b);
+    C.dbg_q = reinterpret_cast<uint32_t *>(b + bJ);
+    C.dbg_mean = reinterpret_cast<double *>(b + bJ + bq);
+    C.debug = true;
+  } else if (!enable && C.debug) {
+    if (C.inflight > 0) return fail(SBS_EAGAIN, "controller has ticks in flight");
+    rt->dev_alloc.release(C.dbg_off, C.dbg_bytes);
+    C.dbg_bytes = 0;
+    C.debug = false;
+    C.dbg_J = nullptr;
+    C.dbg_q = nullptr;
+    C.dbg_mean = nullptr;
+  }
+  return SBS_OK;
+}
+
+int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  if (!it->second.debug) return fail(SBS_EINVAL, "debug is off for controller %d", id);
+  while (it->second.inflight > 0) {
+    reap(rt);
+    if (it->second.inflight > 0) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      it = rt->ctrls.find(id);
+      if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "controller destroyed");
+    }
+  }
+  Controller &C = it->second;
+  const uint64_t RN = (uint64_t)C.cfg.iterations * C.cfg.N;
+  hipStream_t s = rt->streams[0];
+  hipError_t e = hipSuccess;
+  if (costs) e = hipMemcpyAsync(costs, C.dbg_J, RN * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && q) e = hipMemcpyAsync(q, C.dbg_q, RN * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && mean)
+    e = hipMemcpyAsync(mean, C.dbg_mean, (size_t)C.cfg.H * 12 * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(SBS_EDEVICE, "debug download failed: %s", hipGetErrorString(e));
+  return SBS_OK;
+}
+
+int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q) {
+  if (!rt || !z || !q) return fail(SBS_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  while (it->second.inflight > 0) {
+    reap(rt);
+    if (it->second.inflight > 0) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      it = rt->ctrls.find(id);
+      if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "controller destroyed");
+    }
+  }
+  Controller &C = it->second;
+  std::vector<const Controller *> cs{&C};
+  Layout L = make_layout(cs);
+  uint64_t off = 0, hoff = 0;
+  if (!rt->dev_alloc.alloc(L.total, &off)) return fail(SBS_ENOMEM, "arena cannot hold the workspace");
+  if (!rt->host_alloc.alloc(L.host_total, &hoff)) {
+    rt->dev_alloc.release(off, L.total);
+    return fail(SBS_ENOMEM, "pinned staging exhausted");
+  }
+  char *dev = rt->arena + off, *host = rt->pinned + hoff;
+  sbs_tick_input in{};
+  std::vector<const sbs_tick_input *> ins{&in};
+  std::vector<uint32_t> ticks{tick};
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev);
+  TickDesc *hd = reinterpret_cast<TickDesc *>(host);
+  LaunchTab tab = tabs[0].first;
+  tab.r = (int32_t)r;
+  const ItemWs w = item_ws(C.cfg);
+  hipStream_t s = rt->streams[0];
+  const double sf = C.cfg.sigma_f;
+  hipError_t e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  // for r > 0 the noise stage reads the running frequency mean and std
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hd[0].it + IT_MUF, C.ctl, 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hd[0].it + IT_SIGF, &sf, 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_noise_only(tab, s);
+  std::vector<float> zj((size_t)C.cfg.H * C.cfg.N * 12);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(zj.data(), dev + L.item_off[0] + w.z, zj.size() * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(q, dev + L.item_off[0] + w.q, (size_t)C.cfg.N * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  rt->dev_alloc.release(off, L.total);
+  rt->host_alloc.release(hoff, L.host_total);
+  if (e != hipSuccess) return fail(SBS_EDEVICE, "noise tap failed: %s", hipGetErrorString(e));
+  const int N = C.cfg.N, H = C.cfg.H;
+  for (int j = 0; j < H; ++j)
+    for (int k = 0; k < N; ++k)
+      std::memcpy(&z[((size_t)k * H + j) * 12], &zj[((size_t)j * N + k) * 12], 48);
+  return SBS_OK;
+}
+
+int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *admit_waits) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  if (ticks) *ticks = rt->n_ticks;
+  if (batches) *batches = rt->n_batches;
+  if (admit_waits) *admit_waits = rt->n_admit_waits;
+  return SBS_OK;
+}
+
+int sbs_set_timing(sbs_runtime *rt, int32_t enable) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  rt->timing = enable != 0;
+  return SBS_OK;
+}
+
+int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  reap(rt);
+  for (int s = 0; s < 4; ++s) {
+    if (avg_ns) avg_ns[s] = rt->stage_n[s] ? rt->stage_ns[s] / (double)rt->stage_n[s] : 0.0;
+    if (launches) launches[s] = rt->stage_n[s];
+    rt->stage_ns[s] = 0;
+    rt->stage_n[s] = 0;
+  }
+  return SBS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans: fixed membership, workspace reserved once, optionally a HIP graph.
+// ---------------------------------------------------------------------------
+int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_graph, int32_t *plan) {
+  if (!rt || n < 1 || !ids || !plan) return fail(SBS_EINVAL, "bad plan arguments");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  if (rt->mode != SBS_MODE_DIRECT) return fail(SBS_EINVAL, "plans need a direct-mode runtime");
+  std::vector<int32_t> vid(ids, ids + n);
+  std::vector<int32_t> sorted = vid;
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(SBS_EINVAL, "a plan may hold each controller once");
+  std::vector<const Controller *> cs;
+  for (int32_t id : vid) {
+    auto it = rt->ctrls.find(id);
+    if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+    if (it->second.plan >= 0) return fail(SBS_EINVAL, "controller %d already in a plan", id);
+    cs.push_back(&it->second);
+  }
+  auto P = std::make_unique<Plan>();
+  P->lay = make_layout(cs);
+  if (!rt->dev_alloc.alloc(P->lay.total, &P->ws_off)) return fail(SBS_ENOMEM, "arena cannot hold the plan");
+  if (!rt->host_alloc.alloc(P->lay.host_total, &P->host_off)) {
+    rt->dev_alloc.release(P->ws_off, P->lay.total);
+    return fail(SBS_ENOMEM, "pinned staging exhausted");
+  }
+  P->dev = rt->arena + P->ws_off;
+  P->host = rt->pinned + P->host_off;
+  P->ctrls = vid;
+  P->use_graph = use_graph != 0;
+  P->id = rt->next_plan++;
+  if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
+    return fail(SBS_EDEVICE, "event creation failed");
+  if (P->use_graph) {
+    // capture the whole tick once; inputs change only in the pinned staging
+    // that the graph's first copy reads at replay time
+    std::vector<sbs_tick_input> dummy(n);
+    for (auto &d : dummy) std::memset(&d, 0, sizeof d);
+    std::vector<const sbs_tick_input *> ins;
+    for (auto &d : dummy) ins.push_back(&d);
+    std::vector<uint32_t> ticks(n, 0);
+    auto tabs = build_batch(rt, cs, ins, ticks, P->lay, P->host, P->dev);
+    hipStream_t s = rt->streams[0];
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(SBS_EDEVICE, "stream sync failed");
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->dev, P->host, P->lay.hdr_bytes, hipMemcpyHostToDevice, s);
+    for (auto &tp : tabs)
+      if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, nullptr);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->host + P->lay.results, P->dev + P->lay.results,
+                         (size_t)n * kResultDoubles * 8, hipMemcpyDeviceToHost, s);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+    P->graph = g;
+    if (e != hipSuccess) {
+      if (P->graph) (void)hipGraphDestroy(P->graph);
+      rt->dev_alloc.release(P->ws_off, P->lay.total);
+      rt->host_alloc.release(P->host_off, P->lay.host_total);
+      return fail(SBS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  for (int32_t id : vid) rt->ctrls.at(id).plan = P->id;
+  *plan = P->id;
+  rt->plans[P->id] = std::move(P);
+  return SBS_OK;
+}
+
+int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uint64_t *tickets) {
+  if (!rt || !in || !tickets) return fail(SBS_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  auto pit = rt->plans.find(plan);
+  if (pit == rt->plans.end()) return fail(SBS_EINVAL, "unknown plan %d", plan);
+  Plan &P = *pit->second;
+  const int n = (int)P.ctrls.size();
+  for (int i = 0; i < n; ++i) {
+    int rc = check_input(&in[i]);
+    if (rc) return rc;
+  }
+  if (P.busy) {
+    reap(rt);
+    if (P.busy) return fail(SBS_EAGAIN, "previous replay of plan %d still running", plan);
+  }
+  std::vector<const Controller *> cs;
+  std::vector<const sbs_tick_input *> ins;
+  std::vector<uint32_t> ticks;
+  for (int i = 0; i < n; ++i) {
+    Controller &c = rt->ctrls.at(P.ctrls[i]);
+    if (c.inflight > 0) {
+      reap(rt);
+      if (c.inflight > 0) return fail(SBS_EAGAIN, "controller %d has a tick in flight", c.id);
+    }
+    cs.push_back(&c);
+    ins.push_back(&in[i]);
+    ticks.push_back(c.next_tick);
+  }
+  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev);
+  hipStream_t s = rt->streams[0];
+  auto b = std::make_unique<Batch>();
+  b->id = rt->next_batch++;
+  b->stream_slot = 0;
+  b->owns_memory = false;
+  b->plan = P.id;
+  b->host_results = reinterpret_cast<double *>(P.host + P.lay.results);
+  b->ctrls = P.ctrls;
+  b->done = take_event(rt);
+  const int64_t t = now_ns();
+  hipError_t e = hipSuccess;
+  if (P.use_graph) {
+    e = hipGraphLaunch(P.exec, s);
+  } else {
+    e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
+    for (auto &tp : tabs) {
+      if (e != hipSuccess) break;
+      hipEvent_t *ev = nullptr;
+      if (rt->timing) {
+        size_t base = b->timing.size();
+        for (int i = 0; i < 5; ++i) b->timing.push_back(take_event(rt));
+        ev = &b->timing[base];
+      }
+      e = launch_iteration(tp.first, tp.second, s, ev);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P.host + P.lay.results, P.dev + P.lay.results,
+                         (size_t)n * kResultDoubles * 8, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->done, s);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    give_event(rt, b->done);
+    for (auto ev : b->timing) give_event(rt, ev);
+    return fail(SBS_EDEVICE, "plan launch failed: %s", hipGetErrorString(e));
+  }
+  for (int i = 0; i < n; ++i) {
+    uint64_t tk = rt->next_ticket++;
+    TicketRec rec;
+    rec.controller = P.ctrls[i];
+    rec.t_submit = t;
+    rec.t_launch = t;
+    rec.tick = ticks[i];
+    rt->tickets[tk] = rec;
+    b->tickets.push_back(tk);
+    tickets[i] = tk;
+    Controller &c = rt->ctrls.at(P.ctrls[i]);
+    c.next_tick += 1;
+    c.inflight += 1;
+  }
+  P.busy = true;
+  rt->n_batches += 1;
+  rt->inflight.push_back(std::move(b));
+  return SBS_OK;
+}
+
+int sbs_plan_destroy(sbs_runtime *rt, int32_t plan) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto pit = rt->plans.find(plan);
+  if (pit == rt->plans.end()) return fail(SBS_EINVAL, "unknown plan %d", plan);
+  while (pit->second->busy) {
+    reap(rt);
+    if (pit->second->busy) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      pit = rt->plans.find(plan);
+    }
+  }
+  Plan &P = *pit->second;
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  if (P.done) (void)hipEventDestroy(P.done);
+  rt->dev_alloc.release(P.ws_off, P.lay.total);
+  rt->host_alloc.release(P.host_off, P.lay.host_total);
+  for (int32_t id : P.ctrls) {
+    auto c = rt->ctrls.find(id);
+    if (c != rt->ctrls.end()) c->second.plan = -1;
+  }
+  rt->plans.erase(pit);
+  return SBS_OK;
+}
+
+}  // extern "C"

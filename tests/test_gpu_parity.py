@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars:
+* integers (sampled phase increments, contact flags, elite membership):
+  bit-exact; the FP32 noise z: bit-exact.
+* FP64 controllers: costs within 1e-10 relative, means and actions within
+  1e-10 of max(|u|, m g / 2).
+* FP32 controllers: per-sample costs within EPS_J (see cost_tol), actions
+  within 1e-4 of max(|u|, m g / 2) when the oracle is fed the GPU's own costs
+  (selection then identical), and against the oracle's own costs within the
+  bound propagated from EPS_J through the MPPI weights.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_11383_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+MG2 = 0.5 * workloads.MASS * workloads.GRAVITY
+
+
+def cost_tol(J):
+    """FP32 rollout cost tolerance: 1e-4 relative + 1e-3 absolute.  Calibrated:
+    the worst relative error observed on the influential samples of these
+    seeded workloads is 2.2e-5; the bar keeps a 4x margin."""
+    return 1e-4 * np.abs(J) + 1e-3
+
+
+RELEVANT = 60.0  # weight below exp(-60) relative to the best: no influence
+
+
+def check_costs_fp32(Jg, Jr, lam=1.0, elite_ke=None):
+    """FP32 costs against FP64 costs of the same samples.
+
+    A rollout that tumbles is chaotic: its cost is not reproducible across
+    precisions, but it also has no influence on the update.  So
+    * every sample that can influence the update -- MPPI weight above
+      exp(-RELEVANT) in the oracle, or within twice the oracle's elite
+      threshold -- matches within cost_tol;
+    * every other sample is also without influence on the GPU side;
+    * the typical sample (median) agrees to 1e-6 relative.
+    """
+    Jg, Jr = np.asarray(Jg, np.float64), np.asarray(Jr, np.float64)
+    beta_r, beta_g = Jr.min(), Jg.min()
+    if elite_ke is None:
+        rel = Jr <= beta_r + RELEVANT * lam
+        far = Jg > beta_g + 0.5 * RELEVANT * lam
+    else:
+        thr_r = np.sort(Jr)[elite_ke - 1]
+        thr_g = np.sort(Jg)[elite_ke - 1]
+        rel = Jr <= 2.0 * thr_r
+        far = Jg > thr_g
+    err = np.abs(Jg - Jr)
+    bad = rel & (err > cost_tol(Jr))
+    assert not bad.any(), (np.flatnonzero(bad)[:10], err[bad][:10], Jr[bad][:10])
+    assert np.all(far[~rel]), np.flatnonzero(~rel & ~far)[:10]
+    assert np.median(err / np.maximum(np.abs(Jr), 1.0)) <= 1e-6
+    return int(rel.sum())
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2403_11383_amd import binding
+    r = binding.Runtime(arena_bytes=2 << 30)
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    oracle.build()
+
+
+def hover(cfg):
+    return np.tile([0.0, 0.0, MG2] * 4, (cfg["H"], 1))
+
+
+def run_pair(rt, cfg, inp, tick=None, mu=None, mu_f=None, nthreads=8):
+    """One tick on the GPU (debug on) and on the oracle from the same state."""
+    cid = rt.init_controller(cfg)
+    rt.set_debug(cid, True)
+    if mu is None:
+        mu = hover(cfg)
+    if mu_f is None:
+        mu_f = cfg.get("mu_f0", 1.4)
+    t = 0 if tick is None else tick
+    rt.set_state(cid, mu, mu_f, t)
+    mu_gpu_in, _, _ = rt.get_state(cid)  # the mean as the controller holds it
+    act = rt.tick(cid, inp)
+    J, q, mean = rt.debug_fetch(cid)
+    mu_next, mf_next, tk = rt.get_state(cid)
+    ref = oracle.tick(cfg, mu_gpu_in, mu_f, t, inp, nthreads=nthreads)
+    rt.destroy_controller(cid)
+    return {"act": act, "J": J, "q": q, "mean": mean, "mu_next": mu_next, "mf_next": mf_next,
+            "tick_next": tk}, ref
+
+
+# ---------------------------------------------------------------------------
+# noise
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["uniform", "gaussian", "fixed"])
+def test_noise_bit_exact(rt, mode):
+    cfg = workloads.config("c1", N=333, H=7, freq_mode=mode, sigma_f=0.4, seed=0xDEADBEEF12345)
+    cid = rt.init_controller(cfg)
+    for tick, r in ((0, 0), (5, 0), (123456, 2)):
+        z, q = rt.debug_noise(cid, tick, r)
+        zr = oracle.noise_block(cfg["seed"], tick, r, 333, 7)
+        assert np.array_equal(z.view(np.uint32), zr.view(np.uint32)), (tick, r)
+        qr = np.array([oracle.freq_q(cfg, 1.4, 0.4, tick, r, k) for k in range(333)], np.uint32)
+        assert np.array_equal(q, qr), (tick, r)
+    rt.destroy_controller(cid)
+
+
+def test_noise_bit_exact_many_draws(rt):
+    """~1.9M Gaussians: every FP32 bit equal to the oracle's."""
+    cfg = workloads.config("c1", N=4000, H=40, seed=77)
+    cid = rt.init_controller(cfg)
+    z, q = rt.debug_noise(cid, 9, 1)
+    # a strided sample of samples against the oracle (its Python loop is slow)
+    ks = list(range(0, 4000, 37)) + [3999]
+    for k in ks:
+        for j in (0, 13, 39):
+            np.testing.assert_array_equal(z[k, j].view(np.uint32),
+                                          oracle.noise_step(77, 9, 1, k, j).view(np.uint32))
+    assert abs(float(z.mean())) < 5 / np.sqrt(z.size)
+    assert abs(float(z.var()) - 1.0) < 5 * np.sqrt(2.0 / z.size)
+    rt.destroy_controller(cid)
+
+
+# ---------------------------------------------------------------------------
+# FP64 controllers: tight parity
+# ---------------------------------------------------------------------------
+def check_fp64(out, ref, cfg, rel=1e-10):
+    R, N = ref["costs"].shape
+    np.testing.assert_array_equal(out["q"], ref["q_samples"])
+    Jr = ref["costs"]
+    np.testing.assert_allclose(out["J"], Jr, rtol=rel, atol=0)
+    scale = max(np.abs(ref["mean"]).max(), MG2)
+    assert np.abs(out["mean"] - ref["mean"]).max() <= rel * scale
+    assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= rel * scale
+    np.testing.assert_array_equal(out["act"]["contact"], ref["contact"])
+    assert out["act"]["q"] == ref["q"]
+    assert abs(out["act"]["freq_hz"] - ref["freq_hz"]) <= 1e-12 * max(1.0, abs(ref["freq_hz"]))
+    assert np.abs(out["mu_next"] - ref["mu_next"]).max() <= rel * scale
+    assert abs(out["mf_next"] - ref["mu_f_next"]) <= 1e-12
+    assert out["act"]["flags"] == ref["flags"]
+
+
+def test_c0_fp64_plain_mppi(rt):
+    cfg = workloads.config("c0")
+    out, ref = run_pair(rt, cfg, workloads.c0_input())
+    check_fp64(out, ref, cfg)
+    assert out["act"]["best_cost"] == pytest.approx(ref["best_cost"], rel=1e-10)
+
+
+@pytest.mark.parametrize("N,H", [(1, 1), (63, 3), (65, 9), (1025, 4), (3000, 17)])
+def test_fp64_ragged_sizes(rt, N, H):
+    cfg = workloads.config("c1", N=N, H=H, precision="fp64", seed=N * 7 + H)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(N)), phase_robot=N * 99991)
+    out, ref = run_pair(rt, cfg, inp, tick=N)
+    check_fp64(out, ref, cfg)
+
+
+@pytest.mark.parametrize("method", ["elite", "naive"])
+def test_fp64_elite_and_naive(rt, method):
+    cfg = workloads.config("c2", N=2500, H=12, precision="fp64", method=method, iterations=3,
+                           seed=21)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(3)), v_ref=(0.2, 0, 0))
+    out, ref = run_pair(rt, cfg, inp, tick=4)
+    check_fp64(out, ref, cfg)
+
+
+def test_fp64_duty_edges_and_pace(rt):
+    for duty, offs in ((0.0, workloads.TROT_OFFSETS), (1.0, workloads.TROT_OFFSETS),
+                       (0.5, workloads.PACE_OFFSETS), (0.7, (0, 1 << 30, 1 << 31, 3 << 30))):
+        cfg = workloads.config("c1", N=200, H=10, precision="fp64", duty=duty,
+                               phase_offset=list(offs), seed=5)
+        inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(4)))
+        out, ref = run_pair(rt, cfg, inp)
+        check_fp64(out, ref, cfg)
+
+
+def test_nonfinite_costs_keep_mean(rt):
+    cfg = workloads.config("c1", N=128, H=5, precision="fp64")
+    x0 = workloads.initial_state(np.random.default_rng(1))
+    x0[6] = 1e200  # every cost overflows to +inf
+    inp = workloads.tick_input(x0)
+    out, ref = run_pair(rt, cfg, inp)
+    assert ref["flags"] == 1 and out["act"]["flags"] == 1
+    check_fp64(out, ref, cfg)
+
+
+def test_nonfinite_state_rejected(rt):
+    from paper_2403_11383_amd import binding
+    cfg = workloads.config("c1", N=64, H=5)
+    cid = rt.init_controller(cfg)
+    x0 = workloads.initial_state(np.random.default_rng(1))
+    x0[2] = float("nan")
+    with pytest.raises(binding.SBSError) as e:
+        rt.submit_tick(cid, workloads.tick_input(x0))
+    assert e.value.code == binding.EINVAL
+    rt.destroy_controller(cid)
+
+
+# ---------------------------------------------------------------------------
+# FP32 controllers
+# ---------------------------------------------------------------------------
+def mppi_propagated_bound(ref, cfg, epsJ):
+    """|d mean| <= sum_k w_k |theta_k - mean| |dJ_k - sum_i w_i dJ_i| / lambda
+    with |dJ_k| <= epsJ_k; evaluated with the oracle's weights and samples."""
+    J = ref["costs"][-1]
+    w, *_ = oracle.mppi_weights(J, cfg["lambda"])
+    H = cfg["H"]
+    z = oracle.noise_block(cfg["seed"], 0, 0, cfg["N"], 1)[:, 0, :].astype(np.float64)
+    th0 = hover(cfg)[0][None] + cfg["sigma_grf"] * z   # first step only
+    dev = np.abs(th0 - ref["mean"][0][None])
+    spread = epsJ + (w * epsJ).sum()
+    return float((w[:, None] * dev * spread[:, None]).sum(0).max() / cfg["lambda"])
+
+
+def test_fp32_mppi_small(rt):
+    cfg = workloads.config("c1", N=777, H=20, seed=11)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(11)))
+    out, ref = run_pair(rt, cfg, inp)
+    np.testing.assert_array_equal(out["q"], ref["q_samples"])
+    Jr = ref["costs"]
+    check_costs_fp32(out["J"][0], Jr[0], cfg["lambda"])
+    scale = max(np.abs(ref["grf"]).max(), MG2)
+    # selection parity: the oracle's update on the GPU's own costs
+    ref2 = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, costs_override=out["J"], nthreads=8)
+    assert np.abs(out["act"]["grf"] - ref2["grf"]).max() <= 1e-4 * scale
+    assert np.abs(out["mean"] - ref2["mean"]).max() <= 1e-4 * max(np.abs(ref2["mean"]).max(), MG2)
+    # against the oracle's own costs: within the propagated bound
+    bound = mppi_propagated_bound(ref, cfg, cost_tol(Jr[-1]))
+    assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= max(1e-4 * scale, bound)
+    np.testing.assert_array_equal(out["act"]["contact"], ref["contact"])
+
+
+def test_fp32_elite_selection(rt):
+    cfg = workloads.config("c2", N=3000, H=16, seed=12)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(12)), v_ref=(-0.3, 0, 0))
+    out, ref = run_pair(rt, cfg, inp)
+    # iteration 0 samples from the same mean: costs comparable sample by sample
+    check_costs_fp32(out["J"][0], ref["costs"][0], elite_ke=oracle.elite_count(3000, 0.1))
+    np.testing.assert_array_equal(out["q"][0], ref["q_samples"][0])
+    ref2 = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, costs_override=out["J"], nthreads=8)
+    scale = max(np.abs(ref2["mean"]).max(), MG2)
+    assert np.abs(out["mean"] - ref2["mean"]).max() <= 1e-4 * scale
+    assert np.abs(out["act"]["grf"] - ref2["grf"]).max() <= 1e-4 * scale
+    assert abs(out["act"]["freq_hz"] - ref2["freq_hz"]) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# runtime properties
+# ---------------------------------------------------------------------------
+def test_determinism_and_resume(rt):
+    cfg = workloads.config("c1", N=1500, H=15, seed=99)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(5)))
+    a = rt.init_controller(cfg)
+    b = rt.init_controller(cfg)
+    ra = [rt.tick(a, inp) for _ in range(3)]
+    mu, mf, tk = rt.get_state(a)
+    rb = [rt.tick(b, inp) for _ in range(3)]
+    for x, y in zip(ra, rb):
+        np.testing.assert_array_equal(x["grf"], y["grf"])
+        assert x["q"] == y["q"] and x["best_cost"] == y["best_cost"]
+    # export after 3 ticks, import into a fresh controller, continue
+    c = rt.init_controller(cfg)
+    rt.set_state(c, mu, mf, tk)
+    x = rt.tick(a, inp)
+    y = rt.tick(c, inp)
+    np.testing.assert_array_equal(x["grf"], y["grf"])
+    assert x["tick"] == y["tick"] == 3
+    for cid in (a, b, c):
+        rt.destroy_controller(cid)
+
+
+def test_batch_equals_alone(rt):
+    cfgs = [workloads.config("c1", N=n, H=h, seed=s, method=m, iterations=it)
+            for n, h, s, m, it in ((700, 12, 1, "mppi", 1), (2100, 30, 2, "elite", 3),
+                                   (64, 5, 3, "naive", 2), (5000, 21, 4, "mppi", 1))]
+    cfgs.append(workloads.config("c0", N=300, H=8, seed=5))  # an FP64 one in the mix
+    rng = np.random.default_rng(8)
+    inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
+    alone = []
+    for c, i in zip(cfgs, inps):
+        cid = rt.init_controller(c)
+        alone.append(rt.tick(cid, i))
+        rt.destroy_controller(cid)
+    ids = [rt.init_controller(c) for c in cfgs]
+    tks = rt.submit_batch(ids, inps)
+    mixed = [rt.fetch(t) for t in tks]
+    for a, m in zip(alone, mixed):
+        np.testing.assert_array_equal(a["grf"], m["grf"])
+        assert a["q"] == m["q"] and a["best_cost"] == m["best_cost"]
+    for cid in ids:
+        rt.destroy_controller(cid)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_plan_replay_matches_direct(rt, use_graph):
+    cfgs = [workloads.config("c1", N=n, H=h, seed=s) for n, h, s in ((900, 10, 1), (2000, 25, 2))]
+    cfgs.append(workloads.config("c2", N=1200, H=8, seed=3))
+    rng = np.random.default_rng(9)
+    inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
+    direct_ids = [rt.init_controller(c) for c in cfgs]
+    plan_ids = [rt.init_controller(c) for c in cfgs]
+    plan = rt.plan_create(plan_ids, use_graph=use_graph)
+    for t in range(3):
+        d = [rt.fetch(x) for x in rt.submit_batch(direct_ids, inps)]
+        p = [rt.fetch(x) for x in rt.plan_submit(plan, inps)]
+        for a, b in zip(d, p):
+            np.testing.assert_array_equal(a["grf"], b["grf"])
+            assert a["q"] == b["q"] and a["tick"] == b["tick"] == t
+    rt.plan_destroy(plan)
+    for cid in direct_ids + plan_ids:
+        rt.destroy_controller(cid)
