@@ -65,26 +65,21 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     rng = np.random.default_rng(cfg["seed"])
     x0 = workloads.initial_state(rng)
     plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
-    v_ref = (0.3, 0.0, 0.0)
-    lat, acts, times = [], [], []
+    loop = binding.ClosedLoop(rt, cid, plant, v_ref=(0.3, 0.0, 0.0), z_ref=workloads.HEIGHT)
+    lat, acts = [], []
     t_start = None
     import torch
+    no_push, push_f = (0.0, 0.0, 0.0), (0.0, push, 0.0)
     for t in range(warmup + ticks):
         if t == warmup:
             torch.cuda.synchronize()
             rt.timing()  # reset the stage-timing accumulators
             t_start = time.perf_counter()
-        x = plant.x
-        inp = workloads.tick_input(x, v_ref=v_ref, p_ref0=(x[0], x[1], workloads.HEIGHT),
-                                   phase_robot=plant.phase, foot_pos=plant.foot_pos)
-        t0 = time.perf_counter_ns()
-        act = rt.fetch(rt.submit_tick(cid, inp))
-        t1 = time.perf_counter_ns()
-        ext = (0.0, push, 0.0) if t >= push_from else (0.0, 0.0, 0.0)
-        plant.step(act, ext_force=ext, v_ref=v_ref)
+        a = loop.step(push_f if t >= push_from else no_push)
         if t >= warmup:
-            lat.append((t1 - t0) * 1e-6)
-            acts.append(act)
+            # submit-to-visible latency as recorded by the runtime
+            lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
+            acts.append((a.flags, a.freq_hz))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     timing = rt.timing()
@@ -125,6 +120,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing", type=int, default=1,
+                    help="HIP events: 0 none, 1 around the rollout stage, 2 around every stage")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -134,7 +131,7 @@ def main():
     import torch
     cfg = workloads.config("c1")
     rt = binding.Runtime(arena_bytes=4 << 30)
-    rt.set_timing(True)
+    rt.set_timing(args.timing)
     elapsed, lat, acts, timing, plant = closed_loop(rt, binding, workloads, cfg, args.steps,
                                                     args.warmup)
     rt.close()
@@ -153,7 +150,7 @@ def main():
                    "N": N, "H": H, "iterations": R, "ticks": args.steps},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": float(np.max(lat))},
         "stage_us": {k: timing[k] * 1e-3 for k in ("noise_ns", "rollout_ns", "select_ns",
-                                                   "update_ns")},
+                                                   "update_ns") if timing[k] > 0},
         "roofline": {"kernel": "k_rollout<float>", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
@@ -162,8 +159,8 @@ def main():
                      "traffic": stored_traffic("k_rollout", "c1"),
                      "flop_per_launch": N * H * FLOP_PER_ROLLOUT_STEP},
         "closed_loop": {"final_x": [round(float(v), 4) for v in plant.x],
-                        "nonfinite_ticks": int(sum(a["flags"] & 1 for a in acts)),
-                        "freq_hz_last": acts[-1]["freq_hz"]},
+                        "nonfinite_ticks": int(sum(f & 1 for f, _ in acts)),
+                        "freq_hz_last": acts[-1][1]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

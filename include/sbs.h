@@ -177,10 +177,17 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
 /* Serving statistics: ticks completed, batches launched, admission waits. */
 int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *admit_waits);
 
-/* Kernel timing: average device time [ns] of each stage's launches since the
- * last call (0 noise, 1 rollout, 2 select, 3 update), measured with HIP
- * events on the runtime stream when enabled. */
-int sbs_set_timing(sbs_runtime *rt, int32_t enable);
+/* Rollout lanes per sample for FP32 controllers: 4 (one lane per leg, for
+ * launches with few samples), 1 (one lane per sample, for throughput), or 0
+ * (automatic: 4 when a launch holds at most 32768 samples).  Results of the
+ * two forms agree within FP32 rounding, not bit for bit. */
+int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
+
+/* Kernel timing with HIP events on the runtime stream: mode 0 off, 1 events
+ * around the rollout stage only, 2 around every stage.  sbs_timing returns
+ * the average device time [ns] of each stage's launches since the last call
+ * (0 noise, 1 rollout, 2 select, 3 update) and resets it. */
+int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
 
 /* Simulated robot for closed-loop runs (host, FP64, not part of the control

@@ -30,7 +30,7 @@ EXPORTED = [
     "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action",
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
         L.sbs_stats.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
         L.sbs_set_timing.argtypes = [vp, i32]
         L.sbs_timing.argtypes = [vp, vp, vp]
+        L.sbs_set_rollout_lanes.argtypes = [vp, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
         L.sbs_last_error.restype = C.c_char_p
@@ -309,8 +310,13 @@ class Runtime:
         _check(lib().sbs_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"ticks": a.value, "batches": b.value, "admit_waits": c.value}
 
-    def set_timing(self, on: bool = True):
-        _check(lib().sbs_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, mode: int = 1):
+        """0 off, 1 events around the rollout stage, 2 around every stage."""
+        _check(lib().sbs_set_timing(self._h, int(mode)))
+
+    def set_rollout_lanes(self, lanes: int = 0):
+        """0 automatic, 1 one lane per sample, 4 one lane per leg."""
+        _check(lib().sbs_set_rollout_lanes(self._h, int(lanes)))
 
     def timing(self):
         avg = np.zeros(4)
@@ -353,3 +359,37 @@ class Plant:
     @property
     def phase(self):
         return int(self.st.phase)
+
+
+class ClosedLoop:
+    """One controller driving a Plant with preallocated C structs: each step
+    copies the plant state into the tick input, runs the tick, and applies
+    the returned action to the plant (for closed-loop runs and benchmarks)."""
+
+    def __init__(self, rt: Runtime, cid: int, plant: Plant, v_ref=(0.0, 0.0, 0.0),
+                 z_ref: float = 0.35, yaw_ref: float = 0.0):
+        self.rt, self.cid, self.plant = rt, cid, plant
+        self.inp = TickInput()
+        self.inp.v_ref[:] = [float(v) for v in v_ref]
+        self.inp.yaw_ref = float(yaw_ref)
+        self.z_ref = float(z_ref)
+        self.act = Action()
+        self.ticket = C.c_uint64()
+        self.ext = np.zeros(3)
+        self.vref = np.array([float(v) for v in v_ref])
+        self._L = lib()
+
+    def step(self, ext_force=(0.0, 0.0, 0.0)) -> Action:
+        st, inp, L = self.plant.st, self.inp, self._L
+        C.memmove(inp.x0, st.x, 96)
+        C.memmove(inp.foot_pos, st.foot_pos, 96)
+        inp.p_ref0[0] = st.x[0]
+        inp.p_ref0[1] = st.x[1]
+        inp.p_ref0[2] = self.z_ref
+        inp.phase_robot = st.phase
+        _check(L.sbs_submit_tick(self.rt._h, self.cid, C.byref(inp), C.byref(self.ticket)))
+        _check(L.sbs_fetch_action(self.rt._h, self.ticket, C.byref(self.act), -1))
+        self.ext[:] = ext_force
+        _check(L.sbs_plant_step(C.byref(self.plant.cfg), C.byref(st), C.byref(self.act),
+                                self.ext.ctypes.data, self.vref.ctypes.data))
+        return self.act

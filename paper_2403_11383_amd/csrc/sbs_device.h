@@ -11,7 +11,7 @@ namespace sbs {
 constexpr int kRollBlock = 64;     // rollouts per workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
 constexpr int kUpdBlock = 256;     // threads per update workgroup
-constexpr int kUpdChunk = 1024;    // samples reduced by one update workgroup
+constexpr int kUpdChunk = 4096;    // active samples reduced by one update workgroup
 constexpr int kSelBlock = 1024;    // threads of the per-controller select block
 constexpr int kResultDoubles = 24; // action record
 constexpr int kItScalars = 16;     // per-iteration scalars
@@ -37,6 +37,7 @@ enum : int {
   IT_FNEW = 5,     // updated frequency
   IT_FLAGS = 6,
   IT_SKIP = 7,     // 1 when no cost was finite: keep the mean
+  IT_NACT = 8,     // number of samples with non-zero weight
 };
 
 struct TickDesc {
@@ -65,7 +66,8 @@ struct TickDesc {
   float *z;              // [H][N][12] noise of the current iteration
   uint32_t *q;           // [N]
   void *J;               // [N] costs, controller precision
-  void *w;               // [N] weights, controller precision
+  void *w;               // [N] weights of the active samples, controller precision
+  uint32_t *act;         // [N] active sample indices in increasing order
   double *sigma;         // [H][12] elite std of the current iteration
   double *partial;       // [H][nchunk][24] update partial sums
   double *it;            // [kItScalars]
@@ -81,7 +83,9 @@ struct LaunchTab {
   int32_t n;
   int32_t r;             // iteration index
   int32_t total_noise, total_roll, total_upd;
-  int32_t pad;
+  int32_t max_h;         // longest horizon among the items
+  int32_t lanes;         // rollout lanes per sample: 1 or 4 (FP32 only)
+  int32_t pad1;
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

@@ -164,9 +164,33 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab) {
 // ---------------------------------------------------------------------------
 // Rollout
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+// FP32 sine and cosine: Cody-Waite reduction by pi/2 (three-part constant,
+// fused multiply-adds) to |r| <= pi/4, Taylor polynomials through r^9 / r^10
+// (truncation below 4e-9), quadrant by rotation.  Accurate to a few ulp for
+// |x| up to ~1e4 rad; beyond that the result stays bounded.
+__device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
+  const float n = __builtin_rintf(x * 0x1.45f306p-1f);
+  float r = __builtin_fmaf(-n, 0x1.921fb6p+0f, x);
+  r = __builtin_fmaf(-n, -0x1.777a5cp-25f, r);
+  r = __builtin_fmaf(-n, -0x1.0p-49f, r);
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);
+  ps = __builtin_fmaf(r2, ps, 0x1.111112p-7f);
+  ps = __builtin_fmaf(r2, ps, -0x1.555556p-3f);
+  const float sn = __builtin_fmaf(r * r2, ps, r);
+  float pc = __builtin_fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);
+  pc = __builtin_fmaf(r2, pc, -0x1.6c16c2p-10f);
+  pc = __builtin_fmaf(r2, pc, 0x1.555556p-5f);
+  pc = __builtin_fmaf(r2, pc, -0.5f);
+  const float cs = __builtin_fmaf(r2, pc, 1.0f);
+  const int q = (int)n;
+  const bool swap = (q & 1) != 0;
+  const float ss = swap ? cs : sn, cc = swap ? sn : cs;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
 __device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
-__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
@@ -192,52 +216,89 @@ __device__ __forceinline__ void friction_clip(T &fx, T &fy, T &fz, T mu) {
   fy *= s;
 }
 
+// Loop-invariant parameters of one controller in the working precision.
+template <typename T>
+struct RollConst {
+  T dt, inv_m, g, mg, mu_f, rho, f_nom;
+  T I[3], iI[3], hip[12], Q[12], Rw[12], pr[3], vr[3], yaw_ref, inv_g;
+  T sigma0;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
+  c.dt = (T)d.dt; c.inv_m = (T)d.inv_mass; c.g = (T)d.gravity; c.mg = (T)(d.mass * d.gravity);
+  c.mu_f = (T)d.mu_fric; c.rho = (T)d.rho; c.f_nom = (T)d.f_nominal; c.inv_g = (T)d.inv_g;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c.I[i] = (T)d.inertia[i]; c.iI[i] = (T)d.inv_inertia[i];
+    c.pr[i] = (T)d.p_ref0[i]; c.vr[i] = (T)d.v_ref[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) { c.hip[i] = (T)d.hip[i]; c.Q[i] = (T)d.Q[i]; c.Rw[i] = (T)d.Rw[i]; }
+  c.yaw_ref = (T)d.yaw_ref;
+  c.sigma0 = (T)d.sigma0;
+}
+
+// One lane per sample.  The block stages the controller's mean (and the elite
+// std of later iterations) in LDS once; each step reads them as broadcasts,
+// and the noise of step j+1 is requested while step j computes.
 template <typename T>
 __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
+  extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
   const int it = find_item(tab.roll_start, tab.n, b);
   const TickDesc &d = tab.desc[tab.item[it]];
-  const int k = (b - tab.roll_start[it]) * kRollBlock + (int)threadIdx.x;
-  if (k >= d.N) return;
   const int N = d.N, H = d.H;
+  T *s_mu = reinterpret_cast<T *>(roll_lds);
+  T *s_sig = s_mu + (size_t)tab.max_h * 12;
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
-  const T* __restrict__ mu = reinterpret_cast<const T *>(d.mu);
-  const float* __restrict__ zb = d.z;
+  {
+    const T *mu = reinterpret_cast<const T *>(d.mu);
+    for (int i = threadIdx.x; i < H * 12; i += kRollBlock) {
+      s_mu[i] = mu[i];
+      s_sig[i] = elite_sigma ? (T)d.sigma[i] : (T)d.sigma0;
+    }
+  }
+  __syncthreads();
+  const int k = (b - tab.roll_start[it]) * kRollBlock + (int)threadIdx.x;
+  if (k >= N) return;
 
+  RollConst<T> c;
+  load_const<T>(d, c);
   const uint32_t q = d.q[k];
-  const T fk = (T)((double)q * d.inv_q_scale);
-  const T half_tst = (q > 0u) ? (T)(d.half_duty / ((double)q * d.inv_q_scale)) : T(0);
-  const T dt = (T)d.dt, inv_m = (T)d.inv_mass, g = (T)d.gravity, inv_g = (T)d.inv_g;
-  const T mg = (T)(d.mass * d.gravity);
-  const T mu_f = (T)d.mu_fric;
-  const T Ix = (T)d.inertia[0], Iy = (T)d.inertia[1], Iz = (T)d.inertia[2];
-  const T iIx = (T)d.inv_inertia[0], iIy = (T)d.inv_inertia[1], iIz = (T)d.inv_inertia[2];
-  const T vrx = (T)d.v_ref[0], vry = (T)d.v_ref[1], vrz = (T)d.v_ref[2];
+  const double fkd = (double)q * d.inv_q_scale;
+  const T fk = (T)fkd;
+  const T half_tst = (q > 0u) ? (T)(d.half_duty / fkd) : T(0);
+  const uint32_t duty_q = d.duty_q;
+  const bool duty_full = d.duty_full != 0;
+  const bool friction = d.friction_on != 0;
 
-  T x[12];
+  T x[12], pf[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) x[c] = (T)d.x0[c];
-  T pf[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) pf[c] = (T)d.foot[c];
+  for (int i = 0; i < 12; ++i) { x[i] = (T)d.x0[i]; pf[i] = (T)d.foot[i]; }
   uint32_t ph[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) ph[l] = d.phase_robot + d.phase_offset[l];
   bool prev[4] = {false, false, false, false};
-  T J = T(0), Jc = T(0);
+  T J = T(0), Jc = T(0), tj = T(0);
+
+  const float4 *zp = reinterpret_cast<const float4 *>(d.z + (size_t)k * 12);
+  const size_t zstride = (size_t)N * 3;  // float4 per step
+  float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
 
   for (int j = 0; j < H; ++j) {
-    // noise of (j, k): three 16-byte loads, consecutive lanes contiguous
-    const float4 *src = reinterpret_cast<const float4 *>(zb + ((size_t)j * N + k) * 12);
-    const float4 z0 = src[0], z1 = src[1], z2 = src[2];
     const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                           z2.x, z2.y, z2.z, z2.w};
+    if (j + 1 < H) {  // prefetch the next step's noise
+      const float4 *zn = zp + (size_t)(j + 1) * zstride;
+      z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
+    }
     // contact schedule
     bool st[4];
     int nst = 0;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      st[l] = d.duty_full ? true : (ph[l] < d.duty_q);
+      st[l] = duty_full || (ph[l] < duty_q);
       nst += st[l] ? 1 : 0;
     }
     // attitude
@@ -245,19 +306,20 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
     sincos_t(x[3], &sr, &cr);
     sincos_t(x[4], &sp, &cp);
     sincos_t(x[5], &sy, &cy);
-    const T R00 = cy * cp, R01 = cy * sp * sr - sy * cr, R02 = cy * sp * cr + sy * sr;
-    const T R10 = sy * cp, R11 = sy * sp * sr + cy * cr, R12 = sy * sp * cr - cy * sr;
+    const T spsr = sp * sr, spcr = sp * cr;
+    const T R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
+    const T R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
     const T R20 = -sp, R21 = cp * sr, R22 = cp * cr;
-    // footholds of legs touching down at this step (Eq. (2))
+    // footholds of the legs touching down at this step (Eq. (2))
     {
       const T zc = x[2] > T(0) ? x[2] : T(0);
-      const T cap = sqrt_t(zc * inv_g);
-      const T bx = x[0] + half_tst * vrx + cap * (x[6] - vrx);
-      const T by = x[1] + half_tst * vry + cap * (x[7] - vry);
+      const T cap = sqrt_t(zc * c.inv_g);
+      const T bx = x[0] + half_tst * c.vr[0] + cap * (x[6] - c.vr[0]);
+      const T by = x[1] + half_tst * c.vr[1] + cap * (x[7] - c.vr[1]);
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
         const bool td = (j > 0) && st[l] && !prev[l];
-        const T hx = (T)d.hip[3 * l], hy = (T)d.hip[3 * l + 1], hz = (T)d.hip[3 * l + 2];
+        const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
         const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
         const T ny = by + R10 * hx + R11 * hy + R12 * hz;
         pf[3 * l + 0] = td ? nx : pf[3 * l + 0];
@@ -266,52 +328,41 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
         prev[l] = st[l];
       }
     }
-    // policy: theta = mu + sigma z, masked by stance and clipped to the cone
+    // policy: theta = mu + sigma z, clipped to the cone, masked by stance
     T u[12];
-    const T *muj = mu + (size_t)j * 12;
+    const T *muj = s_mu + j * 12;
+    const T *sgj = s_sig + j * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const T sig = elite_sigma ? (T)d.sigma[j * 12 + c] : (T)d.sigma0;
-      u[c] = muj[c] + sig * (T)zz[c];
-    }
-    if (d.friction_on) {
+    for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+    if (friction) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], mu_f);
+      for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
     }
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      if (!st[l]) {
-        u[3 * l] = T(0);
-        u[3 * l + 1] = T(0);
-        u[3 * l + 2] = T(0);
-      }
+      u[3 * l] = st[l] ? u[3 * l] : T(0);
+      u[3 * l + 1] = st[l] ? u[3 * l + 1] : T(0);
+      u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
     }
-    // stage cost (Sec. V): tracking error and GRF error to the gravity share
-    const T tj = (T)((double)j * d.dt);
-    const T share = mg / (T)(nst > 1 ? nst : 1);
-    T xr[12];
-    xr[0] = (T)d.p_ref0[0] + tj * vrx;
-    xr[1] = (T)d.p_ref0[1] + tj * vry;
-    xr[2] = (T)d.p_ref0[2] + tj * vrz;
-    xr[3] = T(0);
-    xr[4] = T(0);
-    xr[5] = (T)d.yaw_ref;
-    xr[6] = vrx;
-    xr[7] = vry;
-    xr[8] = vrz;
-    xr[9] = T(0);
-    xr[10] = T(0);
-    xr[11] = T(0);
+    // stage cost (Sec. V)
+    const T share = (nst == 4) ? c.mg * T(0.25) : (nst == 3) ? c.mg / T(3) : (nst == 2) ? c.mg * T(0.5) : c.mg;
     T stage = T(0);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const T e = x[c] - xr[c];
-      stage += (T)d.Q[c] * e * e;
+    {
+      const T e0 = x[0] - (c.pr[0] + tj * c.vr[0]);
+      const T e1 = x[1] - (c.pr[1] + tj * c.vr[1]);
+      const T e2 = x[2] - (c.pr[2] + tj * c.vr[2]);
+      const T e5 = x[5] - c.yaw_ref;
+      const T e6 = x[6] - c.vr[0], e7 = x[7] - c.vr[1], e8 = x[8] - c.vr[2];
+      stage = c.Q[0] * e0 * e0 + c.Q[1] * e1 * e1 + c.Q[2] * e2 * e2 + c.Q[3] * x[3] * x[3] +
+              c.Q[4] * x[4] * x[4] + c.Q[5] * e5 * e5 + c.Q[6] * e6 * e6 + c.Q[7] * e7 * e7 +
+              c.Q[8] * e8 * e8 + c.Q[9] * x[9] * x[9] + c.Q[10] * x[10] * x[10] +
+              c.Q[11] * x[11] * x[11];
     }
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const T ex = u[3 * l], ey = u[3 * l + 1], ez = u[3 * l + 2] - (st[l] ? share : T(0));
-      stage += (T)d.Rw[3 * l] * ex * ex + (T)d.Rw[3 * l + 1] * ey * ey + (T)d.Rw[3 * l + 2] * ez * ez;
+      const T ez = u[3 * l + 2] - (st[l] ? share : T(0));
+      stage += c.Rw[3 * l] * u[3 * l] * u[3 * l] + c.Rw[3 * l + 1] * u[3 * l + 1] * u[3 * l + 1] +
+               c.Rw[3 * l + 2] * ez * ez;
     }
     {  // compensated accumulation
       const T y = stage - Jc;
@@ -319,53 +370,218 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
       Jc = (t - J) - y;
       J = t;
     }
-    // SRBD derivative, Eq. (1)
+    // SRBD derivative, Eq. (1), with world-frame lever arms to the feet
     T Fx = T(0), Fy = T(0), Fz = T(0), tx = T(0), ty = T(0), tz = T(0);
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const T lx = pf[3 * l] - x[0], ly = pf[3 * l + 1] - x[1], lz = pf[3 * l + 2] - x[2];
       const T ux = u[3 * l], uy = u[3 * l + 1], uz = u[3 * l + 2];
-      Fx += ux;
-      Fy += uy;
-      Fz += uz;
+      Fx += ux; Fy += uy; Fz += uz;
       tx += ly * uz - lz * uy;
       ty += lz * ux - lx * uz;
       tz += lx * uy - ly * ux;
     }
-    const T tbx = R00 * tx + R10 * ty + R20 * tz;   // R^T tau_world
+    const T tbx = R00 * tx + R10 * ty + R20 * tz;  // R^T tau_world
     const T tby = R01 * tx + R11 * ty + R21 * tz;
     const T tbz = R02 * tx + R12 * ty + R22 * tz;
     const T wx = x[9], wy = x[10], wz = x[11];
-    const T Iwx = Ix * wx, Iwy = Iy * wy, Iwz = Iz * wz;
+    const T Iwx = c.I[0] * wx, Iwy = c.I[1] * wy, Iwz = c.I[2] * wz;
     const T gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
     const T icp = rcp_t(cp);
-    const T tpn = sp * icp;
     const T a = sr * wy + cr * wz;
-    const T dphi = wx + a * tpn;
+    const T dphi = wx + a * sp * icp;
     const T dth = cr * wy - sr * wz;
     const T dpsi = a * icp;
-    const T dvx = Fx * inv_m, dvy = Fy * inv_m, dvz = Fz * inv_m - g;
-    const T dwx = (tbx - gx) * iIx, dwy = (tby - gy) * iIy, dwz = (tbz - gz) * iIz;
     // explicit Euler
+    x[0] += c.dt * x[6];
+    x[1] += c.dt * x[7];
+    x[2] += c.dt * x[8];
+    x[3] += c.dt * dphi;
+    x[4] += c.dt * dth;
+    x[5] += c.dt * dpsi;
+    x[6] += c.dt * (Fx * c.inv_m);
+    x[7] += c.dt * (Fy * c.inv_m);
+    x[8] += c.dt * (Fz * c.inv_m - c.g);
+    x[9] += c.dt * ((tbx - gx) * c.iI[0]);
+    x[10] += c.dt * ((tby - gy) * c.iI[1]);
+    x[11] += c.dt * ((tbz - gz) * c.iI[2]);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) ph[l] += q;
+    tj += c.dt;
+  }
+  const T df = fk - c.f_nom;
+  J += c.rho * df * df;
+  if (!(J >= T(0)) || !finite_t(J)) J = inf_t<T>();
+  reinterpret_cast<T *>(d.J)[k] = J;
+}
+
+// ---------------------------------------------------------------------------
+// Rollout, four lanes per sample (FP32).  Lane l of a quad owns leg l: its
+// noise, policy, friction clip, foothold, force and torque, its GRF cost and
+// the cost of state group l ([p, Phi, v, omega][l]).  The three attitude
+// sin/cos pairs are computed by lanes 0..2 and broadcast inside the quad;
+// net force and torque are quad sums (DPP).  Every lane integrates the full
+// state from the same quad-uniform values, so the four copies stay
+// identical.  Used when a launch has few samples: four times the waves at
+// roughly half the instructions per lane-step.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  v = v + dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  return v + dpp<0x4E>(v);  // quad_perm [2,3,0,1]
+}
+
+__global__ void __launch_bounds__(kRollBlock) k_rollout_quad(LaunchTab tab) {
+  extern __shared__ __align__(16) unsigned char roll_lds[];
+  constexpr int kPerBlock = kRollBlock / 4;
+  const int b = blockIdx.x;
+  const int it = find_item(tab.roll_start, tab.n, b);
+  const TickDesc &d = tab.desc[tab.item[it]];
+  const int N = d.N, H = d.H;
+  const bool elite_sigma = (d.method == 1) && (tab.r > 0);
+  float *s_mu = reinterpret_cast<float *>(roll_lds);
+  float *s_sig = s_mu + (size_t)tab.max_h * 12;
+  {
+    const float *mu = reinterpret_cast<const float *>(d.mu);
+    for (int i = threadIdx.x; i < H * 12; i += kRollBlock) {
+      s_mu[i] = mu[i];
+      s_sig[i] = elite_sigma ? (float)d.sigma[i] : (float)d.sigma0;
+    }
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 3;
+  const int k = (b - tab.roll_start[it]) * kPerBlock + (int)(threadIdx.x >> 2);
+  if (k >= N) return;  // whole quads leave together
+
+  const float dt = (float)d.dt, inv_m = (float)d.inv_mass, g = (float)d.gravity;
+  const float mg = (float)(d.mass * d.gravity), mu_f = (float)d.mu_fric, inv_g = (float)d.inv_g;
+  const float I0 = (float)d.inertia[0], I1 = (float)d.inertia[1], I2 = (float)d.inertia[2];
+  const float iI0 = (float)d.inv_inertia[0], iI1 = (float)d.inv_inertia[1],
+              iI2 = (float)d.inv_inertia[2];
+  const float vr0 = (float)d.v_ref[0], vr1 = (float)d.v_ref[1], vr2 = (float)d.v_ref[2];
+  const float hx = (float)d.hip[3 * l], hy = (float)d.hip[3 * l + 1], hz = (float)d.hip[3 * l + 2];
+  const float Rw0 = (float)d.Rw[3 * l], Rw1 = (float)d.Rw[3 * l + 1], Rw2 = (float)d.Rw[3 * l + 2];
+  const float Qa = (float)d.Q[3 * l], Qb = (float)d.Q[3 * l + 1], Qc = (float)d.Q[3 * l + 2];
+  // reference of state group l: position (moves with v_ref), attitude (0, 0,
+  // yaw_ref), velocity v_ref, angular velocity 0
+  const float ra0 = (l == 0) ? (float)d.p_ref0[0] : (l == 2) ? vr0 : 0.f;
+  const float ra1 = (l == 0) ? (float)d.p_ref0[1] : (l == 2) ? vr1 : 0.f;
+  const float ra2 = (l == 0) ? (float)d.p_ref0[2] : (l == 1) ? (float)d.yaw_ref : (l == 2) ? vr2 : 0.f;
+  const float rv0 = (l == 0) ? vr0 : 0.f, rv1 = (l == 0) ? vr1 : 0.f, rv2 = (l == 0) ? vr2 : 0.f;
+  const uint32_t q = d.q[k];
+  const double fkd = (double)q * d.inv_q_scale;
+  const float half_tst = (q > 0u) ? (float)(d.half_duty / fkd) : 0.f;
+  const uint32_t duty_q = d.duty_q;
+  const bool duty_full = d.duty_full != 0;
+  const bool friction = d.friction_on != 0;
+
+  float x[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) x[i] = (float)d.x0[i];
+  float pfx = (float)d.foot[3 * l], pfy = (float)d.foot[3 * l + 1], pfz = (float)d.foot[3 * l + 2];
+  uint32_t ph = d.phase_robot + d.phase_offset[l];
+  bool prev = false;
+  float J = 0.f, Jc = 0.f, tj = 0.f;
+
+  const float *zp = d.z + (size_t)k * 12 + 3 * l;
+  const size_t zstride = (size_t)N * 12;
+  float za = zp[0], zb = zp[1], zc = zp[2];
+
+  for (int j = 0; j < H; ++j) {
+    const float z0 = za, z1 = zb, z2 = zc;
+    if (j + 1 < H) {
+      const float *zn = zp + (size_t)(j + 1) * zstride;
+      za = zn[0]; zb = zn[1]; zc = zn[2];
+    }
+    const bool st = duty_full || (ph < duty_q);
+    const float nst = quad_sum(st ? 1.f : 0.f);
+    // attitude: lanes 0, 1, 2 take roll, pitch, yaw
+    const float ang = (l == 0) ? x[3] : (l == 1) ? x[4] : x[5];
+    float sv, cv;
+    sincos_t(ang, &sv, &cv);
+    const float sr = dpp<0x00>(sv), cr = dpp<0x00>(cv);
+    const float sp = dpp<0x55>(sv), cp = dpp<0x55>(cv);
+    const float sy = dpp<0xAA>(sv), cy = dpp<0xAA>(cv);
+    const float spsr = sp * sr, spcr = sp * cr;
+    const float R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
+    const float R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
+    const float R20 = -sp, R21 = cp * sr, R22 = cp * cr;
+    // foothold of this leg when it touches down (Eq. (2))
+    {
+      const float zcm = x[2] > 0.f ? x[2] : 0.f;
+      const float cap = sqrt_t(zcm * inv_g);
+      const bool td = (j > 0) && st && !prev;
+      const float nx = x[0] + half_tst * vr0 + cap * (x[6] - vr0) + R00 * hx + R01 * hy + R02 * hz;
+      const float ny = x[1] + half_tst * vr1 + cap * (x[7] - vr1) + R10 * hx + R11 * hy + R12 * hz;
+      pfx = td ? nx : pfx;
+      pfy = td ? ny : pfy;
+      pfz = td ? 0.f : pfz;
+      prev = st;
+    }
+    // policy of this leg
+    const int o = j * 12 + 3 * l;
+    float ux = s_mu[o] + s_sig[o] * z0;
+    float uy = s_mu[o + 1] + s_sig[o + 1] * z1;
+    float uz = s_mu[o + 2] + s_sig[o + 2] * z2;
+    if (friction) friction_clip<float>(ux, uy, uz, mu_f);
+    ux = st ? ux : 0.f;
+    uy = st ? uy : 0.f;
+    uz = st ? uz : 0.f;
+    // stage cost: this leg's GRF error and state group l's tracking error
+    const float share = (nst > 3.5f) ? mg * 0.25f : (nst > 2.5f) ? mg / 3.f : (nst > 1.5f) ? mg * 0.5f : mg;
+    const float ez = uz - (st ? share : 0.f);
+    const float ga = (l == 0) ? x[0] : (l == 1) ? x[3] : (l == 2) ? x[6] : x[9];
+    const float gb = (l == 0) ? x[1] : (l == 1) ? x[4] : (l == 2) ? x[7] : x[10];
+    const float gc = (l == 0) ? x[2] : (l == 1) ? x[5] : (l == 2) ? x[8] : x[11];
+    const float e0 = ga - (ra0 + tj * rv0), e1 = gb - (ra1 + tj * rv1), e2 = gc - (ra2 + tj * rv2);
+    const float stage = Qa * e0 * e0 + Qb * e1 * e1 + Qc * e2 * e2 + Rw0 * ux * ux + Rw1 * uy * uy +
+                        Rw2 * ez * ez;
+    {
+      const float y = stage - Jc;
+      const float t = J + y;
+      Jc = (t - J) - y;
+      J = t;
+    }
+    // net force and torque about the CoM (world frame)
+    const float lx = pfx - x[0], ly = pfy - x[1], lz = pfz - x[2];
+    const float Fx = quad_sum(ux), Fy = quad_sum(uy), Fz = quad_sum(uz);
+    const float tx = quad_sum(ly * uz - lz * uy);
+    const float ty = quad_sum(lz * ux - lx * uz);
+    const float tz = quad_sum(lx * uy - ly * ux);
+    const float tbx = R00 * tx + R10 * ty + R20 * tz;
+    const float tby = R01 * tx + R11 * ty + R21 * tz;
+    const float tbz = R02 * tx + R12 * ty + R22 * tz;
+    const float wx = x[9], wy = x[10], wz = x[11];
+    const float Iwx = I0 * wx, Iwy = I1 * wy, Iwz = I2 * wz;
+    const float gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
+    const float icp = rcp_t(cp);
+    const float a = sr * wy + cr * wz;
+    const float dphi = wx + a * sp * icp;
+    const float dth = cr * wy - sr * wz;
+    const float dpsi = a * icp;
     x[0] += dt * x[6];
     x[1] += dt * x[7];
     x[2] += dt * x[8];
     x[3] += dt * dphi;
     x[4] += dt * dth;
     x[5] += dt * dpsi;
-    x[6] += dt * dvx;
-    x[7] += dt * dvy;
-    x[8] += dt * dvz;
-    x[9] += dt * dwx;
-    x[10] += dt * dwy;
-    x[11] += dt * dwz;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) ph[l] += q;
+    x[6] += dt * (Fx * inv_m);
+    x[7] += dt * (Fy * inv_m);
+    x[8] += dt * (Fz * inv_m - g);
+    x[9] += dt * ((tbx - gx) * iI0);
+    x[10] += dt * ((tby - gy) * iI1);
+    x[11] += dt * ((tbz - gz) * iI2);
+    ph += q;
+    tj += dt;
   }
-  const T df = fk - (T)d.f_nominal;
-  J += (T)d.rho * df * df;
-  if (!(J >= T(0)) || !finite_t(J)) J = inf_t<T>();
-  reinterpret_cast<T *>(d.J)[k] = J;
+  float Jt = quad_sum(J);
+  const float df = (float)fkd - (float)d.f_nominal;
+  Jt += (float)d.rho * df * df;
+  if (!(Jt >= 0.f) || !finite_t(Jt)) Jt = inf_t<float>();
+  if (l == 0) reinterpret_cast<float *>(d.J)[k] = Jt;
 }
 
 // ---------------------------------------------------------------------------
@@ -423,32 +639,88 @@ __device__ __forceinline__ uint64_t key_bits(float v) { return (uint64_t)__float
 __device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
 
 // ---------------------------------------------------------------------------
-// Select: one workgroup per controller
+// Select: one workgroup per controller.  Thread t owns the contiguous samples
+// [t P, (t+1) P), P = ceil(N / 1024), held in registers for N <= 16384 (read
+// again from memory beyond).  Output: the samples with non-zero weight in
+// index order (act, actw) -- every MPPI sample whose weight does not
+// underflow, the K_e elites, or the best sample -- and per-iteration scalars.
 // ---------------------------------------------------------------------------
+constexpr int kSelPer = 16;
+
+template <typename V>
+__device__ __forceinline__ V wave_incl_scan(V v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const V u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix of v over the threads of the block, and the block total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wave_tot,
+                                                    uint32_t *total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  __syncthreads();
+  if (lane == 63) wave_tot[wid] = incl;
+  __syncthreads();
+  uint32_t before = incl - v, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const uint32_t c = wave_tot[i];
+    before += (i < wid) ? c : 0u;
+    tot += c;
+  }
+  *total = tot;
+  return before;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
   const TickDesc &d = tab.desc[tab.item[blockIdx.x]];
-  const int N = d.N, tid = threadIdx.x, nt = blockDim.x;
-  const T *J = reinterpret_cast<const T *>(d.J);
-  T *w = reinterpret_cast<T *>(d.w);
+  const int N = d.N, tid = threadIdx.x;
+  const T *Jg = reinterpret_cast<const T *>(d.J);
+  T *actw = reinterpret_cast<T *>(d.w);
+  uint32_t *act = d.act;
   const int r = tab.r;
   __shared__ double lds_d[kSelBlock / 64];
   __shared__ T lds_v[kSelBlock / 64];
   __shared__ int lds_k[kSelBlock / 64];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t s_digit, s_rank;
-  __shared__ uint32_t wave_cnt[kSelBlock / 64];
+  __shared__ uint32_t wave_tot[kSelBlock / 64];
+
+  const int per = (N + kSelBlock - 1) / kSelBlock;
+  const int k0 = tid * per;
+  const int kend = (k0 + per < N) ? k0 + per : N;  // may be <= k0 for idle threads
+  T Jr[kSelPer];
+#pragma unroll
+  for (int i = 0; i < kSelPer; ++i) Jr[i] = (k0 + i < kend) ? Jg[k0 + i] : inf_t<T>();
+  // SEL_FOR(...): visit this thread's samples in index order with the cost
+  // in `cv` and the local position in `i` (registers first, then memory)
+#define SEL_FOR(...)                                                   \
+  _Pragma("unroll") for (int i = 0; i < kSelPer; ++i) {                \
+    if (i < per && k0 + i < kend) {                                    \
+      const T cv = Jr[i];                                              \
+      __VA_ARGS__                                                      \
+    }                                                                  \
+  }                                                                    \
+  for (int i = kSelPer; i < per && k0 + i < kend; ++i) {               \
+    const T cv = Jg[k0 + i];                                           \
+    __VA_ARGS__                                                        \
+  }
 
   if (d.dbg_J) {
-    for (int k = tid; k < N; k += nt) {
-      d.dbg_J[(size_t)r * N + k] = (double)J[k];
+    for (int k = tid; k < N; k += kSelBlock) {
+      d.dbg_J[(size_t)r * N + k] = (double)Jg[k];
       d.dbg_q[(size_t)r * N + k] = d.q[k];
     }
   }
-  // lowest cost and its index
+  // lowest cost and its index (lowest index on ties)
   T bv = inf_t<T>();
   int bk = 0x7fffffff;
-  for (int k = tid; k < N; k += nt) argmin_combine(bv, bk, J[k], k);
+  SEL_FOR(argmin_combine(bv, bk, cv, k0 + i);)
   block_argmin(bv, bk, lds_v, lds_k);
   const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
   const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
@@ -456,47 +728,69 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
   const bool skip = !finite_t(bv);
 
   double omega = 0.0, fnew = cur_mf, mf_next = cur_mf, sf_next = cur_sf;
+  uint32_t nact = 0;
   if (skip) {
-    for (int k = tid; k < N; k += nt) w[k] = T(0);
-  } else if (d.method == 0) {  // MPPI
+    nact = 0;
+  } else if (d.method == 0) {  // MPPI: w_k = exp(-(J_k - beta) / lambda), FP64 normaliser
     const T il = (T)d.inv_lambda;
     double sw = 0.0, swf = 0.0;
-    for (int k = tid; k < N; k += nt) {
-      const T wk = exp_t((bv - J[k]) * il);
-      w[k] = wk;
-      sw += (double)wk;
-      swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
-    }
+    uint32_t cnt = 0;
+    SEL_FOR(cnt += (exp_t((bv - cv) * il) != T(0)) ? 1u : 0u;)
+    uint32_t tot;
+    uint32_t pos = block_excl_scan(cnt, wave_tot, &tot);
+    SEL_FOR(
+      const T wk = exp_t((bv - cv) * il);
+      if (wk != T(0)) {
+        const int k = k0 + i;
+        act[pos] = (uint32_t)k;
+        actw[pos] = wk;
+        ++pos;
+        sw += (double)wk;
+        swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+      })
+    nact = tot;
     sw = block_sum(sw, lds_d);
     swf = block_sum(swf, lds_d);
     omega = sw;
     fnew = swf / sw;
     mf_next = fnew;
-  } else if (d.method == 2) {  // naive: best sample
-    for (int k = tid; k < N; k += nt) w[k] = (k == bk) ? T(1) : T(0);
+  } else if (d.method == 2) {  // naive: the best sample
+    if (tid == 0) {
+      act[0] = (uint32_t)bk;
+      actw[0] = T(1);
+    }
+    nact = 1;
     omega = 1.0;
     fnew = (double)d.q[bk] * d.inv_q_scale;
     mf_next = fnew;
-  } else {  // elite: K_e smallest (cost, index) by radix selection on cost bits
+  } else {  // elite: the K_e smallest (cost, index) by radix selection
     const int nbits = (int)sizeof(T) * 8;
     uint64_t prefix = 0, mask = 0;
     uint32_t rank = (uint32_t)d.Ke;
+    const int lane = tid & 63, wid = tid >> 6;
     for (int shift = nbits - 8; shift >= 0; shift -= 8) {
-      for (int i = tid; i < 256; i += nt) hist[i] = 0u;
+      for (int i = tid; i < 256; i += kSelBlock) hist[i] = 0u;
       __syncthreads();
-      for (int k = tid; k < N; k += nt) {
-        const uint64_t key = key_bits(J[k]);
-        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-      }
+      SEL_FOR(
+        const uint64_t key = key_bits(cv);
+        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);)
       __syncthreads();
-      if (tid == 0) {
-        uint32_t cum = 0, dg = 0;
-        for (dg = 0; dg < 255u; ++dg) {
-          if (cum + hist[dg] >= rank) break;
-          cum += hist[dg];
+      if (wid == 0) {  // first digit whose cumulative count reaches rank
+        const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                       h3 = hist[4 * lane + 3];
+        const uint32_t sum = h0 + h1 + h2 + h3;
+        const uint32_t incl = wave_incl_scan(sum);
+        const uint32_t excl = incl - sum;
+        if (excl < rank && rank <= incl) {
+          uint32_t cum = excl, dg = 0;
+          const uint32_t hh[4] = {h0, h1, h2, h3};
+          for (dg = 0; dg < 3u; ++dg) {
+            if (cum + hh[dg] >= rank) break;
+            cum += hh[dg];
+          }
+          s_digit = 4u * (uint32_t)lane + dg;
+          s_rank = rank - cum;
         }
-        s_digit = dg;
-        s_rank = rank - cum;
       }
       __syncthreads();
       prefix |= (uint64_t)s_digit << shift;
@@ -504,39 +798,41 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
       rank = s_rank;
       __syncthreads();
     }
-    // prefix is the K_e-th smallest cost; the first `rank` ties (by index)
-    // are elite.
+    // prefix is the K_e-th smallest cost; the first `rank` ties by index are in
     const uint64_t thr = prefix;
     const uint32_t need = rank;
-    uint32_t ties_before = 0;
+    uint32_t ntie = 0, nel = 0;
+    SEL_FOR(ntie += (key_bits(cv) == thr) ? 1u : 0u;)
+    uint32_t tot;
+    uint32_t tb = block_excl_scan(ntie, wave_tot, &tot);  // ties before this thread
+    SEL_FOR(
+      const uint64_t key = key_bits(cv);
+      bool el = key < thr;
+      if (key == thr) {
+        el = tb < need;
+        ++tb;
+      }
+      nel += el ? 1u : 0u;)
+    uint32_t pos = block_excl_scan(nel, wave_tot, &tot);
+    tb -= ntie;
     double s1 = 0.0, s2 = 0.0;
-    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
-    for (int base = 0; base < N; base += nt) {
-      const int k = base + tid;
-      const uint64_t key = (k < N) ? key_bits(J[k]) : ~0ull;
-      const bool tie = (k < N) && (key == thr);
-      const uint64_t bal = __ballot(tie);
-      const uint32_t in_wave = __popcll(bal & ((1ull << lane) - 1ull));
-      __syncthreads();
-      if (lane == 0) wave_cnt[wid] = __popcll(bal);
-      __syncthreads();
-      uint32_t before = ties_before + in_wave;
-      uint32_t total = 0;
-      for (int i = 0; i < nw; ++i) {
-        if (i < wid) before += wave_cnt[i];
-        total += wave_cnt[i];
+    SEL_FOR(
+      const uint64_t key = key_bits(cv);
+      bool el = key < thr;
+      if (key == thr) {
+        el = tb < need;
+        ++tb;
       }
-      ties_before += total;
-      if (k < N) {
-        const bool el = (key < thr) || (tie && before < need);
-        w[k] = el ? T(1) : T(0);
-        if (el) {
-          const double f = (double)d.q[k] * d.inv_q_scale;
-          s1 += f;
-          s2 += f * f;
-        }
-      }
-    }
+      if (el) {
+        const int k = k0 + i;
+        act[pos] = (uint32_t)k;
+        actw[pos] = T(1);
+        ++pos;
+        const double f = (double)d.q[k] * d.inv_q_scale;
+        s1 += f;
+        s2 += f * f;
+      })
+    nact = tot;
     s1 = block_sum(s1, lds_d);
     s2 = block_sum(s2, lds_d);
     const double ke = (double)d.Ke;
@@ -549,6 +845,7 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
     const double sfl = __builtin_sqrt(fv);
     sf_next = sfl > d.sigma_min_f ? sfl : d.sigma_min_f;
   }
+#undef SEL_FOR
   if (tid == 0) {
     d.it[IT_BETA] = (double)bv;
     d.it[IT_OMEGA] = omega;
@@ -558,15 +855,16 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
     d.it[IT_SIGF] = sf_next;
     d.it[IT_SKIP] = skip ? 1.0 : 0.0;
     d.it[IT_FLAGS] = (double)((int)prev_flags | (skip ? 1 : 0));
+    d.it[IT_NACT] = (double)nact;
   }
 }
 
-
 // ---------------------------------------------------------------------------
-// Update: S1[j][d] = sum_k w_k z_kjd (and S2 = sum_k w_k z_kjd^2 for elite),
-// reduced per (step, chunk) workgroup, then combined by the last workgroup of
-// the controller to arrive, which writes the new mean, the elite std, the
-// action and the warm-started mean.
+// Update: S1[j][c] = sum over active samples of w_k z_kjc (and S2 = sum of
+// w_k z_kjc^2 for elite).  Workgroup (j, chunk) reduces kUpdChunk active
+// samples of step j; chunks past the active count only arrive.  The last
+// workgroup of the controller to arrive forms the new mean (and elite std),
+// the action and the warm-started mean.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
 #pragma unroll
@@ -588,67 +886,79 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
   const int N = d.N, H = d.H, tid = threadIdx.x;
   const int r = tab.r;
   const bool elite = (d.method == 1);
-  const T *w = reinterpret_cast<const T *>(d.w);
+  const T *actw = reinterpret_cast<const T *>(d.w);
+  const uint32_t *act = d.act;
   __shared__ double lds[kUpdBlock / 64][24];
   __shared__ int s_last;
+  const int nact = (int)d.it[IT_NACT];
 
-  const int k0 = ch * kUpdChunk;
-  const int k1 = (k0 + kUpdChunk < N) ? k0 + kUpdChunk : N;
-  double out1[12], out2[12];
-  if (elite) {
-    double a1[12], a2[12];
+  const int a0 = ch * kUpdChunk;
+  if (a0 < nact) {
+    const int a1 = (a0 + kUpdChunk < nact) ? a0 + kUpdChunk : nact;
+    double out1[12], out2[12];
+    const float *zj = d.z + (size_t)j * N * 12;
+    // four gathers in flight per thread: indices and weights first, then rows
+    double s1[12], s2[12];
+    T f1[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) { a1[c] = 0.0; a2[c] = 0.0; }
-    for (int k = k0 + tid; k < k1; k += kUpdBlock) {
-      const T wk = w[k];
-      if (wk != T(0)) {
-        const float4 *src = reinterpret_cast<const float4 *>(d.z + ((size_t)j * N + k) * 12);
-        const float4 z0 = src[0], z1 = src[1], z2 = src[2];
-        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                              z2.x, z2.y, z2.z, z2.w};
+    for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
+    for (int a = a0 + tid; a < a1; a += 4 * kUpdBlock) {
+      uint32_t ka[4];
+      T wa[4];
+      bool va[4];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const double zc = (double)zz[c];
-          a1[c] += zc;
-          a2[c] += zc * zc;
+      for (int u = 0; u < 4; ++u) {
+        const int aa = a + u * kUpdBlock;
+        va[u] = aa < a1;
+        ka[u] = va[u] ? act[aa] : 0u;
+        wa[u] = va[u] ? actw[aa] : T(0);
+      }
+      float4 zl[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
+        zl[u][0] = src[0];
+        zl[u][1] = src[1];
+        zl[u][2] = src[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!va[u]) continue;
+        const float zz[12] = {zl[u][0].x, zl[u][0].y, zl[u][0].z, zl[u][0].w,
+                              zl[u][1].x, zl[u][1].y, zl[u][1].z, zl[u][1].w,
+                              zl[u][2].x, zl[u][2].y, zl[u][2].z, zl[u][2].w};
+        if (elite) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            const double zc = (double)zz[c];
+            s1[c] += zc;
+            s2[c] += zc * zc;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) f1[c] += wa[u] * (T)zz[c];
         }
       }
     }
+    if (elite) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) { out1[c] = a1[c]; out2[c] = a2[c]; }
-  } else {
-    T a1[12];
+      for (int c = 0; c < 12; ++c) { out1[c] = wave_sum(s1[c]); out2[c] = wave_sum(s2[c]); }
+    } else {
+      // reduce in the working precision within the wave, FP64 across waves
 #pragma unroll
-    for (int c = 0; c < 12; ++c) a1[c] = T(0);
-    for (int k = k0 + tid; k < k1; k += kUpdBlock) {
-      const T wk = w[k];
-      if (wk != T(0)) {
-        const float4 *src = reinterpret_cast<const float4 *>(d.z + ((size_t)j * N + k) * 12);
-        const float4 z0 = src[0], z1 = src[1], z2 = src[2];
-        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                              z2.x, z2.y, z2.z, z2.w};
-#pragma unroll
-        for (int c = 0; c < 12; ++c) a1[c] += wk * (T)zz[c];
-      }
+      for (int c = 0; c < 12; ++c) { out1[c] = (double)wave_sum(f1[c]); out2[c] = 0.0; }
     }
-    // reduce in the working precision within the wave, then FP64 across
+    const int lane = tid & 63, wid = tid >> 6;
+    if (lane == 0) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) { out1[c] = (double)wave_sum(a1[c]); out2[c] = 0.0; }
-  }
-  const int lane = tid & 63, wid = tid >> 6;
-  if (elite) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) { out1[c] = wave_sum(out1[c]); out2[c] = wave_sum(out2[c]); }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
-  }
-  __syncthreads();
-  if (tid < 24) {
-    double s = 0.0;
-    for (int i = 0; i < kUpdBlock / 64; ++i) s += lds[i][tid];
-    d.partial[((size_t)j * d.nchunk + ch) * 24 + tid] = s;
+      for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
+    }
+    __syncthreads();
+    if (tid < 24) {
+      double sacc = 0.0;
+      for (int i = 0; i < kUpdBlock / 64; ++i) sacc += lds[i][tid];
+      d.partial[((size_t)j * d.nchunk + ch) * 24 + tid] = sacc;
+    }
   }
   // arrival: the last workgroup of this controller combines
   __threadfence();
@@ -661,9 +971,10 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
   if (!s_last) return;
   __threadfence();
 
-  __shared__ double newmu[kMaxH * 12];
+  extern __shared__ double newmu[];  // [max_h * 12], used by the last workgroup only
   const bool skip = d.it[IT_SKIP] != 0.0;
   const double omega = d.it[IT_OMEGA];
+  const int nch = (nact + kUpdChunk - 1) / kUpdChunk;
   T *mu = reinterpret_cast<T *>(d.mu);
   for (int idx = tid; idx < H * 12; idx += kUpdBlock) {
     const int jj = idx / 12, c = idx - jj * 12;
@@ -671,10 +982,10 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
     double m_new = m_old;
     if (!skip) {
       double s1 = 0.0, s2 = 0.0;
-      for (int cc = 0; cc < d.nchunk; ++cc) {
-        const double *p = d.partial + ((size_t)jj * d.nchunk + cc) * 24;
-        s1 += p[c];
-        s2 += p[12 + c];
+      const double *p = d.partial + (size_t)jj * d.nchunk * 24;
+      for (int cc = 0; cc < nch; ++cc) {
+        s1 += p[cc * 24 + c];
+        s2 += p[cc * 24 + 12 + c];
       }
       if (elite) {
         const double sig = (r == 0) ? d.sigma0 : d.sigma[idx];
@@ -729,26 +1040,33 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (called by the runtime)
 // ---------------------------------------------------------------------------
-hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s,
-                            hipEvent_t *ev /* 5 events or null */) {
+// timing: 0 none; 1 two events around the rollout stage (ev[0], ev[1]);
+// 2 five events around the four stages (ev[0..4]).
+hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
+                            hipEvent_t *ev) {
   if (tab.n == 0) return hipSuccess;
-  if (ev) (void)hipEventRecord(ev[0], s);
+  const size_t roll_lds = (size_t)tab.max_h * 12 * 2 * (precision == 1 ? 8 : 4);
+  const size_t upd_lds = (size_t)tab.max_h * 12 * 8;
+  if (timing == 2) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_noise, dim3(tab.total_noise), dim3(kNoiseBlock), 0, s, tab);
-  if (ev) (void)hipEventRecord(ev[1], s);
-  if (precision == 1) {
-    hipLaunchKernelGGL(k_rollout<double>, dim3(tab.total_roll), dim3(kRollBlock), 0, s, tab);
-    if (ev) (void)hipEventRecord(ev[2], s);
+  if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 1 : 0], s);
+  if (precision == 1)
+    hipLaunchKernelGGL(k_rollout<double>, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
+  else if (tab.lanes == 4)
+    hipLaunchKernelGGL(k_rollout_quad, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
+  else
+    hipLaunchKernelGGL(k_rollout<float>, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
+  if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 2 : 1], s);
+  if (precision == 1)
     hipLaunchKernelGGL(k_select<double>, dim3(tab.n), dim3(kSelBlock), 0, s, tab);
-    if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_update<double>, dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab);
-  } else {
-    hipLaunchKernelGGL(k_rollout<float>, dim3(tab.total_roll), dim3(kRollBlock), 0, s, tab);
-    if (ev) (void)hipEventRecord(ev[2], s);
+  else
     hipLaunchKernelGGL(k_select<float>, dim3(tab.n), dim3(kSelBlock), 0, s, tab);
-    if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_update<float>, dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab);
-  }
-  if (ev) (void)hipEventRecord(ev[4], s);
+  if (timing == 2) (void)hipEventRecord(ev[3], s);
+  if (precision == 1)
+    hipLaunchKernelGGL(k_update<double>, dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab);
+  else
+    hipLaunchKernelGGL(k_update<float>, dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab);
+  if (timing == 2) (void)hipEventRecord(ev[4], s);
   return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@
 #include "sbs_device.h"
 
 namespace sbs {
-hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
+                            hipEvent_t *ev);
 hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s);
 }
 
@@ -62,6 +63,8 @@ int64_t now_ns() {
 }
 
 constexpr uint64_t kAlign = 256;
+// auto policy: four lanes per sample up to this many samples in one launch
+constexpr long long kQuadMaxSamples = 32768;
 uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
 
 // First-fit allocator over [0, size) with coalescing frees.
@@ -153,7 +156,7 @@ struct Layout {
 };
 
 struct ItemWs {
-  uint64_t z, q, J, w, sigma, partial, it, bytes;
+  uint64_t z, q, J, w, act, sigma, partial, it, bytes;
 };
 
 ItemWs item_ws(const sbs_controller_cfg &c) {
@@ -166,6 +169,7 @@ ItemWs item_ws(const sbs_controller_cfg &c) {
   o.q = p; p = align_up(p + N * 4);
   o.J = p; p = align_up(p + N * ts);
   o.w = p; p = align_up(p + N * ts);
+  o.act = p; p = align_up(p + N * 4);
   o.sigma = p; p = align_up(p + H * 12 * 8);
   o.partial = p; p = align_up(p + H * nchunk * 24 * 8);
   o.it = p; p = align_up(p + kItScalars * 8);
@@ -209,6 +213,7 @@ struct sbs_runtime {
   char *arena = nullptr;
   Carver dev_alloc;
   char *pinned = nullptr;
+  char *pinned_dev = nullptr;  // device-visible address of the pinned block
   Carver host_alloc;
   hipStream_t streams[2] = {nullptr, nullptr};
   int nstreams = 1;
@@ -228,7 +233,8 @@ struct sbs_runtime {
   std::atomic<bool> stop{false};
   uint64_t n_ticks = 0, n_batches = 0, n_admit_waits = 0;
   // timing
-  bool timing = false;
+  int timing = 0;  // 0 off, 1 rollout stage, 2 all stages
+  int rollout_lanes = 0;  // 0 auto, 1, 4
   double stage_ns[4] = {0, 0, 0, 0};
   uint64_t stage_n[4] = {0, 0, 0, 0};
 };
@@ -352,6 +358,7 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   d->q = reinterpret_cast<uint32_t *>(dev_item + w.q);
   d->J = dev_item + w.J;
   d->w = dev_item + w.w;
+  d->act = reinterpret_cast<uint32_t *>(dev_item + w.act);
   d->sigma = reinterpret_cast<double *>(dev_item + w.sigma);
   d->partial = reinterpret_cast<double *>(dev_item + w.partial);
   d->it = reinterpret_cast<double *>(dev_item + w.it);
@@ -393,15 +400,17 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
                                                    const std::vector<const Controller *> &cs,
                                                    const std::vector<const sbs_tick_input *> &ins,
                                                    const std::vector<uint32_t> &ticks,
-                                                   const Layout &L, char *host, char *dev) {
+                                                   const Layout &L, char *host, char *dev,
+                                                   char *host_dev) {
   const int n = (int)cs.size();
   int rmax = 1;
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
   TickDesc *hd = reinterpret_cast<TickDesc *>(host + L.desc);
   for (int i = 0; i < n; ++i) {
+    // the action record goes straight to pinned host memory (no copy back)
     fill_desc(rt, *cs[i], item_ws(cs[i]->cfg), dev + L.item_off[i],
-              reinterpret_cast<double *>(dev + L.results) + (size_t)i * kResultDoubles, *ins[i],
-              ticks[i], i, &hd[i]);
+              reinterpret_cast<double *>(host_dev + L.results) + (size_t)i * kResultDoubles,
+              *ins[i], ticks[i], i, &hd[i]);
   }
   std::vector<std::pair<LaunchTab, int>> out;
   const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
@@ -417,12 +426,24 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
       int m = (int)idx.size();
+      int max_h = 1;
+      // four lanes per sample when the launch has few samples (latency
+      // bound); one lane per sample otherwise
+      long long nsum = 0;
+      for (int t = 0; t < m; ++t) nsum += cs[idx[t]]->cfg.N;
+      int lanes = 1;
+      if (prec == SBS_FP32) {
+        if (rt->rollout_lanes == 4) lanes = 4;
+        else if (rt->rollout_lanes == 0 && nsum <= kQuadMaxSamples) lanes = 4;
+      }
+      const int per_block = kRollBlock / lanes;
       ns[0] = rs[0] = us[0] = 0;
       for (int t = 0; t < m; ++t) {
+        max_h = std::max(max_h, cs[idx[t]]->cfg.H);
         const sbs_controller_cfg &c = cs[idx[t]]->cfg;
         item[t] = idx[t];
         ns[t + 1] = ns[t] + c.H * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
-        rs[t + 1] = rs[t] + (c.N + kRollBlock - 1) / kRollBlock;
+        rs[t + 1] = rs[t] + (c.N + per_block - 1) / per_block;
         us[t + 1] = us[t] + c.H * ((c.N + kUpdChunk - 1) / kUpdChunk);
       }
       if (m == 0) continue;
@@ -432,6 +453,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.total_noise = ns[m];
       tab.total_roll = rs[m];
       tab.total_upd = us[m];
+      tab.max_h = max_h;
+      tab.lanes = lanes;
       tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
       tab.item = reinterpret_cast<const int32_t *>(dev + off);
       tab.noise_start = tab.item + n;
@@ -444,13 +467,16 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
 }
 
 void record_timing(sbs_runtime *rt, Batch &b) {
-  // events come in groups of 5 around the 4 stages
-  for (size_t g = 0; g + 5 <= b.timing.size(); g += 5) {
-    for (int s = 0; s < 4; ++s) {
+  // mode 2: groups of 5 events around the 4 stages; mode 1: pairs around the
+  // rollout stage
+  const size_t g = rt->timing == 2 ? 5 : 2;
+  for (size_t o = 0; o + g <= b.timing.size(); o += g) {
+    for (size_t s = 0; s + 1 < g; ++s) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, b.timing[g + s], b.timing[g + s + 1]) == hipSuccess) {
-        rt->stage_ns[s] += (double)ms * 1e6;
-        rt->stage_n[s] += 1;
+      const int stage = g == 5 ? (int)s : 1;
+      if (hipEventElapsedTime(&ms, b.timing[o + s], b.timing[o + s + 1]) == hipSuccess) {
+        rt->stage_ns[stage] += (double)ms * 1e6;
+        rt->stage_n[stage] += 1;
       }
     }
   }
@@ -529,7 +555,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   char *host = rt->pinned + host_off;
   std::vector<uint32_t> ticks;
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
-  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev);
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off);
   hipStream_t s = rt->streams[slot];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -549,14 +575,12 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     hipEvent_t *ev = nullptr;
     if (rt->timing) {
       size_t base = b->timing.size();
-      for (int i = 0; i < 5; ++i) b->timing.push_back(take_event(rt));
+      const int ne = rt->timing == 2 ? 5 : 2;
+      for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
       ev = &b->timing[base];
     }
-    e = launch_iteration(tp.first, tp.second, s, ev);
+    e = launch_iteration(tp.first, tp.second, s, rt->timing, ev);
   }
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(host + L.results, dev + L.results, ids.size() * kResultDoubles * 8,
-                       hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
   if (e != hipSuccess) {
     // the stream may still run what was enqueued: wait before freeing
@@ -678,8 +702,14 @@ int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *st
   rt->arena = static_cast<char *>(arena);
   rt->dev_alloc.reset(arena_bytes);
   const uint64_t pinned_bytes = 64ull << 20;
-  if (hipHostMalloc((void **)&rt->pinned, pinned_bytes, hipHostMallocDefault) != hipSuccess)
+  // coherent (fine-grained) so that kernels can write action records into it
+  if (hipHostMalloc((void **)&rt->pinned, pinned_bytes,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return fail(SBS_EDEVICE, "hipHostMalloc of %llu bytes failed", (unsigned long long)pinned_bytes);
+  if (hipHostGetDevicePointer((void **)&rt->pinned_dev, rt->pinned, 0) != hipSuccess) {
+    (void)hipHostFree(rt->pinned);
+    return fail(SBS_EDEVICE, "hipHostGetDevicePointer failed");
+  }
   rt->host_alloc.reset(pinned_bytes);
   rt->streams[0] = static_cast<hipStream_t>(stream);
   rt->streams[1] = static_cast<hipStream_t>(stream2);
@@ -1036,7 +1066,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   sbs_tick_input in{};
   std::vector<const sbs_tick_input *> ins{&in};
   std::vector<uint32_t> ticks{tick};
-  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev);
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + hoff);
   TickDesc *hd = reinterpret_cast<TickDesc *>(host);
   LaunchTab tab = tabs[0].first;
   tab.r = (int32_t)r;
@@ -1074,10 +1104,20 @@ int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *adm
   return SBS_OK;
 }
 
-int sbs_set_timing(sbs_runtime *rt, int32_t enable) {
+int sbs_set_timing(sbs_runtime *rt, int32_t mode) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  if (mode < 0 || mode > 2) return fail(SBS_EINVAL, "timing mode must be 0, 1 or 2");
   std::lock_guard<std::mutex> lk(rt->mu);
-  rt->timing = enable != 0;
+  reap(rt);
+  rt->timing = mode;
+  return SBS_OK;
+}
+
+int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  if (lanes != 0 && lanes != 1 && lanes != 4) return fail(SBS_EINVAL, "lanes must be 0, 1 or 4");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  rt->rollout_lanes = lanes;
   return SBS_OK;
 }
 
@@ -1135,16 +1175,14 @@ int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_
     std::vector<const sbs_tick_input *> ins;
     for (auto &d : dummy) ins.push_back(&d);
     std::vector<uint32_t> ticks(n, 0);
-    auto tabs = build_batch(rt, cs, ins, ticks, P->lay, P->host, P->dev);
+    auto tabs = build_batch(rt, cs, ins, ticks, P->lay, P->host, P->dev,
+                            rt->pinned_dev + P->host_off);
     hipStream_t s = rt->streams[0];
     if (hipStreamSynchronize(s) != hipSuccess) return fail(SBS_EDEVICE, "stream sync failed");
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = hipMemcpyAsync(P->dev, P->host, P->lay.hdr_bytes, hipMemcpyHostToDevice, s);
     for (auto &tp : tabs)
-      if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, nullptr);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(P->host + P->lay.results, P->dev + P->lay.results,
-                         (size_t)n * kResultDoubles * 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e == hipSuccess) e = e2;
@@ -1191,7 +1229,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     ins.push_back(&in[i]);
     ticks.push_back(c.next_tick);
   }
-  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev);
+  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off);
   hipStream_t s = rt->streams[0];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -1212,14 +1250,12 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
       hipEvent_t *ev = nullptr;
       if (rt->timing) {
         size_t base = b->timing.size();
-        for (int i = 0; i < 5; ++i) b->timing.push_back(take_event(rt));
+        const int ne = rt->timing == 2 ? 5 : 2;
+        for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
         ev = &b->timing[base];
       }
-      e = launch_iteration(tp.first, tp.second, s, ev);
+      e = launch_iteration(tp.first, tp.second, s, rt->timing, ev);
     }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(P.host + P.lay.results, P.dev + P.lay.results,
-                         (size_t)n * kResultDoubles * 8, hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
   if (e != hipSuccess) {

@@ -221,7 +221,14 @@ def mppi_propagated_bound(ref, cfg, epsJ):
     return float((w[:, None] * dev * spread[:, None]).sum(0).max() / cfg["lambda"])
 
 
-def test_fp32_mppi_small(rt):
+@pytest.fixture(params=[1, 4], ids=["lanes1", "lanes4"])
+def lanes(request, rt):
+    rt.set_rollout_lanes(request.param)
+    yield request.param
+    rt.set_rollout_lanes(0)
+
+
+def test_fp32_mppi_small(rt, lanes):
     cfg = workloads.config("c1", N=777, H=20, seed=11)
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(11)))
     out, ref = run_pair(rt, cfg, inp)
@@ -239,7 +246,7 @@ def test_fp32_mppi_small(rt):
     np.testing.assert_array_equal(out["act"]["contact"], ref["contact"])
 
 
-def test_fp32_elite_selection(rt):
+def test_fp32_elite_selection(rt, lanes):
     cfg = workloads.config("c2", N=3000, H=16, seed=12)
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(12)), v_ref=(-0.3, 0, 0))
     out, ref = run_pair(rt, cfg, inp)
@@ -318,3 +325,24 @@ def test_plan_replay_matches_direct(rt, use_graph):
     rt.plan_destroy(plan)
     for cid in direct_ids + plan_ids:
         rt.destroy_controller(cid)
+
+
+def test_fp32_lane_forms_agree(rt):
+    """The one-lane and four-lane rollouts agree on every cost within FP32
+    rounding of the same arithmetic in a different order."""
+    cfg = workloads.config("c1", N=3000, H=50, seed=31)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(31)))
+    res = {}
+    for lanes in (1, 4):
+        rt.set_rollout_lanes(lanes)
+        cid = rt.init_controller(cfg)
+        rt.set_debug(cid, True)
+        rt.tick(cid, inp)
+        res[lanes] = rt.debug_fetch(cid)
+        rt.destroy_controller(cid)
+    rt.set_rollout_lanes(0)
+    np.testing.assert_array_equal(res[1][1], res[4][1])  # same sampled increments
+    J1, J4 = res[1][0][0], res[4][0][0]
+    ref = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, nthreads=8)["costs"][0]
+    check_costs_fp32(J1, ref, cfg["lambda"])
+    check_costs_fp32(J4, ref, cfg["lambda"])

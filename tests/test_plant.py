@@ -1,0 +1,52 @@
+"""The host plant of closed-loop runs (sbs_plant_step, in libsbs.so) against
+the oracle's model: one plant step equals one explicit-Euler step of Eq. (1)
+with the same footholds (no GPU needed)."""
+import numpy as np
+import pytest
+
+from paper_2403_11383_amd import workloads
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2403_11383_amd import binding, build
+    import os
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding
+
+
+def test_plant_step_matches_oracle_dynamics(orc, binding):
+    rng = np.random.default_rng(0)
+    cfg = workloads.config("c1")
+    for _ in range(50):
+        x = np.array(workloads.initial_state(rng))
+        x[3:6] = rng.uniform(-0.3, 0.3, 3)
+        feet = np.array(workloads.feet_under_hips(x)) + rng.normal(size=(4, 3)) * 0.02
+        contact = rng.integers(0, 2, 4)
+        grf = rng.normal(size=12) * 30 + np.tile([0, 0, 60.0], 4)
+        grf = (grf.reshape(4, 3) * contact[:, None]).reshape(12)
+        ext = rng.normal(size=3) * 10
+        p = binding.Plant(cfg, x, feet, 123)
+        p.st.contact[:] = [int(c) for c in contact]  # no touchdown this step
+        p.step({"grf": grf, "contact": contact, "q": 120259084}, ext_force=ext)
+        lever = (feet - x[0:3][None]).reshape(12)
+        xd = orc.srbd_deriv(cfg, x, grf, lever)
+        xd[6:9] += ext / cfg["mass"]
+        np.testing.assert_allclose(p.x, x + cfg["dt"] * xd, rtol=1e-12, atol=1e-12)
+        assert p.phase == (123 + 120259084) & 0xFFFFFFFF
+
+
+def test_plant_touchdown_uses_eq2(orc, binding):
+    cfg = workloads.config("c1")
+    rng = np.random.default_rng(1)
+    x = np.array(workloads.initial_state(rng))
+    x[3:6] = rng.uniform(-0.2, 0.2, 3)
+    p = binding.Plant(cfg, x, np.zeros((4, 3)), 0)
+    p.st.contact[:] = [0, 0, 0, 0]
+    q = orc.q_of_freq(1.7, cfg["dt"])
+    p.step({"grf": np.zeros(12), "contact": [1, 0, 0, 1], "q": q}, v_ref=(0.3, -0.1, 0.0))
+    for leg in (0, 3):
+        ref = orc.foothold(cfg, x, q, np.array([0.3, -0.1, 0.0]), leg)
+        np.testing.assert_allclose(p.foot_pos[leg], ref, rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(p.foot_pos[1], 0.0)
