@@ -6,7 +6,11 @@ A step is one control tick: noise, rollouts, selection and mean update on
 the GPU (through the C ABI), then one step of the host plant with the
 returned action.  The value is rollout-steps per second (N x H x iterations
 per tick) over the timed ticks, with the inputs already resident.  One JSON
-line is printed; see the design doc for the roofline and baseline definitions.
+line is printed.  Its roofline object rates the rollout kernel: algorithmic
+FP32 FLOP per launch (FLOP_PER_ROLLOUT_STEP x N x H) over the kernel's
+average duration from HIP events on the runtime stream, against the
+non-packed FP32 VALU peak.  Its cpu_baseline object times the FP64 oracle on
+the host cores over a bounded sample of full-size ticks.
 """
 from __future__ import annotations
 
@@ -23,10 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "rollout-steps/sec (N×H per s) + p99 control-tick latency vs plain single MPPI"
-# Algorithmic FP32 work of one rollout step (policy, friction clip, stage cost,
-# attitude, footholds, SRBD derivative and Euler update), counted with
-# add/sub/mul = 1, fma = 2, each transcendental (sin, cos, sqrt, rcp, rsqrt) = 1.
-FLOP_PER_ROLLOUT_STEP = 384
+# Algorithmic FP32 work of one rollout step, counted with add/sub/mul = 1,
+# fma = 2, each sin, cos, sqrt, rcp, rsqrt = 1: policy 24, friction cone 36,
+# attitude 24, footholds at touchdown 3 (0.14 touchdowns per step), stage cost
+# 94, force and torque 72, R^T tau 15, gyroscopic term 12, Euler-angle rates 11,
+# accelerations 10, Euler update and time 25.
+FLOP_PER_ROLLOUT_STEP = 326
 # Non-packed FP32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
 PEAK_FP32_VALU_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
@@ -113,6 +119,86 @@ def cpu_baseline(cfg, seconds=10.0):
                       f"initial state, {dt:.1f} s wall"}
 
 
+def batched(rt, binding, workloads, steps, warmup, cache_path=None):
+    """64 uneven controllers in one fused, graph-replayed tick (autotuned
+    rollout form), fixed per-controller inputs, warm-started means."""
+    import torch
+    cfgs = workloads.c3_controllers()
+    inps = workloads.c3_inputs()
+    ids = [rt.init_controller(c) for c in cfgs]
+    plan = rt.plan_create(ids, use_graph=True)
+    tune = rt.plan_autotune(plan, inps, reps=3, cache_path=cache_path)
+    for _ in range(warmup):
+        for t in rt.plan_submit(plan, inps):
+            rt.fetch(t)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter_ns()
+        for t in rt.plan_submit(plan, inps):
+            rt.fetch(t)
+        lat.append((time.perf_counter_ns() - a) * 1e-6)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    work = sum(c["N"] * c["H"] * c.get("iterations", 1) for c in cfgs)
+    rt.plan_destroy(plan)
+    for c in ids:
+        rt.destroy_controller(c)
+    return elapsed, lat, work, tune, cfgs
+
+
+def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
+    """C4: Poisson arrivals (50 Hz per robot) of control ticks from simulated
+    robots of different N and H; serving mode batches whatever is admitted,
+    direct mode runs every tick as its own launch sequence ("plain single
+    MPPI").  Latency is measured from the scheduled arrival to completion."""
+    import torch
+    fleet = workloads.c4_fleet(robots=robots)
+    arrivals = workloads.c4_arrivals(robots=robots, duration_s=duration)
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
+    ids = [rt.init_controller(c) for c in fleet]
+    rng = np.random.default_rng(5)
+    inputs = [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
+    events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
+    L = binding.lib()
+    import ctypes as C
+    pending = {}
+    lat, done_work = [], 0
+    tk = C.c_uint64()
+    act = binding.Action()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter_ns()
+    i = 0
+    while i < len(events) or pending:
+        now = (time.perf_counter_ns() - t_start) * 1e-9
+        while i < len(events) and events[i][0] <= now:
+            t_arr, r = events[i]
+            rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
+            if rc == binding.ENOMEM:  # arena full: retire finished ticks first
+                break
+            binding._check(rc)
+            pending[tk.value] = (t_arr, r)
+            i += 1
+        for t in list(pending):
+            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
+            if rc == binding.OK:
+                t_arr, r = pending.pop(t)
+                lat.append((act.t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
+                c = fleet[r]
+                done_work += c["N"] * c["H"]
+            elif rc != binding.EAGAIN:
+                binding._check(rc)
+        if mode == "direct" and pending and i < len(events) and events[i][0] > now:
+            time.sleep(0)
+    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    stats = rt.stats()
+    rt.close()
+    return {"ticks": len(lat), "elapsed_s": elapsed, "rollout_steps_per_s": done_work / elapsed,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": float(np.max(lat)),
+            "batches": stats["batches"], "admit_waits": stats["admit_waits"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,10 +208,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 around the rollout stage, 2 around every stage")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+                    help="c1 closed-loop single MPPI (default); c3 batched uneven "
+                         "controllers; c4 serving 256 robots vs plain single MPPI")
+    ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
+    ap.add_argument("--arena-gb", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "c3":
+        return main_c3(args)
+    if args.workload == "c4":
+        return main_c4(args)
 
     from paper_2403_11383_amd import binding, workloads
     import torch
@@ -164,6 +259,70 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def main_c3(args):
+    from paper_2403_11383_amd import binding, workloads
+    rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)))
+    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    elapsed, lat, work, tune, cfgs = batched(rt, binding, workloads, args.steps, args.warmup, cache)
+    # rollout-kernel timing from a separate pass without the graph
+    rt.set_timing(1)
+    ids = [rt.init_controller(c) for c in cfgs]
+    inps = workloads.c3_inputs()
+    plan = rt.plan_create(ids, use_graph=False)
+    rt.plan_set_tune(plan, tune["lanes"], tune["block"], tune["unroll"])
+    for _ in range(3):
+        for t in rt.plan_submit(plan, inps):
+            rt.fetch(t)
+    rt.timing()
+    reps = 5
+    for _ in range(reps):
+        for t in rt.plan_submit(plan, inps):
+            rt.fetch(t)
+    tm = rt.timing()
+    rt.close()
+    roll_ns_total = tm["rollout_ns"] * tm["launches"][1]
+    flop = work * FLOP_PER_ROLLOUT_STEP * reps
+    achieved = flop / (roll_ns_total * 1e-9) / 1e12 if roll_ns_total > 0 else 0.0
+    line = {
+        "metric": METRIC, "value": work * args.steps / elapsed, "unit": "rollout-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3: 64 uneven controllers (N log-uniform 1024..16384, H 20..60, "
+                               "MPPI/elite mix) in one graph-replayed fused tick",
+                   "rollout_steps_per_tick": work, "tune": tune},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "roofline": {"kernel": "k_rollout (tuned form)", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "peak_published_packed": PEAK_FP32_PUBLISHED_TFLOPS,
+                     "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+                     "traffic": stored_traffic("k_rollout", "c3")},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_c4(args):
+    from paper_2403_11383_amd import binding, workloads
+    arena = int(args.arena_gb * (1 << 30))
+    serve = serving_run(binding, workloads, args.duration, "serving", arena)
+    plain = serving_run(binding, workloads, args.duration, "direct", arena)
+    line = {
+        "metric": METRIC, "value": serve["rollout_steps_per_s"], "unit": "rollout-steps/s",
+        "n_gpus": 1, "steps": serve["ticks"], "warmup": 0,
+        "ms_per_step": serve["elapsed_s"] / max(1, serve["ticks"]) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c4: 256 robots, Poisson 50 Hz each, N in {2048,4096,8192}, "
+                               "H in {25,50}, continuous batching vs plain single MPPI",
+                   "duration_s": args.duration, "arena_gb": args.arena_gb},
+        "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"]},
+        "serving": serve, "plain_single_mppi": plain,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -157,6 +157,25 @@ int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_
 int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uint64_t *tickets);
 int sbs_plan_destroy(sbs_runtime *rt, int32_t plan);
 
+/* Rollout form of a plan: lanes per sample (1, or 4 = one lane per leg; 0 =
+ * automatic), workgroup size (64, 128, 256) and step-loop unroll (1, 2).
+ * Supported forms: lanes 4 with (64|128|256, 1); lanes 1 with (64|128|256, 1)
+ * or (64|128, 2).  The form never changes which samples are
+ * drawn; lanes 1 and 4 differ only in FP32 rounding order. */
+typedef struct sbs_tune {
+  int32_t lanes, block, unroll, reserved;
+  double tick_us;       /* measured device time of one tick (autotune)      */
+} sbs_tune;
+int sbs_plan_set_tune(sbs_runtime *rt, int32_t plan, const sbs_tune *t);
+
+/* Autotuner: runs the plan's tick `reps` times (after one warm-up) in every
+ * supported rollout form with the given inputs, restoring each controller's
+ * mean, frequency mean and tick counter after every trial, keeps the form
+ * with the lowest device time (re-recording the plan's graph) and returns it.
+ * Waits for all outstanding work first. */
+int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, int32_t reps,
+                      sbs_tune *best);
+
 /* Synchronous state access (waits for the controller's pending work):
  * mean [H][12], frequency mean and next tick number.  Used for checkpoint
  * and resume: export, then import into a fresh controller, reproduces the

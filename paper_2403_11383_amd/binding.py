@@ -28,7 +28,8 @@ OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EDEVICE, ECANCELED, ENOENT = 0, -1, -2, -
 EXPORTED = [
     "sbs_runtime_create", "sbs_runtime_destroy", "sbs_init_controller",
     "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action",
-    "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_get_state",
+    "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
+    "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
     "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
 ]
@@ -73,6 +74,11 @@ class Action(C.Structure):
     ]
 
 
+class Tune(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("unroll", C.c_int32),
+                ("reserved", C.c_int32), ("tick_us", C.c_double)]
+
+
 class PlantState(C.Structure):
     _fields_ = [
         ("x", C.c_double * 12), ("foot_pos", C.c_double * 12), ("contact", C.c_int32 * 4),
@@ -101,6 +107,8 @@ def lib():
         L.sbs_plan_create.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
         L.sbs_plan_submit.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_plan_destroy.argtypes = [vp, i32]
+        L.sbs_plan_set_tune.argtypes = [vp, i32, C.POINTER(Tune)]
+        L.sbs_plan_autotune.argtypes = [vp, i32, C.POINTER(TickInput), i32, C.POINTER(Tune)]
         L.sbs_get_state.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.POINTER(u32)]
         L.sbs_set_state.argtypes = [vp, i32, vp, C.c_double, u32]
         L.sbs_set_debug.argtypes = [vp, i32, i32]
@@ -187,6 +195,7 @@ class Runtime:
         self.stream = torch.cuda.Stream(self.device)
         self.stream2 = torch.cuda.Stream(self.device) if two_streams else None
         self.cfgs = {}
+        self._plan_cfgs = {}
         h = C.c_void_p()
         _check(lib().sbs_runtime_create(
             C.c_void_p(self.arena.data_ptr()), C.c_uint64(self.arena.numel()),
@@ -257,6 +266,7 @@ class Runtime:
         ids = (C.c_int32 * n)(*cids)
         p = C.c_int32()
         _check(lib().sbs_plan_create(self._h, n, ids, 1 if use_graph else 0, C.byref(p)))
+        self._plan_cfgs[p.value] = [self.cfgs[c] for c in cids]
         return p.value
 
     def plan_submit(self, plan: int, inputs) -> list:
@@ -268,6 +278,51 @@ class Runtime:
 
     def plan_destroy(self, plan: int):
         _check(lib().sbs_plan_destroy(self._h, plan))
+
+    def plan_set_tune(self, plan: int, lanes: int, block: int = 64, unroll: int = 1):
+        t = Tune(lanes, block, unroll, 0, 0.0)
+        _check(lib().sbs_plan_set_tune(self._h, plan, C.byref(t)))
+
+    def plan_autotune(self, plan: int, inputs, reps: int = 3, cache_path: str | None = None):
+        """Pick the fastest rollout form for the plan (device-timed trials that
+        restore every controller's state).  With cache_path, a JSON file keyed
+        by device, kernel build and the plan's (N, H, iterations, method,
+        precision) multiset is consulted first and updated after tuning."""
+        import json
+        key = self._plan_key(plan)
+        if cache_path and os.path.exists(cache_path):
+            try:
+                ent = json.load(open(cache_path)).get(key)
+            except (OSError, ValueError):
+                ent = None
+            if ent:
+                self.plan_set_tune(plan, ent["lanes"], ent["block"], ent["unroll"])
+                return dict(ent, cached=True)
+        n = len(inputs)
+        ins = (TickInput * n)(*[make_input(x) for x in inputs])
+        t = Tune()
+        _check(lib().sbs_plan_autotune(self._h, plan, ins, int(reps), C.byref(t)))
+        res = {"lanes": t.lanes, "block": t.block, "unroll": t.unroll, "tick_us": t.tick_us}
+        if cache_path:
+            doc = {}
+            if os.path.exists(cache_path):
+                try:
+                    doc = json.load(open(cache_path))
+                except (OSError, ValueError):
+                    doc = {}
+            doc[key] = res
+            with open(cache_path, "w") as f:
+                json.dump(doc, f, indent=1, sort_keys=True)
+        return dict(res, cached=False)
+
+    def _plan_key(self, plan: int) -> str:
+        import hashlib
+        members = sorted((int(c["N"]), int(c["H"]), int(c.get("iterations", 1)),
+                          str(c.get("method", "mppi")), str(c.get("precision", "fp32")))
+                         for c in self._plan_cfgs[plan])
+        h = hashlib.sha256(open(LIB_PATH, "rb").read()).hexdigest()[:12]
+        dev = self._torch.cuda.get_device_name(self.device)
+        return f"{dev}|{h}|" + hashlib.sha256(repr(members).encode()).hexdigest()[:16]
 
     # -- state -----------------------------------------------------------------
     def get_state(self, cid: int):

@@ -8,7 +8,7 @@
 
 namespace sbs {
 
-constexpr int kRollBlock = 64;     // rollouts per workgroup (one wave64)
+constexpr int kRollBlock = 64;     // default rollout workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
 constexpr int kUpdBlock = 256;     // threads per update workgroup
 constexpr int kUpdChunk = 4096;    // active samples reduced by one update workgroup
@@ -85,6 +85,8 @@ struct LaunchTab {
   int32_t total_noise, total_roll, total_upd;
   int32_t max_h;         // longest horizon among the items
   int32_t lanes;         // rollout lanes per sample: 1 or 4 (FP32 only)
+  int32_t roll_block;    // rollout workgroup size: 64, 128 or 256
+  int32_t unroll;        // rollout step-loop unroll: 1 or 2
   int32_t pad1;
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index

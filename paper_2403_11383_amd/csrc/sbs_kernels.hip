@@ -242,8 +242,8 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
-template <typename T>
-__global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
+template <typename T, int BLOCK, int UNROLL>
+__global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
   const int it = find_item(tab.roll_start, tab.n, b);
@@ -254,13 +254,13 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   {
     const T *mu = reinterpret_cast<const T *>(d.mu);
-    for (int i = threadIdx.x; i < H * 12; i += kRollBlock) {
+    for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
       s_mu[i] = mu[i];
       s_sig[i] = elite_sigma ? (T)d.sigma[i] : (T)d.sigma0;
     }
   }
   __syncthreads();
-  const int k = (b - tab.roll_start[it]) * kRollBlock + (int)threadIdx.x;
+  const int k = (b - tab.roll_start[it]) * BLOCK + (int)threadIdx.x;
   if (k >= N) return;
 
   RollConst<T> c;
@@ -286,6 +286,7 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout(LaunchTab tab) {
   const size_t zstride = (size_t)N * 3;  // float4 per step
   float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
 
+#pragma unroll UNROLL
   for (int j = 0; j < H; ++j) {
     const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                           z2.x, z2.y, z2.z, z2.w};
@@ -434,9 +435,10 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v + dpp<0x4E>(v);  // quad_perm [2,3,0,1]
 }
 
-__global__ void __launch_bounds__(kRollBlock) k_rollout_quad(LaunchTab tab) {
+template <int BLOCK, int UNROLL>
+__global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
-  constexpr int kPerBlock = kRollBlock / 4;
+  constexpr int kPerBlock = BLOCK / 4;
   const int b = blockIdx.x;
   const int it = find_item(tab.roll_start, tab.n, b);
   const TickDesc &d = tab.desc[tab.item[it]];
@@ -446,7 +448,7 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout_quad(LaunchTab tab) {
   float *s_sig = s_mu + (size_t)tab.max_h * 12;
   {
     const float *mu = reinterpret_cast<const float *>(d.mu);
-    for (int i = threadIdx.x; i < H * 12; i += kRollBlock) {
+    for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
       s_mu[i] = mu[i];
       s_sig[i] = elite_sigma ? (float)d.sigma[i] : (float)d.sigma0;
     }
@@ -490,6 +492,7 @@ __global__ void __launch_bounds__(kRollBlock) k_rollout_quad(LaunchTab tab) {
   const size_t zstride = (size_t)N * 12;
   float za = zp[0], zb = zp[1], zc = zp[2];
 
+#pragma unroll UNROLL
   for (int j = 0; j < H; ++j) {
     const float z0 = za, z1 = zb, z2 = zc;
     if (j + 1 < H) {
@@ -1050,12 +1053,26 @@ hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, 
   if (timing == 2) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_noise, dim3(tab.total_noise), dim3(kNoiseBlock), 0, s, tab);
   if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 1 : 0], s);
-  if (precision == 1)
-    hipLaunchKernelGGL(k_rollout<double>, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
-  else if (tab.lanes == 4)
-    hipLaunchKernelGGL(k_rollout_quad, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
-  else
-    hipLaunchKernelGGL(k_rollout<float>, dim3(tab.total_roll), dim3(kRollBlock), roll_lds, s, tab);
+  const dim3 rg(tab.total_roll);
+  if (precision == 1) {
+    hipLaunchKernelGGL((k_rollout<double, 64, 1>), rg, dim3(64), roll_lds, s, tab);
+  } else if (tab.lanes == 4) {
+    switch (tab.roll_block * 4 + tab.unroll) {
+      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1>), rg, dim3(128), roll_lds, s, tab); break;
+      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1>), rg, dim3(256), roll_lds, s, tab); break;
+      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1>), rg, dim3(64), roll_lds, s, tab); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (tab.roll_block * 4 + tab.unroll) {
+      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1>), rg, dim3(128), roll_lds, s, tab); break;
+      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1>), rg, dim3(256), roll_lds, s, tab); break;
+      case 64 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 64, 2>), rg, dim3(64), roll_lds, s, tab); break;
+      case 128 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 128, 2>), rg, dim3(128), roll_lds, s, tab); break;
+      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1>), rg, dim3(64), roll_lds, s, tab); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 2 : 1], s);
   if (precision == 1)
     hipLaunchKernelGGL(k_select<double>, dim3(tab.n), dim3(kSelBlock), 0, s, tab);

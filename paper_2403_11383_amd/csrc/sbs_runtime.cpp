@@ -65,6 +65,22 @@ int64_t now_ns() {
 constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
+
+// Rollout form: lanes per sample (0 = automatic), workgroup size, step-loop
+// unroll.  Only the forms the kernel dispatcher instantiates are valid.
+struct Tune {
+  int lanes = 0;
+  int block = 64;
+  int unroll = 1;
+};
+
+bool valid_form(int lanes, int block, int unroll) {
+  if (lanes == 4) return unroll == 1 && (block == 64 || block == 128 || block == 256);
+  if (lanes == 1)
+    return (unroll == 1 && (block == 64 || block == 128 || block == 256)) ||
+           (unroll == 2 && (block == 64 || block == 128));
+  return false;
+}
 uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
 
 // First-fit allocator over [0, size) with coalescing frees.
@@ -202,6 +218,7 @@ struct Plan {
   bool use_graph = false;
   bool busy = false;
   hipEvent_t done = nullptr;
+  Tune tune;
 };
 
 }  // namespace
@@ -234,7 +251,7 @@ struct sbs_runtime {
   uint64_t n_ticks = 0, n_batches = 0, n_admit_waits = 0;
   // timing
   int timing = 0;  // 0 off, 1 rollout stage, 2 all stages
-  int rollout_lanes = 0;  // 0 auto, 1, 4
+  Tune tune;  // default rollout form of direct and serving launches
   double stage_ns[4] = {0, 0, 0, 0};
   uint64_t stage_n[4] = {0, 0, 0, 0};
 };
@@ -401,7 +418,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
                                                    const std::vector<const sbs_tick_input *> &ins,
                                                    const std::vector<uint32_t> &ticks,
                                                    const Layout &L, char *host, char *dev,
-                                                   char *host_dev) {
+                                                   char *host_dev, const Tune &tn) {
   const int n = (int)cs.size();
   int rmax = 1;
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
@@ -431,12 +448,15 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       // bound); one lane per sample otherwise
       long long nsum = 0;
       for (int t = 0; t < m; ++t) nsum += cs[idx[t]]->cfg.N;
-      int lanes = 1;
+      int lanes = 1, block = 64, unroll = 1;
       if (prec == SBS_FP32) {
-        if (rt->rollout_lanes == 4) lanes = 4;
-        else if (rt->rollout_lanes == 0 && nsum <= kQuadMaxSamples) lanes = 4;
+        lanes = tn.lanes == 0 ? (nsum <= kQuadMaxSamples ? 4 : 1) : tn.lanes;
+        if (valid_form(lanes, tn.block, tn.unroll)) {
+          block = tn.block;
+          unroll = tn.unroll;
+        }
       }
-      const int per_block = kRollBlock / lanes;
+      const int per_block = block / lanes;
       ns[0] = rs[0] = us[0] = 0;
       for (int t = 0; t < m; ++t) {
         max_h = std::max(max_h, cs[idx[t]]->cfg.H);
@@ -455,6 +475,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.total_upd = us[m];
       tab.max_h = max_h;
       tab.lanes = lanes;
+      tab.roll_block = block;
+      tab.unroll = unroll;
       tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
       tab.item = reinterpret_cast<const int32_t *>(dev + off);
       tab.noise_start = tab.item + n;
@@ -555,7 +577,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   char *host = rt->pinned + host_off;
   std::vector<uint32_t> ticks;
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
-  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off);
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off, rt->tune);
   hipStream_t s = rt->streams[slot];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -661,16 +683,19 @@ void scheduler_loop(sbs_runtime *rt) {
       (void)need;
       if (waited) rt->n_admit_waits += 1;
       if (!ids.empty()) {
-        std::vector<Request> keep;  // inputs must stay valid during launch
         int rc = launch(rt, ids, ins, tks, slot);
         if (rc == SBS_OK) {
           for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
-        } else if (rc != SBS_ENOMEM) {
+          continue;
+        }
+        if (rc != SBS_ENOMEM) {
           for (uint64_t tk : tks) rt->tickets[tk].status = rc;
           for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
           rt->cv.notify_all();
+          continue;
         }
-        continue;
+        // fragmented arena: wait for a batch to retire
+        rt->n_admit_waits += 1;
       }
     }
     // nothing to launch: poll briefly (completion detection latency)
@@ -1066,7 +1091,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   sbs_tick_input in{};
   std::vector<const sbs_tick_input *> ins{&in};
   std::vector<uint32_t> ticks{tick};
-  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + hoff);
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + hoff, rt->tune);
   TickDesc *hd = reinterpret_cast<TickDesc *>(host);
   LaunchTab tab = tabs[0].first;
   tab.r = (int32_t)r;
@@ -1117,7 +1142,7 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   if (lanes != 0 && lanes != 1 && lanes != 4) return fail(SBS_EINVAL, "lanes must be 0, 1 or 4");
   std::lock_guard<std::mutex> lk(rt->mu);
-  rt->rollout_lanes = lanes;
+  rt->tune.lanes = lanes;
   return SBS_OK;
 }
 
@@ -1137,6 +1162,52 @@ int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches) {
 // ---------------------------------------------------------------------------
 // Plans: fixed membership, workspace reserved once, optionally a HIP graph.
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+std::vector<const Controller *> plan_ctrls(sbs_runtime *rt, const Plan &P) {
+  std::vector<const Controller *> cs;
+  for (int32_t id : P.ctrls) cs.push_back(&rt->ctrls.at(id));
+  return cs;
+}
+
+// Records the plan's whole tick as a HIP graph: the header copy from pinned
+// staging (read at replay time, so new inputs need no re-recording), then
+// every stage of every iteration.  Replaces a previous graph.
+hipError_t capture_plan(sbs_runtime *rt, Plan &P) {
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.exec = nullptr;
+  P.graph = nullptr;
+  const int n = (int)P.ctrls.size();
+  auto cs = plan_ctrls(rt, P);
+  std::vector<sbs_tick_input> dummy(n);
+  for (auto &d : dummy) std::memset(&d, 0, sizeof d);
+  std::vector<const sbs_tick_input *> ins;
+  for (auto &d : dummy) ins.push_back(&d);
+  std::vector<uint32_t> ticks(n, 0);
+  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off,
+                          P.tune);
+  hipStream_t s = rt->streams[0];
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
+  for (auto &tp : tabs)
+    if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e == hipSuccess) e = e2;
+  P.graph = g;
+  if (e == hipSuccess) e = hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_graph, int32_t *plan) {
   if (!rt || n < 1 || !ids || !plan) return fail(SBS_EINVAL, "bad plan arguments");
   std::lock_guard<std::mutex> lk(rt->mu);
@@ -1164,32 +1235,19 @@ int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_
   P->host = rt->pinned + P->host_off;
   P->ctrls = vid;
   P->use_graph = use_graph != 0;
+  P->tune = rt->tune;
   P->id = rt->next_plan++;
-  if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
+    rt->dev_alloc.release(P->ws_off, P->lay.total);
+    rt->host_alloc.release(P->host_off, P->lay.host_total);
     return fail(SBS_EDEVICE, "event creation failed");
+  }
   if (P->use_graph) {
-    // capture the whole tick once; inputs change only in the pinned staging
-    // that the graph's first copy reads at replay time
-    std::vector<sbs_tick_input> dummy(n);
-    for (auto &d : dummy) std::memset(&d, 0, sizeof d);
-    std::vector<const sbs_tick_input *> ins;
-    for (auto &d : dummy) ins.push_back(&d);
-    std::vector<uint32_t> ticks(n, 0);
-    auto tabs = build_batch(rt, cs, ins, ticks, P->lay, P->host, P->dev,
-                            rt->pinned_dev + P->host_off);
-    hipStream_t s = rt->streams[0];
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(SBS_EDEVICE, "stream sync failed");
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = hipMemcpyAsync(P->dev, P->host, P->lay.hdr_bytes, hipMemcpyHostToDevice, s);
-    for (auto &tp : tabs)
-      if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
-    P->graph = g;
+    hipError_t e = capture_plan(rt, *P);
     if (e != hipSuccess) {
+      if (P->exec) (void)hipGraphExecDestroy(P->exec);
       if (P->graph) (void)hipGraphDestroy(P->graph);
+      (void)hipEventDestroy(P->done);
       rt->dev_alloc.release(P->ws_off, P->lay.total);
       rt->host_alloc.release(P->host_off, P->lay.host_total);
       return fail(SBS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -1198,6 +1256,130 @@ int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_
   for (int32_t id : vid) rt->ctrls.at(id).plan = P->id;
   *plan = P->id;
   rt->plans[P->id] = std::move(P);
+  return SBS_OK;
+}
+
+int sbs_plan_set_tune(sbs_runtime *rt, int32_t plan, const sbs_tune *t) {
+  if (!rt || !t) return fail(SBS_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  auto pit = rt->plans.find(plan);
+  if (pit == rt->plans.end()) return fail(SBS_EINVAL, "unknown plan %d", plan);
+  Plan &P = *pit->second;
+  if (t->lanes != 0 && !valid_form(t->lanes, t->block, t->unroll))
+    return fail(SBS_EINVAL, "unsupported rollout form (lanes %d, block %d, unroll %d)", t->lanes,
+                t->block, t->unroll);
+  while (P.busy) {
+    reap(rt);
+    if (P.busy) std::this_thread::yield();
+  }
+  P.tune.lanes = t->lanes;
+  P.tune.block = t->block;
+  P.tune.unroll = t->unroll;
+  if (P.use_graph) {
+    hipError_t e = capture_plan(rt, P);
+    if (e != hipSuccess) return fail(SBS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  return SBS_OK;
+}
+
+int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, int32_t reps,
+                      sbs_tune *best) {
+  if (!rt || !in || !best || reps < 1) return fail(SBS_EINVAL, "bad autotune arguments");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  auto pit = rt->plans.find(plan);
+  if (pit == rt->plans.end()) return fail(SBS_EINVAL, "unknown plan %d", plan);
+  Plan &P = *pit->second;
+  const int n = (int)P.ctrls.size();
+  for (int i = 0; i < n; ++i) {
+    int rc = check_input(&in[i]);
+    if (rc) return rc;
+  }
+  hipStream_t s = rt->streams[0];
+  while (P.busy || !rt->inflight.empty()) {
+    reap(rt);
+    if (P.busy || !rt->inflight.empty()) std::this_thread::yield();
+  }
+  auto cs = plan_ctrls(rt, P);
+  // snapshot every controller's state: mean, frequency mean, tick
+  uint64_t snap_bytes = 0;
+  std::vector<uint64_t> mu_bytes(n);
+  for (int i = 0; i < n; ++i) {
+    mu_bytes[i] = align_up((uint64_t)cs[i]->cfg.H * 12 * (cs[i]->cfg.precision == SBS_FP64 ? 8 : 4));
+    snap_bytes += mu_bytes[i] + kAlign;
+  }
+  uint64_t snap_off = 0;
+  if (!rt->dev_alloc.alloc(snap_bytes, &snap_off)) return fail(SBS_ENOMEM, "arena cannot hold the snapshot");
+  char *snap = rt->arena + snap_off;
+  std::vector<uint32_t> ticks0(n);
+  auto copy_state = [&](bool save) -> hipError_t {
+    char *p = snap;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+      const Controller &C = *cs[i];
+      e = save ? hipMemcpyAsync(p, C.mu, mu_bytes[i], hipMemcpyDeviceToDevice, s)
+               : hipMemcpyAsync(C.mu, p, mu_bytes[i], hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = save ? hipMemcpyAsync(p + mu_bytes[i], C.ctl, 8, hipMemcpyDeviceToDevice, s)
+                 : hipMemcpyAsync(C.ctl, p + mu_bytes[i], 8, hipMemcpyDeviceToDevice, s);
+      p += mu_bytes[i] + kAlign;
+    }
+    return e;
+  };
+  for (int i = 0; i < n; ++i) ticks0[i] = cs[i]->next_tick;
+  hipError_t e = copy_state(true);
+  hipEvent_t t0 = take_event(rt), t1 = take_event(rt);
+  static const int forms[][3] = {{4, 64, 1}, {4, 128, 1}, {4, 256, 1}, {1, 64, 1},
+                                 {1, 128, 1}, {1, 256, 1}, {1, 64, 2}, {1, 128, 2}};
+  bool any_fp32 = false;
+  for (auto *c : cs) any_fp32 |= c->cfg.precision == SBS_FP32;
+  const int nforms = any_fp32 ? (int)(sizeof forms / sizeof forms[0]) : 1;
+  double best_us = 1e300;
+  Tune best_t = P.tune;
+  std::vector<const sbs_tick_input *> ins;
+  for (int i = 0; i < n; ++i) ins.push_back(&in[i]);
+  for (int f = 0; f < nforms && e == hipSuccess; ++f) {
+    Tune tn;
+    tn.lanes = forms[f][0];
+    tn.block = forms[f][1];
+    tn.unroll = forms[f][2];
+    double total_ms = 0.0;
+    for (int rep = 0; rep <= reps && e == hipSuccess; ++rep) {  // rep 0 warms up
+      std::vector<uint32_t> ticks;
+      for (int i = 0; i < n; ++i) ticks.push_back(ticks0[i] + (uint32_t)rep);
+      auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev,
+                              rt->pinned_dev + P.host_off, tn);
+      e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipEventRecord(t0, s);
+      for (auto &tp : tabs)
+        if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (rep > 0) total_ms += ms;
+      if (e == hipSuccess) e = copy_state(false);  // every trial starts from the snapshot
+    }
+    const double us = total_ms * 1e3 / reps;
+    if (e == hipSuccess && us < best_us) {
+      best_us = us;
+      best_t = tn;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  give_event(rt, t0);
+  give_event(rt, t1);
+  rt->dev_alloc.release(snap_off, snap_bytes);
+  if (e != hipSuccess) return fail(SBS_EDEVICE, "autotune failed: %s", hipGetErrorString(e));
+  P.tune = best_t;
+  if (P.use_graph) {
+    e = capture_plan(rt, P);
+    if (e != hipSuccess) return fail(SBS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  best->lanes = best_t.lanes;
+  best->block = best_t.block;
+  best->unroll = best_t.unroll;
+  best->reserved = 0;
+  best->tick_us = best_us;
   return SBS_OK;
 }
 
@@ -1229,7 +1411,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     ins.push_back(&in[i]);
     ticks.push_back(c.next_tick);
   }
-  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off);
+  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off, P.tune);
   hipStream_t s = rt->streams[0];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;

@@ -346,3 +346,46 @@ def test_fp32_lane_forms_agree(rt):
     ref = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, nthreads=8)["costs"][0]
     check_costs_fp32(J1, ref, cfg["lambda"])
     check_costs_fp32(J4, ref, cfg["lambda"])
+
+
+def test_plan_forms_and_autotune(rt):
+    """Every rollout form of a plan gives bit-identical results within one
+    lane form (workgroup size and unroll do not change any sample's
+    arithmetic); the autotuner restores the controllers' state and leaves a
+    working plan."""
+    cfgs = [workloads.config("c1", N=n, H=h, seed=s, method=m, iterations=it)
+            for n, h, s, m, it in ((1500, 22, 1, "mppi", 1), (3000, 40, 2, "elite", 3),
+                                   (700, 31, 3, "mppi", 1))]
+    rng = np.random.default_rng(12)
+    inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
+    ids = [rt.init_controller(c) for c in cfgs]
+    plan = rt.plan_create(ids, use_graph=True)
+    state0 = [rt.get_state(c) for c in ids]
+
+    def run(form):
+        rt.plan_set_tune(plan, *form)
+        for c, (mu, mf, tk) in zip(ids, state0):
+            rt.set_state(c, mu, mf, tk)
+        return [rt.fetch(t) for t in rt.plan_submit(plan, inps)]
+
+    for lanes, forms in ((1, [(64, 1), (128, 1), (256, 1), (64, 2), (128, 2)]),
+                         (4, [(64, 1), (128, 1), (256, 1)])):
+        ref = run((lanes, *forms[0]))
+        for f in forms[1:]:
+            out = run((lanes, *f))
+            for a, b in zip(ref, out):
+                np.testing.assert_array_equal(a["grf"], b["grf"])
+                assert a["best_cost"] == b["best_cost"] and a["q"] == b["q"]
+    for c, (mu, mf, tk) in zip(ids, state0):
+        rt.set_state(c, mu, mf, tk)
+    best = rt.plan_autotune(plan, inps, reps=2)
+    assert best["lanes"] in (1, 4) and best["tick_us"] > 0
+    after = [rt.get_state(c) for c in ids]
+    for (mu0, mf0, t0), (mu1, mf1, t1) in zip(state0, after):
+        np.testing.assert_array_equal(mu0, mu1)
+        assert mf0 == mf1 and t0 == t1
+    res = [rt.fetch(t) for t in rt.plan_submit(plan, inps)]
+    assert all(np.isfinite(r["grf"]).all() for r in res)
+    rt.plan_destroy(plan)
+    for c in ids:
+        rt.destroy_controller(c)
