@@ -66,8 +66,11 @@ def stored_traffic(kernel: str, workload: str):
     return None
 
 
-def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=40.0):
+def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=40.0,
+                prefetch=True):
     cid = rt.init_controller(cfg)
+    if prefetch:
+        rt.set_prefetch(cid, True)
     rng = np.random.default_rng(cfg["seed"])
     x0 = workloads.initial_state(rng)
     plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
@@ -213,6 +216,8 @@ def main():
                          "controllers; c4 serving 256 robots vs plain single MPPI")
     ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
     ap.add_argument("--arena-gb", type=float, default=4.0)
+    ap.add_argument("--no-prefetch", action="store_true",
+                    help="c1: generate each tick's noise inside the tick")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -225,10 +230,10 @@ def main():
     from paper_2403_11383_amd import binding, workloads
     import torch
     cfg = workloads.config("c1")
-    rt = binding.Runtime(arena_bytes=4 << 30)
+    rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)), two_streams=True)
     rt.set_timing(args.timing)
     elapsed, lat, acts, timing, plant = closed_loop(rt, binding, workloads, cfg, args.steps,
-                                                    args.warmup)
+                                                    args.warmup, prefetch=not args.no_prefetch)
     rt.close()
     N, H, R = cfg["N"], cfg["H"], cfg["iterations"]
     steps_total = N * H * R * args.steps
@@ -242,7 +247,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c1: closed-loop MPPI, gait frequency ~U[1.0,2.5] Hz per sample, "
                                "N=10240, H=50, dt=0.02 s, 40 N lateral push from tick 30",
-                   "N": N, "H": H, "iterations": R, "ticks": args.steps},
+                   "N": N, "H": H, "iterations": R, "ticks": args.steps,
+                   "noise_prefetch": not args.no_prefetch},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": float(np.max(lat))},
         "stage_us": {k: timing[k] * 1e-3 for k in ("noise_ns", "rollout_ns", "select_ns",
                                                    "update_ns") if timing[k] > 0},

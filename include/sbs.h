@@ -193,6 +193,14 @@ int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable);
 int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean);
 int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q);
 
+/* Noise prefetch for a single controller in direct mode (needs stream2):
+ * the GRF noise depends only on (seed, tick, iteration, sample, step), never
+ * on the state, so every submission also produces the next tick's noise on
+ * the second stream into a second buffer, and the next tick skips its noise
+ * stage.  Results are unchanged; the arena holds two extra noise buffers of
+ * iterations x H x N x 12 floats. */
+int sbs_set_prefetch(sbs_runtime *rt, int32_t id, int32_t enable);
+
 /* Serving statistics: ticks completed, batches launched, admission waits. */
 int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *admit_waits);
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -118,6 +118,7 @@ def lib():
         L.sbs_set_timing.argtypes = [vp, i32]
         L.sbs_timing.argtypes = [vp, vp, vp]
         L.sbs_set_rollout_lanes.argtypes = [vp, i32]
+        L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
         L.sbs_last_error.restype = C.c_char_p
@@ -368,6 +369,10 @@ class Runtime:
     def set_timing(self, mode: int = 1):
         """0 off, 1 events around the rollout stage, 2 around every stage."""
         _check(lib().sbs_set_timing(self._h, int(mode)))
+
+    def set_prefetch(self, cid: int, on: bool = True):
+        """Produce each next tick's noise ahead of time on the second stream."""
+        _check(lib().sbs_set_prefetch(self._h, cid, 1 if on else 0))
 
     def set_rollout_lanes(self, lanes: int = 0):
         """0 automatic, 1 one lane per sample, 4 one lane per leg."""

@@ -63,7 +63,8 @@ struct TickDesc {
   double *ctl;           // [0] frequency mean
   uint32_t *counter;     // update-stage arrival counter (self-resetting)
   // step workspace
-  float *z;              // [H][N][12] noise of the current iteration
+  float *z;              // [H][N][12] noise; iteration r at z + r * z_iter_stride
+  uint64_t z_iter_stride; // 0 (one buffer reused per iteration) or H * N * 12
   uint32_t *q;           // [N]
   void *J;               // [N] costs, controller precision
   void *w;               // [N] weights of the active samples, controller precision
@@ -87,6 +88,9 @@ struct LaunchTab {
   int32_t lanes;         // rollout lanes per sample: 1 or 4 (FP32 only)
   int32_t roll_block;    // rollout workgroup size: 64, 128 or 256
   int32_t unroll;        // rollout step-loop unroll: 1 or 2
+  int32_t r_count;       // iterations covered by a noise launch
+  int32_t write_q;       // noise launch also writes the frequency draws
+  int32_t skip_noise;    // noise already produced (ahead of the tick)
   int32_t pad1;
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index

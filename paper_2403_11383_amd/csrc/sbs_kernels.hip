@@ -114,17 +114,54 @@ __device__ __forceinline__ int find_item(const int32_t *start, int n, int b) {
   return lo;
 }
 
-__global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab) {
-  const int b = blockIdx.x;
-  const int i = find_item(tab.noise_start, tab.n, b);
-  const TickDesc &d = tab.desc[tab.item[i]];
-  const int local = b - tab.noise_start[i];
+// A launch either carries one controller's descriptor by value (INL, the
+// latency path of a single controller: no descriptor copy) or indexes the
+// batch's descriptor array through the stage's block map.
+template <bool INL>
+__device__ __forceinline__ int stage_item(const int32_t *start, int n, int b) {
+  return INL ? 0 : find_item(start, n, b);
+}
+template <bool INL>
+__device__ __forceinline__ int stage_start(const int32_t *start, int i) {
+  return INL ? 0 : start[i];
+}
+
+// Gait-frequency draw of sample k in iteration r (Sec. IV-C): the fixed
+// increment, a uniform integer increment on [q_lo, q_hi] from Philox word 0
+// of call 3, or a Gaussian around the running frequency mean, clamped and
+// quantised in FP64 without contraction.
+__device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
+  if (d.freq_mode == 0) return d.q_fixed;
+  uint32_t c0 = (uint32_t)k, c1 = 0u, c2 = d.tick, c3 = ((uint32_t)r << 8) | 3u;
+  philox4x32_10(c0, c1, c2, c3, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+  if (d.freq_mode == 1) {
+    const uint64_t span = (uint64_t)(d.q_hi - d.q_lo) + 1u;
+    return d.q_lo + (uint32_t)(((uint64_t)c0 * span) >> 32);
+  }
+  const double mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
+  const double sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
+  return freq_gaussian(mf, sf, gauss_pair(c0, c1).x, d.f_min, d.f_max, d.dt);
+}
+
+// GRF noise of iterations tab.r .. tab.r + tab.r_count - 1: one thread per
+// (iteration, step j, sample k); iteration r lands at z + r * z_iter_stride.
+// The noise depends only on (seed, tick, r, k, j), never on the state, so it
+// can be produced ahead of the tick that consumes it.
+template <bool INL>
+__global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc inl) {
+  const int per_iter = tab.total_noise;
+  const int rr = blockIdx.x / per_iter;
+  const int b = blockIdx.x - rr * per_iter;
+  const int i = stage_item<INL>(tab.noise_start, tab.n, b);
+  const TickDesc &d = INL ? inl : tab.desc[tab.item[i]];
+  const int local = b - stage_start<INL>(tab.noise_start, i);
   const int nkb = (d.N + kNoiseBlock - 1) / kNoiseBlock;
   const int j = local / nkb;
   const int k = (local - j * nkb) * kNoiseBlock + (int)threadIdx.x;
   if (k >= d.N) return;
+  const int r = tab.r + rr;
   const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
-  const uint32_t rw = (uint32_t)tab.r << 8;
+  const uint32_t rw = (uint32_t)r << 8;
   float z[12];
 #pragma unroll
   for (uint32_t call = 0; call < 3; ++call) {
@@ -137,28 +174,12 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab) {
     z[4 * call + 2] = gb.x;
     z[4 * call + 3] = gb.y;
   }
-  float4 *dst = reinterpret_cast<float4 *>(d.z + ((size_t)j * d.N + k) * 12);
+  float *zr = d.z + (size_t)r * d.z_iter_stride;
+  float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * d.N + k) * 12);
   dst[0] = make_float4(z[0], z[1], z[2], z[3]);
   dst[1] = make_float4(z[4], z[5], z[6], z[7]);
   dst[2] = make_float4(z[8], z[9], z[10], z[11]);
-  if (j == 0) {
-    uint32_t q;
-    if (d.freq_mode == 0) {
-      q = d.q_fixed;
-    } else {
-      uint32_t c0 = (uint32_t)k, c1 = 0u, c2 = d.tick, c3 = rw | 3u;
-      philox4x32_10(c0, c1, c2, c3, key0, key1);
-      if (d.freq_mode == 1) {
-        const uint64_t span = (uint64_t)(d.q_hi - d.q_lo) + 1u;
-        q = d.q_lo + (uint32_t)(((uint64_t)c0 * span) >> 32);
-      } else {
-        const double mf = (tab.r == 0) ? d.ctl[0] : d.it[IT_MUF];
-        const double sf = (tab.r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
-        q = freq_gaussian(mf, sf, gauss_pair(c0, c1).x, d.f_min, d.f_max, d.dt);
-      }
-    }
-    d.q[k] = q;
-  }
+  if (tab.write_q && j == 0) d.q[k] = draw_q(d, r, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,12 +263,12 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
-template <typename T, int BLOCK, int UNROLL>
-__global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab) {
+template <typename T, int BLOCK, int UNROLL, bool INL>
+__global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
-  const int it = find_item(tab.roll_start, tab.n, b);
-  const TickDesc &d = tab.desc[tab.item[it]];
+  const int it = stage_item<INL>(tab.roll_start, tab.n, b);
+  const TickDesc &d = INL ? inl : tab.desc[tab.item[it]];
   const int N = d.N, H = d.H;
   T *s_mu = reinterpret_cast<T *>(roll_lds);
   T *s_sig = s_mu + (size_t)tab.max_h * 12;
@@ -260,12 +281,13 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab) {
     }
   }
   __syncthreads();
-  const int k = (b - tab.roll_start[it]) * BLOCK + (int)threadIdx.x;
+  const int k = (b - stage_start<INL>(tab.roll_start, it)) * BLOCK + (int)threadIdx.x;
   if (k >= N) return;
 
   RollConst<T> c;
   load_const<T>(d, c);
-  const uint32_t q = d.q[k];
+  const uint32_t q = draw_q(d, tab.r, k);
+  d.q[k] = q;
   const double fkd = (double)q * d.inv_q_scale;
   const T fk = (T)fkd;
   const T half_tst = (q > 0u) ? (T)(d.half_duty / fkd) : T(0);
@@ -282,7 +304,8 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab) {
   bool prev[4] = {false, false, false, false};
   T J = T(0), Jc = T(0), tj = T(0);
 
-  const float4 *zp = reinterpret_cast<const float4 *>(d.z + (size_t)k * 12);
+  const float4 *zp =
+      reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
   const size_t zstride = (size_t)N * 3;  // float4 per step
   float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
 
@@ -435,13 +458,13 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v + dpp<0x4E>(v);  // quad_perm [2,3,0,1]
 }
 
-template <int BLOCK, int UNROLL>
-__global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab) {
+template <int BLOCK, int UNROLL, bool INL>
+__global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   constexpr int kPerBlock = BLOCK / 4;
   const int b = blockIdx.x;
-  const int it = find_item(tab.roll_start, tab.n, b);
-  const TickDesc &d = tab.desc[tab.item[it]];
+  const int it = stage_item<INL>(tab.roll_start, tab.n, b);
+  const TickDesc &d = INL ? inl : tab.desc[tab.item[it]];
   const int N = d.N, H = d.H;
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   float *s_mu = reinterpret_cast<float *>(roll_lds);
@@ -455,7 +478,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab) {
   }
   __syncthreads();
   const int l = threadIdx.x & 3;
-  const int k = (b - tab.roll_start[it]) * kPerBlock + (int)(threadIdx.x >> 2);
+  const int k = (b - stage_start<INL>(tab.roll_start, it)) * kPerBlock + (int)(threadIdx.x >> 2);
   if (k >= N) return;  // whole quads leave together
 
   const float dt = (float)d.dt, inv_m = (float)d.inv_mass, g = (float)d.gravity;
@@ -473,7 +496,8 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab) {
   const float ra1 = (l == 0) ? (float)d.p_ref0[1] : (l == 2) ? vr1 : 0.f;
   const float ra2 = (l == 0) ? (float)d.p_ref0[2] : (l == 1) ? (float)d.yaw_ref : (l == 2) ? vr2 : 0.f;
   const float rv0 = (l == 0) ? vr0 : 0.f, rv1 = (l == 0) ? vr1 : 0.f, rv2 = (l == 0) ? vr2 : 0.f;
-  const uint32_t q = d.q[k];
+  const uint32_t q = draw_q(d, tab.r, k);
+  if (l == 0) d.q[k] = q;
   const double fkd = (double)q * d.inv_q_scale;
   const float half_tst = (q > 0u) ? (float)(d.half_duty / fkd) : 0.f;
   const uint32_t duty_q = d.duty_q;
@@ -488,7 +512,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab) {
   bool prev = false;
   float J = 0.f, Jc = 0.f, tj = 0.f;
 
-  const float *zp = d.z + (size_t)k * 12 + 3 * l;
+  const float *zp = d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12 + 3 * l;
   const size_t zstride = (size_t)N * 12;
   float za = zp[0], zb = zp[1], zc = zp[2];
 
@@ -679,9 +703,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wave_t
   return before;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab) {
-  const TickDesc &d = tab.desc[tab.item[blockIdx.x]];
+template <typename T, bool INL>
+__global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc inl) {
+  const TickDesc &d = INL ? inl : tab.desc[tab.item[blockIdx.x]];
   const int N = d.N, tid = threadIdx.x;
   const T *Jg = reinterpret_cast<const T *>(d.J);
   T *actw = reinterpret_cast<T *>(d.w);
@@ -877,13 +901,13 @@ __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
+template <typename T, bool INL>
+__global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc inl) {
   const int b = blockIdx.x;
-  const int item = find_item(tab.upd_start, tab.n, b);
-  const TickDesc &d = tab.desc[tab.item[item]];
-  const int local = b - tab.upd_start[item];
-  const int nblk = tab.upd_start[item + 1] - tab.upd_start[item];
+  const int item = stage_item<INL>(tab.upd_start, tab.n, b);
+  const TickDesc &d = INL ? inl : tab.desc[tab.item[item]];
+  const int local = b - stage_start<INL>(tab.upd_start, item);
+  const int nblk = INL ? tab.total_upd : tab.upd_start[item + 1] - tab.upd_start[item];
   const int j = local / d.nchunk;
   const int ch = local - j * d.nchunk;
   const int N = d.N, H = d.H, tid = threadIdx.x;
@@ -899,7 +923,7 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
   if (a0 < nact) {
     const int a1 = (a0 + kUpdChunk < nact) ? a0 + kUpdChunk : nact;
     double out1[12], out2[12];
-    const float *zj = d.z + (size_t)j * N * 12;
+    const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
     // four gathers in flight per thread: indices and weights first, then rows
     double s1[12], s2[12];
     T f1[12];
@@ -1045,51 +1069,79 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab) {
 // ---------------------------------------------------------------------------
 // timing: 0 none; 1 two events around the rollout stage (ev[0], ev[1]);
 // 2 five events around the four stages (ev[0..4]).
-hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
-                            hipEvent_t *ev) {
-  if (tab.n == 0) return hipSuccess;
+template <bool INL>
+static hipError_t launch_rollout(const LaunchTab &tab, const TickDesc &inl, int precision,
+                                 size_t lds, hipStream_t s) {
+  const dim3 rg(tab.total_roll);
+  if (precision == 1) {
+    hipLaunchKernelGGL((k_rollout<double, 64, 1, INL>), rg, dim3(64), lds, s, tab, inl);
+    return hipSuccess;
+  }
+  if (tab.lanes == 4) {
+    switch (tab.roll_block * 4 + tab.unroll) {
+      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1, INL>), rg, dim3(64), lds, s, tab, inl); break;
+      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1, INL>), rg, dim3(128), lds, s, tab, inl); break;
+      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1, INL>), rg, dim3(256), lds, s, tab, inl); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+  }
+  switch (tab.roll_block * 4 + tab.unroll) {
+    case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1, INL>), rg, dim3(64), lds, s, tab, inl); break;
+    case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1, INL>), rg, dim3(128), lds, s, tab, inl); break;
+    case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1, INL>), rg, dim3(256), lds, s, tab, inl); break;
+    case 64 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 64, 2, INL>), rg, dim3(64), lds, s, tab, inl); break;
+    case 128 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 128, 2, INL>), rg, dim3(128), lds, s, tab, inl); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+template <bool INL>
+static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int precision,
+                                hipStream_t s, int timing, hipEvent_t *ev) {
   const size_t roll_lds = (size_t)tab.max_h * 12 * 2 * (precision == 1 ? 8 : 4);
   const size_t upd_lds = (size_t)tab.max_h * 12 * 8;
   if (timing == 2) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_noise, dim3(tab.total_noise), dim3(kNoiseBlock), 0, s, tab);
+  if (!tab.skip_noise)
+    hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,
+                       tab, inl);
   if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 1 : 0], s);
-  const dim3 rg(tab.total_roll);
-  if (precision == 1) {
-    hipLaunchKernelGGL((k_rollout<double, 64, 1>), rg, dim3(64), roll_lds, s, tab);
-  } else if (tab.lanes == 4) {
-    switch (tab.roll_block * 4 + tab.unroll) {
-      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1>), rg, dim3(128), roll_lds, s, tab); break;
-      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1>), rg, dim3(256), roll_lds, s, tab); break;
-      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1>), rg, dim3(64), roll_lds, s, tab); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (tab.roll_block * 4 + tab.unroll) {
-      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1>), rg, dim3(128), roll_lds, s, tab); break;
-      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1>), rg, dim3(256), roll_lds, s, tab); break;
-      case 64 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 64, 2>), rg, dim3(64), roll_lds, s, tab); break;
-      case 128 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 128, 2>), rg, dim3(128), roll_lds, s, tab); break;
-      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1>), rg, dim3(64), roll_lds, s, tab); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
+  hipError_t e = launch_rollout<INL>(tab, inl, precision, roll_lds, s);
+  if (e != hipSuccess) return e;
   if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 2 : 1], s);
   if (precision == 1)
-    hipLaunchKernelGGL(k_select<double>, dim3(tab.n), dim3(kSelBlock), 0, s, tab);
+    hipLaunchKernelGGL((k_select<double, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
   else
-    hipLaunchKernelGGL(k_select<float>, dim3(tab.n), dim3(kSelBlock), 0, s, tab);
+    hipLaunchKernelGGL((k_select<float, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
   if (timing == 2) (void)hipEventRecord(ev[3], s);
   if (precision == 1)
-    hipLaunchKernelGGL(k_update<double>, dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab);
+    hipLaunchKernelGGL((k_update<double, INL>), dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab, inl);
   else
-    hipLaunchKernelGGL(k_update<float>, dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab);
+    hipLaunchKernelGGL((k_update<float, INL>), dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab, inl);
   if (timing == 2) (void)hipEventRecord(ev[4], s);
   return hipGetLastError();
 }
 
-hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s) {
+// One iteration of every stage over the launch's controllers.  With `inl`
+// non-null the launch holds exactly one controller whose descriptor travels
+// in the kernel arguments.
+hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
+                            hipEvent_t *ev, const TickDesc *inl) {
   if (tab.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_noise, dim3(tab.total_noise), dim3(kNoiseBlock), 0, s, tab);
+  if (inl) return launch_stages<true>(tab, *inl, precision, s, timing, ev);
+  static const TickDesc none{};
+  return launch_stages<false>(tab, none, precision, s, timing, ev);
+}
+
+// The noise stage alone (iterations tab.r .. tab.r + tab.r_count - 1), with
+// the descriptor inline when `inl` is non-null.
+hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl) {
+  if (tab.n == 0) return hipSuccess;
+  static const TickDesc none{};
+  const dim3 g(tab.total_noise * tab.r_count);
+  if (inl) hipLaunchKernelGGL((k_noise<true>), g, dim3(kNoiseBlock), 0, s, tab, *inl);
+  else hipLaunchKernelGGL((k_noise<false>), g, dim3(kNoiseBlock), 0, s, tab, none);
   return hipGetLastError();
 }
 

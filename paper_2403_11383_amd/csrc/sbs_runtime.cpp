@@ -36,8 +36,8 @@
 
 namespace sbs {
 hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
-                            hipEvent_t *ev);
-hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s);
+                            hipEvent_t *ev, const TickDesc *inl);
+hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl);
 }
 
 using namespace sbs;
@@ -146,6 +146,14 @@ struct Controller {
   double *dbg_mean = nullptr;
   int inflight = 0;
   int plan = -1;
+  // noise prefetch: two buffers of iterations x H x N x 12 floats; the next
+  // tick's noise is written into the idle one on the second stream
+  bool prefetch = false;
+  uint64_t pf_off = 0, pf_bytes = 0;
+  float *pf_z[2] = {nullptr, nullptr};
+  int64_t pf_tick[2] = {-1, -1};
+  hipEvent_t pf_ready[2] = {nullptr, nullptr};
+  hipEvent_t pf_free[2] = {nullptr, nullptr};
 };
 
 struct Request {
@@ -477,6 +485,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.lanes = lanes;
       tab.roll_block = block;
       tab.unroll = unroll;
+      tab.r_count = 1;
       tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
       tab.item = reinterpret_cast<const int32_t *>(dev + off);
       tab.noise_start = tab.item + n;
@@ -590,7 +599,27 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   b->tickets = tks;
   b->ctrls = ids;
   b->done = take_event(rt);
-  hipError_t e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  // a single controller's descriptor travels in the kernel arguments; a
+  // batch's descriptors and block maps go up in one copy
+  TickDesc *inl = ids.size() == 1 ? reinterpret_cast<TickDesc *>(host + L.desc) : nullptr;
+  hipError_t e = inl ? hipSuccess : hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  // noise prefetch (single controller, direct mode): read this tick's noise
+  // from the buffer the previous submission filled ahead of time
+  Controller *pc = nullptr;
+  int pbuf = 0;
+  if (inl && rt->mode == SBS_MODE_DIRECT && slot == 0 && rt->streams[1]) {
+    Controller &C0 = rt->ctrls.at(ids[0]);
+    if (C0.prefetch) {
+      pc = &C0;
+      pbuf = (int)(ticks[0] & 1u);
+      inl->z = C0.pf_z[pbuf];
+      inl->z_iter_stride = (uint64_t)C0.cfg.H * C0.cfg.N * 12;
+      if (C0.pf_tick[pbuf] == (int64_t)ticks[0]) {
+        e = hipStreamWaitEvent(s, C0.pf_ready[pbuf], 0);
+        for (auto &tp : tabs) tp.first.skip_noise = 1;
+      }
+    }
+  }
   const int64_t t_launch = now_ns();
   for (auto &tp : tabs) {
     if (e != hipSuccess) break;
@@ -601,9 +630,29 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
       ev = &b->timing[base];
     }
-    e = launch_iteration(tp.first, tp.second, s, rt->timing, ev);
+    e = launch_iteration(tp.first, tp.second, s, rt->timing, ev, inl);
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
+  if (pc && e == hipSuccess) {
+    // the buffer this tick read is free once the tick is done; the next
+    // tick's noise goes into the other buffer on the second stream, after
+    // the tick that last read it
+    hipStream_t s2 = rt->streams[1];
+    e = hipEventRecord(pc->pf_free[pbuf], s);
+    const int nb = pbuf ^ 1;
+    TickDesc nd = *inl;
+    nd.tick = ticks[0] + 1u;
+    nd.z = pc->pf_z[nb];
+    LaunchTab nt = tabs[0].first;
+    nt.r = 0;
+    nt.r_count = pc->cfg.iterations;
+    nt.skip_noise = 0;
+    nt.write_q = 0;
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, pc->pf_free[nb], 0);
+    if (e == hipSuccess) e = launch_noise_only(nt, s2, &nd);
+    if (e == hipSuccess) e = hipEventRecord(pc->pf_ready[nb], s2);
+    if (e == hipSuccess) pc->pf_tick[nb] = (int64_t)ticks[0] + 1;
+  }
   if (e != hipSuccess) {
     // the stream may still run what was enqueued: wait before freeing
     (void)hipStreamSynchronize(s);
@@ -837,6 +886,14 @@ int sbs_destroy_controller(sbs_runtime *rt, int32_t id) {
   }
   rt->dev_alloc.release(it->second.st_off, it->second.st_bytes);
   if (it->second.dbg_bytes) rt->dev_alloc.release(it->second.dbg_off, it->second.dbg_bytes);
+  if (it->second.prefetch) {
+    (void)hipStreamSynchronize(rt->streams[1]);
+    for (int i = 0; i < 2; ++i) {
+      (void)hipEventDestroy(it->second.pf_ready[i]);
+      (void)hipEventDestroy(it->second.pf_free[i]);
+    }
+    rt->dev_alloc.release(it->second.pf_off, it->second.pf_bytes);
+  }
   rt->ctrls.erase(it);
   rt->cv.notify_all();
   return SBS_OK;
@@ -1000,6 +1057,7 @@ int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, ui
       hipStreamSynchronize(s) != hipSuccess)
     return fail(SBS_EDEVICE, "state upload failed");
   C.next_tick = tick;
+  C.pf_tick[0] = C.pf_tick[1] = -1;
   return SBS_OK;
 }
 
@@ -1095,6 +1153,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   TickDesc *hd = reinterpret_cast<TickDesc *>(host);
   LaunchTab tab = tabs[0].first;
   tab.r = (int32_t)r;
+  tab.write_q = 1;
   const ItemWs w = item_ws(C.cfg);
   hipStream_t s = rt->streams[0];
   const double sf = C.cfg.sigma_f;
@@ -1103,7 +1162,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   if (e == hipSuccess)
     e = hipMemcpyAsync(hd[0].it + IT_MUF, C.ctl, 8, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(hd[0].it + IT_SIGF, &sf, 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_noise_only(tab, s);
+  if (e == hipSuccess) e = launch_noise_only(tab, s, nullptr);
   std::vector<float> zj((size_t)C.cfg.H * C.cfg.N * 12);
   if (e == hipSuccess)
     e = hipMemcpyAsync(zj.data(), dev + L.item_off[0] + w.z, zj.size() * 4, hipMemcpyDeviceToHost, s);
@@ -1117,6 +1176,53 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   for (int j = 0; j < H; ++j)
     for (int k = 0; k < N; ++k)
       std::memcpy(&z[((size_t)k * H + j) * 12], &zj[((size_t)j * N + k) * 12], 48);
+  return SBS_OK;
+}
+
+int sbs_set_prefetch(sbs_runtime *rt, int32_t id, int32_t enable) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::unique_lock<std::mutex> lk(rt->mu);
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  Controller &C = it->second;
+  if (enable && (rt->mode != SBS_MODE_DIRECT || !rt->streams[1]))
+    return fail(SBS_EINVAL, "prefetch needs a direct-mode runtime with a second stream");
+  while (C.inflight > 0) {
+    reap(rt);
+    if (C.inflight > 0) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
+  }
+  if (enable && !C.prefetch) {
+    const uint64_t one = align_up((uint64_t)C.cfg.iterations * C.cfg.H * C.cfg.N * 12 * 4);
+    C.pf_bytes = 2 * one;
+    if (!rt->dev_alloc.alloc(C.pf_bytes, &C.pf_off)) {
+      C.pf_bytes = 0;
+      return fail(SBS_ENOMEM, "arena cannot hold the prefetch buffers");
+    }
+    for (int i = 0; i < 2; ++i) {
+      C.pf_z[i] = reinterpret_cast<float *>(rt->arena + C.pf_off + i * one);
+      C.pf_tick[i] = -1;
+      if (hipEventCreateWithFlags(&C.pf_ready[i], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&C.pf_free[i], hipEventDisableTiming) != hipSuccess)
+        return fail(SBS_EDEVICE, "event creation failed");
+    }
+    C.prefetch = true;
+  } else if (!enable && C.prefetch) {
+    (void)hipStreamSynchronize(rt->streams[1]);
+    for (int i = 0; i < 2; ++i) {
+      (void)hipEventDestroy(C.pf_ready[i]);
+      (void)hipEventDestroy(C.pf_free[i]);
+      C.pf_ready[i] = C.pf_free[i] = nullptr;
+      C.pf_z[i] = nullptr;
+      C.pf_tick[i] = -1;
+    }
+    rt->dev_alloc.release(C.pf_off, C.pf_bytes);
+    C.pf_bytes = 0;
+    C.prefetch = false;
+  }
   return SBS_OK;
 }
 
@@ -1195,7 +1301,7 @@ hipError_t capture_plan(sbs_runtime *rt, Plan &P) {
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
   for (auto &tp : tabs)
-    if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
+    if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (e == hipSuccess) e = e2;
@@ -1351,7 +1457,7 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
       e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
       if (e == hipSuccess) e = hipEventRecord(t0, s);
       for (auto &tp : tabs)
-        if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr);
+        if (e == hipSuccess) e = launch_iteration(tp.first, tp.second, s, 0, nullptr, nullptr);
       if (e == hipSuccess) e = hipEventRecord(t1, s);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
@@ -1436,7 +1542,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
         for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
         ev = &b->timing[base];
       }
-      e = launch_iteration(tp.first, tp.second, s, rt->timing, ev);
+      e = launch_iteration(tp.first, tp.second, s, rt->timing, ev, nullptr);
     }
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);

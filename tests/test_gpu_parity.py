@@ -389,3 +389,28 @@ def test_plan_forms_and_autotune(rt):
     rt.plan_destroy(plan)
     for c in ids:
         rt.destroy_controller(c)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_noise_prefetch_is_transparent(name):
+    """Producing the next tick's noise ahead of time on the second stream
+    changes no result, including after a state import."""
+    from paper_2403_11383_amd import binding
+    cfg = workloads.config(name, N=3000, H=20, seed=41)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(41)))
+    rt = binding.Runtime(arena_bytes=1 << 30, two_streams=True)
+    a = rt.init_controller(cfg)
+    b = rt.init_controller(cfg)
+    rt.set_prefetch(b, True)
+    for t in range(4):
+        x, y = rt.tick(a, inp), rt.tick(b, inp)
+        np.testing.assert_array_equal(x["grf"], y["grf"])
+        assert x["best_cost"] == y["best_cost"] and x["q"] == y["q"] and x["tick"] == y["tick"]
+    mu, mf, tk = rt.get_state(a)
+    rt.set_state(b, mu, mf, tk + 7)  # the prefetched tick no longer matches
+    rt.set_state(a, mu, mf, tk + 7)
+    for t in range(2):
+        x, y = rt.tick(a, inp), rt.tick(b, inp)
+        np.testing.assert_array_equal(x["grf"], y["grf"])
+        assert x["best_cost"] == y["best_cost"]
+    rt.close()
