@@ -88,7 +88,7 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
         if t >= warmup:
             # submit-to-visible latency as recorded by the runtime
             lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
-            acts.append((a.flags, a.freq_hz))
+            acts.append((a.flags, a.freq_hz, a.n_active))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     timing = rt.timing()
@@ -260,8 +260,9 @@ def main():
                      "traffic": stored_traffic("k_rollout", "c1"),
                      "flop_per_launch": N * H * FLOP_PER_ROLLOUT_STEP},
         "closed_loop": {"final_x": [round(float(v), 4) for v in plant.x],
-                        "nonfinite_ticks": int(sum(f & 1 for f, _ in acts)),
-                        "freq_hz_last": acts[-1][1]},
+                        "nonfinite_ticks": int(sum(a[0] & 1 for a in acts)),
+                        "freq_hz_last": acts[-1][1],
+                        "active_samples_median": float(np.median([a[2] for a in acts]))},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

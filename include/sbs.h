@@ -111,6 +111,8 @@ typedef struct sbs_action {
   uint32_t tick;        /* control-step counter of the controller           */
   int32_t controller;
   int64_t t_submit_ns, t_launch_ns, t_done_ns; /* CLOCK_MONOTONIC           */
+  uint32_t n_active;    /* samples with non-zero weight in the last iteration */
+  uint32_t reserved0;
 } sbs_action;
 
 typedef struct sbs_runtime sbs_runtime;

@@ -70,7 +70,8 @@ class Action(C.Structure):
         ("grf", C.c_double * 12), ("contact", C.c_int32 * 4), ("freq_hz", C.c_double),
         ("best_cost", C.c_double), ("q", C.c_uint32), ("flags", C.c_int32),
         ("tick", C.c_uint32), ("controller", C.c_int32), ("t_submit_ns", C.c_int64),
-        ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64),
+        ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64), ("n_active", C.c_uint32),
+        ("reserved0", C.c_uint32),
     ]
 
 
@@ -178,7 +179,7 @@ def action_dict(a: Action) -> dict:
         "freq_hz": a.freq_hz, "best_cost": a.best_cost, "q": int(a.q), "flags": int(a.flags),
         "tick": int(a.tick), "controller": int(a.controller),
         "t_submit_ns": int(a.t_submit_ns), "t_launch_ns": int(a.t_launch_ns),
-        "t_done_ns": int(a.t_done_ns),
+        "t_done_ns": int(a.t_done_ns), "n_active": int(a.n_active),
     }
 
 

@@ -11,7 +11,6 @@ namespace sbs {
 constexpr int kRollBlock = 64;     // default rollout workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
 constexpr int kUpdBlock = 256;     // threads per update workgroup
-constexpr int kUpdChunk = 4096;    // active samples reduced by one update workgroup
 constexpr int kSelBlock = 1024;    // threads of the per-controller select block
 constexpr int kResultDoubles = 24; // action record
 constexpr int kItScalars = 16;     // per-iteration scalars
@@ -25,6 +24,7 @@ enum : int {
   RES_Q = 17,
   RES_BEST = 18,
   RES_FLAGS = 19,
+  RES_NACT = 20,      // samples with non-zero weight in the last iteration
 };
 
 // per-iteration scalars (doubles)
@@ -42,7 +42,8 @@ enum : int {
 
 struct TickDesc {
   int32_t N, H, R, method, freq_mode, friction_on, precision, Ke;
-  int32_t nchunk;        // update chunks of kUpdChunk samples
+  int32_t mu_par0;       // the tick's first iteration reads mu_buf[mu_par0]
+  int32_t shift0;        // 1: that mean is the previous tick's, read shifted
   uint32_t tick;         // control-step counter (noise counter word 2)
   uint32_t phase_robot;
   uint32_t q_fixed, q_lo, q_hi;
@@ -59,9 +60,12 @@ struct TickDesc {
   double inv_q_scale;    // 1 / (dt 2^32): f = q * inv_q_scale
   double x0[12], foot[12], p_ref0[3], v_ref[3], yaw_ref;
   // persistent controller state
-  void *mu;              // [H][12] in the controller precision
+  // Two [H][12] mean buffers in the controller precision.  Iteration r
+  // reads mu_buf[(mu_par0 + r) & 1] and writes the other one.  The warm-start
+  // shift of Sec. III-A is applied when a mean is read (shift0): step j of
+  // the shifted mean is step j + 1 of the stored one, the last step hover.
+  void *mu_buf[2];
   double *ctl;           // [0] frequency mean
-  uint32_t *counter;     // update-stage arrival counter (self-resetting)
   // step workspace
   float *z;              // [H][N][12] noise; iteration r at z + r * z_iter_stride
   uint64_t z_iter_stride; // 0 (one buffer reused per iteration) or H * N * 12
@@ -70,7 +74,6 @@ struct TickDesc {
   void *w;               // [N] weights of the active samples, controller precision
   uint32_t *act;         // [N] active sample indices in increasing order
   double *sigma;         // [H][12] elite std of the current iteration
-  double *partial;       // [H][nchunk][24] update partial sums
   double *it;            // [kItScalars]
   double *result;        // [kResultDoubles]
   double *dbg_J;         // optional [R][N]

@@ -225,6 +225,26 @@ template <typename T> __device__ __forceinline__ T inf_t();
 template <> __device__ __forceinline__ float inf_t<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double inf_t<double>() { return __builtin_huge_val(); }
 
+// The mean that iteration r samples around, step j, dimension c: the
+// iteration's input buffer, read one step ahead (hover at the end) when it
+// still holds the previous tick's mean (the warm-start shift).
+template <typename T>
+__device__ __forceinline__ const T *mean_in(const TickDesc &d, int r) {
+  return reinterpret_cast<const T *>(d.mu_buf[(d.mu_par0 + r) & 1]);
+}
+template <typename T>
+__device__ __forceinline__ T *mean_out(const TickDesc &d, int r) {
+  return reinterpret_cast<T *>(d.mu_buf[(d.mu_par0 + r + 1) & 1]);
+}
+template <typename T>
+__device__ __forceinline__ T mean_at(const TickDesc &d, const T *m, int r, int j, int c) {
+  if (r == 0 && d.shift0) {
+    if (j + 1 < d.H) return m[(j + 1) * 12 + c];
+    return (c % 3 == 2) ? (T)(0.5 * d.mass * d.gravity) : T(0);
+  }
+  return m[j * 12 + c];
+}
+
 // Friction cone: f_z >= 0 and the tangential part scaled radially onto
 // |f_t| <= mu f_z.
 template <typename T>
@@ -274,9 +294,9 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   T *s_sig = s_mu + (size_t)tab.max_h * 12;
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   {
-    const T *mu = reinterpret_cast<const T *>(d.mu);
+    const T *mu = mean_in<T>(d, tab.r);
     for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
-      s_mu[i] = mu[i];
+      s_mu[i] = mean_at<T>(d, mu, tab.r, i / 12, i % 12);
       s_sig[i] = elite_sigma ? (T)d.sigma[i] : (T)d.sigma0;
     }
   }
@@ -470,9 +490,9 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   float *s_mu = reinterpret_cast<float *>(roll_lds);
   float *s_sig = s_mu + (size_t)tab.max_h * 12;
   {
-    const float *mu = reinterpret_cast<const float *>(d.mu);
+    const float *mu = mean_in<float>(d, tab.r);
     for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
-      s_mu[i] = mu[i];
+      s_mu[i] = mean_at<float>(d, mu, tab.r, i / 12, i % 12);
       s_sig[i] = elite_sigma ? (float)d.sigma[i] : (float)d.sigma0;
     }
   }
@@ -887,11 +907,14 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
 }
 
 // ---------------------------------------------------------------------------
-// Update: S1[j][c] = sum over active samples of w_k z_kjc (and S2 = sum of
-// w_k z_kjc^2 for elite).  Workgroup (j, chunk) reduces kUpdChunk active
-// samples of step j; chunks past the active count only arrive.  The last
-// workgroup of the controller to arrive forms the new mean (and elite std),
-// the action and the warm-started mean.
+// Update: one workgroup per (controller, step j).  It reduces
+// S1[c] = sum over active samples of w_k z_kjc (and S2 = sum of z_kjc^2 for
+// the elite, whose weights are 1) and writes step j of the new mean:
+//   MPPI / best sample:  mu'_jc = mu_jc + sigma0 S1 / Omega
+//   elite:               mu'_jc = mu_jc + sigma_jc m,  sigma'_jc = max(sigma_jc sqrt(v), floor)
+// with m = S1 / K_e, v = S2 / K_e - m^2 (FP64).  Each step is independent, so
+// no workgroup waits for another; the warm-start shift is left to the next
+// reader of the mean.  Step 0 of the last iteration also writes the action.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
 #pragma unroll
@@ -906,37 +929,33 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
   const int b = blockIdx.x;
   const int item = stage_item<INL>(tab.upd_start, tab.n, b);
   const TickDesc &d = INL ? inl : tab.desc[tab.item[item]];
-  const int local = b - stage_start<INL>(tab.upd_start, item);
-  const int nblk = INL ? tab.total_upd : tab.upd_start[item + 1] - tab.upd_start[item];
-  const int j = local / d.nchunk;
-  const int ch = local - j * d.nchunk;
-  const int N = d.N, H = d.H, tid = threadIdx.x;
+  const int j = b - stage_start<INL>(tab.upd_start, item);
+  const int N = d.N, tid = threadIdx.x;
   const int r = tab.r;
   const bool elite = (d.method == 1);
   const T *actw = reinterpret_cast<const T *>(d.w);
   const uint32_t *act = d.act;
   __shared__ double lds[kUpdBlock / 64][24];
-  __shared__ int s_last;
-  const int nact = (int)d.it[IT_NACT];
+  __shared__ double s_new[12];
+  const bool skip = d.it[IT_SKIP] != 0.0;
+  const int nact = skip ? 0 : (int)d.it[IT_NACT];
 
-  const int a0 = ch * kUpdChunk;
-  if (a0 < nact) {
-    const int a1 = (a0 + kUpdChunk < nact) ? a0 + kUpdChunk : nact;
-    double out1[12], out2[12];
+  double out1[12], out2[12];
+  {
     const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
     // four gathers in flight per thread: indices and weights first, then rows
     double s1[12], s2[12];
     T f1[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
-    for (int a = a0 + tid; a < a1; a += 4 * kUpdBlock) {
+    for (int a = tid; a < nact; a += 4 * kUpdBlock) {
       uint32_t ka[4];
       T wa[4];
       bool va[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int aa = a + u * kUpdBlock;
-        va[u] = aa < a1;
+        va[u] = aa < nact;
         ka[u] = va[u] ? act[aa] : 0u;
         wa[u] = va[u] ? actw[aa] : T(0);
       }
@@ -975,81 +994,54 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
 #pragma unroll
       for (int c = 0; c < 12; ++c) { out1[c] = (double)wave_sum(f1[c]); out2[c] = 0.0; }
     }
-    const int lane = tid & 63, wid = tid >> 6;
-    if (lane == 0) {
+  }
+  const int lane = tid & 63, wid = tid >> 6;
+  if (lane == 0) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
-    }
-    __syncthreads();
-    if (tid < 24) {
-      double sacc = 0.0;
-      for (int i = 0; i < kUpdBlock / 64; ++i) sacc += lds[i][tid];
-      d.partial[((size_t)j * d.nchunk + ch) * 24 + tid] = sacc;
-    }
-  }
-  // arrival: the last workgroup of this controller combines
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const uint32_t old = atomicAdd(d.counter, 1u);
-    s_last = (old == (uint32_t)(nblk - 1)) ? 1 : 0;
+    for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-
-  extern __shared__ double newmu[];  // [max_h * 12], used by the last workgroup only
-  const bool skip = d.it[IT_SKIP] != 0.0;
-  const double omega = d.it[IT_OMEGA];
-  const int nch = (nact + kUpdChunk - 1) / kUpdChunk;
-  T *mu = reinterpret_cast<T *>(d.mu);
-  for (int idx = tid; idx < H * 12; idx += kUpdBlock) {
-    const int jj = idx / 12, c = idx - jj * 12;
-    const double m_old = (double)mu[idx];
+  const bool last_iter = (r == d.R - 1);
+  if (tid < 12) {
+    const int c = tid, idx = j * 12 + c;
+    double S1 = 0.0, S2 = 0.0;
+    for (int i = 0; i < kUpdBlock / 64; ++i) {
+      S1 += lds[i][c];
+      S2 += lds[i][12 + c];
+    }
+    const double m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, c);
     double m_new = m_old;
-    if (!skip) {
-      double s1 = 0.0, s2 = 0.0;
-      const double *p = d.partial + (size_t)jj * d.nchunk * 24;
-      for (int cc = 0; cc < nch; ++cc) {
-        s1 += p[cc * 24 + c];
-        s2 += p[cc * 24 + 12 + c];
-      }
-      if (elite) {
-        const double sig = (r == 0) ? d.sigma0 : d.sigma[idx];
-        const double mz = s1 / omega;
-        double vz = s2 / omega - mz * mz;
+    const double sig = (elite && r > 0) ? d.sigma[idx] : d.sigma0;
+    if (elite) {
+      double sg = sig;
+      if (!skip) {
+        const double omega = d.it[IT_OMEGA];
+        const double mz = S1 / omega;
+        double vz = S2 / omega - mz * mz;
         vz = vz > 0.0 ? vz : 0.0;
         m_new = m_old + sig * mz;
         const double sn = sig * __builtin_sqrt(vz);
-        d.sigma[idx] = sn > d.sigma_min_grf ? sn : d.sigma_min_grf;
-      } else {
-        m_new = m_old + d.sigma0 * (s1 / omega);
+        sg = sn > d.sigma_min_grf ? sn : d.sigma_min_grf;
       }
+      d.sigma[idx] = sg;
+    } else if (!skip) {
+      m_new = m_old + d.sigma0 * (S1 / d.it[IT_OMEGA]);
     }
-    newmu[idx] = (double)(T)m_new;
+    const T stored = (T)m_new;
+    mean_out<T>(d, r)[idx] = stored;
+    s_new[c] = (double)stored;
+    if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
   }
-  if (tid == 0) *d.counter = 0u;
+  if (!(last_iter && j == 0)) return;
   __syncthreads();
-  const bool last_iter = (r == d.R - 1);
-  if (!last_iter) {
-    for (int idx = tid; idx < H * 12; idx += kUpdBlock) mu[idx] = (T)newmu[idx];
-    return;
-  }
-  const double hover = 0.5 * d.mass * d.gravity;
-  for (int idx = tid; idx < H * 12; idx += kUpdBlock) {
-    if (d.dbg_mean) d.dbg_mean[idx] = newmu[idx];
-    const int jj = idx / 12, c = idx - jj * 12;
-    const double v = (jj < H - 1) ? newmu[idx + 12] : ((c % 3 == 2) ? hover : 0.0);
-    mu[idx] = (T)v;
-  }
-  if (tid == 0) {
+  if (tid == 0) {  // the action: first step of the new mean, masked and clipped
     const double f_final = (d.freq_mode == 0) ? d.f_fixed : d.it[IT_FNEW];
     const uint32_t qf = (d.freq_mode == 0) ? d.q_fixed : q_of_freq(f_final, d.dt);
     bool st[4];
     contact_at(d, st);
     double *res = d.result;
     for (int l = 0; l < 4; ++l) {
-      double fx = newmu[3 * l], fy = newmu[3 * l + 1], fz = newmu[3 * l + 2];
+      double fx = s_new[3 * l], fy = s_new[3 * l + 1], fz = s_new[3 * l + 2];
       if (d.friction_on) friction_clip<double>(fx, fy, fz, d.mu_fric);
       res[RES_GRF + 3 * l + 0] = st[l] ? fx : 0.0;
       res[RES_GRF + 3 * l + 1] = st[l] ? fy : 0.0;
@@ -1060,6 +1052,7 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
     res[RES_Q] = (double)qf;
     res[RES_BEST] = d.it[IT_BETA];
     res[RES_FLAGS] = d.it[IT_FLAGS];
+    res[RES_NACT] = d.it[IT_NACT];
     d.ctl[0] = f_final;
   }
 }
@@ -1101,7 +1094,6 @@ template <bool INL>
 static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int precision,
                                 hipStream_t s, int timing, hipEvent_t *ev) {
   const size_t roll_lds = (size_t)tab.max_h * 12 * 2 * (precision == 1 ? 8 : 4);
-  const size_t upd_lds = (size_t)tab.max_h * 12 * 8;
   if (timing == 2) (void)hipEventRecord(ev[0], s);
   if (!tab.skip_noise)
     hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,
@@ -1116,9 +1108,9 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
     hipLaunchKernelGGL((k_select<float, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
   if (timing == 2) (void)hipEventRecord(ev[3], s);
   if (precision == 1)
-    hipLaunchKernelGGL((k_update<double, INL>), dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab, inl);
+    hipLaunchKernelGGL((k_update<double, INL>), dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab, inl);
   else
-    hipLaunchKernelGGL((k_update<float, INL>), dim3(tab.total_upd), dim3(kUpdBlock), upd_lds, s, tab, inl);
+    hipLaunchKernelGGL((k_update<float, INL>), dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab, inl);
   if (timing == 2) (void)hipEventRecord(ev[4], s);
   return hipGetLastError();
 }

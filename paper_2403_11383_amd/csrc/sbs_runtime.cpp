@@ -135,9 +135,11 @@ struct Controller {
   int32_t id = -1;
   sbs_controller_cfg cfg{};
   uint64_t st_off = 0, st_bytes = 0;
-  void *mu = nullptr;
+  void *mu_buf[2] = {nullptr, nullptr};  // double-buffered mean [H][12]
+  uint64_t mu_bytes = 0;
+  int par = 0;              // buffer holding the current mean
+  bool needs_shift = false; // it is the previous tick's mean (unshifted)
   double *ctl = nullptr;
-  uint32_t *counter = nullptr;
   uint32_t next_tick = 0;
   bool debug = false;
   uint64_t dbg_off = 0, dbg_bytes = 0;
@@ -180,14 +182,13 @@ struct Layout {
 };
 
 struct ItemWs {
-  uint64_t z, q, J, w, act, sigma, partial, it, bytes;
+  uint64_t z, q, J, w, act, sigma, it, bytes;
 };
 
 ItemWs item_ws(const sbs_controller_cfg &c) {
   ItemWs o{};
   const uint64_t N = (uint64_t)c.N, H = (uint64_t)c.H;
   const uint64_t ts = c.precision == SBS_FP64 ? 8 : 4;
-  const uint64_t nchunk = (N + kUpdChunk - 1) / kUpdChunk;
   uint64_t p = 0;
   o.z = p; p = align_up(p + H * N * 12 * 4);
   o.q = p; p = align_up(p + N * 4);
@@ -195,7 +196,6 @@ ItemWs item_ws(const sbs_controller_cfg &c) {
   o.w = p; p = align_up(p + N * ts);
   o.act = p; p = align_up(p + N * 4);
   o.sigma = p; p = align_up(p + H * 12 * 8);
-  o.partial = p; p = align_up(p + H * nchunk * 24 * 8);
   o.it = p; p = align_up(p + kItScalars * 8);
   o.bytes = p;
   return o;
@@ -330,7 +330,8 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   double kef = std::floor(c.elite_frac * (double)c.N);
   int32_t ke = (int32_t)std::min<double>(std::max<double>(kef, 1.0), (double)c.N);
   d->Ke = c.method == SBS_NAIVE ? 1 : ke;
-  d->nchunk = (c.N + kUpdChunk - 1) / kUpdChunk;
+  d->mu_par0 = C.par;
+  d->shift0 = C.needs_shift ? 1 : 0;
   d->tick = tick;
   d->phase_robot = in.phase_robot;
   d->q_fixed = host_q_of_freq(c.f_fixed, c.dt);
@@ -376,16 +377,15 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
     d->v_ref[i] = in.v_ref[i];
   }
   d->yaw_ref = in.yaw_ref;
-  d->mu = C.mu;
+  d->mu_buf[0] = C.mu_buf[0];
+  d->mu_buf[1] = C.mu_buf[1];
   d->ctl = C.ctl;
-  d->counter = C.counter;
   d->z = reinterpret_cast<float *>(dev_item + w.z);
   d->q = reinterpret_cast<uint32_t *>(dev_item + w.q);
   d->J = dev_item + w.J;
   d->w = dev_item + w.w;
   d->act = reinterpret_cast<uint32_t *>(dev_item + w.act);
   d->sigma = reinterpret_cast<double *>(dev_item + w.sigma);
-  d->partial = reinterpret_cast<double *>(dev_item + w.partial);
   d->it = reinterpret_cast<double *>(dev_item + w.it);
   d->result = dev_result;
   if (C.debug) {
@@ -472,7 +472,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         item[t] = idx[t];
         ns[t + 1] = ns[t] + c.H * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
         rs[t + 1] = rs[t] + (c.N + per_block - 1) / per_block;
-        us[t + 1] = us[t] + c.H * ((c.N + kUpdChunk - 1) / kUpdChunk);
+        us[t + 1] = us[t] + c.H;
       }
       if (m == 0) continue;
       LaunchTab tab{};
@@ -666,6 +666,8 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     Controller &c = rt->ctrls.at(ids[i]);
     c.next_tick += 1;
     c.inflight += 1;
+    c.par = (c.par + c.cfg.iterations) & 1;
+    c.needs_shift = true;
     TicketRec &t = rt->tickets[tks[i]];
     t.t_launch = t_launch;
     t.tick = ticks[i];
@@ -827,17 +829,17 @@ int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t 
   Controller C;
   C.cfg = *cfg;
   const uint64_t ts = cfg->precision == SBS_FP64 ? 8 : 4;
-  const uint64_t mu_bytes = align_up((uint64_t)cfg->H * 12 * ts);
-  C.st_bytes = mu_bytes + kAlign + kAlign;
+  C.mu_bytes = align_up((uint64_t)cfg->H * 12 * ts);
+  C.st_bytes = 2 * C.mu_bytes + kAlign;
   if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off)) {
     reap(rt);
     if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off))
       return fail(SBS_ENOMEM, "arena cannot hold the controller state");
   }
   char *base = rt->arena + C.st_off;
-  C.mu = base;
-  C.ctl = reinterpret_cast<double *>(base + mu_bytes);
-  C.counter = reinterpret_cast<uint32_t *>(base + mu_bytes + kAlign);
+  C.mu_buf[0] = base;
+  C.mu_buf[1] = base + C.mu_bytes;
+  C.ctl = reinterpret_cast<double *>(base + 2 * C.mu_bytes);
   // hover mean: (0, 0, m g / 2) on every leg and step
   std::vector<char> hostbuf(C.st_bytes, 0);
   const double hover = 0.5 * cfg->mass * cfg->gravity;
@@ -847,7 +849,7 @@ int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t 
       if (ts == 8) reinterpret_cast<double *>(hostbuf.data())[j * 12 + c] = v;
       else reinterpret_cast<float *>(hostbuf.data())[j * 12 + c] = (float)v;
     }
-  *reinterpret_cast<double *>(hostbuf.data() + mu_bytes) = cfg->mu_f0;
+  *reinterpret_cast<double *>(hostbuf.data() + 2 * C.mu_bytes) = cfg->mu_f0;
   hipStream_t s = rt->streams[0];
   if (hipMemcpyAsync(base, hostbuf.data(), C.st_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
@@ -981,6 +983,7 @@ int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t 
         out->t_submit_ns = t.t_submit;
         out->t_launch_ns = t.t_launch;
         out->t_done_ns = t.t_done;
+        out->n_active = (uint32_t)t.res[RES_NACT];
       }
       rt->tickets.erase(it);
       if (st < 0) return fail(st, "tick failed or was cancelled");
@@ -1010,18 +1013,29 @@ int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_
     }
   }
   Controller &C = it->second;
-  const int n = C.cfg.H * 12;
+  const int H = C.cfg.H, n = H * 12;
   const bool f64 = C.cfg.precision == SBS_FP64;
   std::vector<char> buf((size_t)n * (f64 ? 8 : 4));
   double mf = 0;
   hipStream_t s = rt->streams[0];
-  if (hipMemcpyAsync(buf.data(), C.mu, buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(buf.data(), C.mu_buf[C.par], buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&mf, C.ctl, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(SBS_EDEVICE, "state download failed");
-  if (mu)
-    for (int i = 0; i < n; ++i)
-      mu[i] = f64 ? reinterpret_cast<double *>(buf.data())[i] : (double)reinterpret_cast<float *>(buf.data())[i];
+  if (mu) {
+    // the warm-started mean: shifted by one step when the stored one is
+    // the previous tick's
+    const double hover = 0.5 * C.cfg.mass * C.cfg.gravity;
+    for (int i = 0; i < n; ++i) {
+      const int j = i / 12, c = i % 12;
+      const int src = C.needs_shift ? i + 12 : i;
+      double v;
+      if (C.needs_shift && j == H - 1) v = (c % 3 == 2) ? hover : 0.0;
+      else v = f64 ? reinterpret_cast<double *>(buf.data())[src]
+                   : (double)reinterpret_cast<float *>(buf.data())[src];
+      mu[i] = v;
+    }
+  }
   if (mu_f) *mu_f = mf;
   if (tick) *tick = C.next_tick;
   return SBS_OK;
@@ -1052,10 +1066,11 @@ int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, ui
     else reinterpret_cast<float *>(buf.data())[i] = (float)mu[i];
   }
   hipStream_t s = rt->streams[0];
-  if (hipMemcpyAsync(C.mu, buf.data(), buf.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+  if (hipMemcpyAsync(C.mu_buf[C.par], buf.data(), buf.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(C.ctl, &mu_f, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(SBS_EDEVICE, "state upload failed");
+  C.needs_shift = false;
   C.next_tick = tick;
   C.pf_tick[0] = C.pf_tick[1] = -1;
   return SBS_OK;
@@ -1410,7 +1425,7 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
   uint64_t snap_bytes = 0;
   std::vector<uint64_t> mu_bytes(n);
   for (int i = 0; i < n; ++i) {
-    mu_bytes[i] = align_up((uint64_t)cs[i]->cfg.H * 12 * (cs[i]->cfg.precision == SBS_FP64 ? 8 : 4));
+    mu_bytes[i] = cs[i]->mu_bytes;
     snap_bytes += mu_bytes[i] + kAlign;
   }
   uint64_t snap_off = 0;
@@ -1422,8 +1437,9 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
     hipError_t e = hipSuccess;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
       const Controller &C = *cs[i];
-      e = save ? hipMemcpyAsync(p, C.mu, mu_bytes[i], hipMemcpyDeviceToDevice, s)
-               : hipMemcpyAsync(C.mu, p, mu_bytes[i], hipMemcpyDeviceToDevice, s);
+      void *cur = C.mu_buf[C.par];  // the plan's trials never change the host parity
+      e = save ? hipMemcpyAsync(p, cur, mu_bytes[i], hipMemcpyDeviceToDevice, s)
+               : hipMemcpyAsync(cur, p, mu_bytes[i], hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess)
         e = save ? hipMemcpyAsync(p + mu_bytes[i], C.ctl, 8, hipMemcpyDeviceToDevice, s)
                  : hipMemcpyAsync(C.ctl, p + mu_bytes[i], 8, hipMemcpyDeviceToDevice, s);
@@ -1565,6 +1581,8 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     Controller &c = rt->ctrls.at(P.ctrls[i]);
     c.next_tick += 1;
     c.inflight += 1;
+    c.par = (c.par + c.cfg.iterations) & 1;
+    c.needs_shift = true;
   }
   P.busy = true;
   rt->n_batches += 1;
