@@ -211,9 +211,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 around the rollout stage, 2 around every stage")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "copy"],
                     help="c1 closed-loop single MPPI (default); c3 batched uneven "
-                         "controllers; c4 serving 256 robots vs plain single MPPI")
+                         "controllers; c4 serving 256 robots vs plain single MPPI; copy: "
+                         "a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
     ap.add_argument("--arena-gb", type=float, default=4.0)
     ap.add_argument("--no-prefetch", action="store_true",
@@ -222,6 +223,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "copy":
+        return main_copy(args)
     if args.workload == "c3":
         return main_c3(args)
     if args.workload == "c4":
@@ -311,6 +314,24 @@ def main_c3(args):
                      "traffic": stored_traffic("k_rollout", "c3")},
     }
     print(json.dumps(line), flush=True)
+
+
+def main_copy(args):
+    """Copies a 1 GiB device buffer `steps` times: 1 GiB read + 1 GiB written
+    per copy kernel, the known-size reference for FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"workload": "copy", "bytes_per_copy": n, "copies": args.steps,
+                      "GBps_read_plus_write": 2 * n * args.steps / dt / 1e9}), flush=True)
 
 
 def main_c4(args):

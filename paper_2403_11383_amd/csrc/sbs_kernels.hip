@@ -732,6 +732,7 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   uint32_t *act = d.act;
   const int r = tab.r;
   __shared__ double lds_d[kSelBlock / 64];
+  __shared__ double lds_d2[kSelBlock / 64];
   __shared__ T lds_v[kSelBlock / 64];
   __shared__ int lds_k[kSelBlock / 64];
   __shared__ uint32_t hist[256];
@@ -782,25 +783,45 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
     const T il = (T)d.inv_lambda;
     double sw = 0.0, swf = 0.0;
     uint32_t cnt = 0;
-    SEL_FOR(cnt += (exp_t((bv - cv) * il) != T(0)) ? 1u : 0u;)
-    uint32_t tot;
-    uint32_t pos = block_excl_scan(cnt, wave_tot, &tot);
     SEL_FOR(
       const T wk = exp_t((bv - cv) * il);
       if (wk != T(0)) {
-        const int k = k0 + i;
-        act[pos] = (uint32_t)k;
-        actw[pos] = wk;
-        ++pos;
+        ++cnt;
         sw += (double)wk;
-        swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+        swf += (double)wk * ((double)d.q[k0 + i] * d.inv_q_scale);
       })
-    nact = tot;
-    sw = block_sum(sw, lds_d);
-    swf = block_sum(swf, lds_d);
-    omega = sw;
-    fnew = swf / sw;
-    mf_next = fnew;
+    // one block round: exclusive scan of the counts and the two FP64 sums
+    {
+      const int lane = tid & 63, wid = tid >> 6;
+      const uint32_t incl = wave_incl_scan(cnt);
+      const double wsw = wave_sum(sw), wswf = wave_sum(swf);
+      if (lane == 63) wave_tot[wid] = incl;
+      if (lane == 0) {
+        lds_d[wid] = wsw;
+        lds_d2[wid] = wswf;
+      }
+      __syncthreads();
+      uint32_t pos = incl - cnt, tot = 0;
+      double tsw = 0.0, tswf = 0.0;
+      for (int w = 0; w < kSelBlock / 64; ++w) {
+        const uint32_t c = wave_tot[w];
+        pos += (w < wid) ? c : 0u;
+        tot += c;
+        tsw += lds_d[w];
+        tswf += lds_d2[w];
+      }
+      SEL_FOR(
+        const T wk = exp_t((bv - cv) * il);
+        if (wk != T(0)) {
+          act[pos] = (uint32_t)(k0 + i);
+          actw[pos] = wk;
+          ++pos;
+        })
+      nact = tot;
+      omega = tsw;
+      fnew = tswf / tsw;
+      mf_next = fnew;
+    }
   } else if (d.method == 2) {  // naive: the best sample
     if (tid == 0) {
       act[0] = (uint32_t)bk;

@@ -65,8 +65,10 @@ def test_serving_tick_order_per_robot():
 def test_serving_memory_admission():
     cfgs, inps = fleet()
     direct, _ = run("direct", cfgs, inps, ticks=2)
-    # an arena that holds the persistent state and only a few steps' workspaces
-    small = 24 << 20
+    # an arena that holds the persistent state and the workspaces of only a
+    # few of the twelve controllers at once (the largest, N=2048 H=25, takes
+    # about 2.5 MB; the fleet together about 12 MB)
+    small = 6 << 20
     served, st = run("serving", cfgs, inps, ticks=2, arena=small)
     for a, b in zip(direct, served):
         same(a, b)
