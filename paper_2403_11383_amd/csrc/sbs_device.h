@@ -10,7 +10,8 @@ namespace sbs {
 
 constexpr int kRollBlock = 64;     // default rollout workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
-constexpr int kUpdBlock = 256;     // threads per update workgroup
+constexpr int kUpdBlock = 256;     // threads per update workgroup (elite, best sample)
+constexpr int kMppiBlock = 1024;   // threads per fused MPPI update workgroup
 constexpr int kSelBlock = 1024;    // threads of the per-controller select block
 constexpr int kResultDoubles = 24; // action record
 constexpr int kItScalars = 16;     // per-iteration scalars
@@ -94,7 +95,7 @@ struct LaunchTab {
   int32_t r_count;       // iterations covered by a noise launch
   int32_t write_q;       // noise launch also writes the frequency draws
   int32_t skip_noise;    // noise already produced (ahead of the tick)
-  int32_t pad1;
+  int32_t n_select;      // items with an elite or best-sample update
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

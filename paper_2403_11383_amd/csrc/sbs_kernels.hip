@@ -117,6 +117,19 @@ __device__ __forceinline__ int find_item(const int32_t *start, int n, int b) {
 // A launch either carries one controller's descriptor by value (INL, the
 // latency path of a single controller: no descriptor copy) or indexes the
 // batch's descriptor array through the stage's block map.
+// The descriptor of a single-controller launch, read in place from the
+// kernel-argument segment, where it follows the LaunchTab argument (explicit
+// arguments are laid out in order at their natural alignment).  Naming the
+// by-value parameter instead lets the compiler copy the whole descriptor into
+// per-lane scratch whenever a field's address meets a global address in a
+// conditional choice.
+__device__ __forceinline__ const TickDesc &inline_desc() {
+  constexpr size_t kOff =
+      (sizeof(LaunchTab) + alignof(TickDesc) - 1) / alignof(TickDesc) * alignof(TickDesc);
+  const char *seg = (const char *)__builtin_amdgcn_kernarg_segment_ptr();
+  return *reinterpret_cast<const TickDesc *>(seg + kOff);
+}
+
 template <bool INL>
 __device__ __forceinline__ int stage_item(const int32_t *start, int n, int b) {
   return INL ? 0 : find_item(start, n, b);
@@ -153,7 +166,7 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
   const int rr = blockIdx.x / per_iter;
   const int b = blockIdx.x - rr * per_iter;
   const int i = stage_item<INL>(tab.noise_start, tab.n, b);
-  const TickDesc &d = INL ? inl : tab.desc[tab.item[i]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[i]];
   const int local = b - stage_start<INL>(tab.noise_start, i);
   const int nkb = (d.N + kNoiseBlock - 1) / kNoiseBlock;
   const int j = local / nkb;
@@ -185,30 +198,16 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
 // ---------------------------------------------------------------------------
 // Rollout
 // ---------------------------------------------------------------------------
-// FP32 sine and cosine: Cody-Waite reduction by pi/2 (three-part constant,
-// fused multiply-adds) to |r| <= pi/4, Taylor polynomials through r^9 / r^10
-// (truncation below 4e-9), quadrant by rotation.  Accurate to a few ulp for
-// |x| up to ~1e4 rad; beyond that the result stays bounded.
+// FP32 sine and cosine on the transcendental unit: the hardware takes the
+// angle in turns, so the argument is scaled by 1/(2 pi) and reduced to
+// [0, 1) first (exact for the fraction; the scaling rounds once).  The
+// attitude angles of a rollout stay within a few radians unless it tumbles,
+// and a tumbling rollout carries no weight; the FP32 cost tolerance of the
+// parity tests covers the approximation.
 __device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
-  const float n = __builtin_rintf(x * 0x1.45f306p-1f);
-  float r = __builtin_fmaf(-n, 0x1.921fb6p+0f, x);
-  r = __builtin_fmaf(-n, -0x1.777a5cp-25f, r);
-  r = __builtin_fmaf(-n, -0x1.0p-49f, r);
-  const float r2 = r * r;
-  float ps = __builtin_fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);
-  ps = __builtin_fmaf(r2, ps, 0x1.111112p-7f);
-  ps = __builtin_fmaf(r2, ps, -0x1.555556p-3f);
-  const float sn = __builtin_fmaf(r * r2, ps, r);
-  float pc = __builtin_fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);
-  pc = __builtin_fmaf(r2, pc, -0x1.6c16c2p-10f);
-  pc = __builtin_fmaf(r2, pc, 0x1.555556p-5f);
-  pc = __builtin_fmaf(r2, pc, -0.5f);
-  const float cs = __builtin_fmaf(r2, pc, 1.0f);
-  const int q = (int)n;
-  const bool swap = (q & 1) != 0;
-  const float ss = swap ? cs : sn, cc = swap ? sn : cs;
-  *s = (q & 2) ? -ss : ss;
-  *c = ((q + 1) & 2) ? -cc : cc;
+  const float t = __builtin_amdgcn_fractf(x * 0x1.45f306p-3f);
+  *s = __builtin_amdgcn_sinf(t);
+  *c = __builtin_amdgcn_cosf(t);
 }
 __device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -288,7 +287,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
   const int it = stage_item<INL>(tab.roll_start, tab.n, b);
-  const TickDesc &d = INL ? inl : tab.desc[tab.item[it]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[it]];
   const int N = d.N, H = d.H;
   T *s_mu = reinterpret_cast<T *>(roll_lds);
   T *s_sig = s_mu + (size_t)tab.max_h * 12;
@@ -484,7 +483,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   constexpr int kPerBlock = BLOCK / 4;
   const int b = blockIdx.x;
   const int it = stage_item<INL>(tab.roll_start, tab.n, b);
-  const TickDesc &d = INL ? inl : tab.desc[tab.item[it]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[it]];
   const int N = d.N, H = d.H;
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   float *s_mu = reinterpret_cast<float *>(roll_lds);
@@ -686,11 +685,12 @@ __device__ __forceinline__ uint64_t key_bits(float v) { return (uint64_t)__float
 __device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
 
 // ---------------------------------------------------------------------------
-// Select: one workgroup per controller.  Thread t owns the contiguous samples
-// [t P, (t+1) P), P = ceil(N / 1024), held in registers for N <= 16384 (read
-// again from memory beyond).  Output: the samples with non-zero weight in
-// index order (act, actw) -- every MPPI sample whose weight does not
-// underflow, the K_e elites, or the best sample -- and per-iteration scalars.
+// Select (elite and best-sample updates): one workgroup per controller.
+// Thread t owns the contiguous samples [t P, (t+1) P), P = ceil(N / 1024),
+// held in registers for N <= 16384 (read again from memory beyond).  Output:
+// the chosen samples in index order (act, actw) -- the K_e elites or the best
+// sample -- and per-iteration scalars.  MPPI controllers form their weights
+// inside k_update_mppi and leave this stage at once.
 // ---------------------------------------------------------------------------
 constexpr int kSelPer = 16;
 
@@ -725,14 +725,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wave_t
 
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc inl) {
-  const TickDesc &d = INL ? inl : tab.desc[tab.item[blockIdx.x]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[blockIdx.x]];
+  if (d.method == 0) return;  // MPPI: see k_update_mppi
   const int N = d.N, tid = threadIdx.x;
   const T *Jg = reinterpret_cast<const T *>(d.J);
   T *actw = reinterpret_cast<T *>(d.w);
   uint32_t *act = d.act;
   const int r = tab.r;
   __shared__ double lds_d[kSelBlock / 64];
-  __shared__ double lds_d2[kSelBlock / 64];
   __shared__ T lds_v[kSelBlock / 64];
   __shared__ int lds_k[kSelBlock / 64];
   __shared__ uint32_t hist[256];
@@ -779,49 +779,6 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   uint32_t nact = 0;
   if (skip) {
     nact = 0;
-  } else if (d.method == 0) {  // MPPI: w_k = exp(-(J_k - beta) / lambda), FP64 normaliser
-    const T il = (T)d.inv_lambda;
-    double sw = 0.0, swf = 0.0;
-    uint32_t cnt = 0;
-    SEL_FOR(
-      const T wk = exp_t((bv - cv) * il);
-      if (wk != T(0)) {
-        ++cnt;
-        sw += (double)wk;
-        swf += (double)wk * ((double)d.q[k0 + i] * d.inv_q_scale);
-      })
-    // one block round: exclusive scan of the counts and the two FP64 sums
-    {
-      const int lane = tid & 63, wid = tid >> 6;
-      const uint32_t incl = wave_incl_scan(cnt);
-      const double wsw = wave_sum(sw), wswf = wave_sum(swf);
-      if (lane == 63) wave_tot[wid] = incl;
-      if (lane == 0) {
-        lds_d[wid] = wsw;
-        lds_d2[wid] = wswf;
-      }
-      __syncthreads();
-      uint32_t pos = incl - cnt, tot = 0;
-      double tsw = 0.0, tswf = 0.0;
-      for (int w = 0; w < kSelBlock / 64; ++w) {
-        const uint32_t c = wave_tot[w];
-        pos += (w < wid) ? c : 0u;
-        tot += c;
-        tsw += lds_d[w];
-        tswf += lds_d2[w];
-      }
-      SEL_FOR(
-        const T wk = exp_t((bv - cv) * il);
-        if (wk != T(0)) {
-          act[pos] = (uint32_t)(k0 + i);
-          actw[pos] = wk;
-          ++pos;
-        })
-      nact = tot;
-      omega = tsw;
-      fnew = tswf / tsw;
-      mf_next = fnew;
-    }
   } else if (d.method == 2) {  // naive: the best sample
     if (tid == 0) {
       act[0] = (uint32_t)bk;
@@ -929,13 +886,15 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
 
 // ---------------------------------------------------------------------------
 // Update: one workgroup per (controller, step j).  It reduces
-// S1[c] = sum over active samples of w_k z_kjc (and S2 = sum of z_kjc^2 for
-// the elite, whose weights are 1) and writes step j of the new mean:
+// S1[c] = sum over the chosen samples of w_k z_kjc (and S2 = sum of z_kjc^2
+// for the elite, whose weights are 1) and writes step j of the new mean:
 //   MPPI / best sample:  mu'_jc = mu_jc + sigma0 S1 / Omega
 //   elite:               mu'_jc = mu_jc + sigma_jc m,  sigma'_jc = max(sigma_jc sqrt(v), floor)
 // with m = S1 / K_e, v = S2 / K_e - m^2 (FP64).  Each step is independent, so
 // no workgroup waits for another; the warm-start shift is left to the next
 // reader of the mean.  Step 0 of the last iteration also writes the action.
+// k_update serves the elite and best-sample controllers from k_select's
+// output; k_update_mppi forms the MPPI weights itself.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
 #pragma unroll
@@ -945,11 +904,40 @@ __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
   }
 }
 
+// The action record (Fig. 2: the first step of the new mean goes to the
+// low-level controller): u_0 masked by the contact flags at the robot's
+// phase and clipped to the friction cone, the executed frequency and its
+// phase increment, the lowest cost, flags and the number of samples that
+// carried weight.  Also stores the frequency mean for the next tick.
+__device__ __forceinline__ void emit_action(const TickDesc &d, const double *s_new, double f_new,
+                                            double beta, double flags, double nact) {
+  const double f_final = (d.freq_mode == 0) ? d.f_fixed : f_new;
+  const uint32_t qf = (d.freq_mode == 0) ? d.q_fixed : q_of_freq(f_final, d.dt);
+  bool st[4];
+  contact_at(d, st);
+  double *res = d.result;
+  for (int l = 0; l < 4; ++l) {
+    double fx = s_new[3 * l], fy = s_new[3 * l + 1], fz = s_new[3 * l + 2];
+    if (d.friction_on) friction_clip<double>(fx, fy, fz, d.mu_fric);
+    res[RES_GRF + 3 * l + 0] = st[l] ? fx : 0.0;
+    res[RES_GRF + 3 * l + 1] = st[l] ? fy : 0.0;
+    res[RES_GRF + 3 * l + 2] = st[l] ? fz : 0.0;
+    res[RES_CONTACT + l] = st[l] ? 1.0 : 0.0;
+  }
+  res[RES_FREQ] = f_final;
+  res[RES_Q] = (double)qf;
+  res[RES_BEST] = beta;
+  res[RES_FLAGS] = flags;
+  res[RES_NACT] = nact;
+  d.ctl[0] = f_final;
+}
+
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc inl) {
   const int b = blockIdx.x;
   const int item = stage_item<INL>(tab.upd_start, tab.n, b);
-  const TickDesc &d = INL ? inl : tab.desc[tab.item[item]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[item]];
+  if (d.method == 0) return;  // MPPI: k_update_mppi
   const int j = b - stage_start<INL>(tab.upd_start, item);
   const int N = d.N, tid = threadIdx.x;
   const int r = tab.r;
@@ -1055,26 +1043,120 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
   }
   if (!(last_iter && j == 0)) return;
   __syncthreads();
-  if (tid == 0) {  // the action: first step of the new mean, masked and clipped
-    const double f_final = (d.freq_mode == 0) ? d.f_fixed : d.it[IT_FNEW];
-    const uint32_t qf = (d.freq_mode == 0) ? d.q_fixed : q_of_freq(f_final, d.dt);
-    bool st[4];
-    contact_at(d, st);
-    double *res = d.result;
-    for (int l = 0; l < 4; ++l) {
-      double fx = s_new[3 * l], fy = s_new[3 * l + 1], fz = s_new[3 * l + 2];
-      if (d.friction_on) friction_clip<double>(fx, fy, fz, d.mu_fric);
-      res[RES_GRF + 3 * l + 0] = st[l] ? fx : 0.0;
-      res[RES_GRF + 3 * l + 1] = st[l] ? fy : 0.0;
-      res[RES_GRF + 3 * l + 2] = st[l] ? fz : 0.0;
-      res[RES_CONTACT + l] = st[l] ? 1.0 : 0.0;
+  if (tid == 0)
+    emit_action(d, s_new, d.it[IT_FNEW], d.it[IT_BETA], d.it[IT_FLAGS], d.it[IT_NACT]);
+}
+
+// MPPI update (Alg. 4) with the weighting fused in: every workgroup of a
+// controller forms beta = min J (lowest index on ties), w_k = exp((beta -
+// J_k) / lambda) in the working precision, Omega = sum w_k and the weighted
+// frequency sum in FP64, in the same order, and reduces S1 over the samples
+// whose weight does not underflow.  Thread t visits samples t, t + B, ...
+// (coalesced cost reads and noise-row gathers).  Step 0 also leaves the
+// per-iteration scalars (next iteration's frequency mean) and, in the last
+// iteration, the action.
+template <typename T, bool INL>
+__global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
+  const int b = blockIdx.x;
+  const int item = stage_item<INL>(tab.upd_start, tab.n, b);
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[item]];
+  if (d.method != 0) return;  // elite / best sample: k_select + k_update
+  const int j = b - stage_start<INL>(tab.upd_start, item);
+  const int N = d.N, tid = threadIdx.x, r = tab.r;
+  constexpr int kW = kMppiBlock / 64;
+  __shared__ double lds[kW][16];
+  __shared__ T lds_v[kW];
+  __shared__ int lds_k[kW];
+  __shared__ double s_new[12];
+  const T *Jg = reinterpret_cast<const T *>(d.J);
+
+  T bv = inf_t<T>();
+  int bk = 0x7fffffff;
+  for (int k = tid; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
+  block_argmin(bv, bk, lds_v, lds_k);
+  const bool skip = !finite_t(bv);
+
+  const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
+  T f1[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) f1[c] = T(0);
+  double sw = 0.0, swf = 0.0, cnt = 0.0;
+  if (!skip) {
+    const T il = (T)d.inv_lambda;
+    for (int k = tid; k < N; k += kMppiBlock) {
+      const T wk = exp_t((bv - Jg[k]) * il);
+      if (wk != T(0)) {
+        const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)k * 12);
+        const float4 z0 = src[0], z1 = src[1], z2 = src[2];
+        cnt += 1.0;
+        sw += (double)wk;
+        swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                              z2.x, z2.y, z2.z, z2.w};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
+      }
     }
-    res[RES_FREQ] = f_final;
-    res[RES_Q] = (double)qf;
-    res[RES_BEST] = d.it[IT_BETA];
-    res[RES_FLAGS] = d.it[IT_FLAGS];
-    res[RES_NACT] = d.it[IT_NACT];
-    d.ctl[0] = f_final;
+  }
+  // within a wave in the working precision (FP64 for the normaliser), then
+  // FP64 across waves
+  const int lane = tid & 63, wid = tid >> 6;
+  double o[15];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) o[c] = (double)wave_sum(f1[c]);
+  o[12] = wave_sum(sw);
+  o[13] = wave_sum(swf);
+  o[14] = wave_sum(cnt);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 15; ++c) lds[wid][c] = o[c];
+  }
+  __syncthreads();
+  const bool last_iter = (r == d.R - 1);
+  if (tid < 12) {
+    const int c = tid, idx = j * 12 + c;
+    double S1 = 0.0, omega = 0.0;
+    for (int i = 0; i < kW; ++i) {
+      S1 += lds[i][c];
+      omega += lds[i][12];
+    }
+    const double m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, c);
+    const double m_new = skip ? m_old : m_old + d.sigma0 * (S1 / omega);
+    const T stored = (T)m_new;
+    mean_out<T>(d, r)[idx] = stored;
+    s_new[c] = (double)stored;
+    if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
+  }
+  if (j != 0) return;
+  if (d.dbg_J) {
+    for (int k = tid; k < N; k += kMppiBlock) {
+      d.dbg_J[(size_t)r * N + k] = (double)Jg[k];
+      d.dbg_q[(size_t)r * N + k] = d.q[k];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double omega = 0.0, sf = 0.0, nact = 0.0;
+    for (int i = 0; i < kW; ++i) {
+      omega += lds[i][12];
+      sf += lds[i][13];
+      nact += lds[i][14];
+    }
+    const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
+    const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
+    const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
+    const double fnew = skip ? cur_mf : sf / omega;
+    const double flags = (double)((int)prev_flags | (skip ? 1 : 0));
+    d.it[IT_BETA] = (double)bv;
+    d.it[IT_OMEGA] = omega;
+    d.it[IT_BEST] = (double)bk;
+    d.it[IT_FNEW] = fnew;
+    d.it[IT_MUF] = fnew;
+    d.it[IT_SIGF] = cur_sf;
+    d.it[IT_SKIP] = skip ? 1.0 : 0.0;
+    d.it[IT_FLAGS] = flags;
+    d.it[IT_NACT] = nact;
+    if (last_iter) emit_action(d, s_new, fnew, (double)bv, flags, nact);
   }
 }
 
@@ -1123,15 +1205,28 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
   hipError_t e = launch_rollout<INL>(tab, inl, precision, roll_lds, s);
   if (e != hipSuccess) return e;
   if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 2 : 1], s);
-  if (precision == 1)
-    hipLaunchKernelGGL((k_select<double, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
-  else
-    hipLaunchKernelGGL((k_select<float, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
+  // elite / best-sample controllers: selection, then the update; MPPI
+  // controllers: the fused update alone (each kernel skips the others' items)
+  const dim3 ug(tab.total_upd);
+  if (tab.n_select > 0) {
+    if (precision == 1)
+      hipLaunchKernelGGL((k_select<double, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
+    else
+      hipLaunchKernelGGL((k_select<float, INL>), dim3(tab.n), dim3(kSelBlock), 0, s, tab, inl);
+  }
   if (timing == 2) (void)hipEventRecord(ev[3], s);
-  if (precision == 1)
-    hipLaunchKernelGGL((k_update<double, INL>), dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab, inl);
-  else
-    hipLaunchKernelGGL((k_update<float, INL>), dim3(tab.total_upd), dim3(kUpdBlock), 0, s, tab, inl);
+  if (tab.n_select > 0) {
+    if (precision == 1)
+      hipLaunchKernelGGL((k_update<double, INL>), ug, dim3(kUpdBlock), 0, s, tab, inl);
+    else
+      hipLaunchKernelGGL((k_update<float, INL>), ug, dim3(kUpdBlock), 0, s, tab, inl);
+  }
+  if (tab.n_select < tab.n) {
+    if (precision == 1)
+      hipLaunchKernelGGL((k_update_mppi<double, INL>), ug, dim3(kMppiBlock), 0, s, tab, inl);
+    else
+      hipLaunchKernelGGL((k_update_mppi<float, INL>), ug, dim3(kMppiBlock), 0, s, tab, inl);
+  }
   if (timing == 2) (void)hipEventRecord(ev[4], s);
   return hipGetLastError();
 }

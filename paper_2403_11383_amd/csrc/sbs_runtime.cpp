@@ -486,6 +486,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.roll_block = block;
       tab.unroll = unroll;
       tab.r_count = 1;
+      for (int t = 0; t < m; ++t) tab.n_select += cs[idx[t]]->cfg.method != SBS_MPPI ? 1 : 0;
       tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
       tab.item = reinterpret_cast<const int32_t *>(dev + off);
       tab.noise_start = tab.item + n;
