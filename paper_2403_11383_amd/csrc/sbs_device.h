@@ -26,6 +26,8 @@ enum : int {
   RES_BEST = 18,
   RES_FLAGS = 19,
   RES_NACT = 20,      // samples with non-zero weight in the last iteration
+  RES_SEQ = 21,       // uint64 bits: tick + 1, stored last with system-scope
+                      // release, so a host that reads it sees a whole record
 };
 
 // per-iteration scalars (doubles)

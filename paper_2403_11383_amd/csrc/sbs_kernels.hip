@@ -305,6 +305,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 
   RollConst<T> c;
   load_const<T>(d, c);
+  const T mg2 = c.mg * T(0.5), mg3 = c.mg / T(3), mg4 = c.mg * T(0.25);
   const uint32_t q = draw_q(d, tab.r, k);
   d.q[k] = q;
   const double fkd = (double)q * d.inv_q_scale;
@@ -388,7 +389,10 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
       u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
     }
     // stage cost (Sec. V)
-    const T share = (nst == 4) ? c.mg * T(0.25) : (nst == 3) ? c.mg / T(3) : (nst == 2) ? c.mg * T(0.5) : c.mg;
+    T share = c.mg;  // m g / n_stance, selected without branches
+    share = (nst >= 2) ? mg2 : share;
+    share = (nst >= 3) ? mg3 : share;
+    share = (nst >= 4) ? mg4 : share;
     T stage = T(0);
     {
       const T e0 = x[0] - (c.pr[0] + tj * c.vr[0]);
@@ -468,9 +472,12 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 // identical.  Used when a launch has few samples: four times the waves at
 // roughly half the instructions per lane-step.
 // ---------------------------------------------------------------------------
+// Quad permutation (every source lane lies inside the quad and quads leave
+// the kernel whole, so bound_ctrl never applies; setting it lets the compiler
+// fold the move into the consuming add as a DPP operand).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float quad_sum(float v) {
   v = v + dpp<0xB1>(v);   // quad_perm [1,0,3,2]
@@ -502,6 +509,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
 
   const float dt = (float)d.dt, inv_m = (float)d.inv_mass, g = (float)d.gravity;
   const float mg = (float)(d.mass * d.gravity), mu_f = (float)d.mu_fric, inv_g = (float)d.inv_g;
+  const float mg2 = mg * 0.5f, mg3 = mg / 3.f, mg4 = mg * 0.25f;
   const float I0 = (float)d.inertia[0], I1 = (float)d.inertia[1], I2 = (float)d.inertia[2];
   const float iI0 = (float)d.inv_inertia[0], iI1 = (float)d.inv_inertia[1],
               iI2 = (float)d.inv_inertia[2];
@@ -577,7 +585,10 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     uy = st ? uy : 0.f;
     uz = st ? uz : 0.f;
     // stage cost: this leg's GRF error and state group l's tracking error
-    const float share = (nst > 3.5f) ? mg * 0.25f : (nst > 2.5f) ? mg / 3.f : (nst > 1.5f) ? mg * 0.5f : mg;
+    float share = mg;  // m g / n_stance, selected without branches
+    share = (nst > 1.5f) ? mg2 : share;
+    share = (nst > 2.5f) ? mg3 : share;
+    share = (nst > 3.5f) ? mg4 : share;
     const float ez = uz - (st ? share : 0.f);
     const float ga = (l == 0) ? x[0] : (l == 1) ? x[3] : (l == 2) ? x[6] : x[9];
     const float gb = (l == 0) ? x[1] : (l == 1) ? x[4] : (l == 2) ? x[7] : x[10];
@@ -908,7 +919,8 @@ __device__ __forceinline__ void contact_at(const TickDesc &d, bool st[4]) {
 // low-level controller): u_0 masked by the contact flags at the robot's
 // phase and clipped to the friction cone, the executed frequency and its
 // phase increment, the lowest cost, flags and the number of samples that
-// carried weight.  Also stores the frequency mean for the next tick.
+// carried weight; the record's sequence word goes last.  Also stores the
+// frequency mean for the next tick.
 __device__ __forceinline__ void emit_action(const TickDesc &d, const double *s_new, double f_new,
                                             double beta, double flags, double nact) {
   const double f_final = (d.freq_mode == 0) ? d.f_fixed : f_new;
@@ -930,6 +942,8 @@ __device__ __forceinline__ void emit_action(const TickDesc &d, const double *s_n
   res[RES_FLAGS] = flags;
   res[RES_NACT] = nact;
   d.ctl[0] = f_final;
+  __hip_atomic_store(reinterpret_cast<uint64_t *>(res + RES_SEQ), (uint64_t)d.tick + 1u,
+                     __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <typename T, bool INL>

@@ -171,7 +171,22 @@ struct TicketRec {
   int status = 1;  // 1 pending, 0 done, <0 error
   int64_t t_submit = 0, t_launch = 0, t_done = 0;
   double res[kResultDoubles];
+  // the launched tick's action record in pinned memory: complete once its
+  // sequence word reads tick + 1 (before the batch itself has retired)
+  const double *rec = nullptr;
 };
+
+// Completes a pending ticket from its action record if the kernel has
+// finished writing it.
+bool complete_from_record(TicketRec &t) {
+  if (t.status != 1 || !t.rec) return false;
+  const uint64_t *seq = reinterpret_cast<const uint64_t *>(t.rec + RES_SEQ);
+  if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) != (uint64_t)t.tick + 1u) return false;
+  std::memcpy(t.res, t.rec, sizeof t.res);
+  t.status = 0;
+  t.t_done = now_ns();
+  return true;
+}
 
 // Byte layout of one batch (device workspace and host staging share the
 // header part so that one copy uploads it).
@@ -432,6 +447,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
   TickDesc *hd = reinterpret_cast<TickDesc *>(host + L.desc);
   for (int i = 0; i < n; ++i) {
+    uint64_t *seq = reinterpret_cast<uint64_t *>(host + L.results) + (size_t)i * kResultDoubles + RES_SEQ;
+    __atomic_store_n(seq, (uint64_t)0, __ATOMIC_RELEASE);
     // the action record goes straight to pinned host memory (no copy back)
     fill_desc(rt, *cs[i], item_ws(cs[i]->cfg), dev + L.item_off[i],
               reinterpret_cast<double *>(host_dev + L.results) + (size_t)i * kResultDoubles,
@@ -521,11 +538,12 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
   const int64_t t = now_ns();
   for (size_t i = 0; i < b.tickets.size(); ++i) {
     auto it = rt->tickets.find(b.tickets[i]);
-    if (it != rt->tickets.end()) {
+    if (it != rt->tickets.end() && it->second.status == 1) {
       std::memcpy(it->second.res, b.host_results + i * kResultDoubles, sizeof(it->second.res));
       it->second.status = 0;
       it->second.t_done = t;
     }
+    if (it != rt->tickets.end()) it->second.rec = nullptr;  // the record is released below
     auto c = rt->ctrls.find(b.ctrls[i]);
     if (c != rt->ctrls.end()) c->second.inflight -= 1;
   }
@@ -672,6 +690,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     TicketRec &t = rt->tickets[tks[i]];
     t.t_launch = t_launch;
     t.tick = ticks[i];
+    t.rec = b->host_results + i * kResultDoubles;
   }
   rt->n_batches += 1;
   rt->inflight.push_back(std::move(b));
@@ -968,7 +987,7 @@ int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t 
     auto it = rt->tickets.find(ticket);
     if (it == rt->tickets.end()) return fail(SBS_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
     TicketRec &t = it->second;
-    if (t.status == 1 && rt->mode == SBS_MODE_DIRECT) reap(rt);
+    if (t.status == 1 && !complete_from_record(t) && rt->mode == SBS_MODE_DIRECT) reap(rt);
     if (t.status <= 0) {
       int st = t.status;
       if (st == 0) {
@@ -1576,6 +1595,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     rec.t_submit = t;
     rec.t_launch = t;
     rec.tick = ticks[i];
+    rec.rec = b->host_results + i * kResultDoubles;
     rt->tickets[tk] = rec;
     b->tickets.push_back(tk);
     tickets[i] = tk;
