@@ -41,6 +41,7 @@ class Cfg(C.Structure):
     _fields_ = [
         ("N", C.c_int32), ("H", C.c_int32), ("iterations", C.c_int32),
         ("method", C.c_int32), ("freq_mode", C.c_int32), ("friction_on", C.c_int32),
+        ("knots", C.c_int32),
         ("dt", C.c_double), ("lam", C.c_double), ("elite_frac", C.c_double),
         ("mu_fric", C.c_double), ("rho", C.c_double), ("f_nominal", C.c_double),
         ("sigma_grf", C.c_double), ("sigma_f", C.c_double),
@@ -98,6 +99,9 @@ def lib():
         L.orc_euler_rate_matrix.argtypes = [_dp, _dp]
         L.orc_srbd_deriv.argtypes = [C.POINTER(Cfg), _dp, _dp, _dp, _dp]
         L.orc_foothold.argtypes = [C.POINTER(Cfg), _dp, C.c_uint32, _dp, C.c_int32, _dp]
+        L.orc_knot_time.argtypes = [C.POINTER(Cfg), C.c_int32]
+        L.orc_knot_time.restype = C.c_double
+        L.orc_spline_eval.argtypes = [C.POINTER(Cfg), _dp, C.c_double, _dp]
         L.orc_rollout.argtypes = [C.POINTER(Cfg), C.POINTER(Input), _dp, C.c_uint32,
                                   C.c_void_p, C.c_void_p]
         L.orc_rollout.restype = C.c_double
@@ -126,6 +130,7 @@ def make_cfg(d: dict) -> Cfg:
     c.method = METHODS[d.get("method", "mppi")]
     c.freq_mode = FREQ_MODES[d.get("freq_mode", "fixed")]
     c.friction_on = 1 if d.get("friction_on", False) else 0
+    c.knots = int(d.get("knots", 0))
     c.dt, c.lam = float(d["dt"]), float(d.get("lambda", 1.0))
     c.elite_frac, c.mu_fric = float(d.get("elite_frac", 0.1)), float(d.get("mu_fric", 0.5))
     c.rho, c.f_nominal = float(d.get("rho", 0.0)), float(d.get("f_nominal", 1.4))
@@ -240,11 +245,30 @@ def foothold(cfg: dict, x, q, v_ref, leg):
     return out
 
 
+def rows(cfg: dict) -> int:
+    """Rows of the GRF decision variable: the knot count, else H."""
+    k = int(cfg.get("knots", 0))
+    return k if k > 0 else int(cfg["H"])
+
+
+def knot_time(cfg: dict, p: int) -> float:
+    return float(lib().orc_knot_time(C.byref(make_cfg(cfg)), p))
+
+
+def spline_eval(cfg: dict, theta, t: float):
+    """The 12 GRFs of the spline through the knots theta [P][12] at time t."""
+    out = np.zeros(12)
+    lib().orc_spline_eval(C.byref(make_cfg(cfg)),
+                          np.ascontiguousarray(theta, np.float64).reshape(-1), float(t), out)
+    return out
+
+
 def rollout(cfg: dict, inp: dict, theta, q, return_states=False):
-    """J, or (J, states[H+1][12], footholds[H][4][3]) with return_states."""
+    """J, or (J, states[H+1][12], footholds[H][4][3]) with return_states.
+    theta is [H][12], or [P][12] knots for a spline configuration."""
     c, i = make_cfg(cfg), make_input(inp)
     th = np.ascontiguousarray(theta, np.float64).reshape(-1)
-    assert th.size == 12 * c.H
+    assert th.size == 12 * rows(cfg)
     xs = np.zeros((c.H + 1, 12)) if return_states else None
     feet = np.zeros((c.H, 4, 3)) if return_states else None
     J = lib().orc_rollout(C.byref(c), C.byref(i), th, q & 0xFFFFFFFF,
@@ -293,7 +317,7 @@ def tick(cfg: dict, mu, mu_f, tick_no, inp: dict, nthreads=1, costs_override=Non
     """One control step.  Returns a dict with the action, the warm-started
     mean, the updated frequency mean, all costs and sampled increments."""
     c, i = make_cfg(cfg), make_input(inp)
-    N, H, R = c.N, c.H, c.iterations
+    N, H, R = c.N, rows(cfg), c.iterations  # H: rows of the mean
     mu = np.array(mu, dtype=np.float64).reshape(-1).copy()
     assert mu.size == 12 * H
     mf = C.c_double(float(mu_f))

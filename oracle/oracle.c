@@ -293,7 +293,8 @@ void orc_foothold(const orc_cfg *cfg, const double x[12], uint32_t q,
 /* Rollout(theta_k), Alg. 2: for j = 0..H-1, u_j = pi(theta_k, x_j, t_j),     */
 /* J += r(u_j, x_j, x^r_j), x_{j+1} = x_j + dt F(x_j, u_j) (explicit Euler).  */
 /* The stage cost is the quadratic form of Sec. V; the gait frequency adds   */
-/* rho (f_k - f_n)^2 once (Sec. V).  theta is [H][12] world-frame GRFs.      */
+/* rho (f_k - f_n)^2 once (Sec. V).  theta is [H][12] world-frame GRFs, or   */
+/* [P][12] spline knots whose interpolant gives the GRFs of each step.       */
 /* Feet stay where they touched down: legs in stance at the first step use   */
 /* the tick's footholds, a leg that touches down later is placed by Eq. (2)  */
 /* from the state at that step.                                             */
@@ -314,11 +315,13 @@ double orc_rollout(const orc_cfg *cfg, const orc_input *in, const double *theta,
     for (int i = 0; i < 4; ++i)
       if (j > 0 && delta[i] && !prev[i]) orc_foothold(cfg, x, q, in->v_ref, i, &pf[3 * i]);
     if (feet) memcpy(&feet[12 * j], pf, sizeof pf);
-    double u[12], ur[12], lever[12];
+    double u[12], ur[12], lever[12], grf[12];
     double share = cfg->mass * cfg->gravity / (nst > 1 ? (double)nst : 1.0);
+    if (cfg->knots > 0) orc_spline_eval(cfg, theta, (double)j * cfg->dt, grf);
+    else memcpy(grf, &theta[12 * j], sizeof grf);
     for (int i = 0; i < 4; ++i) {
       double f[3];
-      const double *th = &theta[12 * j + 3 * i];
+      const double *th = &grf[3 * i];
       if (cfg->friction_on) orc_friction_clip(th, cfg->mu_fric, f);
       else { f[0] = th[0]; f[1] = th[1]; f[2] = th[2]; }
       for (int c = 0; c < 3; ++c) {
@@ -358,6 +361,41 @@ double orc_rollout(const orc_cfg *cfg, const orc_input *in, const double *theta,
   J += cfg->rho * df * df;
   if (!isfinite(J)) J = INFINITY;
   return J;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GRF spline, Sec. IV-B: the decision variable holds P knots theta_2 at      */
+/* instants t^knot_p spread evenly from the first to the last step of the    */
+/* horizon, t_p = p (H - 1) dt / (P - 1).  Between knots the force is the     */
+/* cubic Hermite interpolant whose slopes are finite differences of the      */
+/* knots: centred inside, one-sided at the two ends.  Outside [t_0, t_{P-1}]  */
+/* the argument is clamped to the nearest end.                               */
+/* ------------------------------------------------------------------------ */
+double orc_knot_time(const orc_cfg *cfg, int32_t p) {
+  return (double)p * ((double)(cfg->H - 1) * cfg->dt) / (double)(cfg->knots - 1);
+}
+
+static double knot_slope(const orc_cfg *cfg, const double *theta, int32_t p, int d) {
+  const int32_t P = cfg->knots;
+  int32_t a = p > 0 ? p - 1 : 0, b = p < P - 1 ? p + 1 : P - 1;
+  return (theta[12 * b + d] - theta[12 * a + d]) / (orc_knot_time(cfg, b) - orc_knot_time(cfg, a));
+}
+
+void orc_spline_eval(const orc_cfg *cfg, const double *theta, double t, double out[12]) {
+  const int32_t P = cfg->knots;
+  const double T = orc_knot_time(cfg, P - 1);
+  if (t < 0.0) t = 0.0;
+  if (t > T) t = T;
+  int32_t p = 0;
+  while (p < P - 2 && t >= orc_knot_time(cfg, p + 1)) ++p;  /* segment [t_p, t_{p+1}] */
+  const double t0 = orc_knot_time(cfg, p), t1 = orc_knot_time(cfg, p + 1);
+  const double h = t1 - t0, s = (t - t0) / h;
+  const double s2 = s * s, s3 = s2 * s;
+  const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
+  const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
+  for (int d = 0; d < 12; ++d)
+    out[d] = h00 * theta[12 * p + d] + h10 * h * knot_slope(cfg, theta, p, d) +
+             h01 * theta[12 * (p + 1) + d] + h11 * h * knot_slope(cfg, theta, p + 1, d);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -450,19 +488,21 @@ typedef struct {
   double mu_f, sigma_f;
   uint32_t tick, r;
   int32_t k0, k1;
-  double *theta;   /* [N][H*12] */
+  double *theta;   /* [N][M*12], M = H or the knot count */
   uint32_t *q;     /* [N] */
   double *J;       /* [N] */
   int rollout;
 } worker_args;
 
+static int32_t decision_rows(const orc_cfg *cfg) { return cfg->knots > 0 ? cfg->knots : cfg->H; }
+
 static void *sample_and_rollout(void *arg) {
   worker_args *a = (worker_args *)arg;
   const orc_cfg *cfg = a->cfg;
-  int32_t D = 12 * cfg->H;
+  const int32_t M = decision_rows(cfg), D = 12 * M;
   for (int32_t k = a->k0; k < a->k1; ++k) {
     double *th = &a->theta[(size_t)k * D];
-    for (int32_t j = 0; j < cfg->H; ++j) {
+    for (int32_t j = 0; j < M; ++j) {
       float z[12];
       orc_noise_step(cfg->seed, a->tick, a->r, (uint32_t)k, (uint32_t)j, z);
       for (int d = 0; d < 12; ++d)
@@ -478,8 +518,10 @@ int orc_tick(const orc_cfg *cfg, double *mu, double *mu_f, uint32_t tick,
              const orc_input *in, orc_action *out, double *costs_out,
              const double *costs_override, double *mean_out, uint32_t *q_out,
              int32_t nthreads) {
-  const int32_t N = cfg->N, H = cfg->H, D = 12 * H, R = cfg->iterations;
+  const int32_t N = cfg->N, H = cfg->H, R = cfg->iterations;
+  const int32_t M = decision_rows(cfg), D = 12 * M;
   if (N < 1 || H < 1 || R < 1) return -1;
+  if (cfg->knots < 0 || cfg->knots == 1 || cfg->knots > H) return -1;
   for (int d = 0; d < 12; ++d)
     if (!isfinite(in->x0[d])) return -1;
   if (nthreads < 1) nthreads = 1;
@@ -573,13 +615,17 @@ int orc_tick(const orc_cfg *cfg, double *mu, double *mu_f, uint32_t tick,
   out->flags = flags;
 
   /* Warm start: shift by one step, hover forces (m g / 2 per leg) at the   */
-  /* end; the frequency mean carries over.                                   */
-  for (int32_t j = 0; j + 1 < H; ++j)
-    memcpy(&mu[12 * j], &cur[12 * (j + 1)], sizeof(double) * 12);
+  /* end; the frequency mean carries over.  A spline mean is shifted by      */
+  /* re-sampling it one step later at every knot but the last, which takes   */
+  /* the hover forces.                                                       */
+  for (int32_t j = 0; j + 1 < M; ++j) {
+    if (cfg->knots > 0) orc_spline_eval(cfg, cur, orc_knot_time(cfg, j) + cfg->dt, &mu[12 * j]);
+    else memcpy(&mu[12 * j], &cur[12 * (j + 1)], sizeof(double) * 12);
+  }
   for (int i = 0; i < 4; ++i) {
-    mu[12 * (H - 1) + 3 * i + 0] = 0.0;
-    mu[12 * (H - 1) + 3 * i + 1] = 0.0;
-    mu[12 * (H - 1) + 3 * i + 2] = 0.5 * cfg->mass * cfg->gravity;
+    mu[12 * (M - 1) + 3 * i + 0] = 0.0;
+    mu[12 * (M - 1) + 3 * i + 1] = 0.0;
+    mu[12 * (M - 1) + 3 * i + 2] = 0.5 * cfg->mass * cfg->gravity;
   }
   *mu_f = (cfg->freq_mode == ORC_FREQ_FIXED) ? cfg->f_fixed : mf;
 

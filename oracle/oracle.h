@@ -27,6 +27,8 @@
  *   orc_srbd_deriv      Single-rigid-body dynamics, Eq. (1).
  *   orc_foothold        Foothold reference, Eq. (2) (Sec. IV-D), used at
  *                       every touchdown inside a rollout.
+ *   orc_knot_time       Knot instants t^knot_p of the GRF spline (Sec. IV-B).
+ *   orc_spline_eval     The GRF spline sigma((t^knot, theta_2), t) of Sec. IV-B.
  *   orc_rollout         Rollout(theta_k), Alg. 2, with the quadratic cost of
  *                       Sec. V and the frequency regulariser of Sec. V.
  *   orc_mppi_*          MPPI UpdateMean, Sec. III-C / Alg. 4.
@@ -40,7 +42,9 @@
  * FP64 libm Box-Muller and distribution tests; dynamics against closed forms
  * (free fall, ballistic, hover, torque-free spin), scipy rotations and the
  * momentum theorems; MPPI against scipy.special.softmax and its limits;
- * elite against numpy sort/mean/var on brute-forced tiny cases.
+ * elite against numpy sort/mean/var on brute-forced tiny cases; the GRF
+ * spline against scipy's cubic Hermite interpolant with numpy's gradient
+ * slopes, knot interpolation and exactness on linear data.
  * Parity unpinned: the closed-loop behaviour over many ticks (no values in
  * the paper to compare against).
  */
@@ -64,6 +68,9 @@ typedef struct {
   int32_t method;       /* ORC_MPPI / ORC_ELITE / ORC_NAIVE                 */
   int32_t freq_mode;    /* ORC_FREQ_*                                       */
   int32_t friction_on;  /* apply the friction-cone clip                     */
+  int32_t knots;        /* 0: one GRF vector per step (theta is [H][12]);   */
+                        /* P >= 2: cubic spline through P knots (theta is   */
+                        /* [P][12]), Sec. IV-B                              */
   double dt, lambda, elite_frac, mu_fric, rho, f_nominal;
   double sigma_grf, sigma_f, sigma_min_grf, sigma_min_f;
   double f_min, f_max, f_fixed, duty;
@@ -112,6 +119,8 @@ void orc_srbd_deriv(const orc_cfg *cfg, const double x[12], const double u[12],
                     const double lever[12], double xdot[12]);
 void orc_foothold(const orc_cfg *cfg, const double x[12], uint32_t q,
                   const double v_ref[3], int32_t leg, double out[3]);
+double orc_knot_time(const orc_cfg *cfg, int32_t p);
+void orc_spline_eval(const orc_cfg *cfg, const double *theta, double t, double out[12]);
 double orc_rollout(const orc_cfg *cfg, const orc_input *in, const double *theta,
                    uint32_t q, double *xs, double *feet);
 int orc_mppi_weights(int32_t n, const double *J, double lambda, double *omega,
