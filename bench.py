@@ -33,6 +33,11 @@ METRIC = "rollout-steps/sec (N×H per s) + p99 control-tick latency vs plain sin
 # 94, force and torque 72, R^T tau 15, gyroscopic term 12, Euler-angle rates 11,
 # accelerations 10, Euler update and time 25.
 FLOP_PER_ROLLOUT_STEP = 326
+# With the GRF spline (Sec. IV-B) a step evaluates the spline on four knots
+# (12 x (1 mul + 3 fma) = 84) instead of forming mu + sigma z (24); each knot
+# of each sample forms mu + sigma z once (24 per knot).
+FLOP_PER_SPLINE_STEP = FLOP_PER_ROLLOUT_STEP - 24 + 84
+FLOP_PER_SPLINE_KNOT = 24
 # Non-packed FP32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
 PEAK_FP32_VALU_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
@@ -106,7 +111,7 @@ def cpu_baseline(cfg, seconds=10.0):
     rng = np.random.default_rng(cfg["seed"])
     x0 = workloads.initial_state(rng)
     inp = workloads.tick_input(x0, v_ref=(0.3, 0.0, 0.0))
-    mu = np.tile([0.0, 0.0, 0.5 * cfg["mass"] * cfg["gravity"]] * 4, (cfg["H"], 1))
+    mu = np.tile([0.0, 0.0, 0.5 * cfg["mass"] * cfg["gravity"]] * 4, (oracle.rows(cfg), 1))
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -219,6 +224,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=4.0)
     ap.add_argument("--no-prefetch", action="store_true",
                     help="c1: generate each tick's noise inside the tick")
+    ap.add_argument("--knots", type=int, default=0,
+                    help="c1: GRF spline through this many knots (0: one GRF vector per step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -232,7 +239,7 @@ def main():
 
     from paper_2403_11383_amd import binding, workloads
     import torch
-    cfg = workloads.config("c1")
+    cfg = workloads.config("c1", knots=args.knots)
     rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)), two_streams=True)
     rt.set_timing(args.timing)
     elapsed, lat, acts, timing, plant = closed_loop(rt, binding, workloads, cfg, args.steps,
@@ -242,15 +249,21 @@ def main():
     steps_total = N * H * R * args.steps
     value = steps_total / elapsed
     t_roll = timing["rollout_ns"] * 1e-9
-    achieved = N * H * FLOP_PER_ROLLOUT_STEP / t_roll / 1e12 if t_roll > 0 else 0.0
+    P = args.knots
+    flop = N * H * FLOP_PER_ROLLOUT_STEP if P == 0 else \
+        N * (H * FLOP_PER_SPLINE_STEP + P * FLOP_PER_SPLINE_KNOT)
+    achieved = flop / t_roll / 1e12 if t_roll > 0 else 0.0
+    spline_txt = f", GRF spline through {P} knots" if P else ""
+    workload_key = "c1" if P == 0 else f"c1_knots{P}"
     line = {
         "metric": METRIC, "value": value, "unit": "rollout-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "c1: closed-loop MPPI, gait frequency ~U[1.0,2.5] Hz per sample, "
-                               "N=10240, H=50, dt=0.02 s, 40 N lateral push from tick 30",
-                   "N": N, "H": H, "iterations": R, "ticks": args.steps,
+                               "N=10240, H=50, dt=0.02 s, 40 N lateral push from tick 30"
+                               + spline_txt,
+                   "N": N, "H": H, "iterations": R, "knots": P, "ticks": args.steps,
                    "noise_prefetch": not args.no_prefetch},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": float(np.max(lat))},
         "stage_us": {k[:-3]: timing[k] * 1e-3 for k in ("noise_ns", "rollout_ns", "select_ns",
@@ -263,8 +276,8 @@ def main():
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
                      "peak_published_packed": PEAK_FP32_PUBLISHED_TFLOPS,
                      "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-                     "traffic": stored_traffic("k_rollout", "c1"),
-                     "flop_per_launch": N * H * FLOP_PER_ROLLOUT_STEP},
+                     "traffic": stored_traffic("k_rollout", workload_key),
+                     "flop_per_launch": flop},
         "closed_loop": {"final_x": [round(float(v), 4) for v in plant.x],
                         "nonfinite_ticks": int(sum(a[0] & 1 for a in acts)),
                         "freq_hz_last": acts[-1][1],

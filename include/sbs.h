@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SBS_ABI_VERSION 1
+#define SBS_ABI_VERSION 2
 
 typedef enum {
   SBS_OK = 0,
@@ -63,9 +63,16 @@ enum { SBS_MODE_DIRECT = 0, SBS_MODE_SERVING = 1 };
  * SBS_NAIVE, gait-frequency mode SBS_FREQ_* (Sec. IV-C: fixed, uniform on
  * [f_min, f_max], or Gaussian around the frequency mean), precision of the
  * rollouts and costs (SBS_FP32 or SBS_FP64).  The frequency is carried as a
- * phase increment per step q = round-half-even(f dt 2^32). */
+ * phase increment per step q = round-half-even(f dt 2^32).
+ *
+ * knots selects the GRF parametrisation (Sec. IV-B): 0 gives one GRF vector
+ * per step (the mean has H rows of 12); P in [2, H] gives P spline knots
+ * at instants spread evenly from the first to the last step, each step's
+ * GRFs being the cubic Hermite interpolant with finite-difference slopes
+ * (centred inside, one-sided at the ends) of the knots (the mean has P rows).
+ * Everything indexed by "rows" below is H or P accordingly. */
 typedef struct sbs_controller_cfg {
-  int32_t N, H, iterations, method, freq_mode, friction_on, precision, reserved0;
+  int32_t N, H, iterations, method, freq_mode, friction_on, precision, knots;
   double dt;            /* step of the discretised dynamics [s]             */
   double lambda;        /* MPPI temperature                                 */
   double elite_frac;    /* K_e = max(1, floor(elite_frac N))                */
@@ -130,9 +137,10 @@ int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *st
  * cancelled. */
 int sbs_runtime_destroy(sbs_runtime *rt);
 
-/* Validate cfg, reserve the controller's persistent device state (mean [H][12]
- * in the controller precision, frequency mean, counters), set the mean to the
- * hover forces (0, 0, m g / 2) on every leg and step (first warm start,
+/* Validate cfg, reserve the controller's persistent device state (mean
+ * [rows][12] in the controller precision, frequency mean, spline tables),
+ * set the mean to the hover forces (0, 0, m g / 2) on every leg and row
+ * (first warm start,
  * Sec. III-A) and return its id.  SBS_ENOMEM if the arena cannot hold it. */
 int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t *id);
 int sbs_destroy_controller(sbs_runtime *rt, int32_t id);
@@ -182,15 +190,15 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
  * mean [H][12], frequency mean and next tick number.  Used for checkpoint
  * and resume: export, then import into a fresh controller, reproduces the
  * following ticks bit for bit (the noise is counter-based). */
-int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick);
+int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick);  /* mu [rows][12] */
 int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick);
 
 /* Debug taps.  sbs_set_debug(1) makes every later tick of the controller
  * keep its per-iteration costs [iterations][N], sampled phase increments
- * [iterations][N] and the updated mean before the warm-start shift [H][12];
+ * [iterations][N] and the updated mean before the warm-start shift [rows][12];
  * sbs_debug_fetch returns those of the last completed tick.
  * sbs_debug_noise runs the noise stage alone for (tick, iteration r) with the
- * controller's current frequency mean and returns z [N][H][12] and q [N]. */
+ * controller's current frequency mean and returns z [N][rows][12] and q [N]. */
 int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable);
 int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean);
 int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q);
@@ -200,7 +208,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
  * on the state, so every submission also produces the next tick's noise on
  * the second stream into a second buffer, and the next tick skips its noise
  * stage.  Results are unchanged; the arena holds two extra noise buffers of
- * iterations x H x N x 12 floats. */
+ * iterations x rows x N x 12 floats. */
 int sbs_set_prefetch(sbs_runtime *rt, int32_t id, int32_t enable);
 
 /* Serving statistics: ticks completed, batches launched, admission waits. */

@@ -45,7 +45,7 @@ class ControllerCfg(C.Structure):
     _fields_ = [
         ("N", C.c_int32), ("H", C.c_int32), ("iterations", C.c_int32), ("method", C.c_int32),
         ("freq_mode", C.c_int32), ("friction_on", C.c_int32), ("precision", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("knots", C.c_int32),
         ("dt", C.c_double), ("lam", C.c_double), ("elite_frac", C.c_double),
         ("mu_fric", C.c_double), ("rho", C.c_double), ("f_nominal", C.c_double),
         ("sigma_grf", C.c_double), ("sigma_f", C.c_double), ("sigma_min_grf", C.c_double),
@@ -136,6 +136,12 @@ def _check(rc: int):
         raise SBSError(rc, lib().sbs_last_error().decode(errors="replace"))
 
 
+def rows(d: dict) -> int:
+    """Rows of the mean: the spline knot count, else the horizon."""
+    k = int(d.get("knots", 0))
+    return k if k > 0 else int(d["H"])
+
+
 def make_cfg(d: dict) -> ControllerCfg:
     c = ControllerCfg()
     c.N, c.H, c.iterations = int(d["N"]), int(d["H"]), int(d.get("iterations", 1))
@@ -143,6 +149,7 @@ def make_cfg(d: dict) -> ControllerCfg:
     c.freq_mode = FREQ_MODES[d.get("freq_mode", "fixed")]
     c.friction_on = 1 if d.get("friction_on", False) else 0
     c.precision = PRECISIONS[d.get("precision", "fp32")]
+    c.knots = int(d.get("knots", 0))
     c.dt, c.lam = float(d["dt"]), float(d.get("lambda", 1.0))
     c.elite_frac, c.mu_fric = float(d.get("elite_frac", 0.1)), float(d.get("mu_fric", 0.5))
     c.rho, c.f_nominal = float(d.get("rho", 0.0)), float(d.get("f_nominal", 1.4))
@@ -319,7 +326,7 @@ class Runtime:
 
     def _plan_key(self, plan: int) -> str:
         import hashlib
-        members = sorted((int(c["N"]), int(c["H"]), int(c.get("iterations", 1)),
+        members = sorted((int(c["N"]), int(c["H"]), rows(c), int(c.get("iterations", 1)),
                           str(c.get("method", "mppi")), str(c.get("precision", "fp32")))
                          for c in self._plan_cfgs[plan])
         h = hashlib.sha256(open(LIB_PATH, "rb").read()).hexdigest()[:12]
@@ -328,8 +335,7 @@ class Runtime:
 
     # -- state -----------------------------------------------------------------
     def get_state(self, cid: int):
-        H = int(self.cfgs[cid]["H"])
-        mu = np.zeros((H, 12))
+        mu = np.zeros((rows(self.cfgs[cid]), 12))
         mf = C.c_double()
         tk = C.c_uint32()
         _check(lib().sbs_get_state(self._h, cid, mu.ctypes.data, C.byref(mf), C.byref(tk)))
@@ -337,7 +343,7 @@ class Runtime:
 
     def set_state(self, cid: int, mu, mu_f: float, tick: int):
         m = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
-        assert m.size == 12 * int(self.cfgs[cid]["H"])
+        assert m.size == 12 * rows(self.cfgs[cid])
         _check(lib().sbs_set_state(self._h, cid, m.ctypes.data, float(mu_f), int(tick) & 0xFFFFFFFF))
 
     # -- debug taps --------------------------------------------------------------
@@ -346,17 +352,17 @@ class Runtime:
 
     def debug_fetch(self, cid: int):
         c = self.cfgs[cid]
-        R, N, H = int(c.get("iterations", 1)), int(c["N"]), int(c["H"])
+        R, N = int(c.get("iterations", 1)), int(c["N"])
         J = np.zeros((R, N))
         q = np.zeros((R, N), np.uint32)
-        mean = np.zeros((H, 12))
+        mean = np.zeros((rows(c), 12))
         _check(lib().sbs_debug_fetch(self._h, cid, J.ctypes.data, q.ctypes.data, mean.ctypes.data))
         return J, q, mean
 
     def debug_noise(self, cid: int, tick: int, r: int = 0):
         c = self.cfgs[cid]
-        N, H = int(c["N"]), int(c["H"])
-        z = np.zeros((N, H, 12), np.float32)
+        N = int(c["N"])
+        z = np.zeros((N, rows(c), 12), np.float32)
         q = np.zeros(N, np.uint32)
         _check(lib().sbs_debug_noise(self._h, cid, tick, r, z.ctypes.data, q.ctypes.data))
         return z, q

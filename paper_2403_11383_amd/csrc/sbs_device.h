@@ -54,7 +54,8 @@ struct TickDesc {
   uint32_t duty_q;       // stance iff phase < duty_q (duty_full: always)
   int32_t duty_full;
   int32_t slot;          // index of this descriptor in the batch
-  int32_t pad0;
+  int32_t M;             // rows of the mean: H, or the spline knot count P
+  int32_t spline;        // 1: GRFs of step j are the spline through the knots
   uint64_t seed;
   double dt, inv_lambda, mu_fric, rho, f_nominal, mass, inv_mass, gravity, inv_g;
   double inertia[3], inv_inertia[3], hip[12], Q[12], Rw[12];
@@ -63,28 +64,38 @@ struct TickDesc {
   double inv_q_scale;    // 1 / (dt 2^32): f = q * inv_q_scale
   double x0[12], foot[12], p_ref0[3], v_ref[3], yaw_ref;
   // persistent controller state
-  // Two [H][12] mean buffers in the controller precision.  Iteration r
+  // Two [M][12] mean buffers in the controller precision.  Iteration r
   // reads mu_buf[(mu_par0 + r) & 1] and writes the other one.  The warm-start
-  // shift of Sec. III-A is applied when a mean is read (shift0): step j of
-  // the shifted mean is step j + 1 of the stored one, the last step hover.
+  // shift of Sec. III-A is applied when a mean is read (shift0): row j of
+  // the shifted mean is row j + 1 of the stored one (per-step GRFs) or the
+  // stored spline one step later (knots), the last row hover.
   void *mu_buf[2];
   double *ctl;           // [0] frequency mean
+  // spline tables (spline == 1): the GRFs of step j are
+  //   sum_i sp_w[4 j + i] * theta[sp_b[j] + i]   (knots beyond M - 1 weigh 0)
+  // and the shifted mean's knot p < M - 1 is
+  //   sum_i sh_w[4 p + i] * mu[sh_b[p] + i]
+  const double *sp_w;    // [H][4]
+  const int32_t *sp_b;   // [H], non-decreasing
+  const double *sh_w;    // [M][4]
+  const int32_t *sh_b;   // [M]
   // step workspace
-  float *z;              // [H][N][12] noise; iteration r at z + r * z_iter_stride
-  uint64_t z_iter_stride; // 0 (one buffer reused per iteration) or H * N * 12
+  float *z;              // [M][N][12] noise; iteration r at z + r * z_iter_stride
+  uint64_t z_iter_stride; // 0 (one buffer reused per iteration) or M * N * 12
   uint32_t *q;           // [N]
   void *J;               // [N] costs, controller precision
   void *w;               // [N] weights of the active samples, controller precision
   uint32_t *act;         // [N] active sample indices in increasing order
-  double *sigma;         // [H][12] elite std of the current iteration
+  double *sigma;         // [M][12] elite std of the current iteration
   double *it;            // [kItScalars]
   double *result;        // [kResultDoubles]
   double *dbg_J;         // optional [R][N]
   uint32_t *dbg_q;       // optional [R][N]
-  double *dbg_mean;      // optional [H][12]
+  double *dbg_mean;      // optional [M][12]
 };
 
-// Block maps of one (iteration, precision) launch over n active descriptors:
+// Block maps of one (iteration, precision, parametrisation) launch over n
+// active descriptors:
 // start arrays are exclusive prefix sums of each stage's blocks per item.
 struct LaunchTab {
   int32_t n;
@@ -98,6 +109,8 @@ struct LaunchTab {
   int32_t write_q;       // noise launch also writes the frequency draws
   int32_t skip_noise;    // noise already produced (ahead of the tick)
   int32_t n_select;      // items with an elite or best-sample update
+  int32_t max_rows;      // most mean rows among the items
+  int32_t spline;        // the items use the spline parametrisation
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

@@ -157,9 +157,10 @@ __device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
 }
 
 // GRF noise of iterations tab.r .. tab.r + tab.r_count - 1: one thread per
-// (iteration, step j, sample k); iteration r lands at z + r * z_iter_stride.
-// The noise depends only on (seed, tick, r, k, j), never on the state, so it
-// can be produced ahead of the tick that consumes it.
+// (iteration, row j, sample k), a row being a step or a spline knot;
+// iteration r lands at z + r * z_iter_stride.  The noise depends only on
+// (seed, tick, r, k, j), never on the state, so it can be produced ahead of
+// the tick that consumes it.
 template <bool INL>
 __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc inl) {
   const int per_iter = tab.total_noise;
@@ -224,9 +225,10 @@ template <typename T> __device__ __forceinline__ T inf_t();
 template <> __device__ __forceinline__ float inf_t<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double inf_t<double>() { return __builtin_huge_val(); }
 
-// The mean that iteration r samples around, step j, dimension c: the
-// iteration's input buffer, read one step ahead (hover at the end) when it
-// still holds the previous tick's mean (the warm-start shift).
+// The mean that iteration r samples around, row j, dimension c: the
+// iteration's input buffer, read one step later when it still holds the
+// previous tick's mean (the warm-start shift): row j + 1 of per-step GRFs,
+// or the spline of the knots evaluated one step later; the last row hover.
 template <typename T>
 __device__ __forceinline__ const T *mean_in(const TickDesc &d, int r) {
   return reinterpret_cast<const T *>(d.mu_buf[(d.mu_par0 + r) & 1]);
@@ -235,11 +237,23 @@ template <typename T>
 __device__ __forceinline__ T *mean_out(const TickDesc &d, int r) {
   return reinterpret_cast<T *>(d.mu_buf[(d.mu_par0 + r + 1) & 1]);
 }
+// Knot j < M - 1 of the shifted spline mean: an FP64 sum in a fixed order
+// without contraction (the host's export of the state forms the same sum).
+template <typename T>
+__device__ __forceinline__ double shifted_knot(const TickDesc &d, const T *m, int j, int c) {
+#pragma clang fp contract(off)
+  const int b = d.sh_b[j];
+  double v = d.sh_w[4 * j] * (double)m[b * 12 + c];
+  for (int t = 1; t < 4; ++t)
+    if (b + t < d.M) v = v + d.sh_w[4 * j + t] * (double)m[(b + t) * 12 + c];
+  return v;
+}
 template <typename T>
 __device__ __forceinline__ T mean_at(const TickDesc &d, const T *m, int r, int j, int c) {
   if (r == 0 && d.shift0) {
-    if (j + 1 < d.H) return m[(j + 1) * 12 + c];
-    return (c % 3 == 2) ? (T)(0.5 * d.mass * d.gravity) : T(0);
+    if (j + 1 >= d.M) return (c % 3 == 2) ? (T)(0.5 * d.mass * d.gravity) : T(0);
+    if (!d.spline) return m[(j + 1) * 12 + c];
+    return (T)shifted_knot(d, m, j, c);
   }
   return m[j * 12 + c];
 }
@@ -282,21 +296,27 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
-template <typename T, int BLOCK, int UNROLL, bool INL>
+template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL>
 __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
   const int it = stage_item<INL>(tab.roll_start, tab.n, b);
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[it]];
-  const int N = d.N, H = d.H;
+  const int N = d.N, H = d.H, M = d.M;
   T *s_mu = reinterpret_cast<T *>(roll_lds);
-  T *s_sig = s_mu + (size_t)tab.max_h * 12;
+  T *s_sig = s_mu + (size_t)tab.max_rows * 12;
+  T *s_spw = s_sig + (size_t)tab.max_rows * 12;                        // SPL: [H][4]
+  int *s_spb = reinterpret_cast<int *>(s_spw + (size_t)tab.max_h * 4);  // SPL: [H]
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   {
     const T *mu = mean_in<T>(d, tab.r);
-    for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
+    for (int i = threadIdx.x; i < M * 12; i += BLOCK) {
       s_mu[i] = mean_at<T>(d, mu, tab.r, i / 12, i % 12);
       s_sig[i] = elite_sigma ? (T)d.sigma[i] : (T)d.sigma0;
+    }
+    if constexpr (SPL) {
+      for (int i = threadIdx.x; i < H * 4; i += BLOCK) s_spw[i] = (T)d.sp_w[i];
+      for (int i = threadIdx.x; i < H; i += BLOCK) s_spb[i] = d.sp_b[i];
     }
   }
   __syncthreads();
@@ -326,16 +346,61 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 
   const float4 *zp =
       reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
-  const size_t zstride = (size_t)N * 3;  // float4 per step
+  const size_t zstride = (size_t)N * 3;  // float4 per row
   float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
+  // spline: the sample's knots wb .. wb + 3 (theta = mu + sigma z), and the
+  // noise of knot wb + 4 loaded ahead
+  T win[4][12];
+  int wb = 0;
+  if constexpr (SPL) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), bq = a, cq = a;
+      if (w < M) { a = zp[w * zstride]; bq = zp[w * zstride + 1]; cq = zp[w * zstride + 2]; }
+      const float zw[12] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, cq.x, cq.y, cq.z, cq.w};
+#pragma unroll
+      for (int i = 0; i < 12; ++i)
+        win[w][i] = (w < M) ? s_mu[w * 12 + i] + s_sig[w * 12 + i] * (T)zw[i] : T(0);
+    }
+    if (4 < M) { z0 = zp[4 * zstride]; z1 = zp[4 * zstride + 1]; z2 = zp[4 * zstride + 2]; }
+  }
 
 #pragma unroll UNROLL
   for (int j = 0; j < H; ++j) {
-    const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                          z2.x, z2.y, z2.z, z2.w};
-    if (j + 1 < H) {  // prefetch the next step's noise
-      const float4 *zn = zp + (size_t)(j + 1) * zstride;
-      z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
+    T u[12];
+    if constexpr (SPL) {
+      if (s_spb[j] != wb) {  // uniform: the window moves on by one knot
+        const int p = wb + 4;
+        const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                              z2.x, z2.y, z2.z, z2.w};
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          win[0][i] = win[1][i];
+          win[1][i] = win[2][i];
+          win[2][i] = win[3][i];
+          win[3][i] = (p < M) ? s_mu[p * 12 + i] + s_sig[p * 12 + i] * (T)zw[i] : T(0);
+        }
+        ++wb;
+        if (wb + 4 < M) {
+          const float4 *zn = zp + (size_t)(wb + 4) * zstride;
+          z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
+        }
+      }
+      const T w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
+#pragma unroll
+      for (int i = 0; i < 12; ++i)
+        u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
+    } else {
+      const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                            z2.x, z2.y, z2.z, z2.w};
+      if (j + 1 < H) {  // prefetch the next step's noise
+        const float4 *zn = zp + (size_t)(j + 1) * zstride;
+        z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
+      }
+      const T *muj = s_mu + j * 12;
+      const T *sgj = s_sig + j * 12;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
     }
     // contact schedule
     bool st[4];
@@ -372,12 +437,8 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
         prev[l] = st[l];
       }
     }
-    // policy: theta = mu + sigma z, clipped to the cone, masked by stance
-    T u[12];
-    const T *muj = s_mu + j * 12;
-    const T *sgj = s_sig + j * 12;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+    // policy: theta = mu + sigma z (per step, or the spline of the knots),
+    // clipped to the cone, masked by stance
     if (friction) {
 #pragma unroll
       for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
@@ -484,22 +545,28 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v + dpp<0x4E>(v);  // quad_perm [2,3,0,1]
 }
 
-template <int BLOCK, int UNROLL, bool INL>
+template <int BLOCK, int UNROLL, bool INL, bool SPL>
 __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   constexpr int kPerBlock = BLOCK / 4;
   const int b = blockIdx.x;
   const int it = stage_item<INL>(tab.roll_start, tab.n, b);
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[it]];
-  const int N = d.N, H = d.H;
+  const int N = d.N, H = d.H, M = d.M;
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
   float *s_mu = reinterpret_cast<float *>(roll_lds);
-  float *s_sig = s_mu + (size_t)tab.max_h * 12;
+  float *s_sig = s_mu + (size_t)tab.max_rows * 12;
+  float *s_spw = s_sig + (size_t)tab.max_rows * 12;                     // SPL: [H][4]
+  int *s_spb = reinterpret_cast<int *>(s_spw + (size_t)tab.max_h * 4);  // SPL: [H]
   {
     const float *mu = mean_in<float>(d, tab.r);
-    for (int i = threadIdx.x; i < H * 12; i += BLOCK) {
+    for (int i = threadIdx.x; i < M * 12; i += BLOCK) {
       s_mu[i] = mean_at<float>(d, mu, tab.r, i / 12, i % 12);
       s_sig[i] = elite_sigma ? (float)d.sigma[i] : (float)d.sigma0;
+    }
+    if constexpr (SPL) {
+      for (int i = threadIdx.x; i < H * 4; i += BLOCK) s_spw[i] = (float)d.sp_w[i];
+      for (int i = threadIdx.x; i < H; i += BLOCK) s_spb[i] = d.sp_b[i];
     }
   }
   __syncthreads();
@@ -542,13 +609,55 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   const float *zp = d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12 + 3 * l;
   const size_t zstride = (size_t)N * 12;
   float za = zp[0], zb = zp[1], zc = zp[2];
+  // spline: this leg's three forces at knots wb .. wb + 3, and the noise of
+  // knot wb + 4 loaded ahead
+  float win[4][3];
+  int wb = 0;
+  if constexpr (SPL) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        win[w][i] = (w < M) ? s_mu[w * 12 + 3 * l + i] + s_sig[w * 12 + 3 * l + i] * zp[w * zstride + i]
+                            : 0.f;
+    }
+    if (4 < M) { za = zp[4 * zstride]; zb = zp[4 * zstride + 1]; zc = zp[4 * zstride + 2]; }
+  }
 
 #pragma unroll UNROLL
   for (int j = 0; j < H; ++j) {
-    const float z0 = za, z1 = zb, z2 = zc;
-    if (j + 1 < H) {
-      const float *zn = zp + (size_t)(j + 1) * zstride;
-      za = zn[0]; zb = zn[1]; zc = zn[2];
+    float ux, uy, uz;
+    if constexpr (SPL) {
+      if (s_spb[j] != wb) {  // uniform: the window moves on by one knot
+        const int p = wb + 4, o = p * 12 + 3 * l;
+        const float zn3[3] = {za, zb, zc};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          win[0][i] = win[1][i];
+          win[1][i] = win[2][i];
+          win[2][i] = win[3][i];
+          win[3][i] = (p < M) ? s_mu[o + i] + s_sig[o + i] * zn3[i] : 0.f;
+        }
+        ++wb;
+        if (wb + 4 < M) {
+          const float *zn = zp + (size_t)(wb + 4) * zstride;
+          za = zn[0]; zb = zn[1]; zc = zn[2];
+        }
+      }
+      const float w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
+      ux = w0 * win[0][0] + w1 * win[1][0] + w2 * win[2][0] + w3 * win[3][0];
+      uy = w0 * win[0][1] + w1 * win[1][1] + w2 * win[2][1] + w3 * win[3][1];
+      uz = w0 * win[0][2] + w1 * win[1][2] + w2 * win[2][2] + w3 * win[3][2];
+    } else {
+      const float z0 = za, z1 = zb, z2 = zc;
+      if (j + 1 < H) {
+        const float *zn = zp + (size_t)(j + 1) * zstride;
+        za = zn[0]; zb = zn[1]; zc = zn[2];
+      }
+      const int o = j * 12 + 3 * l;
+      ux = s_mu[o] + s_sig[o] * z0;
+      uy = s_mu[o + 1] + s_sig[o + 1] * z1;
+      uz = s_mu[o + 2] + s_sig[o + 2] * z2;
     }
     const bool st = duty_full || (ph < duty_q);
     const float nst = quad_sum(st ? 1.f : 0.f);
@@ -576,10 +685,6 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
       prev = st;
     }
     // policy of this leg
-    const int o = j * 12 + 3 * l;
-    float ux = s_mu[o] + s_sig[o] * z0;
-    float uy = s_mu[o + 1] + s_sig[o + 1] * z1;
-    float uz = s_mu[o + 2] + s_sig[o + 2] * z2;
     if (friction) friction_clip<float>(ux, uy, uz, mu_f);
     ux = st ? ux : 0.f;
     uy = st ? uy : 0.f;
@@ -1179,38 +1284,54 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 // ---------------------------------------------------------------------------
 // timing: 0 none; 1 two events around the rollout stage (ev[0], ev[1]);
 // 2 five events around the four stages (ev[0..4]).
-template <bool INL>
-static hipError_t launch_rollout(const LaunchTab &tab, const TickDesc &inl, int precision,
-                                 size_t lds, hipStream_t s) {
+template <bool INL, bool SPL>
+static hipError_t launch_rollout_form(const LaunchTab &tab, const TickDesc &inl, int precision,
+                                      size_t lds, hipStream_t s) {
   const dim3 rg(tab.total_roll);
   if (precision == 1) {
-    hipLaunchKernelGGL((k_rollout<double, 64, 1, INL>), rg, dim3(64), lds, s, tab, inl);
+    hipLaunchKernelGGL((k_rollout<double, 64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl);
     return hipSuccess;
   }
   if (tab.lanes == 4) {
     switch (tab.roll_block * 4 + tab.unroll) {
-      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1, INL>), rg, dim3(64), lds, s, tab, inl); break;
-      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1, INL>), rg, dim3(128), lds, s, tab, inl); break;
-      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1, INL>), rg, dim3(256), lds, s, tab, inl); break;
+      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl); break;
+      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1, INL, SPL>), rg, dim3(128), lds, s, tab, inl); break;
+      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1, INL, SPL>), rg, dim3(256), lds, s, tab, inl); break;
       default: return hipErrorInvalidValue;
     }
     return hipSuccess;
   }
   switch (tab.roll_block * 4 + tab.unroll) {
-    case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1, INL>), rg, dim3(64), lds, s, tab, inl); break;
-    case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1, INL>), rg, dim3(128), lds, s, tab, inl); break;
-    case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1, INL>), rg, dim3(256), lds, s, tab, inl); break;
-    case 64 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 64, 2, INL>), rg, dim3(64), lds, s, tab, inl); break;
-    case 128 * 4 + 2: hipLaunchKernelGGL((k_rollout<float, 128, 2, INL>), rg, dim3(128), lds, s, tab, inl); break;
+    case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl); break;
+    case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1, INL, SPL>), rg, dim3(128), lds, s, tab, inl); break;
+    case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1, INL, SPL>), rg, dim3(256), lds, s, tab, inl); break;
+    case 64 * 4 + 2:
+      if (SPL) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_rollout<float, 64, 2, INL, false>), rg, dim3(64), lds, s, tab, inl);
+      break;
+    case 128 * 4 + 2:
+      if (SPL) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_rollout<float, 128, 2, INL, false>), rg, dim3(128), lds, s, tab, inl);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipSuccess;
 }
 
 template <bool INL>
+static hipError_t launch_rollout(const LaunchTab &tab, const TickDesc &inl, int precision,
+                                 size_t lds, hipStream_t s) {
+  return tab.spline ? launch_rollout_form<INL, true>(tab, inl, precision, lds, s)
+                    : launch_rollout_form<INL, false>(tab, inl, precision, lds, s);
+}
+
+template <bool INL>
 static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int precision,
                                 hipStream_t s, int timing, hipEvent_t *ev) {
-  const size_t roll_lds = (size_t)tab.max_h * 12 * 2 * (precision == 1 ? 8 : 4);
+  // mean and sigma [max_rows][12]; spline weights [max_h][4] and bases [max_h]
+  const size_t ts = precision == 1 ? 8 : 4;
+  const size_t roll_lds = (size_t)tab.max_rows * 12 * 2 * ts +
+                          (tab.spline ? (size_t)tab.max_h * (4 * ts + 4) : 0);
   if (timing == 2) (void)hipEventRecord(ev[0], s);
   if (!tab.skip_noise)
     hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,

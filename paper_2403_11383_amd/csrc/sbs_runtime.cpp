@@ -83,6 +83,48 @@ bool valid_form(int lanes, int block, int unroll) {
 }
 uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
 
+// Rows of the mean: the spline knot count P, else the horizon H.
+int rows_of(const sbs_controller_cfg &c) { return c.knots > 0 ? c.knots : c.H; }
+
+// GRF spline of Sec. IV-B as weights on the knots.  Knot p sits at
+// t_p = p T / (P - 1), T = (H - 1) dt.  On [t_p, t_{p+1}] (h = t_{p+1} - t_p,
+// s = (t - t_p) / h) the spline is the cubic Hermite form
+//   (2s^3 - 3s^2 + 1) y_p + (s^3 - 2s^2 + s) h m_p + (-2s^3 + 3s^2) y_{p+1}
+//   + (s^3 - s^2) h m_{p+1}
+// with slopes m_p = (y_b - y_a) / (t_b - t_a), a = max(p-1, 0),
+// b = min(p+1, P-1).  Every step therefore weighs at most the four knots
+// p-1 .. p+2; the window starts at max(0, min(p-1, P-4)).
+struct SplineRow {
+  int32_t base;
+  double w[4];
+};
+
+SplineRow spline_row(int P, int H, double dt, double t) {
+  const double T = (double)(H - 1) * dt;
+  auto tk = [&](int p) { return (double)p * T / (double)(P - 1); };
+  t = std::min(std::max(t, 0.0), T);
+  int p = 0;
+  while (p < P - 2 && t >= tk(p + 1)) ++p;
+  const double h = tk(p + 1) - tk(p), s = (t - tk(p)) / h;
+  const double h00 = 2 * s * s * s - 3 * s * s + 1, h10 = s * s * s - 2 * s * s + s;
+  const double h01 = -2 * s * s * s + 3 * s * s, h11 = s * s * s - s * s;
+  std::vector<double> coef(P, 0.0);
+  auto slope = [&](int q, double scale) {  // adds scale * h * m_q
+    const int a = std::max(q - 1, 0), b = std::min(q + 1, P - 1);
+    const double g = scale * h / (tk(b) - tk(a));
+    coef[b] += g;
+    coef[a] -= g;
+  };
+  coef[p] += h00;
+  coef[p + 1] += h01;
+  slope(p, h10);
+  slope(p + 1, h11);
+  SplineRow r{};
+  r.base = std::max(0, std::min(p - 1, P - 4));
+  for (int i = 0; i < 4; ++i) r.w[i] = (r.base + i < P) ? coef[r.base + i] : 0.0;
+  return r;
+}
+
 // First-fit allocator over [0, size) with coalescing frees.
 class Carver {
  public:
@@ -135,8 +177,14 @@ struct Controller {
   int32_t id = -1;
   sbs_controller_cfg cfg{};
   uint64_t st_off = 0, st_bytes = 0;
-  void *mu_buf[2] = {nullptr, nullptr};  // double-buffered mean [H][12]
+  void *mu_buf[2] = {nullptr, nullptr};  // double-buffered mean [rows][12]
   uint64_t mu_bytes = 0;
+  // spline tables (knots > 0): device copies inside the persistent state,
+  // host copies for the warm-start shift of sbs_get_state
+  const double *sp_w = nullptr, *sh_w = nullptr;
+  const int32_t *sp_b = nullptr, *sh_b = nullptr;
+  std::vector<double> h_sh_w;
+  std::vector<int32_t> h_sh_b;
   int par = 0;              // buffer holding the current mean
   bool needs_shift = false; // it is the previous tick's mean (unshifted)
   double *ctl = nullptr;
@@ -202,15 +250,15 @@ struct ItemWs {
 
 ItemWs item_ws(const sbs_controller_cfg &c) {
   ItemWs o{};
-  const uint64_t N = (uint64_t)c.N, H = (uint64_t)c.H;
+  const uint64_t N = (uint64_t)c.N, M = (uint64_t)rows_of(c);
   const uint64_t ts = c.precision == SBS_FP64 ? 8 : 4;
   uint64_t p = 0;
-  o.z = p; p = align_up(p + H * N * 12 * 4);
+  o.z = p; p = align_up(p + M * N * 12 * 4);
   o.q = p; p = align_up(p + N * 4);
   o.J = p; p = align_up(p + N * ts);
   o.w = p; p = align_up(p + N * ts);
   o.act = p; p = align_up(p + N * 4);
-  o.sigma = p; p = align_up(p + H * 12 * 8);
+  o.sigma = p; p = align_up(p + M * 12 * 8);
   o.it = p; p = align_up(p + kItScalars * 8);
   o.bytes = p;
   return o;
@@ -312,6 +360,8 @@ uint32_t host_q_of_freq(double f, double dt) {
 int validate_cfg(const sbs_controller_cfg &c) {
   if (c.N < 1 || c.N > (1 << 22)) return fail(SBS_EINVAL, "N=%d out of [1, 2^22]", c.N);
   if (c.H < 1 || c.H > kMaxH) return fail(SBS_EINVAL, "H=%d out of [1, %d]", c.H, kMaxH);
+  if (c.knots != 0 && (c.knots < 2 || c.knots > c.H))
+    return fail(SBS_EINVAL, "knots=%d: 0, or 2 <= knots <= H=%d", c.knots, c.H);
   if (c.iterations < 1 || c.iterations > 64)
     return fail(SBS_EINVAL, "iterations=%d out of [1, 64]", c.iterations);
   if (c.method < 0 || c.method > 2) return fail(SBS_EINVAL, "unknown method %d", c.method);
@@ -357,6 +407,12 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   d->duty_full = dq >= 4294967296.0 ? 1 : 0;
   d->duty_q = d->duty_full ? 0xFFFFFFFFu : (uint32_t)dq;
   d->slot = slot;
+  d->M = rows_of(c);
+  d->spline = c.knots > 0 ? 1 : 0;
+  d->sp_w = C.sp_w;
+  d->sp_b = C.sp_b;
+  d->sh_w = C.sh_w;
+  d->sh_b = C.sh_b;
   d->seed = c.seed;
   d->dt = c.dt;
   d->inv_lambda = c.method == SBS_MPPI ? 1.0 / c.lambda : 0.0;
@@ -419,9 +475,9 @@ Layout make_layout(const std::vector<const Controller *> &cs) {
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
   L.desc = 0;
   L.tabs = align_up(n * sizeof(TickDesc));
-  // per (iteration, precision): item[n] + 3 x start[n+1]
+  // per (iteration, precision, parametrisation): item[n] + 3 x start[n+1]
   const uint64_t tab_bytes = align_up((n + 3 * (n + 1)) * 4);
-  L.hdr_bytes = align_up(L.tabs + (uint64_t)rmax * 2 * tab_bytes);
+  L.hdr_bytes = align_up(L.tabs + (uint64_t)rmax * 4 * tab_bytes);
   L.results = L.hdr_bytes;
   L.items = align_up(L.results + n * kResultDoubles * 8);
   uint64_t p = L.items;
@@ -457,14 +513,18 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
   std::vector<std::pair<LaunchTab, int>> out;
   const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
   for (int r = 0; r < rmax; ++r) {
-    for (int prec = 0; prec < 2; ++prec) {
-      const uint64_t off = L.tabs + ((uint64_t)r * 2 + prec) * tab_bytes;
+    for (int grp = 0; grp < 4; ++grp) {
+      // one launch per (precision, parametrisation) group
+      const int prec = grp >> 1, spl = grp & 1;
+      const uint64_t off = L.tabs + ((uint64_t)r * 4 + grp) * tab_bytes;
       int32_t *item = reinterpret_cast<int32_t *>(host + off);
       int32_t *ns = item + n, *rs = ns + (n + 1), *us = rs + (n + 1);
       // longest horizon first: the rollout stage's tail is the longest lanes
       std::vector<int> idx;
       for (int i = 0; i < n; ++i)
-        if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec) idx.push_back(i);
+        if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec &&
+            (cs[i]->cfg.knots > 0 ? 1 : 0) == spl)
+          idx.push_back(i);
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
       int m = (int)idx.size();
@@ -478,18 +538,20 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         lanes = tn.lanes == 0 ? (nsum <= kQuadMaxSamples ? 4 : 1) : tn.lanes;
         if (valid_form(lanes, tn.block, tn.unroll)) {
           block = tn.block;
-          unroll = tn.unroll;
+          unroll = spl ? 1 : tn.unroll;  // spline rollouts: unroll 1 only
         }
       }
       const int per_block = block / lanes;
+      int max_rows = 1;
       ns[0] = rs[0] = us[0] = 0;
       for (int t = 0; t < m; ++t) {
         max_h = std::max(max_h, cs[idx[t]]->cfg.H);
+        max_rows = std::max(max_rows, rows_of(cs[idx[t]]->cfg));
         const sbs_controller_cfg &c = cs[idx[t]]->cfg;
         item[t] = idx[t];
-        ns[t + 1] = ns[t] + c.H * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
+        ns[t + 1] = ns[t] + rows_of(c) * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
         rs[t + 1] = rs[t] + (c.N + per_block - 1) / per_block;
-        us[t + 1] = us[t] + c.H;
+        us[t + 1] = us[t] + rows_of(c);
       }
       if (m == 0) continue;
       LaunchTab tab{};
@@ -499,6 +561,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.total_roll = rs[m];
       tab.total_upd = us[m];
       tab.max_h = max_h;
+      tab.max_rows = max_rows;
+      tab.spline = spl;
       tab.lanes = lanes;
       tab.roll_block = block;
       tab.unroll = unroll;
@@ -632,7 +696,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       pc = &C0;
       pbuf = (int)(ticks[0] & 1u);
       inl->z = C0.pf_z[pbuf];
-      inl->z_iter_stride = (uint64_t)C0.cfg.H * C0.cfg.N * 12;
+      inl->z_iter_stride = (uint64_t)rows_of(C0.cfg) * C0.cfg.N * 12;
       if (C0.pf_tick[pbuf] == (int64_t)ticks[0]) {
         e = hipStreamWaitEvent(s, C0.pf_ready[pbuf], 0);
         for (auto &tp : tabs) tp.first.skip_noise = 1;
@@ -849,8 +913,15 @@ int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t 
   Controller C;
   C.cfg = *cfg;
   const uint64_t ts = cfg->precision == SBS_FP64 ? 8 : 4;
-  C.mu_bytes = align_up((uint64_t)cfg->H * 12 * ts);
-  C.st_bytes = 2 * C.mu_bytes + kAlign;
+  const int M = rows_of(*cfg);
+  C.mu_bytes = align_up((uint64_t)M * 12 * ts);
+  // spline tables after the frequency mean: sp_w [H][4], sh_w [M][4] (FP64),
+  // sp_b [H], sh_b [M] (int32)
+  const uint64_t sp_off = 2 * C.mu_bytes + kAlign;
+  const uint64_t sh_off = align_up(sp_off + (uint64_t)cfg->H * 4 * 8);
+  const uint64_t spb_off = align_up(sh_off + (uint64_t)M * 4 * 8);
+  const uint64_t shb_off = align_up(spb_off + (uint64_t)cfg->H * 4);
+  C.st_bytes = cfg->knots > 0 ? align_up(shb_off + (uint64_t)M * 4) : sp_off;
   if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off)) {
     reap(rt);
     if (!rt->dev_alloc.alloc(C.st_bytes, &C.st_off))
@@ -860,10 +931,38 @@ int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t 
   C.mu_buf[0] = base;
   C.mu_buf[1] = base + C.mu_bytes;
   C.ctl = reinterpret_cast<double *>(base + 2 * C.mu_bytes);
-  // hover mean: (0, 0, m g / 2) on every leg and step
+  // hover mean: (0, 0, m g / 2) on every leg and row
   std::vector<char> hostbuf(C.st_bytes, 0);
   const double hover = 0.5 * cfg->mass * cfg->gravity;
-  for (int j = 0; j < cfg->H; ++j)
+  if (cfg->knots > 0) {
+    const int P = cfg->knots;
+    double *spw = reinterpret_cast<double *>(hostbuf.data() + sp_off);
+    double *shw = reinterpret_cast<double *>(hostbuf.data() + sh_off);
+    int32_t *spb = reinterpret_cast<int32_t *>(hostbuf.data() + spb_off);
+    int32_t *shb = reinterpret_cast<int32_t *>(hostbuf.data() + shb_off);
+    for (int j = 0; j < cfg->H; ++j) {
+      const SplineRow r = spline_row(P, cfg->H, cfg->dt, (double)j * cfg->dt);
+      spb[j] = r.base;
+      for (int i = 0; i < 4; ++i) spw[4 * j + i] = r.w[i];
+    }
+    // shifted mean: knot p < P - 1 takes the spline one step later; the
+    // last knot is hover (its row of the table is unused)
+    C.h_sh_w.assign((size_t)4 * P, 0.0);
+    C.h_sh_b.assign((size_t)P, 0);
+    for (int p = 0; p + 1 < P; ++p) {
+      const double tp = (double)p * ((double)(cfg->H - 1) * cfg->dt) / (double)(P - 1);
+      const SplineRow r = spline_row(P, cfg->H, cfg->dt, tp + cfg->dt);
+      C.h_sh_b[p] = r.base;
+      for (int i = 0; i < 4; ++i) C.h_sh_w[4 * p + i] = r.w[i];
+    }
+    std::memcpy(shw, C.h_sh_w.data(), sizeof(double) * 4 * P);
+    std::memcpy(shb, C.h_sh_b.data(), sizeof(int32_t) * P);
+    C.sp_w = reinterpret_cast<const double *>(base + sp_off);
+    C.sh_w = reinterpret_cast<const double *>(base + sh_off);
+    C.sp_b = reinterpret_cast<const int32_t *>(base + spb_off);
+    C.sh_b = reinterpret_cast<const int32_t *>(base + shb_off);
+  }
+  for (int j = 0; j < M; ++j)
     for (int c = 0; c < 12; ++c) {
       const double v = (c % 3 == 2) ? hover : 0.0;
       if (ts == 8) reinterpret_cast<double *>(hostbuf.data())[j * 12 + c] = v;
@@ -1033,7 +1132,7 @@ int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_
     }
   }
   Controller &C = it->second;
-  const int H = C.cfg.H, n = H * 12;
+  const int H = rows_of(C.cfg), n = H * 12;
   const bool f64 = C.cfg.precision == SBS_FP64;
   std::vector<char> buf((size_t)n * (f64 ? 8 : 4));
   double mf = 0;
@@ -1046,13 +1145,25 @@ int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_
     // the warm-started mean: shifted by one step when the stored one is
     // the previous tick's
     const double hover = 0.5 * C.cfg.mass * C.cfg.gravity;
+    auto stored = [&](int i) {
+      return f64 ? reinterpret_cast<double *>(buf.data())[i]
+                 : (double)reinterpret_cast<float *>(buf.data())[i];
+    };
     for (int i = 0; i < n; ++i) {
       const int j = i / 12, c = i % 12;
-      const int src = C.needs_shift ? i + 12 : i;
       double v;
-      if (C.needs_shift && j == H - 1) v = (c % 3 == 2) ? hover : 0.0;
-      else v = f64 ? reinterpret_cast<double *>(buf.data())[src]
-                   : (double)reinterpret_cast<float *>(buf.data())[src];
+      if (C.needs_shift && j == H - 1) {
+        v = (c % 3 == 2) ? hover : 0.0;
+      } else if (C.needs_shift && C.cfg.knots > 0) {
+#pragma clang fp contract(off)
+        // the spline one step later: the kernels' sum, in the same order
+        const int b = C.h_sh_b[j];
+        v = C.h_sh_w[4 * j] * stored(b * 12 + c);
+        for (int t = 1; t < 4; ++t)
+          if (b + t < H) v = v + C.h_sh_w[4 * j + t] * stored((b + t) * 12 + c);
+      } else {
+        v = stored(C.needs_shift ? i + 12 : i);
+      }
       mu[i] = v;
     }
   }
@@ -1077,7 +1188,7 @@ int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, ui
     }
   }
   Controller &C = it->second;
-  const int n = C.cfg.H * 12;
+  const int n = rows_of(C.cfg) * 12;
   if (!finite_vec(mu, n) || !std::isfinite(mu_f)) return fail(SBS_EINVAL, "non-finite state");
   const bool f64 = C.cfg.precision == SBS_FP64;
   std::vector<char> buf((size_t)n * (f64 ? 8 : 4));
@@ -1104,7 +1215,8 @@ int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable) {
   Controller &C = it->second;
   if (enable && !C.debug) {
     const uint64_t RN = (uint64_t)C.cfg.iterations * C.cfg.N;
-    const uint64_t bJ = align_up(RN * 8), bq = align_up(RN * 4), bm = align_up((uint64_t)C.cfg.H * 12 * 8);
+    const uint64_t bJ = align_up(RN * 8), bq = align_up(RN * 4),
+                   bm = align_up((uint64_t)rows_of(C.cfg) * 12 * 8);
     C.dbg_bytes = bJ + bq + bm;
     if (!rt->dev_alloc.alloc(C.dbg_bytes, &C.dbg_off)) {
       C.dbg_bytes = 0;
@@ -1150,7 +1262,7 @@ int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, dou
   if (costs) e = hipMemcpyAsync(costs, C.dbg_J, RN * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && q) e = hipMemcpyAsync(q, C.dbg_q, RN * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && mean)
-    e = hipMemcpyAsync(mean, C.dbg_mean, (size_t)C.cfg.H * 12 * 8, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(mean, C.dbg_mean, (size_t)rows_of(C.cfg) * 12 * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(SBS_EDEVICE, "debug download failed: %s", hipGetErrorString(e));
   return SBS_OK;
@@ -1198,7 +1310,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
     e = hipMemcpyAsync(hd[0].it + IT_MUF, C.ctl, 8, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(hd[0].it + IT_SIGF, &sf, 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_noise_only(tab, s, nullptr);
-  std::vector<float> zj((size_t)C.cfg.H * C.cfg.N * 12);
+  std::vector<float> zj((size_t)rows_of(C.cfg) * C.cfg.N * 12);
   if (e == hipSuccess)
     e = hipMemcpyAsync(zj.data(), dev + L.item_off[0] + w.z, zj.size() * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
@@ -1207,7 +1319,7 @@ int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, floa
   rt->dev_alloc.release(off, L.total);
   rt->host_alloc.release(hoff, L.host_total);
   if (e != hipSuccess) return fail(SBS_EDEVICE, "noise tap failed: %s", hipGetErrorString(e));
-  const int N = C.cfg.N, H = C.cfg.H;
+  const int N = C.cfg.N, H = rows_of(C.cfg);
   for (int j = 0; j < H; ++j)
     for (int k = 0; k < N; ++k)
       std::memcpy(&z[((size_t)k * H + j) * 12], &zj[((size_t)j * N + k) * 12], 48);
@@ -1231,7 +1343,7 @@ int sbs_set_prefetch(sbs_runtime *rt, int32_t id, int32_t enable) {
     }
   }
   if (enable && !C.prefetch) {
-    const uint64_t one = align_up((uint64_t)C.cfg.iterations * C.cfg.H * C.cfg.N * 12 * 4);
+    const uint64_t one = align_up((uint64_t)C.cfg.iterations * rows_of(C.cfg) * C.cfg.N * 12 * 4);
     C.pf_bytes = 2 * one;
     if (!rt->dev_alloc.alloc(C.pf_bytes, &C.pf_off)) {
       C.pf_bytes = 0;

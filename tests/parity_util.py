@@ -1,0 +1,95 @@
+"""Shared checks of the GPU parity tests: the FP64 oracle against the HIP
+path on the same seeded inputs (see the bars in test_gpu_parity)."""
+import numpy as np
+
+import oracle
+from paper_2403_11383_amd import workloads
+
+MG2 = 0.5 * workloads.MASS * workloads.GRAVITY
+
+
+def cost_tol(J):
+    """FP32 rollout cost tolerance: 1e-4 relative + 1e-3 absolute.  Calibrated:
+    the worst relative error observed on the influential samples of these
+    seeded workloads is 2.2e-5; the bar keeps a 4x margin."""
+    return 1e-4 * np.abs(J) + 1e-3
+
+
+RELEVANT = 60.0  # weight below exp(-60) relative to the best: no influence
+
+
+def check_costs_fp32(Jg, Jr, lam=1.0, elite_ke=None):
+    """FP32 costs against FP64 costs of the same samples.
+
+    A rollout that tumbles is chaotic: its cost is not reproducible across
+    precisions, but it also has no influence on the update.  So
+    * every sample that can influence the update -- MPPI weight above
+      exp(-RELEVANT) in the oracle, or within twice the oracle's elite
+      threshold -- matches within cost_tol;
+    * every other sample is also without influence on the GPU side;
+    * the typical influential sample (median) agrees to 1e-5 relative (at
+      H = 50 most rollouts tumble, so the median over all samples says
+      nothing about the arithmetic).
+    """
+    Jg, Jr = np.asarray(Jg, np.float64), np.asarray(Jr, np.float64)
+    beta_r, beta_g = Jr.min(), Jg.min()
+    if elite_ke is None:
+        rel = Jr <= beta_r + RELEVANT * lam
+        far = Jg > beta_g + 0.5 * RELEVANT * lam
+    else:
+        thr_r = np.sort(Jr)[elite_ke - 1]
+        thr_g = np.sort(Jg)[elite_ke - 1]
+        rel = Jr <= 2.0 * thr_r
+        far = Jg > thr_g
+    # equal infinities agree; a finite cost against a non-finite one is an
+    # infinite error (allowed only where the sample has no influence)
+    with np.errstate(invalid="ignore"):
+        err = np.where(Jg == Jr, 0.0, np.abs(Jg - Jr))
+    err = np.where(np.isnan(err), np.inf, err)
+    bad = rel & (err > cost_tol(Jr))
+    assert not bad.any(), (np.flatnonzero(bad)[:10], err[bad][:10], Jr[bad][:10])
+    assert np.all(far[~rel]), np.flatnonzero(~rel & ~far)[:10]
+    if rel.any():
+        assert np.median(err[rel] / np.maximum(np.abs(Jr[rel]), 1.0)) <= 1e-5
+    return int(rel.sum())
+
+
+def hover(cfg):
+    """The hover mean, one row per step or spline knot."""
+    return np.tile([0.0, 0.0, MG2] * 4, (oracle.rows(cfg), 1))
+
+
+def run_pair(rt, cfg, inp, tick=None, mu=None, mu_f=None, nthreads=8):
+    """One tick on the GPU (debug on) and on the oracle from the same state."""
+    cid = rt.init_controller(cfg)
+    rt.set_debug(cid, True)
+    if mu is None:
+        mu = hover(cfg)
+    if mu_f is None:
+        mu_f = cfg.get("mu_f0", 1.4)
+    t = 0 if tick is None else tick
+    rt.set_state(cid, mu, mu_f, t)
+    mu_gpu_in, _, _ = rt.get_state(cid)  # the mean as the controller holds it
+    act = rt.tick(cid, inp)
+    J, q, mean = rt.debug_fetch(cid)
+    mu_next, mf_next, tk = rt.get_state(cid)
+    ref = oracle.tick(cfg, mu_gpu_in, mu_f, t, inp, nthreads=nthreads)
+    rt.destroy_controller(cid)
+    return {"act": act, "J": J, "q": q, "mean": mean, "mu_next": mu_next, "mf_next": mf_next,
+            "tick_next": tk}, ref
+
+
+def check_fp64(out, ref, cfg, rel=1e-10):
+    R, N = ref["costs"].shape
+    np.testing.assert_array_equal(out["q"], ref["q_samples"])
+    Jr = ref["costs"]
+    np.testing.assert_allclose(out["J"], Jr, rtol=rel, atol=0)
+    scale = max(np.abs(ref["mean"]).max(), MG2)
+    assert np.abs(out["mean"] - ref["mean"]).max() <= rel * scale
+    assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= rel * scale
+    np.testing.assert_array_equal(out["act"]["contact"], ref["contact"])
+    assert out["act"]["q"] == ref["q"]
+    assert abs(out["act"]["freq_hz"] - ref["freq_hz"]) <= 1e-12 * max(1.0, abs(ref["freq_hz"]))
+    assert np.abs(out["mu_next"] - ref["mu_next"]).max() <= rel * scale
+    assert abs(out["mf_next"] - ref["mu_f_next"]) <= 1e-12
+    assert out["act"]["flags"] == ref["flags"]
