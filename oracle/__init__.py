@@ -20,10 +20,11 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
 
 MPPI, ELITE, NAIVE = 0, 1, 2
-FREQ_FIXED, FREQ_UNIFORM, FREQ_GAUSSIAN = 0, 1, 2
+FREQ_FIXED, FREQ_UNIFORM, FREQ_GAUSSIAN, FREQ_SET = 0, 1, 2, 3
 FLAG_NONFINITE = 1
 METHODS = {"mppi": MPPI, "elite": ELITE, "naive": NAIVE}
-FREQ_MODES = {"fixed": FREQ_FIXED, "uniform": FREQ_UNIFORM, "gaussian": FREQ_GAUSSIAN}
+FREQ_MODES = {"fixed": FREQ_FIXED, "uniform": FREQ_UNIFORM, "gaussian": FREQ_GAUSSIAN,
+              "set": FREQ_SET}
 
 
 def build() -> str:
@@ -51,6 +52,7 @@ class Cfg(C.Structure):
         ("inertia", C.c_double * 3), ("hip", C.c_double * 12),
         ("Q", C.c_double * 12), ("R", C.c_double * 12),
         ("phase_offset", C.c_uint32 * 4), ("seed", C.c_uint64),
+        ("f_set", C.c_double * 4), ("n_fset", C.c_int32),
     ]
 
 
@@ -146,6 +148,9 @@ def make_cfg(d: dict) -> Cfg:
     c.R[:] = [float(v) for v in d["R"]]
     c.phase_offset[:] = [int(v) & 0xFFFFFFFF for v in d["phase_offset"]]
     c.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    fs = [float(v) for v in d.get("f_set", ())]
+    c.n_fset = len(fs)
+    c.f_set[:] = (fs + [0.0] * 4)[:4]
     return c
 
 

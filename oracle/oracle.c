@@ -146,6 +146,11 @@ uint32_t orc_freq_q(const orc_cfg *cfg, double mu_f, double sigma_f, uint32_t ti
     uint64_t span = (uint64_t)(qhi - qlo) + 1u;
     return qlo + (uint32_t)(((uint64_t)w[0] * span) >> 32);
   }
+  if (cfg->freq_mode == ORC_FREQ_SET) {
+    /* one of the n admissible frequencies, each with probability 1/n */
+    uint32_t i = (uint32_t)(((uint64_t)w[0] * (uint64_t)cfg->n_fset) >> 32);
+    return orc_q_of_freq(cfg->f_set[i], cfg->dt);
+  }
   /* Gaussian around the current mean, clamped to the admissible range */
   float g[2];
   orc_gauss_pair(w[0], w[1], g);
@@ -522,6 +527,7 @@ int orc_tick(const orc_cfg *cfg, double *mu, double *mu_f, uint32_t tick,
   const int32_t M = decision_rows(cfg), D = 12 * M;
   if (N < 1 || H < 1 || R < 1) return -1;
   if (cfg->knots < 0 || cfg->knots == 1 || cfg->knots > H) return -1;
+  if (cfg->freq_mode == ORC_FREQ_SET && (cfg->n_fset < 1 || cfg->n_fset > 4)) return -1;
   for (int d = 0; d < 12; ++d)
     if (!isfinite(in->x0[d])) return -1;
   if (nthreads < 1) nthreads = 1;

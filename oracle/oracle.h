@@ -58,7 +58,7 @@ extern "C" {
 #endif
 
 enum { ORC_MPPI = 0, ORC_ELITE = 1, ORC_NAIVE = 2 };
-enum { ORC_FREQ_FIXED = 0, ORC_FREQ_UNIFORM = 1, ORC_FREQ_GAUSSIAN = 2 };
+enum { ORC_FREQ_FIXED = 0, ORC_FREQ_UNIFORM = 1, ORC_FREQ_GAUSSIAN = 2, ORC_FREQ_SET = 3 };
 enum { ORC_FLAG_NONFINITE = 1 };
 
 typedef struct {
@@ -81,6 +81,8 @@ typedef struct {
   double R[12];         /* diagonal GRF weight                              */
   uint32_t phase_offset[4]; /* leg phase offsets, 2^32 = one gait cycle     */
   uint64_t seed;
+  double f_set[4];      /* ORC_FREQ_SET: the admissible frequencies, drawn  */
+  int32_t n_fset;       /* with equal probability (n_fset in [1, 4])        */
 } orc_cfg;
 
 typedef struct {
