@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SBS_ABI_VERSION 2
+#define SBS_ABI_VERSION 3
 
 typedef enum {
   SBS_OK = 0,
@@ -52,7 +52,7 @@ typedef enum {
 } sbs_status;
 
 enum { SBS_MPPI = 0, SBS_ELITE = 1, SBS_NAIVE = 2 };
-enum { SBS_FREQ_FIXED = 0, SBS_FREQ_UNIFORM = 1, SBS_FREQ_GAUSSIAN = 2 };
+enum { SBS_FREQ_FIXED = 0, SBS_FREQ_UNIFORM = 1, SBS_FREQ_GAUSSIAN = 2, SBS_FREQ_SET = 3 };
 enum { SBS_FP32 = 0, SBS_FP64 = 1 };
 enum { SBS_FLAG_NONFINITE = 1 };
 enum { SBS_MODE_DIRECT = 0, SBS_MODE_SERVING = 1 };
@@ -61,7 +61,8 @@ enum { SBS_MODE_DIRECT = 0, SBS_MODE_SERVING = 1 };
  * horizon steps (the paper's N), `iterations` SBS iterations per control step
  * (Alg. 1 repeated from the same state), method SBS_MPPI / SBS_ELITE /
  * SBS_NAIVE, gait-frequency mode SBS_FREQ_* (Sec. IV-C: fixed, uniform on
- * [f_min, f_max], or Gaussian around the frequency mean), precision of the
+ * [f_min, f_max], Gaussian around the frequency mean, or one of a small set
+ * drawn uniformly as in Sec. V), precision of the
  * rollouts and costs (SBS_FP32 or SBS_FP64).  The frequency is carried as a
  * phase increment per step q = round-half-even(f dt 2^32).
  *
@@ -93,6 +94,9 @@ typedef struct sbs_controller_cfg {
   double R[12];         /* diagonal GRF weights                             */
   uint32_t phase_offset[4]; /* leg phase offsets, 2^32 = one gait cycle     */
   uint64_t seed;        /* key of the counter-based noise stream            */
+  double f_set[4];      /* SBS_FREQ_SET: the admissible frequencies [Hz],   */
+  int32_t n_fset;       /* each drawn with probability 1 / n_fset (1..4)    */
+  int32_t reserved1;
 } sbs_controller_cfg;
 
 /* One control-step request ("Given x0", Alg. 5). */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsbs.so")
 
 MPPI, ELITE, NAIVE = 0, 1, 2
 METHODS = {"mppi": MPPI, "elite": ELITE, "naive": NAIVE}
-FREQ_MODES = {"fixed": 0, "uniform": 1, "gaussian": 2}
+FREQ_MODES = {"fixed": 0, "uniform": 1, "gaussian": 2, "set": 3}
 PRECISIONS = {"fp32": 0, "fp64": 1}
 MODES = {"direct": 0, "serving": 1}
 FLAG_NONFINITE = 1
@@ -54,6 +54,7 @@ class ControllerCfg(C.Structure):
         ("mass", C.c_double), ("gravity", C.c_double), ("inertia", C.c_double * 3),
         ("hip", C.c_double * 12), ("Q", C.c_double * 12), ("R", C.c_double * 12),
         ("phase_offset", C.c_uint32 * 4), ("seed", C.c_uint64),
+        ("f_set", C.c_double * 4), ("n_fset", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -166,6 +167,9 @@ def make_cfg(d: dict) -> ControllerCfg:
     c.R[:] = [float(v) for v in d["R"]]
     c.phase_offset[:] = [int(v) & 0xFFFFFFFF for v in d["phase_offset"]]
     c.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    fs = [float(v) for v in d.get("f_set", ())]
+    c.n_fset = len(fs)
+    c.f_set[:] = (fs + [0.0] * 4)[:4]
     return c
 
 

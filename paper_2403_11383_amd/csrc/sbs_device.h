@@ -50,6 +50,9 @@ struct TickDesc {
   uint32_t tick;         // control-step counter (noise counter word 2)
   uint32_t phase_robot;
   uint32_t q_fixed, q_lo, q_hi;
+  uint32_t q_set[4];     // frequency-set mode: phase increments of the members
+  int32_t n_fset;
+  int32_t pad1;
   uint32_t phase_offset[4];
   uint32_t duty_q;       // stance iff phase < duty_q (duty_full: always)
   int32_t duty_full;

@@ -151,6 +151,10 @@ __device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
     const uint64_t span = (uint64_t)(d.q_hi - d.q_lo) + 1u;
     return d.q_lo + (uint32_t)(((uint64_t)c0 * span) >> 32);
   }
+  if (d.freq_mode == 3) {  // one member of the frequency set, each with probability 1/n
+    const uint32_t i = (uint32_t)(((uint64_t)c0 * (uint64_t)d.n_fset) >> 32);
+    return d.q_set[i];
+  }
   const double mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
   const double sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
   return freq_gaussian(mf, sf, gauss_pair(c0, c1).x, d.f_min, d.f_max, d.dt);

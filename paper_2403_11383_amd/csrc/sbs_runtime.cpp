@@ -365,7 +365,12 @@ int validate_cfg(const sbs_controller_cfg &c) {
   if (c.iterations < 1 || c.iterations > 64)
     return fail(SBS_EINVAL, "iterations=%d out of [1, 64]", c.iterations);
   if (c.method < 0 || c.method > 2) return fail(SBS_EINVAL, "unknown method %d", c.method);
-  if (c.freq_mode < 0 || c.freq_mode > 2) return fail(SBS_EINVAL, "unknown freq_mode %d", c.freq_mode);
+  if (c.freq_mode < 0 || c.freq_mode > 3) return fail(SBS_EINVAL, "unknown freq_mode %d", c.freq_mode);
+  if (c.freq_mode == SBS_FREQ_SET) {
+    if (c.n_fset < 1 || c.n_fset > 4) return fail(SBS_EINVAL, "n_fset=%d out of [1, 4]", c.n_fset);
+    for (int i = 0; i < c.n_fset; ++i)
+      if (!(c.f_set[i] > 0)) return fail(SBS_EINVAL, "frequency set members must be > 0");
+  }
   if (c.precision != SBS_FP32 && c.precision != SBS_FP64)
     return fail(SBS_EINVAL, "unknown precision %d", c.precision);
   if (!(c.dt > 0) || !(c.mass > 0) || !(c.gravity > 0) || !(c.inertia[0] > 0) ||
@@ -374,7 +379,8 @@ int validate_cfg(const sbs_controller_cfg &c) {
   if (c.method == SBS_MPPI && !(c.lambda > 0)) return fail(SBS_EINVAL, "lambda must be positive");
   if (!(c.duty >= 0.0 && c.duty <= 1.0)) return fail(SBS_EINVAL, "duty must be in [0, 1]");
   if (!(c.sigma_grf >= 0.0)) return fail(SBS_EINVAL, "sigma_grf must be >= 0");
-  if (c.freq_mode != SBS_FREQ_FIXED && !(c.f_min > 0 && c.f_max >= c.f_min))
+  if ((c.freq_mode == SBS_FREQ_UNIFORM || c.freq_mode == SBS_FREQ_GAUSSIAN) &&
+      !(c.f_min > 0 && c.f_max >= c.f_min))
     return fail(SBS_EINVAL, "frequency range must satisfy 0 < f_min <= f_max");
   if (c.freq_mode == SBS_FREQ_FIXED && !(c.f_fixed > 0)) return fail(SBS_EINVAL, "f_fixed must be > 0");
   return SBS_OK;
@@ -402,6 +408,8 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   d->q_fixed = host_q_of_freq(c.f_fixed, c.dt);
   d->q_lo = host_q_of_freq(c.f_min, c.dt);
   d->q_hi = host_q_of_freq(c.f_max, c.dt);
+  d->n_fset = c.freq_mode == SBS_FREQ_SET ? c.n_fset : 0;
+  for (int i = 0; i < 4; ++i) d->q_set[i] = i < d->n_fset ? host_q_of_freq(c.f_set[i], c.dt) : 0u;
   for (int l = 0; l < 4; ++l) d->phase_offset[l] = c.phase_offset[l];
   const double dq = std::rint(c.duty * 4294967296.0);
   d->duty_full = dq >= 4294967296.0 ? 1 : 0;

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(built):
 
 def test_abi_version_and_error_string(built):
     L = built.lib()
-    assert L.sbs_abi_version() == 2
+    assert L.sbs_abi_version() == 3
     assert isinstance(L.sbs_last_error(), bytes)
 
 

@@ -37,9 +37,10 @@ def _oracle_built():
 # ---------------------------------------------------------------------------
 # noise
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", ["uniform", "gaussian", "fixed"])
+@pytest.mark.parametrize("mode", ["uniform", "gaussian", "fixed", "set"])
 def test_noise_bit_exact(rt, mode):
-    cfg = workloads.config("c1", N=333, H=7, freq_mode=mode, sigma_f=0.4, seed=0xDEADBEEF12345)
+    cfg = workloads.config("c1", N=333, H=7, freq_mode=mode, sigma_f=0.4, seed=0xDEADBEEF12345,
+                           f_set=(1.4, 2.0, 2.4))
     cid = rt.init_controller(cfg)
     for tick, r in ((0, 0), (5, 0), (123456, 2)):
         z, q = rt.debug_noise(cid, tick, r)
@@ -101,6 +102,21 @@ def test_fp64_duty_edges_and_pace(rt):
         inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(4)))
         out, ref = run_pair(rt, cfg, inp)
         check_fp64(out, ref, cfg)
+
+
+@pytest.mark.parametrize("method", ["naive", "mppi"])
+def test_fp64_frequency_set_and_pace(rt, method):
+    """The paper's discrete frequency set (nominal, 2.0, 2.4 Hz) with the
+    best-sample update and a pacing gait."""
+    cfg = workloads.config("c2", N=1200, H=14, precision="fp64", method=method, iterations=2,
+                           freq_mode="set", f_set=(1.4, 2.0, 2.4),
+                           phase_offset=list(workloads.PACE_OFFSETS), seed=31)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(31)),
+                               phase_robot=1 << 30)
+    out, ref = run_pair(rt, cfg, inp, tick=6)
+    check_fp64(out, ref, cfg)
+    qs = {oracle.q_of_freq(f, cfg["dt"]) for f in (1.4, 2.0, 2.4)}
+    assert set(np.unique(out["q"])) <= qs
 
 
 def test_nonfinite_costs_keep_mean(rt):
