@@ -1,0 +1,120 @@
+"""Parity at the benchmark's full sizes and launch configurations.
+
+C1 (N=10240, H=50, MPPI, FP32, four lanes per sample, noise produced ahead on
+the second stream) and C2 (N=16384, H=50, elite, 3 iterations) are checked on
+sampled outputs the oracle computes one by one: every sampled phase
+increment, the costs of a strided subset of samples (re-rolled by the oracle
+from the documented noise), and the update (the oracle's update fed the GPU's
+own costs).  A slice of the C3 mix runs as the benchmark runs it: a
+graph-replayed plan with the autotuned rollout form."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_11383_amd import workloads
+from parity_util import MG2, cost_tol, hover
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    oracle.build()
+
+
+def sampled_costs(cfg, inp, mu, tick, r, ks, q):
+    out = []
+    for k in ks:
+        z = np.array([oracle.noise_step(cfg["seed"], tick, r, int(k), j) for j in range(cfg["H"])],
+                     np.float64)
+        out.append(oracle.rollout(cfg, inp, mu + cfg["sigma_grf"] * z, int(q[k])))
+    return np.array(out)
+
+
+def check_sampled(Jg, Jr, ks, beta_g):
+    """Samples near the best (the ones that carry weight) agree within the
+    FP32 cost tolerance; the typical one to 1e-5 relative."""
+    Jg = np.asarray(Jg, np.float64)[ks]
+    near = Jr <= np.min(Jr) + 1e3
+    assert np.all(np.abs(Jg[near] - Jr[near]) <= cost_tol(Jr[near]))
+    fin = np.isfinite(Jr) & np.isfinite(Jg)
+    rel = np.abs(Jg[fin] - Jr[fin]) / np.maximum(np.abs(Jr[fin]), 1.0)
+    assert np.median(rel) <= 1e-5
+
+
+def test_c1_full_size_bench_configuration():
+    from paper_2403_11383_amd import binding
+    rt = binding.Runtime(arena_bytes=2 << 30, two_streams=True)
+    cfg = workloads.config("c1")
+    x0 = workloads.initial_state(np.random.default_rng(cfg["seed"]))
+    inp = workloads.tick_input(x0, v_ref=(0.3, 0.0, 0.0))
+    cid = rt.init_controller(cfg)
+    rt.set_prefetch(cid, True)
+    rt.set_debug(cid, True)
+    act = rt.tick(cid, inp)
+    J, q, mean = rt.debug_fetch(cid)
+    N = cfg["N"]
+    qr = np.array([oracle.freq_q(cfg, 1.4, 0.0, 0, 0, k) for k in range(N)], np.uint32)
+    np.testing.assert_array_equal(q[0], qr)
+    # the best sample and a strided subset, re-rolled by the oracle
+    best = int(np.argmin(J[0]))
+    ks = np.unique(np.concatenate([np.arange(0, N, 97), [best, N - 1]]))
+    Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
+    check_sampled(J[0], Jr, ks, J[0].min())
+    # the update on the GPU's own costs
+    ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
+    scale = max(np.abs(ref["grf"]).max(), MG2)
+    assert np.abs(act["grf"] - ref["grf"]).max() <= 1e-4 * scale
+    assert np.abs(mean - ref["mean"]).max() <= 1e-4 * max(np.abs(ref["mean"]).max(), MG2)
+    assert act["q"] == ref["q"]
+    # a second tick reads the prefetched noise and the shifted mean
+    act2 = rt.tick(cid, inp)
+    J2, q2, mean2 = rt.debug_fetch(cid)
+    ref2 = oracle.tick(cfg, ref["mu_next"], ref["mu_f_next"], 1, inp, costs_override=J2, nthreads=8)
+    assert np.abs(act2["grf"] - ref2["grf"]).max() <= 1e-4 * max(np.abs(ref2["grf"]).max(), MG2)
+    rt.close()
+
+
+def test_c2_full_size_elite():
+    from paper_2403_11383_amd import binding
+    rt = binding.Runtime(arena_bytes=2 << 30)
+    cfg = workloads.config("c2")
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(2)),
+                               v_ref=workloads.c2_episode_vref())
+    cid = rt.init_controller(cfg)
+    rt.set_debug(cid, True)
+    act = rt.tick(cid, inp)
+    J, q, mean = rt.debug_fetch(cid)
+    N = cfg["N"]
+    ks = np.arange(0, N, 211)
+    Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
+    check_sampled(J[0], Jr, ks, J[0].min())
+    ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
+    np.testing.assert_array_equal(q, ref["q_samples"])  # every iteration's draws
+    scale = max(np.abs(ref["mean"]).max(), MG2)
+    assert np.abs(mean - ref["mean"]).max() <= 1e-4 * scale
+    assert np.abs(act["grf"] - ref["grf"]).max() <= 1e-4 * scale
+    rt.close()
+
+
+def test_c3_slice_graph_plan_autotuned():
+    from paper_2403_11383_amd import binding
+    rt = binding.Runtime(arena_bytes=4 << 30)
+    cfgs = workloads.c3_controllers()[:6]
+    inps = workloads.c3_inputs()[:6]
+    ids = [rt.init_controller(c) for c in cfgs]
+    plan = rt.plan_create(ids, use_graph=True)
+    rt.plan_autotune(plan, inps, reps=1)
+    for cid in ids:
+        rt.set_debug(cid, True)
+    acts = [rt.fetch(t) for t in rt.plan_submit(plan, inps)]
+    for cid, cfg, inp, act in zip(ids, cfgs, inps, acts):
+        J, q, mean = rt.debug_fetch(cid)
+        mu0, mf0, _ = rt.get_state(cid)  # after the tick; the tick started from hover
+        ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], act["tick"], inp, costs_override=J,
+                          nthreads=8)
+        np.testing.assert_array_equal(q, ref["q_samples"])
+        scale = max(np.abs(ref["mean"]).max(), MG2)
+        assert np.abs(act["grf"] - ref["grf"]).max() <= 1e-4 * scale
+    rt.plan_destroy(plan)
+    rt.close()
