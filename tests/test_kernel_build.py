@@ -31,6 +31,8 @@ def metadata():
         field = lambda f: int(re.search(r"\." + f + r":\s+(\d+)", block).group(1))
         kernels[name] = {f: field(f) for f in ("private_segment_fixed_size", "vgpr_spill_count",
                                                "sgpr_spill_count", "vgpr_count")}
+        kernels[name]["args"] = [(int(o), int(z)) for o, z in
+                                 re.findall(r"\.offset:\s+(\d+)\n\s+\.size:\s+(\d+)", block)][:2]
     return kernels
 
 
@@ -44,3 +46,11 @@ def test_no_scratch_and_no_vector_spills(metadata):
     bad = {n: m for n, m in metadata.items()
            if m["private_segment_fixed_size"] or m["vgpr_spill_count"]}
     assert not bad, bad
+
+
+def test_inline_descriptor_offset(metadata):
+    """Every kernel takes (LaunchTab, TickDesc) and reads the descriptor in
+    place at the LaunchTab's size rounded up to 8 bytes."""
+    for name, m in metadata.items():
+        (o0, z0), (o1, z1) = m["args"]
+        assert o0 == 0 and o1 == (z0 + 7) // 8 * 8, (name, m["args"])
