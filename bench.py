@@ -350,11 +350,61 @@ def main_copy(args):
                       "GBps_read_plus_write": 2 * n * args.steps / dt / 1e9}), flush=True)
 
 
+def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256):
+    """The C4 fleet with every robot's next tick submitted as soon as its
+    previous one completes (no arrival gaps): the most ticks per second each
+    mode sustains, and their submit-to-done latency."""
+    import ctypes as C
+    import torch
+    fleet = workloads.c4_fleet(robots=robots)
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
+    ids = [rt.init_controller(c) for c in fleet]
+    rng = np.random.default_rng(6)
+    inputs = [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
+    L = binding.lib()
+    tk = C.c_uint64()
+    act = binding.Action()
+    torch.cuda.synchronize()
+    pending = {}
+    lat, done_work = [], 0
+    t_start = time.perf_counter_ns()
+    t_end = t_start + int(duration * 1e9)
+    idle = list(range(robots))
+    while time.perf_counter_ns() < t_end or pending:
+        if time.perf_counter_ns() < t_end:
+            still = []
+            for r in idle:
+                rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
+                if rc == binding.ENOMEM:
+                    still.append(r)
+                    continue
+                binding._check(rc)
+                pending[tk.value] = r
+            idle = still
+        for t in list(pending):
+            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
+            if rc == binding.OK:
+                r = pending.pop(t)
+                lat.append((act.t_done_ns - act.t_submit_ns) * 1e-6)
+                done_work += fleet[r]["N"] * fleet[r]["H"]
+                idle.append(r)
+            elif rc != binding.EAGAIN:
+                binding._check(rc)
+    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    stats = rt.stats()
+    rt.close()
+    return {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
+            "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
+            "p99_ms": pct(lat, 99), "batches": stats["batches"]}
+
+
 def main_c4(args):
     from paper_2403_11383_amd import binding, workloads
     arena = int(args.arena_gb * (1 << 30))
     serve = serving_run(binding, workloads, args.duration, "serving", arena)
     plain = serving_run(binding, workloads, args.duration, "direct", arena)
+    sat_serve = saturated_run(binding, workloads, 3.0, "serving", arena)
+    sat_plain = saturated_run(binding, workloads, 3.0, "direct", arena)
     line = {
         "metric": METRIC, "value": serve["rollout_steps_per_s"], "unit": "rollout-steps/s",
         "n_gpus": 1, "steps": serve["ticks"], "warmup": 0,
@@ -366,6 +416,7 @@ def main_c4(args):
                    "duration_s": args.duration, "arena_gb": args.arena_gb},
         "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"]},
         "serving": serve, "plain_single_mppi": plain,
+        "saturated": {"serving": sat_serve, "plain_single_mppi": sat_plain},
     }
     print(json.dumps(line), flush=True)
 

@@ -614,12 +614,12 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
       std::memcpy(it->second.res, b.host_results + i * kResultDoubles, sizeof(it->second.res));
       it->second.status = 0;
       it->second.t_done = t;
+      rt->n_ticks += 1;
     }
     if (it != rt->tickets.end()) it->second.rec = nullptr;  // the record is released below
     auto c = rt->ctrls.find(b.ctrls[i]);
     if (c != rt->ctrls.end()) c->second.inflight -= 1;
   }
-  rt->n_ticks += b.tickets.size();
   if (rt->timing) record_timing(rt, b);
   else {
     for (auto e : b.timing) give_event(rt, e);
@@ -1094,7 +1094,10 @@ int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t 
     auto it = rt->tickets.find(ticket);
     if (it == rt->tickets.end()) return fail(SBS_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
     TicketRec &t = it->second;
-    if (t.status == 1 && !complete_from_record(t) && rt->mode == SBS_MODE_DIRECT) reap(rt);
+    if (t.status == 1) {
+      if (complete_from_record(t)) rt->n_ticks += 1;  // counted once: the batch then skips it
+      else if (rt->mode == SBS_MODE_DIRECT) reap(rt);
+    }
     if (t.status <= 0) {
       int st = t.status;
       if (st == 0) {

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2403_11383_amd import workloads
-from parity_util import MG2, cost_tol, hover
+from parity_util import MG2, conditioning, cost_tol, hover
 
 pytestmark = pytest.mark.gpu
 
@@ -31,14 +31,16 @@ def sampled_costs(cfg, inp, mu, tick, r, ks, q):
     return np.array(out)
 
 
-def check_sampled(Jg, Jr, ks, beta_g):
-    """Samples near the best (the ones that carry weight) agree within the
-    FP32 cost tolerance; the typical one to 1e-5 relative."""
+def check_sampled(Jg, Jr, ks, amp):
+    """Well-conditioned samples (cost amplification of input perturbations
+    <= 100, see parity_util.conditioning) agree within the FP32 cost
+    tolerance, the typical one to 1e-5 relative; most sampled rollouts at
+    H = 50 tumble, and those cannot agree across precisions."""
     Jg = np.asarray(Jg, np.float64)[ks]
-    near = Jr <= np.min(Jr) + 1e3
-    assert np.all(np.abs(Jg[near] - Jr[near]) <= cost_tol(Jr[near]))
-    fin = np.isfinite(Jr) & np.isfinite(Jg)
-    rel = np.abs(Jg[fin] - Jr[fin]) / np.maximum(np.abs(Jr[fin]), 1.0)
+    well = (amp <= 100.0) & np.isfinite(Jr)
+    assert well.sum() >= 10
+    assert np.all(np.abs(Jg[well] - Jr[well]) <= cost_tol(Jr[well]))
+    rel = np.abs(Jg[well] - Jr[well]) / np.maximum(np.abs(Jr[well]), 1.0)
     assert np.median(rel) <= 1e-5
 
 
@@ -60,7 +62,11 @@ def test_c1_full_size_bench_configuration():
     best = int(np.argmin(J[0]))
     ks = np.unique(np.concatenate([np.arange(0, N, 97), [best, N - 1]]))
     Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
-    check_sampled(J[0], Jr, ks, J[0].min())
+    amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, q[0])
+    check_sampled(J[0], Jr, ks, amp)
+    # the best sample carries the weight: it must be well-conditioned and match
+    ib = int(np.flatnonzero(ks == best)[0])
+    assert amp[ib] <= 100.0 and abs(J[0][best] - Jr[ib]) <= cost_tol(Jr[ib])
     # the update on the GPU's own costs
     ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
     scale = max(np.abs(ref["grf"]).max(), MG2)
@@ -88,7 +94,8 @@ def test_c2_full_size_elite():
     N = cfg["N"]
     ks = np.arange(0, N, 211)
     Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
-    check_sampled(J[0], Jr, ks, J[0].min())
+    amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, q[0])
+    check_sampled(J[0], Jr, ks, amp)
     ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
     np.testing.assert_array_equal(q, ref["q_samples"])  # every iteration's draws
     scale = max(np.abs(ref["mean"]).max(), MG2)
