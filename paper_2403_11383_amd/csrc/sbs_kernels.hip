@@ -15,6 +15,7 @@
 //              controller to arrive forms the new mean (and elite std), the
 //              action and the warm-started mean (Sec. III-A)
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "sbs_device.h"
@@ -203,16 +204,33 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
 // ---------------------------------------------------------------------------
 // Rollout
 // ---------------------------------------------------------------------------
-// FP32 sine and cosine on the transcendental unit: the hardware takes the
-// angle in turns, so the argument is scaled by 1/(2 pi) and reduced to
-// [0, 1) first (exact for the fraction; the scaling rounds once).  The
-// attitude angles of a rollout stay within a few radians unless it tumbles,
-// and a tumbling rollout carries no weight; the FP32 cost tolerance of the
-// parity tests covers the approximation.
+// FP32 sine and cosine: Cody-Waite reduction by pi/2 (three-part constant,
+// fused multiply-adds) to |r| <= pi/4, Taylor polynomials through r^9 / r^10
+// (truncation below 4e-9), quadrant by rotation.  Accurate to a few ulp for
+// |x| up to ~1e4 rad; beyond that the result stays bounded.  (The
+// transcendental unit's sine and cosine are about twice as fast here, but
+// their error, injected at every step, costs an order of magnitude in the
+// agreement of FP32 rollout costs with the FP64 oracle.)
 __device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
-  const float t = __builtin_amdgcn_fractf(x * 0x1.45f306p-3f);
-  *s = __builtin_amdgcn_sinf(t);
-  *c = __builtin_amdgcn_cosf(t);
+  const float n = __builtin_rintf(x * 0x1.45f306p-1f);
+  float r = __builtin_fmaf(-n, 0x1.921fb6p+0f, x);
+  r = __builtin_fmaf(-n, -0x1.777a5cp-25f, r);
+  r = __builtin_fmaf(-n, -0x1.0p-49f, r);
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);
+  ps = __builtin_fmaf(r2, ps, 0x1.111112p-7f);
+  ps = __builtin_fmaf(r2, ps, -0x1.555556p-3f);
+  const float sn = __builtin_fmaf(r * r2, ps, r);
+  float pc = __builtin_fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);
+  pc = __builtin_fmaf(r2, pc, -0x1.6c16c2p-10f);
+  pc = __builtin_fmaf(r2, pc, 0x1.555556p-5f);
+  pc = __builtin_fmaf(r2, pc, -0.5f);
+  const float cs = __builtin_fmaf(r2, pc, 1.0f);
+  const int q = (int)n;
+  const bool swap = (q & 1) != 0;
+  const float ss = swap ? cs : sn, cc = swap ? sn : cs;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
 }
 __device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -1178,6 +1196,8 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
 // (coalesced cost reads and noise-row gathers).  Step 0 also leaves the
 // per-iteration scalars (next iteration's frequency mean) and, in the last
 // iteration, the action.
+constexpr int kMppiPer = 16;
+
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
   const int b = blockIdx.x;
@@ -1193,9 +1213,20 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   __shared__ double s_new[12];
   const T *Jg = reinterpret_cast<const T *>(d.J);
 
+  // the first kMppiPer costs of each thread are loaded at once into
+  // registers (independent loads, one memory latency); beyond that (N above
+  // kMppiPer * kMppiBlock) they are read again from memory
+  T Jr[kMppiPer];
+#pragma unroll
+  for (int i = 0; i < kMppiPer; ++i) {
+    const int k = tid + i * kMppiBlock;
+    Jr[i] = (k < N) ? Jg[k] : inf_t<T>();
+  }
   T bv = inf_t<T>();
   int bk = 0x7fffffff;
-  for (int k = tid; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
+#pragma unroll
+  for (int i = 0; i < kMppiPer; ++i) argmin_combine(bv, bk, Jr[i], tid + i * kMppiBlock);
+  for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
   block_argmin(bv, bk, lds_v, lds_k);
   const bool skip = !finite_t(bv);
 
@@ -1206,8 +1237,8 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   double sw = 0.0, swf = 0.0, cnt = 0.0;
   if (!skip) {
     const T il = (T)d.inv_lambda;
-    for (int k = tid; k < N; k += kMppiBlock) {
-      const T wk = exp_t((bv - Jg[k]) * il);
+    auto visit = [&](int k, T Jk) {
+      const T wk = exp_t((bv - Jk) * il);
       if (wk != T(0)) {
         const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)k * 12);
         const float4 z0 = src[0], z1 = src[1], z2 = src[2];
@@ -1219,7 +1250,11 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 #pragma unroll
         for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
       }
-    }
+    };
+#pragma unroll
+    for (int i = 0; i < kMppiPer; ++i)
+      if (tid + i * kMppiBlock < N) visit(tid + i * kMppiBlock, Jr[i]);
+    for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) visit(k, Jg[k]);
   }
   // within a wave in the working precision (FP64 for the normaliser), then
   // FP64 across waves
@@ -1288,34 +1323,44 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 // ---------------------------------------------------------------------------
 // timing: 0 none; 1 two events around the rollout stage (ev[0], ev[1]);
 // 2 five events around the four stages (ev[0..4]).
+// One rollout launch; with e0 (and e1) the events take the kernel's own
+// start and end times (the dispatch carries them), so the measured duration
+// is the kernel's and not that of two separate event commands around it.
+template <typename K>
+static void launch_timed(K kernel, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, const LaunchTab &tab, const TickDesc &inl) {
+  if (e0) hipExtLaunchKernelGGL(kernel, g, b, (uint32_t)lds, s, e0, e1, 0, tab, inl);
+  else hipLaunchKernelGGL(kernel, g, b, lds, s, tab, inl);
+}
+
 template <bool INL, bool SPL>
 static hipError_t launch_rollout_form(const LaunchTab &tab, const TickDesc &inl, int precision,
-                                      size_t lds, hipStream_t s) {
+                                      size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 rg(tab.total_roll);
   if (precision == 1) {
-    hipLaunchKernelGGL((k_rollout<double, 64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl);
+    launch_timed(k_rollout<double, 64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl);
     return hipSuccess;
   }
   if (tab.lanes == 4) {
     switch (tab.roll_block * 4 + tab.unroll) {
-      case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl); break;
-      case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<128, 1, INL, SPL>), rg, dim3(128), lds, s, tab, inl); break;
-      case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout_quad<256, 1, INL, SPL>), rg, dim3(256), lds, s, tab, inl); break;
+      case 64 * 4 + 1: launch_timed(k_rollout_quad<64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
+      case 128 * 4 + 1: launch_timed(k_rollout_quad<128, 1, INL, SPL>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
+      case 256 * 4 + 1: launch_timed(k_rollout_quad<256, 1, INL, SPL>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
       default: return hipErrorInvalidValue;
     }
     return hipSuccess;
   }
   switch (tab.roll_block * 4 + tab.unroll) {
-    case 64 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 64, 1, INL, SPL>), rg, dim3(64), lds, s, tab, inl); break;
-    case 128 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 128, 1, INL, SPL>), rg, dim3(128), lds, s, tab, inl); break;
-    case 256 * 4 + 1: hipLaunchKernelGGL((k_rollout<float, 256, 1, INL, SPL>), rg, dim3(256), lds, s, tab, inl); break;
+    case 64 * 4 + 1: launch_timed(k_rollout<float, 64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
+    case 128 * 4 + 1: launch_timed(k_rollout<float, 128, 1, INL, SPL>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
+    case 256 * 4 + 1: launch_timed(k_rollout<float, 256, 1, INL, SPL>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
     case 64 * 4 + 2:
       if (SPL) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_rollout<float, 64, 2, INL, false>), rg, dim3(64), lds, s, tab, inl);
+      launch_timed(k_rollout<float, 64, 2, INL, false>, rg, dim3(64), lds, s, e0, e1, tab, inl);
       break;
     case 128 * 4 + 2:
       if (SPL) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_rollout<float, 128, 2, INL, false>), rg, dim3(128), lds, s, tab, inl);
+      launch_timed(k_rollout<float, 128, 2, INL, false>, rg, dim3(128), lds, s, e0, e1, tab, inl);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1324,9 +1369,9 @@ static hipError_t launch_rollout_form(const LaunchTab &tab, const TickDesc &inl,
 
 template <bool INL>
 static hipError_t launch_rollout(const LaunchTab &tab, const TickDesc &inl, int precision,
-                                 size_t lds, hipStream_t s) {
-  return tab.spline ? launch_rollout_form<INL, true>(tab, inl, precision, lds, s)
-                    : launch_rollout_form<INL, false>(tab, inl, precision, lds, s);
+                                 size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return tab.spline ? launch_rollout_form<INL, true>(tab, inl, precision, lds, s, e0, e1)
+                    : launch_rollout_form<INL, false>(tab, inl, precision, lds, s, e0, e1);
 }
 
 template <bool INL>
@@ -1340,10 +1385,13 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
   if (!tab.skip_noise)
     hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,
                        tab, inl);
-  if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 1 : 0], s);
-  hipError_t e = launch_rollout<INL>(tab, inl, precision, roll_lds, s);
+  // mode 1: the rollout kernel's own start and end; mode 2: event commands
+  // between all stages
+  if (timing == 2) (void)hipEventRecord(ev[1], s);
+  hipError_t e = launch_rollout<INL>(tab, inl, precision, roll_lds, s,
+                                     timing == 1 ? ev[0] : nullptr, timing == 1 ? ev[1] : nullptr);
   if (e != hipSuccess) return e;
-  if (timing >= 1) (void)hipEventRecord(ev[timing == 2 ? 2 : 1], s);
+  if (timing == 2) (void)hipEventRecord(ev[2], s);
   // elite / best-sample controllers: selection, then the update; MPPI
   // controllers: the fused update alone (each kernel skips the others' items)
   const dim3 ug(tab.total_upd);

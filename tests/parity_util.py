@@ -102,11 +102,24 @@ def run_pair(rt, cfg, inp, tick=None, mu=None, mu_f=None, nthreads=8):
             "tick_next": tk}, ref
 
 
-def check_fp64(out, ref, cfg, rel=1e-10):
+def check_fp64(out, ref, cfg, rel=1e-10, influential_only=False):
+    """FP64 parity.  With influential_only, the per-sample costs are compared
+    only where the sample can influence the update (MPPI weight above
+    exp(-RELEVANT), or cost within twice the elite threshold): a rollout that
+    tumbles amplifies last-bit differences past any fixed bar and carries no
+    weight; the mean and the action are compared in full either way."""
     R, N = ref["costs"].shape
     np.testing.assert_array_equal(out["q"], ref["q_samples"])
     Jr = ref["costs"]
-    np.testing.assert_allclose(out["J"], Jr, rtol=rel, atol=0)
+    if influential_only:
+        for r in range(R):
+            if cfg.get("method", "mppi") == "mppi":
+                m = Jr[r] <= Jr[r].min() + RELEVANT * cfg.get("lambda", 1.0)
+            else:
+                m = Jr[r] <= 2.0 * np.sort(Jr[r])[oracle.elite_count(N, cfg.get("elite_frac", 0.1)) - 1]
+            np.testing.assert_allclose(out["J"][r][m], Jr[r][m], rtol=rel, atol=0)
+    else:
+        np.testing.assert_allclose(out["J"], Jr, rtol=rel, atol=0)
     scale = max(np.abs(ref["mean"]).max(), MG2)
     assert np.abs(out["mean"] - ref["mean"]).max() <= rel * scale
     assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= rel * scale

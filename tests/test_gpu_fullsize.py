@@ -31,15 +31,18 @@ def sampled_costs(cfg, inp, mu, tick, r, ks, q):
     return np.array(out)
 
 
-def check_sampled(Jg, Jr, ks, amp):
-    """Well-conditioned samples (cost amplification of input perturbations
-    <= 100, see parity_util.conditioning) agree within the FP32 cost
-    tolerance, the typical one to 1e-5 relative; most sampled rollouts at
-    H = 50 tumble, and those cannot agree across precisions."""
+def check_sampled(Jg, Jr, ks, amp, band):
+    """Sampled costs within `band` of the lowest sampled cost (the ones that
+    can carry weight) and well-conditioned (cost amplification of input
+    perturbations <= 100, see parity_util.conditioning) agree within the
+    FP32 cost tolerance; across all well-conditioned samples the typical one
+    agrees to 1e-5 relative.  Most sampled rollouts at H = 50 tumble, and
+    those cannot agree across precisions."""
     Jg = np.asarray(Jg, np.float64)[ks]
     well = (amp <= 100.0) & np.isfinite(Jr)
     assert well.sum() >= 10
-    assert np.all(np.abs(Jg[well] - Jr[well]) <= cost_tol(Jr[well]))
+    near = well & (Jr <= np.min(Jr) + band)
+    assert np.all(np.abs(Jg[near] - Jr[near]) <= cost_tol(Jr[near]))
     rel = np.abs(Jg[well] - Jr[well]) / np.maximum(np.abs(Jr[well]), 1.0)
     assert np.median(rel) <= 1e-5
 
@@ -63,7 +66,7 @@ def test_c1_full_size_bench_configuration():
     ks = np.unique(np.concatenate([np.arange(0, N, 97), [best, N - 1]]))
     Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
     amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, q[0])
-    check_sampled(J[0], Jr, ks, amp)
+    check_sampled(J[0], Jr, ks, amp, band=60.0 * cfg["lambda"])
     # the best sample carries the weight: it must be well-conditioned and match
     ib = int(np.flatnonzero(ks == best)[0])
     assert amp[ib] <= 100.0 and abs(J[0][best] - Jr[ib]) <= cost_tol(Jr[ib])
@@ -95,7 +98,8 @@ def test_c2_full_size_elite():
     ks = np.arange(0, N, 211)
     Jr = sampled_costs(cfg, inp, hover(cfg), 0, 0, ks, q[0])
     amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, q[0])
-    check_sampled(J[0], Jr, ks, amp)
+    thr = np.sort(J[0])[oracle.elite_count(N, cfg["elite_frac"]) - 1]
+    check_sampled(J[0], Jr, ks, amp, band=thr - J[0].min())
     ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
     np.testing.assert_array_equal(q, ref["q_samples"])  # every iteration's draws
     scale = max(np.abs(ref["mean"]).max(), MG2)
