@@ -72,14 +72,14 @@ def stored_traffic(kernel: str, workload: str):
 
 
 def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=40.0,
-                prefetch=True):
+                prefetch=True, v_ref=(0.3, 0.0, 0.0)):
     cid = rt.init_controller(cfg)
     if prefetch:
         rt.set_prefetch(cid, True)
     rng = np.random.default_rng(cfg["seed"])
     x0 = workloads.initial_state(rng)
     plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
-    loop = binding.ClosedLoop(rt, cid, plant, v_ref=(0.3, 0.0, 0.0), z_ref=workloads.HEIGHT)
+    loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
     lat, acts = [], []
     t_start = None
     import torch
@@ -210,14 +210,16 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1,
-                    help="HIP events: 0 none, 1 around the rollout stage, 2 around every stage")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "copy"],
-                    help="c1 closed-loop single MPPI (default); c3 batched uneven "
+                    help="HIP events: 0 none, 1 the rollout kernel's own dispatch events on "
+                         "one tick in 16, 2 event commands around every stage of every tick")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy"],
+                    help="c1 closed-loop single MPPI (default); c2 closed-loop elite "
+                         "sampler (N=16384, H=50, 3 iterations); c3 batched uneven "
                          "controllers; c4 serving 256 robots vs plain single MPPI; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
@@ -239,11 +241,13 @@ def main():
 
     from paper_2403_11383_amd import binding, workloads
     import torch
-    cfg = workloads.config("c1", knots=args.knots)
+    c2 = args.workload == "c2"
+    cfg = workloads.config(args.workload, knots=args.knots)
     rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)), two_streams=True)
     rt.set_timing(args.timing)
-    elapsed, lat, acts, timing, plant = closed_loop(rt, binding, workloads, cfg, args.steps,
-                                                    args.warmup, prefetch=not args.no_prefetch)
+    elapsed, lat, acts, timing, plant = closed_loop(
+        rt, binding, workloads, cfg, args.steps, args.warmup, prefetch=not args.no_prefetch,
+        push=0.0 if c2 else 40.0, v_ref=workloads.c2_episode_vref() if c2 else (0.3, 0.0, 0.0))
     rt.close()
     N, H, R = cfg["N"], cfg["H"], cfg["iterations"]
     steps_total = N * H * R * args.steps
@@ -254,15 +258,20 @@ def main():
         N * (H * FLOP_PER_SPLINE_STEP + P * FLOP_PER_SPLINE_KNOT)
     achieved = flop / t_roll / 1e12 if t_roll > 0 else 0.0
     spline_txt = f", GRF spline through {P} knots" if P else ""
-    workload_key = "c1" if P == 0 else f"c1_knots{P}"
+    workload_key = args.workload if P == 0 else f"{args.workload}_knots{P}"
+    if c2:
+        desc = ("c2: closed-loop elite sampler, top 10% of N=16384, H=50, 3 iterations per "
+                "tick, Gaussian gait frequency 1.4 +- 0.4 Hz, reference velocity "
+                f"{workloads.c2_episode_vref()[0]:+.3f} m/s")
+    else:
+        desc = ("c1: closed-loop MPPI, gait frequency ~U[1.0,2.5] Hz per sample, "
+                "N=10240, H=50, dt=0.02 s, 40 N lateral push from tick 30")
     line = {
         "metric": METRIC, "value": value, "unit": "rollout-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "c1: closed-loop MPPI, gait frequency ~U[1.0,2.5] Hz per sample, "
-                               "N=10240, H=50, dt=0.02 s, 40 N lateral push from tick 30"
-                               + spline_txt,
+        "config": {"workload": desc + spline_txt,
                    "N": N, "H": H, "iterations": R, "knots": P, "ticks": args.steps,
                    "noise_prefetch": not args.no_prefetch},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": float(np.max(lat))},
@@ -271,6 +280,7 @@ def main():
         # the automatic lane policy runs one controller of up to 32768
         # samples with four lanes per sample
         "roofline": {"kernel": "k_rollout_quad" if N <= 32768 else "k_rollout<float>",
+                     "launches_per_tick": R,
                      "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,

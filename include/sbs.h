@@ -224,10 +224,13 @@ int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *adm
  * two forms agree within FP32 rounding, not bit for bit. */
 int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
 
-/* Kernel timing with HIP events on the runtime stream: mode 0 off, 1 events
- * around the rollout stage only, 2 around every stage.  sbs_timing returns
- * the average device time [ns] of each stage's launches since the last call
- * (0 noise, 1 rollout, 2 select, 3 update) and resets it. */
+/* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
+ * rollout kernel's own start and end (events carried by its dispatch) on
+ * one launch in 16, counted from this call; 2 event commands between every
+ * stage of every launch (diagnostic: each adds a few microseconds).
+ * sbs_timing returns the average device time [ns] of each stage's timed
+ * launches since the last call (0 noise, 1 rollout, 2 select, 3 update) and
+ * resets it. */
 int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
 

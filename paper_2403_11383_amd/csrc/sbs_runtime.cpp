@@ -321,7 +321,8 @@ struct sbs_runtime {
   std::atomic<bool> stop{false};
   uint64_t n_ticks = 0, n_batches = 0, n_admit_waits = 0;
   // timing
-  int timing = 0;  // 0 off, 1 rollout stage, 2 all stages
+  int timing = 0;  // 0 off, 1 rollout kernel (sampled launches), 2 all stages
+  uint64_t timing_seq = 0;  // launches seen in mode 1
   Tune tune;  // default rollout form of direct and serving launches
   double stage_ns[4] = {0, 0, 0, 0};
   uint64_t stage_n[4] = {0, 0, 0, 0};
@@ -587,6 +588,15 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
   return out;
 }
 
+// Timing mode of the next launch: mode 1 attaches the rollout's dispatch
+// events to one launch in kTimingStride (attaching them costs the tick about
+// as much as the kernel's own launch), mode 2 every launch.
+constexpr uint64_t kTimingStride = 16;
+int timing_mode_now(sbs_runtime *rt) {
+  if (rt->timing != 1) return rt->timing;
+  return (rt->timing_seq++ % kTimingStride) == 0 ? 1 : 0;
+}
+
 void record_timing(sbs_runtime *rt, Batch &b) {
   // mode 2: groups of 5 events around the 4 stages; mode 1: pairs around the
   // rollout stage
@@ -712,16 +722,17 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     }
   }
   const int64_t t_launch = now_ns();
+  const int tmode = timing_mode_now(rt);
   for (auto &tp : tabs) {
     if (e != hipSuccess) break;
     hipEvent_t *ev = nullptr;
-    if (rt->timing) {
+    if (tmode) {
       size_t base = b->timing.size();
-      const int ne = rt->timing == 2 ? 5 : 2;
+      const int ne = tmode == 2 ? 5 : 2;
       for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
       ev = &b->timing[base];
     }
-    e = launch_iteration(tp.first, tp.second, s, rt->timing, ev, inl);
+    e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl);
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
   if (pc && e == hipSuccess) {
@@ -1399,6 +1410,7 @@ int sbs_set_timing(sbs_runtime *rt, int32_t mode) {
   std::lock_guard<std::mutex> lk(rt->mu);
   reap(rt);
   rt->timing = mode;
+  rt->timing_seq = 0;
   return SBS_OK;
 }
 
@@ -1692,16 +1704,17 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     e = hipGraphLaunch(P.exec, s);
   } else {
     e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
+    const int tmode = timing_mode_now(rt);
     for (auto &tp : tabs) {
       if (e != hipSuccess) break;
       hipEvent_t *ev = nullptr;
-      if (rt->timing) {
+      if (tmode) {
         size_t base = b->timing.size();
-        const int ne = rt->timing == 2 ? 5 : 2;
+        const int ne = tmode == 2 ? 5 : 2;
         for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
         ev = &b->timing[base];
       }
-      e = launch_iteration(tp.first, tp.second, s, rt->timing, ev, nullptr);
+      e = launch_iteration(tp.first, tp.second, s, tmode, ev, nullptr);
     }
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);

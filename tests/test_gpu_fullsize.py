@@ -34,12 +34,12 @@ def sampled_costs(cfg, inp, mu, tick, r, ks, q):
 def check_sampled(Jg, Jr, ks, amp, band):
     """Sampled costs within `band` of the lowest sampled cost (the ones that
     can carry weight) and well-conditioned (cost amplification of input
-    perturbations <= 100, see parity_util.conditioning) agree within the
+    perturbations <= 20, see parity_util.conditioning) agree within the
     FP32 cost tolerance; across all well-conditioned samples the typical one
     agrees to 1e-5 relative.  Most sampled rollouts at H = 50 tumble, and
     those cannot agree across precisions."""
     Jg = np.asarray(Jg, np.float64)[ks]
-    well = (amp <= 100.0) & np.isfinite(Jr)
+    well = (amp <= 20.0) & np.isfinite(Jr)
     assert well.sum() >= 10
     near = well & (Jr <= np.min(Jr) + band)
     assert np.all(np.abs(Jg[near] - Jr[near]) <= cost_tol(Jr[near]))
@@ -69,7 +69,7 @@ def test_c1_full_size_bench_configuration():
     check_sampled(J[0], Jr, ks, amp, band=60.0 * cfg["lambda"])
     # the best sample carries the weight: it must be well-conditioned and match
     ib = int(np.flatnonzero(ks == best)[0])
-    assert amp[ib] <= 100.0 and abs(J[0][best] - Jr[ib]) <= cost_tol(Jr[ib])
+    assert amp[ib] <= 50.0 and abs(J[0][best] - Jr[ib]) <= cost_tol(Jr[ib])
     # the update on the GPU's own costs
     ref = oracle.tick(cfg, hover(cfg), cfg["mu_f0"], 0, inp, costs_override=J, nthreads=8)
     scale = max(np.abs(ref["grf"]).max(), MG2)

@@ -109,7 +109,10 @@ def test_spline_fp32_elite(rt, lanes):
     # elite influence reaches up to the K_e-th cost, so judge conditioning
     ks = np.arange(cfg["N"])
     amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, ref["q_samples"][0])
-    well = amp <= 100.0
+    # FP32 rounds every step's arithmetic (~6e-8): a sample whose cost
+    # amplifies input perturbations A-fold over H steps can move by up to
+    # ~H A 6e-8; A <= 20 keeps that below the 1e-4 cost tolerance
+    well = amp <= 20.0
     assert well.sum() >= 300
     check_costs_fp32(out["J"][0], ref["costs"][0], elite_ke=oracle.elite_count(3000, 0.1),
                      well=well)
