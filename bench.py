@@ -72,24 +72,31 @@ def stored_traffic(kernel: str, workload: str):
 
 
 def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=40.0,
-                prefetch=True, v_ref=(0.3, 0.0, 0.0)):
+                prefetch=True, v_ref=(0.3, 0.0, 0.0), episode=100):
+    """Receding-horizon episodes of `episode` ticks (the workload's 100): each
+    starts the plant from the seeded initial state (the controller keeps its
+    warm start and tick counter); the push acts from tick `push_from` of each
+    episode.  The first `warmup` ticks are untimed."""
     cid = rt.init_controller(cfg)
     if prefetch:
         rt.set_prefetch(cid, True)
     rng = np.random.default_rng(cfg["seed"])
     x0 = workloads.initial_state(rng)
-    plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
-    loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
     lat, acts = [], []
     t_start = None
     import torch
     no_push, push_f = (0.0, 0.0, 0.0), (0.0, push, 0.0)
+    loop = None
     for t in range(warmup + ticks):
+        e = (t - warmup) % episode if t >= warmup else t
+        if t == warmup or e == 0:
+            plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
+            loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
         if t == warmup:
             torch.cuda.synchronize()
             rt.timing()  # reset the stage-timing accumulators
             t_start = time.perf_counter()
-        a = loop.step(push_f if t >= push_from else no_push)
+        a = loop.step(push_f if e >= push_from else no_push)
         if t >= warmup:
             # submit-to-visible latency as recorded by the runtime
             lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
@@ -98,7 +105,7 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     elapsed = time.perf_counter() - t_start
     timing = rt.timing()
     rt.destroy_controller(cid)
-    return elapsed, lat, acts, timing, plant
+    return elapsed, lat, acts, timing, loop.plant
 
 
 def cpu_baseline(cfg, seconds=10.0):
@@ -210,7 +217,8 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="timed ticks (c1/c2: episodes of 100 ticks from the seeded start)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -105,8 +105,26 @@ __device__ __forceinline__ uint32_t freq_gaussian(double mf, double sf, float z,
   return q_of_freq(f, dt);
 }
 
+// Item of flattened block b: the largest i < n with start[i] <= b, start
+// being a stage's non-decreasing block prefix sums (n + 1 entries).  Every
+// lane of the wave tests one boundary and a ballot counts those <= b: one
+// memory round trip for n < 64, two (coarse, then fine) up to 4032 items, a
+// binary search inside the coarse segment beyond.  Called by whole waves.
 __device__ __forceinline__ int find_item(const int32_t *start, int n, int b) {
-  int lo = 0, hi = n;
+  const int lane = threadIdx.x & 63;
+  if (n < 64) {
+    const bool le = lane <= n && start[lane] <= b;
+    return (int)__popcll(__ballot(le)) - 1;
+  }
+  const int step = (n + 64) / 64;  // 64 coarse boundaries cover all n + 1
+  const int i0 = lane * step;
+  const int c = (int)__popcll(__ballot(i0 <= n && start[i0] <= b)) - 1;
+  const int base = c * step;
+  if (step <= 64) {
+    const int i1 = base + lane;
+    return base + (int)__popcll(__ballot(lane < step && i1 <= n && start[i1] <= b)) - 1;
+  }
+  int lo = base, hi = base + step < n ? base + step : n;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (start[mid] <= b) lo = mid;
@@ -115,9 +133,6 @@ __device__ __forceinline__ int find_item(const int32_t *start, int n, int b) {
   return lo;
 }
 
-// A launch either carries one controller's descriptor by value (INL, the
-// latency path of a single controller: no descriptor copy) or indexes the
-// batch's descriptor array through the stage's block map.
 // The descriptor of a single-controller launch, read in place from the
 // kernel-argument segment, where it follows the LaunchTab argument (explicit
 // arguments are laid out in order at their natural alignment).  Naming the
@@ -131,6 +146,9 @@ __device__ __forceinline__ const TickDesc &inline_desc() {
   return *reinterpret_cast<const TickDesc *>(seg + kOff);
 }
 
+// A launch either carries one controller's descriptor by value (INL, the
+// latency path of a single controller: no descriptor copy) or indexes the
+// batch's descriptor array through the stage's block map.
 template <bool INL>
 __device__ __forceinline__ int stage_item(const int32_t *start, int n, int b) {
   return INL ? 0 : find_item(start, n, b);
@@ -819,6 +837,21 @@ __device__ void block_argmin(T &v, int &k, T *lv, int *lk) {
   for (int i = 1; i < nw; ++i) argmin_combine(v, k, lv[i], lk[i]);
 }
 
+__device__ uint64_t block_max_u64(uint64_t v, uint64_t *lds) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  uint64_t r = lds[0];
+  for (int i = 1; i < nw; ++i) r = lds[i] > r ? lds[i] : r;
+  return r;
+}
+
 __device__ __forceinline__ uint64_t key_bits(float v) { return (uint64_t)__float_as_uint(v); }
 __device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
 
@@ -874,6 +907,7 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   __shared__ T lds_v[kSelBlock / 64];
   __shared__ int lds_k[kSelBlock / 64];
   __shared__ uint32_t hist[256];
+  __shared__ uint64_t lds_u64[kSelBlock / 64];
   __shared__ uint32_t s_digit, s_rank;
   __shared__ uint32_t wave_tot[kSelBlock / 64];
 
@@ -927,16 +961,30 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
     fnew = (double)d.q[bk] * d.inv_q_scale;
     mf_next = fnew;
   } else {  // elite: the K_e smallest (cost, index) by radix selection
+    // Costs are >= 0 or +inf, so their bit patterns order like the values and
+    // every key shares the bits above the highest bit in which the lowest and
+    // the highest key differ: the digits start there (up to 8 bits each), so
+    // no pass is spent on a digit every key shares (whose histogram would
+    // also pile every atomic onto one bin).
     const int nbits = (int)sizeof(T) * 8;
-    uint64_t prefix = 0, mask = 0;
+    uint64_t kmax = 0;
+    SEL_FOR(kmax = key_bits(cv) > kmax ? key_bits(cv) : kmax;)
+    kmax = block_max_u64(kmax, lds_u64);
+    const uint64_t kmin = key_bits(bv);
+    const uint64_t all = nbits == 64 ? ~0ull : ((1ull << nbits) - 1ull);
+    int hi = (kmin == kmax) ? -1 : 63 - __builtin_clzll(kmin ^ kmax);
+    const uint64_t below = hi < 0 ? 0ull : (hi >= 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull));
+    uint64_t mask = all & ~below, prefix = kmin & mask;
     uint32_t rank = (uint32_t)d.Ke;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int shift = nbits - 8; shift >= 0; shift -= 8) {
+    while (hi >= 0) {
+      const int lo = hi >= 7 ? hi - 7 : 0;
+      const uint64_t dmask = (1ull << (hi - lo + 1)) - 1ull;
       for (int i = tid; i < 256; i += kSelBlock) hist[i] = 0u;
       __syncthreads();
       SEL_FOR(
         const uint64_t key = key_bits(cv);
-        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);)
+        if ((key & mask) == prefix) atomicAdd(&hist[(key >> lo) & dmask], 1u);)
       __syncthreads();
       if (wid == 0) {  // first digit whose cumulative count reaches rank
         const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
@@ -956,9 +1004,10 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
         }
       }
       __syncthreads();
-      prefix |= (uint64_t)s_digit << shift;
-      mask |= (uint64_t)255u << shift;
+      prefix |= (uint64_t)s_digit << lo;
+      mask |= dmask << lo;
       rank = s_rank;
+      hi = lo - 1;
       __syncthreads();
     }
     // prefix is the K_e-th smallest cost; the first `rank` ties by index are in
