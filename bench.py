@@ -76,7 +76,9 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     """Receding-horizon episodes of `episode` ticks (the workload's 100): each
     starts the plant from the seeded initial state (the controller keeps its
     warm start and tick counter); the push acts from tick `push_from` of each
-    episode.  The first `warmup` ticks are untimed."""
+    episode.  An episode also ends when the robot falls (roll or pitch beyond
+    1.5 rad, CoM height outside [0.05, 1] m, or a non-finite state).  The
+    first `warmup` ticks are untimed."""
     cid = rt.init_controller(cfg)
     if prefetch:
         rt.set_prefetch(cid, True)
@@ -87,9 +89,11 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     import torch
     no_push, push_f = (0.0, 0.0, 0.0), (0.0, push, 0.0)
     loop = None
+    e, falls = 0, 0
     for t in range(warmup + ticks):
-        e = (t - warmup) % episode if t >= warmup else t
-        if t == warmup or e == 0:
+        if t == warmup or e == episode:
+            e = 0
+        if e == 0:
             plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
             loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
         if t == warmup:
@@ -97,6 +101,11 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
             rt.timing()  # reset the stage-timing accumulators
             t_start = time.perf_counter()
         a = loop.step(push_f if e >= push_from else no_push)
+        e += 1
+        x = loop.plant.st.x
+        if not (abs(x[3]) < 1.5 and abs(x[4]) < 1.5 and 0.05 < x[2] < 1.0):  # NaN fails too
+            e = 0
+            falls += 1 if t >= warmup else 0
         if t >= warmup:
             # submit-to-visible latency as recorded by the runtime
             lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
@@ -105,7 +114,7 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     elapsed = time.perf_counter() - t_start
     timing = rt.timing()
     rt.destroy_controller(cid)
-    return elapsed, lat, acts, timing, loop.plant
+    return elapsed, lat, acts, timing, (loop.plant, falls)
 
 
 def cpu_baseline(cfg, seconds=10.0):
@@ -296,7 +305,8 @@ def main():
                      "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
                      "traffic": stored_traffic("k_rollout", workload_key),
                      "flop_per_launch": flop},
-        "closed_loop": {"final_x": [round(float(v), 4) for v in plant.x],
+        "closed_loop": {"episodes_ended_by_falls": plant[1],
+                        "final_x": [round(float(v), 4) for v in plant[0].x],
                         "nonfinite_ticks": int(sum(a[0] & 1 for a in acts)),
                         "freq_hz_last": acts[-1][1],
                         "active_samples_median": float(np.median([a[2] for a in acts]))},

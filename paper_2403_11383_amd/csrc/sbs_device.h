@@ -114,6 +114,8 @@ struct LaunchTab {
   int32_t n_select;      // items with an elite or best-sample update
   int32_t max_rows;      // most mean rows among the items
   int32_t spline;        // the items use the spline parametrisation
+  int32_t noise_rpt;     // noise rows per thread (single-controller launches; 0 = 1)
+  int32_t pad2;
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

@@ -193,30 +193,37 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[i]];
   const int local = b - stage_start<INL>(tab.noise_start, i);
   const int nkb = (d.N + kNoiseBlock - 1) / kNoiseBlock;
-  const int j = local / nkb;
-  const int k = (local - j * nkb) * kNoiseBlock + (int)threadIdx.x;
+  const int jb = local / nkb;
+  const int k = (local - jb * nkb) * kNoiseBlock + (int)threadIdx.x;
   if (k >= d.N) return;
   const int r = tab.r + rr;
   const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
   const uint32_t rw = (uint32_t)r << 8;
-  float z[12];
-#pragma unroll
-  for (uint32_t call = 0; call < 3; ++call) {
-    uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = d.tick, c3 = rw | call;
-    philox4x32_10(c0, c1, c2, c3, key0, key1);
-    const float2 ga = gauss_pair(c0, c1);
-    const float2 gb = gauss_pair(c2, c3);
-    z[4 * call + 0] = ga.x;
-    z[4 * call + 1] = ga.y;
-    z[4 * call + 2] = gb.x;
-    z[4 * call + 3] = gb.y;
-  }
   float *zr = d.z + (size_t)r * d.z_iter_stride;
-  float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * d.N + k) * 12);
-  dst[0] = make_float4(z[0], z[1], z[2], z[3]);
-  dst[1] = make_float4(z[4], z[5], z[6], z[7]);
-  dst[2] = make_float4(z[8], z[9], z[10], z[11]);
-  if (tab.write_q && j == 0) d.q[k] = draw_q(d, r, k);
+  // rows jb * rpt .. jb * rpt + rpt - 1 of sample k (rpt = 1 in batched
+  // launches; a single controller's ahead-of-time noise uses fewer, longer
+  // waves so that it leaves more of the chip to the tick in flight)
+  const int rpt = tab.noise_rpt > 1 ? tab.noise_rpt : 1;
+  const int j0 = jb * rpt, j1 = j0 + rpt < d.M ? j0 + rpt : d.M;
+  for (int j = j0; j < j1; ++j) {
+    float z[12];
+#pragma unroll
+    for (uint32_t call = 0; call < 3; ++call) {
+      uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = d.tick, c3 = rw | call;
+      philox4x32_10(c0, c1, c2, c3, key0, key1);
+      const float2 ga = gauss_pair(c0, c1);
+      const float2 gb = gauss_pair(c2, c3);
+      z[4 * call + 0] = ga.x;
+      z[4 * call + 1] = ga.y;
+      z[4 * call + 2] = gb.x;
+      z[4 * call + 3] = gb.y;
+    }
+    float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * d.N + k) * 12);
+    dst[0] = make_float4(z[0], z[1], z[2], z[3]);
+    dst[1] = make_float4(z[4], z[5], z[6], z[7]);
+    dst[2] = make_float4(z[8], z[9], z[10], z[11]);
+  }
+  if (tab.write_q && j0 == 0) d.q[k] = draw_q(d, r, k);
 }
 
 // ---------------------------------------------------------------------------

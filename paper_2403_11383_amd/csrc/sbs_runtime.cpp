@@ -65,6 +65,8 @@ int64_t now_ns() {
 constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
+// noise rows per thread of a single controller's ahead-of-time noise
+constexpr int kPrefetchRows = 1;
 
 // Rollout form: lanes per sample (0 = automatic), workgroup size, step-loop
 // unroll.  Only the forms the kernel dispatcher instantiates are valid.
@@ -750,6 +752,10 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     nt.r_count = pc->cfg.iterations;
     nt.skip_noise = 0;
     nt.write_q = 0;
+    // fewer, longer noise waves: each thread makes kPrefetchRows rows
+    const int rows = rows_of(pc->cfg), nkb = (pc->cfg.N + kNoiseBlock - 1) / kNoiseBlock;
+    nt.noise_rpt = kPrefetchRows;
+    nt.total_noise = ((rows + kPrefetchRows - 1) / kPrefetchRows) * nkb;
     if (e == hipSuccess) e = hipStreamWaitEvent(s2, pc->pf_free[nb], 0);
     if (e == hipSuccess) e = launch_noise_only(nt, s2, &nd);
     if (e == hipSuccess) e = hipEventRecord(pc->pf_ready[nb], s2);
