@@ -859,8 +859,12 @@ __device__ uint64_t block_max_u64(uint64_t v, uint64_t *lds) {
   return r;
 }
 
-__device__ __forceinline__ uint64_t key_bits(float v) { return (uint64_t)__float_as_uint(v); }
+// Ordering keys of costs (>= 0 or +inf): the bit patterns, in the width of
+// the working precision.
+__device__ __forceinline__ uint32_t key_bits(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ int top_bit(uint32_t v) { return 31 - __builtin_clz(v); }
+__device__ __forceinline__ int top_bit(uint64_t v) { return 63 - __builtin_clzll(v); }
 
 // ---------------------------------------------------------------------------
 // Select (elite and best-sample updates): one workgroup per controller.
@@ -973,25 +977,24 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
     // the highest key differ: the digits start there (up to 8 bits each), so
     // no pass is spent on a digit every key shares (whose histogram would
     // also pile every atomic onto one bin).
-    const int nbits = (int)sizeof(T) * 8;
-    uint64_t kmax = 0;
+    using K = decltype(key_bits(T(0)));
+    K kmax = 0;
     SEL_FOR(kmax = key_bits(cv) > kmax ? key_bits(cv) : kmax;)
-    kmax = block_max_u64(kmax, lds_u64);
-    const uint64_t kmin = key_bits(bv);
-    const uint64_t all = nbits == 64 ? ~0ull : ((1ull << nbits) - 1ull);
-    int hi = (kmin == kmax) ? -1 : 63 - __builtin_clzll(kmin ^ kmax);
-    const uint64_t below = hi < 0 ? 0ull : (hi >= 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull));
-    uint64_t mask = all & ~below, prefix = kmin & mask;
+    kmax = (K)block_max_u64((uint64_t)kmax, lds_u64);
+    const K kmin = key_bits(bv);
+    int hi = (kmin == kmax) ? -1 : top_bit((K)(kmin ^ kmax));
+    const K below = hi < 0 ? K(0) : (K)((K(2) << hi) - K(1));  // bits 0..hi (wraps to all)
+    K mask = (K)~below, prefix = (K)(kmin & mask);
     uint32_t rank = (uint32_t)d.Ke;
     const int lane = tid & 63, wid = tid >> 6;
     while (hi >= 0) {
       const int lo = hi >= 7 ? hi - 7 : 0;
-      const uint64_t dmask = (1ull << (hi - lo + 1)) - 1ull;
+      const K dmask = (K)((K(1) << (hi - lo + 1)) - K(1));
       for (int i = tid; i < 256; i += kSelBlock) hist[i] = 0u;
       __syncthreads();
       SEL_FOR(
-        const uint64_t key = key_bits(cv);
-        if ((key & mask) == prefix) atomicAdd(&hist[(key >> lo) & dmask], 1u);)
+        const K key = key_bits(cv);
+        if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)((key >> lo) & dmask)], 1u);)
       __syncthreads();
       if (wid == 0) {  // first digit whose cumulative count reaches rank
         const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
@@ -1011,21 +1014,21 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
         }
       }
       __syncthreads();
-      prefix |= (uint64_t)s_digit << lo;
-      mask |= dmask << lo;
+      prefix |= (K)((K)s_digit << lo);
+      mask |= (K)(dmask << lo);
       rank = s_rank;
       hi = lo - 1;
       __syncthreads();
     }
     // prefix is the K_e-th smallest cost; the first `rank` ties by index are in
-    const uint64_t thr = prefix;
+    const K thr = prefix;
     const uint32_t need = rank;
     uint32_t ntie = 0, nel = 0;
     SEL_FOR(ntie += (key_bits(cv) == thr) ? 1u : 0u;)
     uint32_t tot;
     uint32_t tb = block_excl_scan(ntie, wave_tot, &tot);  // ties before this thread
     SEL_FOR(
-      const uint64_t key = key_bits(cv);
+      const K key = key_bits(cv);
       bool el = key < thr;
       if (key == thr) {
         el = tb < need;
@@ -1036,7 +1039,7 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
     tb -= ntie;
     double s1 = 0.0, s2 = 0.0;
     SEL_FOR(
-      const uint64_t key = key_bits(cv);
+      const K key = key_bits(cv);
       bool el = key < thr;
       if (key == thr) {
         el = tb < need;
