@@ -322,8 +322,9 @@ def main_c3(args):
     cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     elapsed, lat, work, tune, cfgs = batched(rt, binding, workloads, args.steps, args.warmup, cache)
-    # rollout-kernel timing from a separate pass without the graph
-    rt.set_timing(1)
+    # rollout-kernel timing from a separate pass without the graph: the
+    # rollout's own dispatch events on every launch (timing mode 3)
+    rt.set_timing(3)
     ids = [rt.init_controller(c) for c in cfgs]
     inps = workloads.c3_inputs()
     plan = rt.plan_create(ids, use_graph=False)

@@ -227,7 +227,8 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
 /* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
  * rollout kernel's own start and end (events carried by its dispatch) on
  * one launch in 16, counted from this call; 2 event commands between every
- * stage of every launch (diagnostic: each adds a few microseconds).
+ * stage of every launch (diagnostic: each adds a few microseconds); 3 as 1
+ * on every launch.
  * sbs_timing returns the average device time [ns] of each stage's timed
  * launches since the last call (0 noise, 1 rollout, 2 select, 3 update) and
  * resets it. */

@@ -378,7 +378,8 @@ class Runtime:
         return {"ticks": a.value, "batches": b.value, "admit_waits": c.value}
 
     def set_timing(self, mode: int = 1):
-        """0 off, 1 events around the rollout stage, 2 around every stage."""
+        """0 off; 1 the rollout kernel's own dispatch events on one launch in
+        16; 2 event commands around every stage; 3 as 1 on every launch."""
         _check(lib().sbs_set_timing(self._h, int(mode)))
 
     def set_prefetch(self, cid: int, on: bool = True):

@@ -794,13 +794,68 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup reductions (wave64 shuffles, then LDS across waves)
+// Workgroup reductions (wave64 DPP adds, then LDS across waves)
 // ---------------------------------------------------------------------------
+// Uniform value of lane l (a scalar read, no LDS traffic).
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// v moved by the DPP control CTRL; lanes outside the row/bank masks, and
+// lanes whose source lies outside their row, read zero.
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ float dpp_z(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_z(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, RM, BM, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, RM, BM, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes, in every lane.  Within each row of 16 lanes, lane i
+// gathers x[i-3..i] (row shifts 1, 2, 3), then the partial sums of lanes
+// i-4 and i-8 (banks 1-3, then 2-3), so lane 15 of a row holds the row's
+// sum; row broadcasts add row 0 into row 1 and row 2 into row 3 (lane 15),
+// then lane 31 into rows 2 and 3: lane 63 holds the total, read as a
+// scalar.  A fixed tree, so the result is deterministic.
 template <typename V>
-__device__ __forceinline__ V wave_sum(V v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+__device__ __forceinline__ V wave_sum(V x) {
+  V v = x + dpp_z<0x111, 0xF, 0xF>(x);   // row_shr:1
+  v = v + dpp_z<0x112, 0xF, 0xF>(x);     // row_shr:2 (of x)
+  v = v + dpp_z<0x113, 0xF, 0xF>(x);     // row_shr:3 (of x)
+  v = v + dpp_z<0x114, 0xF, 0xE>(v);     // row_shr:4, banks 1-3
+  v = v + dpp_z<0x118, 0xF, 0xC>(v);     // row_shr:8, banks 2-3
+  v = v + dpp_z<0x142, 0xA, 0xF>(v);     // row_bcast:15, rows 1 and 3
+  v = v + dpp_z<0x143, 0xC, 0xF>(v);     // row_bcast:31, rows 2 and 3
+  return read_lane(v, 63);
+}
+
+// Wave sum of v where only the lanes in `mask` (a ballot, uniform) may be
+// non-zero: none -> 0, up to 8 lanes -> their values added in lane order
+// through scalar reads, else the shuffle tree.  Deterministic: the path
+// depends on the data alone.
+template <typename V>
+__device__ __forceinline__ V wave_sum_sparse(V v, uint64_t mask) {
+  if (mask == 0) return V(0);
+  if (__popcll(mask) <= 8) {
+    V acc = V(0);
+    while (mask) {
+      const int l = __ffsll((long long)mask) - 1;
+      acc += read_lane(v, l);
+      mask &= mask - 1;
+    }
+    return acc;
+  }
+  return wave_sum(v);
 }
 
 template <typename V>
@@ -925,20 +980,36 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   const int per = (N + kSelBlock - 1) / kSelBlock;
   const int k0 = tid * per;
   const int kend = (k0 + per < N) ? k0 + per : N;  // may be <= k0 for idle threads
+  // costs (and, for the elite update, phase increments) of this thread's
+  // first kSelPer samples in registers: independent loads, one latency
+  // (FP64 controllers read the increments from memory: their costs already
+  // take twice the registers)
+  constexpr bool kQReg = sizeof(T) == 4;
   T Jr[kSelPer];
+  uint32_t Qr[kQReg ? kSelPer : 1];
+  const bool want_q = d.method == 1;
 #pragma unroll
-  for (int i = 0; i < kSelPer; ++i) Jr[i] = (k0 + i < kend) ? Jg[k0 + i] : inf_t<T>();
+  for (int i = 0; i < kSelPer; ++i) {
+    Jr[i] = (k0 + i < kend) ? Jg[k0 + i] : inf_t<T>();
+    if (kQReg) Qr[kQReg ? i : 0] = (want_q && k0 + i < kend) ? d.q[k0 + i] : 0u;
+  }
   // SEL_FOR(...): visit this thread's samples in index order with the cost
-  // in `cv` and the local position in `i` (registers first, then memory)
+  // in `cv`, the phase increment in `qv` (elite update only) and the local
+  // position in `i` (registers first, then memory)
 #define SEL_FOR(...)                                                   \
   _Pragma("unroll") for (int i = 0; i < kSelPer; ++i) {                \
     if (i < per && k0 + i < kend) {                                    \
       const T cv = Jr[i];                                              \
+      const uint32_t qv = kQReg ? Qr[kQReg ? i : 0]                    \
+                                : (want_q ? d.q[k0 + i] : 0u);         \
+      (void)qv;                                                        \
       __VA_ARGS__                                                      \
     }                                                                  \
   }                                                                    \
   for (int i = kSelPer; i < per && k0 + i < kend; ++i) {               \
     const T cv = Jg[k0 + i];                                           \
+    const uint32_t qv = want_q ? d.q[k0 + i] : 0u;                     \
+    (void)qv;                                                          \
     __VA_ARGS__                                                        \
   }
 
@@ -1050,7 +1121,7 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
         act[pos] = (uint32_t)k;
         actw[pos] = T(1);
         ++pos;
-        const double f = (double)d.q[k] * d.inv_q_scale;
+        const double f = (double)qv * d.inv_q_scale;
         s1 += f;
         s2 += f * f;
       })
@@ -1317,13 +1388,16 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   }
   // within a wave in the working precision (FP64 for the normaliser), then
   // FP64 across waves
+  // (usually a handful of samples carry weight, so most waves have nothing
+  // to add and the rest add a few lanes through scalar reads)
   const int lane = tid & 63, wid = tid >> 6;
+  const uint64_t live = __ballot(cnt != 0.0);
   double o[15];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) o[c] = (double)wave_sum(f1[c]);
-  o[12] = wave_sum(sw);
-  o[13] = wave_sum(swf);
-  o[14] = wave_sum(cnt);
+  for (int c = 0; c < 12; ++c) o[c] = (double)wave_sum_sparse(f1[c], live);
+  o[12] = wave_sum_sparse(sw, live);
+  o[13] = wave_sum_sparse(swf, live);
+  o[14] = wave_sum_sparse(cnt, live);
   if (lane == 0) {
 #pragma unroll
     for (int c = 0; c < 15; ++c) lds[wid][c] = o[c];

@@ -595,6 +595,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
 // as much as the kernel's own launch), mode 2 every launch.
 constexpr uint64_t kTimingStride = 16;
 int timing_mode_now(sbs_runtime *rt) {
+  if (rt->timing == 3) return 1;  // dispatch events on every launch
   if (rt->timing != 1) return rt->timing;
   return (rt->timing_seq++ % kTimingStride) == 0 ? 1 : 0;
 }
@@ -602,7 +603,7 @@ int timing_mode_now(sbs_runtime *rt) {
 void record_timing(sbs_runtime *rt, Batch &b) {
   // mode 2: groups of 5 events around the 4 stages; mode 1: pairs around the
   // rollout stage
-  const size_t g = rt->timing == 2 ? 5 : 2;
+  const size_t g = rt->timing == 2 ? 5 : 2;  // modes 1 and 3: rollout pairs
   for (size_t o = 0; o + g <= b.timing.size(); o += g) {
     for (size_t s = 0; s + 1 < g; ++s) {
       float ms = 0.f;
@@ -1412,7 +1413,7 @@ int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *adm
 
 int sbs_set_timing(sbs_runtime *rt, int32_t mode) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
-  if (mode < 0 || mode > 2) return fail(SBS_EINVAL, "timing mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(SBS_EINVAL, "timing mode must be 0, 1, 2 or 3");
   std::lock_guard<std::mutex> lk(rt->mu);
   reap(rt);
   rt->timing = mode;
