@@ -988,10 +988,17 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   T Jr[kSelPer];
   uint32_t Qr[kQReg ? kSelPer : 1];
   const bool want_q = d.method == 1;
+  // (loads from a clamped, always valid index, so that all of them issue
+  // back to back instead of one exec-masked load and wait per slot)
 #pragma unroll
   for (int i = 0; i < kSelPer; ++i) {
-    Jr[i] = (k0 + i < kend) ? Jg[k0 + i] : inf_t<T>();
-    if (kQReg) Qr[kQReg ? i : 0] = (want_q && k0 + i < kend) ? d.q[k0 + i] : 0u;
+    const int kc = k0 + i < N ? k0 + i : N - 1;
+    const T jv = Jg[kc];
+    Jr[i] = (k0 + i < kend) ? jv : inf_t<T>();
+    if (kQReg) {
+      const uint32_t qq = d.q[kc];
+      Qr[kQReg ? i : 0] = (want_q && k0 + i < kend) ? qq : 0u;
+    }
   }
   // SEL_FOR(...): visit this thread's samples in index order with the cost
   // in `cv`, the phase increment in `qv` (elite update only) and the local
@@ -1235,9 +1242,12 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int aa = a + u * kUpdBlock;
+        const int ac = aa < nact ? aa : nact - 1;  // always valid: loads issue together
+        const uint32_t kv = act[ac];
+        const T wv = actw[ac];
         va[u] = aa < nact;
-        ka[u] = va[u] ? act[aa] : 0u;
-        wa[u] = va[u] ? actw[aa] : T(0);
+        ka[u] = va[u] ? kv : 0u;
+        wa[u] = va[u] ? wv : T(0);
       }
       float4 zl[4][3];
 #pragma unroll
@@ -1350,7 +1360,8 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 #pragma unroll
   for (int i = 0; i < kMppiPer; ++i) {
     const int k = tid + i * kMppiBlock;
-    Jr[i] = (k < N) ? Jg[k] : inf_t<T>();
+    const T jv = Jg[k < N ? k : N - 1];  // always valid: the loads issue together
+    Jr[i] = (k < N) ? jv : inf_t<T>();
   }
   T bv = inf_t<T>();
   int bk = 0x7fffffff;
