@@ -977,27 +977,62 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
   __shared__ uint32_t s_digit, s_rank;
   __shared__ uint32_t wave_tot[kSelBlock / 64];
 
-  const int per = (N + kSelBlock - 1) / kSelBlock;
+  // thread t owns samples [t P, t P + P), P = max(kSelPer, ceil(N / 1024))
+  const int per0 = (N + kSelBlock - 1) / kSelBlock;
+  const int per = per0 > kSelPer ? per0 : kSelPer;
   const int k0 = tid * per;
   const int kend = (k0 + per < N) ? k0 + per : N;  // may be <= k0 for idle threads
   // costs (and, for the elite update, phase increments) of this thread's
-  // first kSelPer samples in registers: independent loads, one latency
-  // (FP64 controllers read the increments from memory: their costs already
-  // take twice the registers)
+  // first kSelPer samples in registers (FP64 controllers read the increments
+  // from memory: their costs already take twice the registers).  A whole
+  // slice in range is read with 16-byte loads: one wave instruction then
+  // covers 1 KB, where one element per lane would touch 64 cache lines to
+  // use 4 bytes of each, sixteen times over (the single workgroup's memory
+  // pipeline, not the latency, bounded that phase).
   constexpr bool kQReg = sizeof(T) == 4;
   T Jr[kSelPer];
   uint32_t Qr[kQReg ? kSelPer : 1];
   const bool want_q = d.method == 1;
-  // (loads from a clamped, always valid index, so that all of them issue
-  // back to back instead of one exec-masked load and wait per slot)
+  if (per == kSelPer && k0 + kSelPer <= N) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(Jg + k0);
+    constexpr int kVec = kSelPer * (int)sizeof(T) / 16;
 #pragma unroll
-  for (int i = 0; i < kSelPer; ++i) {
-    const int kc = k0 + i < N ? k0 + i : N - 1;
-    const T jv = Jg[kc];
-    Jr[i] = (k0 + i < kend) ? jv : inf_t<T>();
-    if (kQReg) {
-      const uint32_t qq = d.q[kc];
-      Qr[kQReg ? i : 0] = (want_q && k0 + i < kend) ? qq : 0u;
+    for (int v = 0; v < kVec; ++v) {
+      const uint4 w = src[v];
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Jr[4 * v + e] = __uint_as_float(ww[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          Jr[2 * v + e] = __longlong_as_double((long long)(((uint64_t)ww[2 * e + 1] << 32) | ww[2 * e]));
+      }
+    }
+    if (kQReg && want_q) {
+      const uint4 *qs = reinterpret_cast<const uint4 *>(d.q + k0);
+#pragma unroll
+      for (int v = 0; v < kSelPer / 4; ++v) {
+        const uint4 w = qs[v];
+        Qr[kQReg ? 4 * v : 0] = w.x;
+        Qr[kQReg ? 4 * v + 1 : 0] = w.y;
+        Qr[kQReg ? 4 * v + 2 : 0] = w.z;
+        Qr[kQReg ? 4 * v + 3 : 0] = w.w;
+      }
+    } else if (kQReg) {
+#pragma unroll
+      for (int i = 0; i < kSelPer; ++i) Qr[kQReg ? i : 0] = 0u;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSelPer; ++i) {
+      const int kc = k0 + i < N ? k0 + i : N - 1;
+      const T jv = Jg[kc];
+      Jr[i] = (k0 + i < kend) ? jv : inf_t<T>();
+      if (kQReg) {
+        const uint32_t qq = d.q[kc];
+        Qr[kQReg ? i : 0] = (want_q && k0 + i < kend) ? qq : 0u;
+      }
     }
   }
   // SEL_FOR(...): visit this thread's samples in index order with the cost
