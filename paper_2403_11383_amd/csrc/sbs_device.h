@@ -10,7 +10,7 @@ namespace sbs {
 
 constexpr int kRollBlock = 64;     // default rollout workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
-constexpr int kUpdBlock = 256;     // threads per update workgroup (elite, best sample)
+constexpr int kUpdBlock = 512;     // threads per update workgroup (elite, best sample)
 constexpr int kMppiBlock = 1024;   // threads per fused MPPI update workgroup
 constexpr int kSelBlock = 1024;    // threads of the per-controller select block
 constexpr int kResultDoubles = 24; // action record

@@ -6,14 +6,21 @@
 //              increments q[k] (Sampling)
 //   k_rollout  one lane per sample: SRBD rollout of Eq. (1) with explicit
 //              Euler, world-fixed footholds placed by Eq. (2) at touchdown,
-//              quadratic cost of Sec. V (Alg. 2, Evaluation)
-//   k_select   one workgroup per controller: lowest cost, MPPI weights with
-//              an FP64 normaliser (Alg. 4), top-K_e radix selection (Alg. 1)
-//              or the best sample (Alg. 3); frequency update
-//   k_update   weighted sums of the noise over samples, split over
-//              (step, sample chunk) workgroups; the last workgroup of a
-//              controller to arrive forms the new mean (and elite std), the
-//              action and the warm-started mean (Sec. III-A)
+//              quadratic cost of Sec. V (Alg. 2, Evaluation); k_rollout_quad
+//              is the same rollout on four lanes per sample (one per leg)
+//   k_select   elite and best-sample controllers, one workgroup per
+//              controller: lowest cost, top-K_e radix selection (Alg. 1) or
+//              the best sample (Alg. 3), frequency moments (Sorting)
+//   k_update   elite and best-sample controllers, one workgroup per
+//              (controller, step): FP64 moments of the chosen noise rows,
+//              new mean and elite std; step 0 of the last iteration writes
+//              the action (Update)
+//   k_update_mppi  MPPI controllers, one workgroup per (controller, step):
+//              log-sum-exp weighting with an FP64 normaliser and the
+//              weighted noise sum fused (Alg. 4); step 0 writes the
+//              per-iteration scalars and, last, the action
+// The warm-started mean (Sec. III-A) is the previous tick's mean read one
+// step (or knot) shifted by the next reader.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <stdint.h>
@@ -858,18 +865,6 @@ __device__ __forceinline__ V wave_sum_sparse(V v, uint64_t mask) {
   return wave_sum(v);
 }
 
-template <typename V>
-__device__ V block_sum(V v, V *lds) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  V r = V(0);
-  for (int i = 0; i < nw; ++i) r += lds[i];
-  return r;
-}
-
 // (cost, index) minimum with the lowest index winning ties
 template <typename T>
 __device__ __forceinline__ void argmin_combine(T &v, int &k, T v2, int k2) {
@@ -899,21 +894,6 @@ __device__ void block_argmin(T &v, int &k, T *lv, int *lk) {
   for (int i = 1; i < nw; ++i) argmin_combine(v, k, lv[i], lk[i]);
 }
 
-__device__ uint64_t block_max_u64(uint64_t v, uint64_t *lds) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  uint64_t r = lds[0];
-  for (int i = 1; i < nw; ++i) r = lds[i] > r ? lds[i] : r;
-  return r;
-}
-
 // Ordering keys of costs (>= 0 or +inf): the bit patterns, in the width of
 // the working precision.
 __device__ __forceinline__ uint32_t key_bits(float v) { return __float_as_uint(v); }
@@ -923,59 +903,150 @@ __device__ __forceinline__ int top_bit(uint64_t v) { return 63 - __builtin_clzll
 
 // ---------------------------------------------------------------------------
 // Select (elite and best-sample updates): one workgroup per controller.
-// Thread t owns the contiguous samples [t P, (t+1) P), P = ceil(N / 1024),
-// held in registers for N <= 16384 (read again from memory beyond).  Output:
-// the chosen samples in index order (act, actw) -- the K_e elites or the best
-// sample -- and per-iteration scalars.  MPPI controllers form their weights
-// inside k_update_mppi and leave this stage at once.
+// Thread t owns the contiguous samples [t P, (t+1) P), P = max(16,
+// ceil(N / 1024)), the first 16 held in registers (the rest read again from
+// memory).  Output: the chosen samples in index order (act, actw) -- the K_e
+// elites or the best sample -- and per-iteration scalars.  MPPI controllers
+// form their weights inside k_update_mppi and leave this stage at once.
+//
+// Every workgroup-wide step costs one barrier: wave results go through DPP
+// (no LDS permutes) and each step has LDS slots of its own, so no barrier
+// guards a slot's reuse.  Steps: lowest (cost, index) and highest cost key;
+// per radix digit a histogram pass; one prefix scan of the below-threshold
+// and tie counts; one sum of the elite frequency moments.
 // ---------------------------------------------------------------------------
 constexpr int kSelPer = 16;
+// Radix histograms: kSelCopies copies of 256 bins, copy = lane mod
+// kSelCopies, rows padded to kHistStride words so that one bin of different
+// copies sits in different LDS banks.  Lanes that share a digit then add into
+// different words: a skewed cost distribution (most samples in one bin, as
+// the +inf costs of diverged rollouts are) no longer serialises a wave's
+// atomics on one address.
+constexpr int kSelCopies = 16;
+constexpr int kHistStride = 257;
+static_assert(kSelBlock == 4 * 256, "the histogram reduction gives each bin one quad of threads");
 
-template <typename V>
-__device__ __forceinline__ V wave_incl_scan(V v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const V u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ uint32_t dpp_zu(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, BM, true);
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ uint64_t dpp_zu(uint64_t v) {
+  const uint32_t lo = dpp_zu<CTRL, RM, BM>((uint32_t)v);
+  const uint32_t hi = dpp_zu<CTRL, RM, BM>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Inclusive prefix sum over the 64 lanes: the DPP tree of wave_sum with
+// every lane's partial kept (lane i ends with x[0] + ... + x[i]).
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  uint32_t v = x + dpp_zu<0x111, 0xF, 0xF>(x);
+  v += dpp_zu<0x112, 0xF, 0xF>(x);
+  v += dpp_zu<0x113, 0xF, 0xF>(x);
+  v += dpp_zu<0x114, 0xF, 0xE>(v);
+  v += dpp_zu<0x118, 0xF, 0xC>(v);
+  v += dpp_zu<0x142, 0xA, 0xF>(v);
+  v += dpp_zu<0x143, 0xC, 0xF>(v);
   return v;
 }
 
-// Exclusive prefix of v over the threads of the block, and the block total.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wave_tot,
-                                                    uint32_t *total) {
+// Largest unsigned value over the 64 lanes, in every lane (the same tree;
+// zero, the identity, fills lanes outside a move's reach).
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+  uint64_t v = umax64(x, dpp_zu<0x111, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x112, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x113, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x114, 0xF, 0xE>(v));
+  v = umax64(v, dpp_zu<0x118, 0xF, 0xC>(v));
+  v = umax64(v, dpp_zu<0x142, 0xA, 0xF>(v));
+  v = umax64(v, dpp_zu<0x143, 0xC, 0xF>(v));
+  const uint32_t lo = read_lane_u32((uint32_t)v, 63), hi = read_lane_u32((uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Workgroup maxima of two unsigned values (one barrier; `red` is used by
+// this call alone).
+__device__ __forceinline__ void block_max2_u64(uint64_t a, uint64_t b, uint64_t (*red)[2],
+                                               uint64_t &ra, uint64_t &rb) {
+  a = wave_max_u64(a);
+  b = wave_max_u64(b);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const uint32_t incl = wave_incl_scan(v);
-  __syncthreads();
-  if (lane == 63) wave_tot[wid] = incl;
-  __syncthreads();
-  uint32_t before = incl - v, tot = 0;
-  for (int i = 0; i < nw; ++i) {
-    const uint32_t c = wave_tot[i];
-    before += (i < wid) ? c : 0u;
-    tot += c;
+  if (lane == 0) {
+    red[wid][0] = a;
+    red[wid][1] = b;
   }
-  *total = tot;
-  return before;
+  __syncthreads();
+  ra = 0;
+  rb = 0;
+  for (int i = 0; i < nw; ++i) {
+    ra = umax64(ra, red[i][0]);
+    rb = umax64(rb, red[i][1]);
+  }
+}
+
+// Exclusive workgroup prefixes of two counts and their totals (one barrier).
+__device__ __forceinline__ void block_excl_scan2(uint32_t a, uint32_t b, uint2 *red,
+                                                 uint32_t &a_before, uint32_t &b_before,
+                                                 uint32_t &a_tot, uint32_t &b_tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t ia = wave_incl_scan_u32(a), ib = wave_incl_scan_u32(b);
+  if (lane == 63) red[wid] = make_uint2(ia, ib);
+  __syncthreads();
+  a_before = ia - a;
+  b_before = ib - b;
+  a_tot = 0;
+  b_tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const uint2 c = red[i];
+    a_before += (i < wid) ? c.x : 0u;
+    b_before += (i < wid) ? c.y : 0u;
+    a_tot += c.x;
+    b_tot += c.y;
+  }
+}
+
+// Workgroup sums of two FP64 values, waves added in order (one barrier).
+__device__ __forceinline__ void block_sum2(double &a, double &b, double2 *red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) red[wid] = make_double2(a, b);
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    a += red[i].x;
+    b += red[i].y;
+  }
+}
+
+__device__ __forceinline__ float key_value(uint32_t k, float) { return __uint_as_float(k); }
+__device__ __forceinline__ double key_value(uint64_t k, double) {
+  return __longlong_as_double((long long)k);
 }
 
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc inl) {
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[blockIdx.x]];
   if (d.method == 0) return;  // MPPI: see k_update_mppi
-  const int N = d.N, tid = threadIdx.x;
+  const int N = d.N, tid = threadIdx.x, lane = tid & 63;
   const T *Jg = reinterpret_cast<const T *>(d.J);
   T *actw = reinterpret_cast<T *>(d.w);
   uint32_t *act = d.act;
   const int r = tab.r;
-  __shared__ double lds_d[kSelBlock / 64];
-  __shared__ T lds_v[kSelBlock / 64];
-  __shared__ int lds_k[kSelBlock / 64];
-  __shared__ uint32_t hist[256];
-  __shared__ uint64_t lds_u64[kSelBlock / 64];
-  __shared__ uint32_t s_digit, s_rank;
-  __shared__ uint32_t wave_tot[kSelBlock / 64];
+  using K = decltype(key_bits(T(0)));
+  __shared__ uint32_t hist[kSelCopies * kHistStride];
+  __shared__ __align__(16) uint32_t bin_tot[256];  // the bin totals of a radix pass
+  __shared__ uint64_t red_min[kSelBlock / 64][2];
+  __shared__ uint64_t red_idx[kSelBlock / 64][2];
+  __shared__ uint2 red_scan[kSelBlock / 64];
+  __shared__ double2 red_sum[kSelBlock / 64];
+
+  for (int i = tid; i < kSelCopies * kHistStride; i += kSelBlock) hist[i] = 0u;
 
   // thread t owns samples [t P, t P + P), P = max(kSelPer, ceil(N / 1024))
   const int per0 = (N + kSelBlock - 1) / kSelBlock;
@@ -1061,11 +1132,36 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
       d.dbg_q[(size_t)r * N + k] = d.q[k];
     }
   }
-  // lowest cost and its index (lowest index on ties)
-  T bv = inf_t<T>();
-  int bk = 0x7fffffff;
-  SEL_FOR(argmin_combine(bv, bk, cv, k0 + i);)
-  block_argmin(bv, bk, lds_v, lds_k);
+  // Costs are >= 0 or +inf, so their bit patterns order like the values.
+  // Lowest (cost, index), lowest index on ties, and the highest key, as
+  // maxima of complemented keys: FP32 keys pack with the index into one
+  // 64-bit word; FP64 keys take a second step for the index.
+  uint64_t m_lo = 0, m_hi = 0;
+  SEL_FOR(
+    const K key = key_bits(cv);
+    m_hi = umax64(m_hi, (uint64_t)key);
+    if constexpr (sizeof(K) == 4) {
+      m_lo = umax64(m_lo, ~(((uint64_t)key << 32) | (uint32_t)(k0 + i)));
+    } else {
+      m_lo = umax64(m_lo, ~(uint64_t)key);
+    })
+  uint64_t r_lo, r_hi;
+  block_max2_u64(m_lo, m_hi, red_min, r_lo, r_hi);
+  K kmin;
+  int bk;
+  if constexpr (sizeof(K) == 4) {
+    kmin = (K)(~r_lo >> 32);
+    bk = (int)(uint32_t)~r_lo;
+  } else {
+    kmin = (K)~r_lo;
+    uint64_t m_k = 0;
+    SEL_FOR(if (key_bits(cv) == kmin) m_k = umax64(m_k, ~(uint64_t)(uint32_t)(k0 + i));)
+    uint64_t r_k, unused;
+    block_max2_u64(m_k, 0, red_idx, r_k, unused);
+    bk = (int)(uint32_t)~r_k;
+  }
+  const K kmax = (K)r_hi;
+  const T bv = key_value(kmin, T(0));
   const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
   const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
   const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
@@ -1085,71 +1181,70 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
     fnew = (double)d.q[bk] * d.inv_q_scale;
     mf_next = fnew;
   } else {  // elite: the K_e smallest (cost, index) by radix selection
-    // Costs are >= 0 or +inf, so their bit patterns order like the values and
-    // every key shares the bits above the highest bit in which the lowest and
-    // the highest key differ: the digits start there (up to 8 bits each), so
-    // no pass is spent on a digit every key shares (whose histogram would
-    // also pile every atomic onto one bin).
-    using K = decltype(key_bits(T(0)));
-    K kmax = 0;
-    SEL_FOR(kmax = key_bits(cv) > kmax ? key_bits(cv) : kmax;)
-    kmax = (K)block_max_u64((uint64_t)kmax, lds_u64);
-    const K kmin = key_bits(bv);
+    // Every key shares the bits above the highest bit in which the lowest
+    // and the highest key differ: the digits start there (up to 8 bits
+    // each), so no pass is spent on a digit every key shares.
     int hi = (kmin == kmax) ? -1 : top_bit((K)(kmin ^ kmax));
     const K below = hi < 0 ? K(0) : (K)((K(2) << hi) - K(1));  // bits 0..hi (wraps to all)
     K mask = (K)~below, prefix = (K)(kmin & mask);
     uint32_t rank = (uint32_t)d.Ke;
-    const int lane = tid & 63, wid = tid >> 6;
+    uint32_t *my_hist = hist + (lane & (kSelCopies - 1)) * kHistStride;
+    const int bin = tid >> 2, part = tid & 3;
     while (hi >= 0) {
       const int lo = hi >= 7 ? hi - 7 : 0;
       const K dmask = (K)((K(1) << (hi - lo + 1)) - K(1));
-      for (int i = tid; i < 256; i += kSelBlock) hist[i] = 0u;
-      __syncthreads();
       SEL_FOR(
         const K key = key_bits(cv);
-        if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)((key >> lo) & dmask)], 1u);)
+        if ((key & mask) == prefix) atomicAdd(&my_hist[(uint32_t)((key >> lo) & dmask)], 1u);)
       __syncthreads();
-      if (wid == 0) {  // first digit whose cumulative count reaches rank
-        const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
-                       h3 = hist[4 * lane + 3];
-        const uint32_t sum = h0 + h1 + h2 + h3;
-        const uint32_t incl = wave_incl_scan(sum);
-        const uint32_t excl = incl - sum;
-        if (excl < rank && rank <= incl) {
-          uint32_t cum = excl, dg = 0;
-          const uint32_t hh[4] = {h0, h1, h2, h3};
-          for (dg = 0; dg < 3u; ++dg) {
-            if (cum + hh[dg] >= rank) break;
-            cum += hh[dg];
-          }
-          s_digit = 4u * (uint32_t)lane + dg;
-          s_rank = rank - cum;
-        }
+      // bin totals: quad (bin, part) adds copies 4 part .. 4 part + 3 and
+      // clears them for the next pass
+      uint32_t c = 0;
+#pragma unroll
+      for (int cc = 0; cc < kSelCopies / 4; ++cc) {
+        uint32_t *h = &hist[(4 * part + cc) * kHistStride + bin];
+        c += *h;
+        *h = 0u;
       }
+      c += (uint32_t)__builtin_amdgcn_mov_dpp((int)c, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+      c += (uint32_t)__builtin_amdgcn_mov_dpp((int)c, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+      if (part == 0) bin_tot[bin] = c;
       __syncthreads();
-      prefix |= (K)((K)s_digit << lo);
+      // every wave finds the first digit whose cumulative count reaches
+      // `rank` (lane l holds digits 4l .. 4l + 3); exactly one lane's range
+      // (excl, incl] holds it, since the counts add up to the keys that
+      // match the prefix, at least `rank` of them
+      const uint32_t hh[4] = {bin_tot[4 * lane], bin_tot[4 * lane + 1], bin_tot[4 * lane + 2],
+                              bin_tot[4 * lane + 3]};
+      const uint32_t sum = hh[0] + hh[1] + hh[2] + hh[3];
+      const uint32_t incl = wave_incl_scan_u32(sum), excl = incl - sum;
+      uint32_t cum = excl, dg = 0;
+      for (dg = 0; dg < 3u; ++dg) {
+        if (cum + hh[dg] >= rank) break;
+        cum += hh[dg];
+      }
+      const uint64_t owner = __ballot(excl < rank && rank <= incl);
+      const int src = __ffsll((long long)owner) - 1;
+      const uint32_t digit = read_lane_u32(4u * (uint32_t)lane + dg, src);
+      rank = read_lane_u32(rank - cum, src);
+      prefix |= (K)((K)digit << lo);
       mask |= (K)(dmask << lo);
-      rank = s_rank;
       hi = lo - 1;
-      __syncthreads();
     }
     // prefix is the K_e-th smallest cost; the first `rank` ties by index are in
     const K thr = prefix;
     const uint32_t need = rank;
-    uint32_t ntie = 0, nel = 0;
-    SEL_FOR(ntie += (key_bits(cv) == thr) ? 1u : 0u;)
-    uint32_t tot;
-    uint32_t tb = block_excl_scan(ntie, wave_tot, &tot);  // ties before this thread
+    uint32_t nless = 0, ntie = 0;
     SEL_FOR(
       const K key = key_bits(cv);
-      bool el = key < thr;
-      if (key == thr) {
-        el = tb < need;
-        ++tb;
-      }
-      nel += el ? 1u : 0u;)
-    uint32_t pos = block_excl_scan(nel, wave_tot, &tot);
-    tb -= ntie;
+      nless += (key < thr) ? 1u : 0u;
+      ntie += (key == thr) ? 1u : 0u;)
+    uint32_t less_before, tie_before, tot_less, tot_tie;
+    block_excl_scan2(nless, ntie, red_scan, less_before, tie_before, tot_less, tot_tie);
+    // elites before this thread: every lower key, and the ties of lower
+    // index up to `need`
+    uint32_t tb = tie_before;
+    uint32_t pos = less_before + (tie_before < need ? tie_before : need);
     double s1 = 0.0, s2 = 0.0;
     SEL_FOR(
       const K key = key_bits(cv);
@@ -1167,9 +1262,8 @@ __global__ void __launch_bounds__(kSelBlock) k_select(LaunchTab tab, TickDesc in
         s1 += f;
         s2 += f * f;
       })
-    nact = tot;
-    s1 = block_sum(s1, lds_d);
-    s2 = block_sum(s2, lds_d);
+    nact = tot_less + (tot_tie < need ? tot_tie : need);
+    block_sum2(s1, s2, red_sum);
     const double ke = (double)d.Ke;
     const double fm = s1 / ke;
     double fv = s2 / ke - fm * fm;
@@ -1259,6 +1353,19 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
   const uint32_t *act = d.act;
   __shared__ double lds[kUpdBlock / 64][24];
   __shared__ double s_new[12];
+  const bool last_iter = (r == d.R - 1);
+  // What does not depend on the select's output is read first, so that its
+  // latency overlaps the gathers: this step's old mean and std.
+  double m_old = 0.0, sig = 0.0;
+  if (tid < 12) {
+    m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, tid);
+    sig = (elite && r > 0) ? d.sigma[j * 12 + tid] : d.sigma0;
+  }
+  // The chosen samples number at most K_e (elite) or one (best sample): their
+  // indices are read together with the count instead of after it, clamped
+  // into [0, N) so that a stale entry never leaves the noise rows, and the
+  // count (zero on a skipped iteration) masks them afterwards.
+  const int nmax = elite ? d.Ke : 1;
   const bool skip = d.it[IT_SKIP] != 0.0;
   const int nact = skip ? 0 : (int)d.it[IT_NACT];
 
@@ -1270,18 +1377,18 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
     T f1[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
-    for (int a = tid; a < nact; a += 4 * kUpdBlock) {
+    for (int a = tid; a < nmax; a += 4 * kUpdBlock) {
       uint32_t ka[4];
       T wa[4];
       bool va[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int aa = a + u * kUpdBlock;
-        const int ac = aa < nact ? aa : nact - 1;  // always valid: loads issue together
+        const int ac = aa < nmax ? aa : nmax - 1;  // always valid: loads issue together
         const uint32_t kv = act[ac];
         const T wv = actw[ac];
         va[u] = aa < nact;
-        ka[u] = va[u] ? kv : 0u;
+        ka[u] = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
         wa[u] = va[u] ? wv : T(0);
       }
       float4 zl[4][3];
@@ -1326,7 +1433,6 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
     for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
   }
   __syncthreads();
-  const bool last_iter = (r == d.R - 1);
   if (tid < 12) {
     const int c = tid, idx = j * 12 + c;
     double S1 = 0.0, S2 = 0.0;
@@ -1334,9 +1440,7 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
       S1 += lds[i][c];
       S2 += lds[i][12 + c];
     }
-    const double m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, c);
     double m_new = m_old;
-    const double sig = (elite && r > 0) ? d.sigma[idx] : d.sigma0;
     if (elite) {
       double sg = sig;
       if (!skip) {
