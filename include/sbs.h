@@ -251,6 +251,13 @@ typedef struct sbs_plant_state {
 } sbs_plant_state;
 int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st, const sbs_action *act,
                    const double ext_force[3], const double v_ref[3]);
+/* The same step under an external wrench on the CoM: ext_wrench = world-frame
+ * force [N] (0..2) and world-frame torque [N m] (3..5), the disturbances of
+ * the simulated robustness tests of Sec. V.  Returns SBS_EINVAL on a
+ * null pointer; the state is left unchanged then. */
+int sbs_plant_step_wrench(const sbs_controller_cfg *cfg, sbs_plant_state *st,
+                          const sbs_action *act, const double ext_wrench[6],
+                          const double v_ref[3]);
 
 const char *sbs_last_error(void);
 int32_t sbs_abi_version(void);

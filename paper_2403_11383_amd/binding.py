@@ -31,7 +31,7 @@ EXPORTED = [
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -122,6 +122,8 @@ def lib():
         L.sbs_set_rollout_lanes.argtypes = [vp, i32]
         L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
+                                     C.POINTER(Action), vp, vp]
+        L.sbs_plant_step_wrench.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
         L.sbs_last_error.restype = C.c_char_p
         L.sbs_abi_version.restype = i32
@@ -407,18 +409,22 @@ class Plant:
         self.st.x[:] = [float(v) for v in x0]
         self.st.foot_pos[:] = [float(v) for v in np.asarray(foot_pos, np.float64).reshape(12)]
         self.st.phase = int(phase) & 0xFFFFFFFF
-        self._ext = np.zeros(3)
+        self._ext = np.zeros(6)
         self._vref = np.zeros(3)
 
-    def step(self, act: dict, ext_force=(0.0, 0.0, 0.0), v_ref=(0.0, 0.0, 0.0)):
+    def step(self, act: dict, ext_force=(0.0, 0.0, 0.0), v_ref=(0.0, 0.0, 0.0), ext_torque=None):
+        """One plant step; ext_force [N] and ext_torque [N m] act on the CoM in
+        the world frame (sbs_plant_step_wrench when a torque is given)."""
         a = Action()
         a.grf[:] = [float(v) for v in act["grf"]]
         a.contact[:] = [int(v) for v in act["contact"]]
         a.q = int(act["q"]) & 0xFFFFFFFF
-        self._ext[:] = ext_force
+        self._ext[:3] = ext_force
+        self._ext[3:] = 0.0 if ext_torque is None else ext_torque
         self._vref[:] = v_ref
-        _check(lib().sbs_plant_step(C.byref(self.cfg), C.byref(self.st), C.byref(a),
-                                    self._ext.ctypes.data, self._vref.ctypes.data))
+        fn = lib().sbs_plant_step if ext_torque is None else lib().sbs_plant_step_wrench
+        _check(fn(C.byref(self.cfg), C.byref(self.st), C.byref(a), self._ext.ctypes.data,
+                  self._vref.ctypes.data))
 
     @property
     def x(self):
@@ -447,11 +453,11 @@ class ClosedLoop:
         self.z_ref = float(z_ref)
         self.act = Action()
         self.ticket = C.c_uint64()
-        self.ext = np.zeros(3)
+        self.ext = np.zeros(6)
         self.vref = np.array([float(v) for v in v_ref])
         self._L = lib()
 
-    def step(self, ext_force=(0.0, 0.0, 0.0)) -> Action:
+    def step(self, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0)) -> Action:
         st, inp, L = self.plant.st, self.inp, self._L
         C.memmove(inp.x0, st.x, 96)
         C.memmove(inp.foot_pos, st.foot_pos, 96)
@@ -461,7 +467,8 @@ class ClosedLoop:
         inp.phase_robot = st.phase
         _check(L.sbs_submit_tick(self.rt._h, self.cid, C.byref(inp), C.byref(self.ticket)))
         _check(L.sbs_fetch_action(self.rt._h, self.ticket, C.byref(self.act), -1))
-        self.ext[:] = ext_force
-        _check(L.sbs_plant_step(C.byref(self.plant.cfg), C.byref(st), C.byref(self.act),
-                                self.ext.ctypes.data, self.vref.ctypes.data))
+        self.ext[:3] = ext_force
+        self.ext[3:] = ext_torque
+        _check(L.sbs_plant_step_wrench(C.byref(self.plant.cfg), C.byref(st), C.byref(self.act),
+                                       self.ext.ctypes.data, self.vref.ctypes.data))
         return self.act

@@ -874,26 +874,6 @@ __device__ __forceinline__ void argmin_combine(T &v, int &k, T v2, int k2) {
   }
 }
 
-template <typename T>
-__device__ void block_argmin(T &v, int &k, T *lv, int *lk) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const T v2 = __shfl_xor(v, o, 64);
-    const int k2 = __shfl_xor(k, o, 64);
-    argmin_combine(v, k, v2, k2);
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    lv[wid] = v;
-    lk[wid] = k;
-  }
-  __syncthreads();
-  v = lv[0];
-  k = lk[0];
-  for (int i = 1; i < nw; ++i) argmin_combine(v, k, lv[i], lk[i]);
-}
-
 // Ordering keys of costs (>= 0 or +inf): the bit patterns, in the width of
 // the working precision.
 __device__ __forceinline__ uint32_t key_bits(float v) { return __float_as_uint(v); }
@@ -985,6 +965,28 @@ __device__ __forceinline__ void block_max2_u64(uint64_t a, uint64_t b, uint64_t 
   for (int i = 0; i < nw; ++i) {
     ra = umax64(ra, red[i][0]);
     rb = umax64(rb, red[i][1]);
+  }
+}
+
+// Lowest (cost, index) over the workgroup, lowest index on ties, from each
+// thread's own minimum; costs are >= 0 or +inf, so their bit patterns order
+// like the values.  FP32: key and index packed into one word (one barrier);
+// FP64: the key, then the index among the threads that hold it (two).
+template <typename T>
+__device__ __forceinline__ void block_argmin_packed(T &v, int &k, uint64_t (*red_a)[2],
+                                                    uint64_t (*red_b)[2]) {
+  uint64_t ra, unused;
+  if constexpr (sizeof(T) == 4) {
+    block_max2_u64(~(((uint64_t)key_bits(v) << 32) | (uint32_t)k), 0, red_a, ra, unused);
+    v = __uint_as_float((uint32_t)(~ra >> 32));
+    k = (int)(uint32_t)~ra;
+  } else {
+    block_max2_u64(~key_bits(v), 0, red_a, ra, unused);
+    const uint64_t kmin = ~ra;
+    uint64_t rk;
+    block_max2_u64(key_bits(v) == kmin ? ~(uint64_t)(uint32_t)k : 0, 0, red_b, rk, unused);
+    v = __longlong_as_double((long long)kmin);
+    k = (int)(uint32_t)~rk;
   }
 }
 
@@ -1487,10 +1489,17 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   const int N = d.N, tid = threadIdx.x, r = tab.r;
   constexpr int kW = kMppiBlock / 64;
   __shared__ double lds[kW][16];
-  __shared__ T lds_v[kW];
-  __shared__ int lds_k[kW];
+  __shared__ uint64_t red_a[kW][2], red_b[kW][2];
   __shared__ double s_new[12];
   const T *Jg = reinterpret_cast<const T *>(d.J);
+  // What does not depend on the costs is read first, so that its latency
+  // overlaps the cost loads: this step's old mean and the running
+  // per-iteration scalars.
+  const bool last_iter = (r == d.R - 1);
+  const double m_old = (tid < 12) ? (double)mean_at<T>(d, mean_in<T>(d, r), r, j, tid) : 0.0;
+  const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
+  const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
+  const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
 
   // the first kMppiPer costs of each thread are loaded at once into
   // registers (independent loads, one memory latency); beyond that (N above
@@ -1507,7 +1516,7 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 #pragma unroll
   for (int i = 0; i < kMppiPer; ++i) argmin_combine(bv, bk, Jr[i], tid + i * kMppiBlock);
   for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
-  block_argmin(bv, bk, lds_v, lds_k);
+  block_argmin_packed(bv, bk, red_a, red_b);
   const bool skip = !finite_t(bv);
 
   const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
@@ -1553,7 +1562,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
     for (int c = 0; c < 15; ++c) lds[wid][c] = o[c];
   }
   __syncthreads();
-  const bool last_iter = (r == d.R - 1);
   if (tid < 12) {
     const int c = tid, idx = j * 12 + c;
     double S1 = 0.0, omega = 0.0;
@@ -1561,7 +1569,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
       S1 += lds[i][c];
       omega += lds[i][12];
     }
-    const double m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, c);
     const double m_new = skip ? m_old : m_old + d.sigma0 * (S1 / omega);
     const T stored = (T)m_new;
     mean_out<T>(d, r)[idx] = stored;
@@ -1583,9 +1590,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
       sf += lds[i][13];
       nact += lds[i][14];
     }
-    const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
-    const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
-    const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
     const double fnew = skip ? cur_mf : sf / omega;
     const double flags = (double)((int)prev_flags | (skip ? 1 : 0));
     d.it[IT_BETA] = (double)bv;

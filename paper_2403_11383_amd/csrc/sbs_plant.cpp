@@ -2,7 +2,7 @@
 // robot of closed-loop runs (the paper's experiments run MuJoCo; this plant
 // stands in for it).  Same model as the controller: Eq. (1) with world-fixed
 // footholds placed by Eq. (2) at touchdown, explicit Euler at the control
-// step, plus an external force on the CoM.
+// step, plus an external wrench (world-frame force and torque) on the CoM.
 #include <cmath>
 #include <cstring>
 
@@ -21,10 +21,10 @@ void rotation(const double *phi, double R[9]) {
 
 }  // namespace
 
-extern "C" int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st,
-                              const sbs_action *act, const double ext_force[3],
-                              const double v_ref[3]) {
-  if (!cfg || !st || !act || !ext_force || !v_ref) return SBS_EINVAL;
+extern "C" int sbs_plant_step_wrench(const sbs_controller_cfg *cfg, sbs_plant_state *st,
+                                     const sbs_action *act, const double ext_wrench[6],
+                                     const double v_ref[3]) {
+  if (!cfg || !st || !act || !ext_wrench || !v_ref) return SBS_EINVAL;
   double *x = st->x;
   double R[9];
   rotation(&x[3], R);
@@ -43,7 +43,8 @@ extern "C" int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st
     }
     st->contact[l] = stance ? 1 : 0;
   }
-  double F[3] = {ext_force[0], ext_force[1], ext_force[2]}, tw[3] = {0, 0, 0};
+  double F[3] = {ext_wrench[0], ext_wrench[1], ext_wrench[2]};
+  double tw[3] = {ext_wrench[3], ext_wrench[4], ext_wrench[5]};
   for (int l = 0; l < 4; ++l) {
     if (!act->contact[l]) continue;
     const double *u = &act->grf[3 * l];
@@ -74,4 +75,12 @@ extern "C" int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st
   for (int c = 0; c < 12; ++c) x[c] += cfg->dt * xd[c];
   st->phase += act->q;
   return SBS_OK;
+}
+
+extern "C" int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st,
+                              const sbs_action *act, const double ext_force[3],
+                              const double v_ref[3]) {
+  if (!ext_force) return SBS_EINVAL;
+  const double w[6] = {ext_force[0], ext_force[1], ext_force[2], 0.0, 0.0, 0.0};
+  return sbs_plant_step_wrench(cfg, st, act, w, v_ref);
 }

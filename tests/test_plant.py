@@ -50,3 +50,33 @@ def test_plant_touchdown_uses_eq2(orc, binding):
         ref = orc.foothold(cfg, x, q, np.array([0.3, -0.1, 0.0]), leg)
         np.testing.assert_allclose(p.foot_pos[leg], ref, rtol=0, atol=1e-14)
     np.testing.assert_array_equal(p.foot_pos[1], 0.0)
+
+
+def test_plant_wrench_torque_enters_body_rates(orc, binding):
+    """An external world-frame torque adds I^-1 R^T tau to the body angular
+    acceleration (Euler's equation of Eq. (1)); with zero torque the wrench
+    step equals the force-only step."""
+    rng = np.random.default_rng(2)
+    cfg = workloads.config("c1")
+    for _ in range(20):
+        x = np.array(workloads.initial_state(rng))
+        x[3:6] = rng.uniform(-0.4, 0.4, 3)
+        feet = np.array(workloads.feet_under_hips(x))
+        contact = rng.integers(0, 2, 4)
+        grf = (rng.normal(size=(4, 3)) * 20 * contact[:, None]).reshape(12)
+        force, tau = rng.normal(size=3) * 10, rng.normal(size=3) * 5
+        act = {"grf": grf, "contact": contact, "q": 120259084}
+        p0 = binding.Plant(cfg, x, feet, 0)
+        p0.st.contact[:] = [int(c) for c in contact]
+        p0.step(act, ext_force=force)
+        p1 = binding.Plant(cfg, x, feet, 0)
+        p1.st.contact[:] = [int(c) for c in contact]
+        p1.step(act, ext_force=force, ext_torque=np.zeros(3))
+        np.testing.assert_array_equal(p0.x, p1.x)
+        p2 = binding.Plant(cfg, x, feet, 0)
+        p2.st.contact[:] = [int(c) for c in contact]
+        p2.step(act, ext_force=force, ext_torque=tau)
+        R = np.array(orc.rotation(x[3:6])).reshape(3, 3)
+        dw = (R.T @ tau) / np.array(cfg["inertia"])
+        np.testing.assert_allclose(p2.x[9:12] - p0.x[9:12], cfg["dt"] * dw, rtol=1e-10, atol=1e-13)
+        np.testing.assert_array_equal(p2.x[:9], p0.x[:9])
