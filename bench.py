@@ -234,11 +234,13 @@ def main():
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 the rollout kernel's own dispatch events on "
                          "one tick in 16, 2 event commands around every stage of every tick")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy", "study"],
                     help="c1 closed-loop single MPPI (default); c2 closed-loop elite "
                          "sampler (N=16384, H=50, 3 iterations); c3 batched uneven "
                          "controllers; c4 serving 256 robots vs plain single MPPI; copy: "
-                         "a plain 1 GiB device copy, the reference for HBM byte counters")
+                         "a plain 1 GiB device copy, the reference for HBM byte counters; "
+                         "study: closed-loop push episodes with and without gait adaptation")
+    ap.add_argument("--episodes", type=int, default=20, help="study: seeded episodes per setting")
     ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
     ap.add_argument("--arena-gb", type=float, default=4.0)
     ap.add_argument("--no-prefetch", action="store_true",
@@ -255,6 +257,8 @@ def main():
         return main_c3(args)
     if args.workload == "c4":
         return main_c4(args)
+    if args.workload == "study":
+        return main_study(args)
 
     from paper_2403_11383_amd import binding, workloads
     import torch
@@ -377,6 +381,82 @@ def main_copy(args):
     dt = time.perf_counter() - t0
     print(json.dumps({"workload": "copy", "bytes_per_copy": n, "copies": args.steps,
                       "GBps_read_plus_write": 2 * n * args.steps / dt / 1e9}), flush=True)
+
+
+def study_episode(rt, binding, workloads, cfg, seed):
+    """One push episode of the disturbance study on the host plant: returns
+    the tick of the fall (None if the robot stays up), the executed frequency
+    per tick and the submit-to-visible latency per tick [ms]."""
+    cid = rt.init_controller(cfg)
+    x0 = workloads.initial_state(np.random.default_rng(seed))
+    plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
+    loop = binding.ClosedLoop(rt, cid, plant, v_ref=workloads.STUDY_VREF, z_ref=workloads.HEIGHT)
+    fell, freq, lat = None, [], []
+    for t in range(workloads.STUDY_TICKS):
+        w = workloads.study_wrench(t)
+        a = loop.step(w[:3], w[3:])
+        freq.append(a.freq_hz)
+        lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
+        x = loop.plant.st.x
+        if not (abs(x[3]) < 0.8 and abs(x[4]) < 0.8 and 0.2 < x[2] < 0.6):  # NaN fails too
+            fell = t
+            break
+    rt.destroy_controller(cid)
+    return fell, freq, lat
+
+
+def main_study(args):
+    """Closed-loop disturbance study (the shape of the paper's Fig. 4 test):
+    seeded episodes of a 40 N lateral push for 3 s, for the best-sample and
+    MPPI controllers with gait adaptation (frequency set, at two weights of
+    the frequency regulariser) and without it (fixed f_n).  Reports the
+    episodes survived and, with adaptation, the mean executed frequency
+    before, during and after the push over the surviving episodes."""
+    from paper_2403_11383_amd import binding, workloads
+    import torch
+    rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)))
+    p0, p1, _ = workloads.STUDY_PUSH
+    settings = []
+    for method in ("naive", "mppi"):
+        settings += [(method, True, 1.0), (method, True, 300.0), (method, False, 1.0)]
+    out, lat_all = [], []
+    t0 = time.perf_counter()
+    for method, adapt, rho in settings:
+        cfg = workloads.study_config(method, adapt=adapt, rho=rho)
+        falls, fpre, fpush, fpost = [], [], [], []
+        for ep in range(args.episodes):
+            fell, freq, lat = study_episode(rt, binding, workloads, cfg, seed=1 + ep)
+            falls.append(fell)
+            lat_all += lat
+            if fell is None:
+                f = np.asarray(freq)
+                fpre.append(f[:p0].mean())
+                fpush.append(f[p0:p1].mean())
+                fpost.append(f[p1 + 10:].mean())
+        rec = {"method": method, "gait_adaptation": adapt, "rho": rho,
+               "survived": sum(f is None for f in falls), "episodes": len(falls),
+               "fall_ticks": [f for f in falls if f is not None]}
+        if adapt and fpre:
+            rec["freq_hz_before_during_after"] = [round(float(np.mean(v)), 3)
+                                                  for v in (fpre, fpush, fpost)]
+        out.append(rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rt.close()
+    def rate(adapt):
+        rs = [r for r in out if r["gait_adaptation"] == adapt]
+        return sum(r["survived"] for r in rs) / max(1, sum(r["episodes"] for r in rs))
+    print(json.dumps({
+        "metric": "closed-loop push survival with gait adaptation",
+        "value": rate(True), "without_gait_adaptation": rate(False),
+        "unit": "fraction of episodes", "higher_is_better": True, "n_gpus": 1,
+        "data": "synthetic",
+        "config": {"workload": "study: 40 N lateral push for 3 s from 2 s, 0.1 m/s lateral "
+                               "command, 8 s episodes, N=10240, H=25, host SRBD plant",
+                   "episodes_per_setting": args.episodes},
+        "settings": out,
+        "tick_latency_ms": {"p50": pct(lat_all, 50), "p99": pct(lat_all, 99)},
+        "wall_s": round(elapsed, 2)}), flush=True)
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256):

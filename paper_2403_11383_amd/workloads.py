@@ -157,3 +157,43 @@ def c4_arrivals(seed: int = 4, robots: int = 256, rate_hz: float = 50.0,
             ts.append(t)
         out.append(ts)
     return out
+
+
+# Closed-loop disturbance study in the shape of the paper's gait-adaptation
+# test (Sec. V-C, Fig. 4): the robot trots with a lateral velocity command of
+# 0.1 m/s; from 2 s a 40 N lateral push acts on the CoM for 3 s; an episode
+# lasts 8 s (400 control ticks at 50 Hz).  The paper's cost weights are not
+# given, so the study weights stiffen height and attitude against the GRF
+# effort (a 5 cm height error then costs as much as a 158 N error in one GRF
+# component).
+STUDY_Q = [10.0, 10.0, 1000.0, 1000.0, 1000.0, 100.0, 10.0, 10.0, 10.0, 1.0, 1.0, 1.0]
+STUDY_TICKS = 400
+STUDY_PUSH = (100, 250, 40.0)  # first tick, end tick, lateral force [N]
+STUDY_VREF = (0.0, 0.1, 0.0)
+STUDY_FSET = [1.4, 2.0, 2.4]   # f_n, 2.0, 2.4 Hz (Sec. V)
+
+
+def study_config(method: str = "naive", adapt: bool = True, rho: float = 1.0,
+                 **over) -> dict:
+    """Controller of the disturbance study: best-sample (Alg. 3) or MPPI, one
+    iteration per tick, N = 10240, H = 25 (0.5 s), 10 N GRF noise; with gait
+    adaptation the frequency is drawn from the paper's set, without it the
+    trot runs at f_n = 1.4 Hz."""
+    c = config("c1", N=10240, H=25, sigma_grf=10.0, method=method, iterations=1, rho=rho,
+               **{"lambda": 30.0})
+    c["Q"] = list(STUDY_Q)
+    c["R"] = [1e-4] * 12
+    if adapt:
+        c.update(freq_mode="set", f_set=list(STUDY_FSET))
+    else:
+        c.update(freq_mode="fixed", f_fixed=STUDY_FSET[0])
+    c.update(over)
+    return c
+
+
+def study_wrench(t: int) -> np.ndarray:
+    """External wrench [Fx, Fy, Fz, Tx, Ty, Tz] on the CoM at tick t."""
+    w = np.zeros(6)
+    if STUDY_PUSH[0] <= t < STUDY_PUSH[1]:
+        w[1] = STUDY_PUSH[2]
+    return w
