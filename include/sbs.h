@@ -234,6 +234,13 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
  * resets it. */
 int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
+/* Fixed overhead of dispatch-carried timing events: the average interval [ns]
+ * that an empty one-workgroup kernel launched with start/stop events on the
+ * runtime's stream spans, over reps launches (1..4096; each waits for its own
+ * events).  Every launch timed in modes 1 and 3 includes it once; subtracting
+ * it leaves the kernel's execution time as a kernel trace records it.
+ * SBS_EINVAL on a null pointer or reps out of range. */
+int sbs_timing_overhead(sbs_runtime *rt, int32_t reps, double *avg_ns);
 
 /* Simulated robot for closed-loop runs (host, FP64, not part of the control
  * step): advances the single-rigid-body plant of Eq. (1) by one step dt

@@ -31,7 +31,7 @@ EXPORTED = [
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -119,6 +119,7 @@ def lib():
         L.sbs_stats.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
         L.sbs_set_timing.argtypes = [vp, i32]
         L.sbs_timing.argtypes = [vp, vp, vp]
+        L.sbs_timing_overhead.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.sbs_set_rollout_lanes.argtypes = [vp, i32]
         L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
@@ -398,6 +399,12 @@ class Runtime:
         _check(lib().sbs_timing(self._h, avg.ctypes.data, n.ctypes.data))
         return {"noise_ns": avg[0], "rollout_ns": avg[1], "select_ns": avg[2],
                 "update_ns": avg[3], "launches": n.tolist()}
+
+    def timing_overhead_ns(self, reps: int = 64) -> float:
+        """Interval that the start/stop events of an empty dispatch span [ns]."""
+        v = C.c_double()
+        _check(lib().sbs_timing_overhead(self._h, int(reps), C.byref(v)))
+        return v.value
 
 
 class Plant:

@@ -1718,6 +1718,16 @@ hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, 
 
 // The noise stage alone (iterations tab.r .. tab.r + tab.r_count - 1), with
 // the descriptor inline when `inl` is non-null.
+// An empty one-workgroup dispatch carrying start/stop events: the interval
+// it spans is the events' own overhead (the start marker's completion to the
+// dispatch's first wave), which every event-timed launch includes once.
+__global__ void k_empty() {}
+
+hipError_t launch_empty_timed(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  hipExtLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, e0, e1, 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl) {
   if (tab.n == 0) return hipSuccess;
   static const TickDesc none{};

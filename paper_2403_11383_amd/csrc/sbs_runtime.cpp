@@ -38,6 +38,7 @@ namespace sbs {
 hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
                             hipEvent_t *ev, const TickDesc *inl);
 hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl);
+hipError_t launch_empty_timed(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 }
 
 using namespace sbs;
@@ -318,6 +319,7 @@ struct sbs_runtime {
   std::unordered_map<int, std::unique_ptr<Plan>> plans;
   int next_plan = 0;
   std::vector<hipEvent_t> event_pool;
+  std::vector<hipEvent_t> timing_pool;  // hipEventDisableSystemFence: timing only
   // serving
   std::thread sched;
   std::atomic<bool> stop{false};
@@ -345,6 +347,25 @@ hipEvent_t take_event(sbs_runtime *rt) {
 
 void give_event(sbs_runtime *rt, hipEvent_t e) {
   if (e) rt->event_pool.push_back(e);
+}
+
+// Events that only time work: without the system-scope fence, recording one
+// does not write back and invalidate the caches, so the measured interval is
+// the bracketed work's own (with the fence, the write-back of whatever the
+// concurrent noise kernel left dirty lands inside the rollout's interval).
+hipEvent_t take_timing_event(sbs_runtime *rt) {
+  if (!rt->timing_pool.empty()) {
+    hipEvent_t e = rt->timing_pool.back();
+    rt->timing_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+  return e;
+}
+
+void give_timing_event(sbs_runtime *rt, hipEvent_t e) {
+  if (e) rt->timing_pool.push_back(e);
 }
 
 bool finite_vec(const double *v, int n) {
@@ -614,7 +635,7 @@ void record_timing(sbs_runtime *rt, Batch &b) {
       }
     }
   }
-  for (auto e : b.timing) give_event(rt, e);
+  for (auto e : b.timing) give_timing_event(rt, e);
   b.timing.clear();
 }
 
@@ -635,7 +656,7 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
   }
   if (rt->timing) record_timing(rt, b);
   else {
-    for (auto e : b.timing) give_event(rt, e);
+    for (auto e : b.timing) give_timing_event(rt, e);
     b.timing.clear();
   }
   if (b.owns_memory) {
@@ -732,7 +753,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     if (tmode) {
       size_t base = b->timing.size();
       const int ne = tmode == 2 ? 5 : 2;
-      for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
+      for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
       ev = &b->timing[base];
     }
     e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl);
@@ -768,7 +789,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     rt->dev_alloc.release(ws_off, L.total);
     rt->host_alloc.release(host_off, L.host_total);
     give_event(rt, b->done);
-    for (auto ev : b->timing) give_event(rt, ev);
+    for (auto ev : b->timing) give_timing_event(rt, ev);
     return fail(SBS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   }
   for (size_t i = 0; i < ids.size(); ++i) {
@@ -925,6 +946,7 @@ int sbs_runtime_destroy(sbs_runtime *rt) {
       if (p.second->done) (void)hipEventDestroy(p.second->done);
     }
     for (auto e : rt->event_pool) (void)hipEventDestroy(e);
+    for (auto e : rt->timing_pool) (void)hipEventDestroy(e);
   }
   (void)hipHostFree(rt->pinned);
   delete rt;
@@ -1442,6 +1464,33 @@ int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches) {
   return SBS_OK;
 }
 
+int sbs_timing_overhead(sbs_runtime *rt, int32_t reps, double *avg_ns) {
+  if (!rt || !avg_ns) return fail(SBS_EINVAL, "runtime or output is NULL");
+  if (reps < 1 || reps > 4096) return fail(SBS_EINVAL, "reps=%d out of [1, 4096]", reps);
+  std::lock_guard<std::mutex> lk(rt->mu);
+  reap(rt);
+  hipEvent_t e0 = take_timing_event(rt), e1 = take_timing_event(rt);
+  if (!e0 || !e1) {
+    give_timing_event(rt, e0);
+    give_timing_event(rt, e1);
+    return fail(SBS_EDEVICE, "event creation failed");
+  }
+  double total = 0.0;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    e = launch_empty_timed(rt->streams[0], e0, e1);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    total += (double)ms * 1e6;
+  }
+  give_timing_event(rt, e0);
+  give_timing_event(rt, e1);
+  if (e != hipSuccess) return fail(SBS_EDEVICE, "timing overhead: %s", hipGetErrorString(e));
+  *avg_ns = total / reps;
+  return SBS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Plans: fixed membership, workspace reserved once, optionally a HIP graph.
 // ---------------------------------------------------------------------------
@@ -1611,7 +1660,7 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
   };
   for (int i = 0; i < n; ++i) ticks0[i] = cs[i]->next_tick;
   hipError_t e = copy_state(true);
-  hipEvent_t t0 = take_event(rt), t1 = take_event(rt);
+  hipEvent_t t0 = take_timing_event(rt), t1 = take_timing_event(rt);
   static const int forms[][3] = {{4, 64, 1}, {4, 128, 1}, {4, 256, 1}, {1, 64, 1},
                                  {1, 128, 1}, {1, 256, 1}, {1, 64, 2}, {1, 128, 2}};
   bool any_fp32 = false;
@@ -1650,8 +1699,8 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  give_event(rt, t0);
-  give_event(rt, t1);
+  give_timing_event(rt, t0);
+  give_timing_event(rt, t1);
   rt->dev_alloc.release(snap_off, snap_bytes);
   if (e != hipSuccess) return fail(SBS_EDEVICE, "autotune failed: %s", hipGetErrorString(e));
   P.tune = best_t;
@@ -1718,7 +1767,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
       if (tmode) {
         size_t base = b->timing.size();
         const int ne = tmode == 2 ? 5 : 2;
-        for (int i = 0; i < ne; ++i) b->timing.push_back(take_event(rt));
+        for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
         ev = &b->timing[base];
       }
       e = launch_iteration(tp.first, tp.second, s, tmode, ev, nullptr);
@@ -1728,7 +1777,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);
     give_event(rt, b->done);
-    for (auto ev : b->timing) give_event(rt, ev);
+    for (auto ev : b->timing) give_timing_event(rt, ev);
     return fail(SBS_EDEVICE, "plan launch failed: %s", hipGetErrorString(e));
   }
   for (int i = 0; i < n; ++i) {

@@ -350,3 +350,11 @@ def test_noise_prefetch_is_transparent(name):
         np.testing.assert_array_equal(x["grf"], y["grf"])
         assert x["best_cost"] == y["best_cost"]
     rt.close()
+
+
+def test_timing_overhead_probe(rt):
+    """sbs_timing_overhead: the interval that an empty dispatch's own events
+    span is positive and a few microseconds at most."""
+    v = rt.timing_overhead_ns(16)
+    print("event overhead ns", v, flush=True)
+    assert 0.0 < v < 50_000.0

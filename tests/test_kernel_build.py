@@ -52,5 +52,8 @@ def test_inline_descriptor_offset(metadata):
     """Every kernel takes (LaunchTab, TickDesc) and reads the descriptor in
     place at the LaunchTab's size rounded up to 8 bytes."""
     for name, m in metadata.items():
+        if "k_empty" in name:  # the argument-free event-overhead probe
+            assert not m["args"], (name, m["args"])
+            continue
         (o0, z0), (o1, z1) = m["args"]
         assert o0 == 0 and o1 == (z0 + 7) // 8 * 8, (name, m["args"])
