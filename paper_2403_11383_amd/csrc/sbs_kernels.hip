@@ -25,6 +25,8 @@
 #include <hip/hip_ext.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "sbs_device.h"
 
 namespace sbs {
@@ -231,6 +233,171 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
     dst[2] = make_float4(z[8], z[9], z[10], z[11]);
   }
   if (tab.write_q && j0 == 0) d.q[k] = draw_q(d, r, k);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup reductions (wave64 DPP adds, then LDS across waves)
+// ---------------------------------------------------------------------------
+// Uniform value of lane l (a scalar read, no LDS traffic).
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// v moved by the DPP control CTRL; lanes outside the row/bank masks, and
+// lanes whose source lies outside their row, read zero.
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ float dpp_z(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_z(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, RM, BM, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, RM, BM, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes, in every lane.  Within each row of 16 lanes, lane i
+// gathers x[i-3..i] (row shifts 1, 2, 3), then the partial sums of lanes
+// i-4 and i-8 (banks 1-3, then 2-3), so lane 15 of a row holds the row's
+// sum; row broadcasts add row 0 into row 1 and row 2 into row 3 (lane 15),
+// then lane 31 into rows 2 and 3: lane 63 holds the total, read as a
+// scalar.  A fixed tree, so the result is deterministic.
+template <typename V>
+__device__ __forceinline__ V wave_sum(V x) {
+  V v = x + dpp_z<0x111, 0xF, 0xF>(x);   // row_shr:1
+  v = v + dpp_z<0x112, 0xF, 0xF>(x);     // row_shr:2 (of x)
+  v = v + dpp_z<0x113, 0xF, 0xF>(x);     // row_shr:3 (of x)
+  v = v + dpp_z<0x114, 0xF, 0xE>(v);     // row_shr:4, banks 1-3
+  v = v + dpp_z<0x118, 0xF, 0xC>(v);     // row_shr:8, banks 2-3
+  v = v + dpp_z<0x142, 0xA, 0xF>(v);     // row_bcast:15, rows 1 and 3
+  v = v + dpp_z<0x143, 0xC, 0xF>(v);     // row_bcast:31, rows 2 and 3
+  return read_lane(v, 63);
+}
+
+// Wave sum of v where only the lanes in `mask` (a ballot, uniform) may be
+// non-zero: none -> 0, up to 8 lanes -> their values added in lane order
+// through scalar reads, else the shuffle tree.  Deterministic: the path
+// depends on the data alone.
+template <typename V>
+__device__ __forceinline__ V wave_sum_sparse(V v, uint64_t mask) {
+  if (mask == 0) return V(0);
+  if (__popcll(mask) <= 8) {
+    V acc = V(0);
+    while (mask) {
+      const int l = __ffsll((long long)mask) - 1;
+      acc += read_lane(v, l);
+      mask &= mask - 1;
+    }
+    return acc;
+  }
+  return wave_sum(v);
+}
+
+// (cost, index) minimum with the lowest index winning ties
+template <typename T>
+__device__ __forceinline__ void argmin_combine(T &v, int &k, T v2, int k2) {
+  if (v2 < v || (v2 == v && k2 < k)) {
+    v = v2;
+    k = k2;
+  }
+}
+
+// Ordering keys of costs (>= 0 or +inf): the bit patterns, in the width of
+// the working precision.
+__device__ __forceinline__ uint32_t key_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ int top_bit(uint32_t v) { return 31 - __builtin_clz(v); }
+__device__ __forceinline__ int top_bit(uint64_t v) { return 63 - __builtin_clzll(v); }
+
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ uint32_t dpp_zu(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, BM, true);
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ uint64_t dpp_zu(uint64_t v) {
+  const uint32_t lo = dpp_zu<CTRL, RM, BM>((uint32_t)v);
+  const uint32_t hi = dpp_zu<CTRL, RM, BM>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Inclusive prefix sum over the 64 lanes: the DPP tree of wave_sum with
+// every lane's partial kept (lane i ends with x[0] + ... + x[i]).
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  uint32_t v = x + dpp_zu<0x111, 0xF, 0xF>(x);
+  v += dpp_zu<0x112, 0xF, 0xF>(x);
+  v += dpp_zu<0x113, 0xF, 0xF>(x);
+  v += dpp_zu<0x114, 0xF, 0xE>(v);
+  v += dpp_zu<0x118, 0xF, 0xC>(v);
+  v += dpp_zu<0x142, 0xA, 0xF>(v);
+  v += dpp_zu<0x143, 0xC, 0xF>(v);
+  return v;
+}
+
+// Largest unsigned value over the 64 lanes, in every lane (the same tree;
+// zero, the identity, fills lanes outside a move's reach).
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+  uint64_t v = umax64(x, dpp_zu<0x111, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x112, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x113, 0xF, 0xF>(x));
+  v = umax64(v, dpp_zu<0x114, 0xF, 0xE>(v));
+  v = umax64(v, dpp_zu<0x118, 0xF, 0xC>(v));
+  v = umax64(v, dpp_zu<0x142, 0xA, 0xF>(v));
+  v = umax64(v, dpp_zu<0x143, 0xC, 0xF>(v));
+  const uint32_t lo = read_lane_u32((uint32_t)v, 63), hi = read_lane_u32((uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Workgroup maxima of two unsigned values (one barrier; `red` is used by
+// this call alone).
+__device__ __forceinline__ void block_max2_u64(uint64_t a, uint64_t b, uint64_t (*red)[2],
+                                               uint64_t &ra, uint64_t &rb) {
+  a = wave_max_u64(a);
+  b = wave_max_u64(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    red[wid][0] = a;
+    red[wid][1] = b;
+  }
+  __syncthreads();
+  ra = 0;
+  rb = 0;
+  for (int i = 0; i < nw; ++i) {
+    ra = umax64(ra, red[i][0]);
+    rb = umax64(rb, red[i][1]);
+  }
+}
+
+// Lowest (cost, index) over the workgroup, lowest index on ties, from each
+// thread's own minimum; costs are >= 0 or +inf, so their bit patterns order
+// like the values.  FP32: key and index packed into one word (one barrier);
+// FP64: the key, then the index among the threads that hold it (two).
+template <typename T>
+__device__ __forceinline__ void block_argmin_packed(T &v, int &k, uint64_t (*red_a)[2],
+                                                    uint64_t (*red_b)[2]) {
+  uint64_t ra, unused;
+  if constexpr (sizeof(T) == 4) {
+    block_max2_u64(~(((uint64_t)key_bits(v) << 32) | (uint32_t)k), 0, red_a, ra, unused);
+    v = __uint_as_float((uint32_t)(~ra >> 32));
+    k = (int)(uint32_t)~ra;
+  } else {
+    block_max2_u64(~key_bits(v), 0, red_a, ra, unused);
+    const uint64_t kmin = ~ra;
+    uint64_t rk;
+    block_max2_u64(key_bits(v) == kmin ? ~(uint64_t)(uint32_t)k : 0, 0, red_b, rk, unused);
+    v = __longlong_as_double((long long)kmin);
+    k = (int)(uint32_t)~rk;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -801,87 +968,6 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup reductions (wave64 DPP adds, then LDS across waves)
-// ---------------------------------------------------------------------------
-// Uniform value of lane l (a scalar read, no LDS traffic).
-__device__ __forceinline__ float read_lane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// v moved by the DPP control CTRL; lanes outside the row/bank masks, and
-// lanes whose source lies outside their row, read zero.
-template <int CTRL, int RM, int BM>
-__device__ __forceinline__ float dpp_z(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
-}
-template <int CTRL, int RM, int BM>
-__device__ __forceinline__ double dpp_z(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, RM, BM, true);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, RM, BM, true);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// Sum over the 64 lanes, in every lane.  Within each row of 16 lanes, lane i
-// gathers x[i-3..i] (row shifts 1, 2, 3), then the partial sums of lanes
-// i-4 and i-8 (banks 1-3, then 2-3), so lane 15 of a row holds the row's
-// sum; row broadcasts add row 0 into row 1 and row 2 into row 3 (lane 15),
-// then lane 31 into rows 2 and 3: lane 63 holds the total, read as a
-// scalar.  A fixed tree, so the result is deterministic.
-template <typename V>
-__device__ __forceinline__ V wave_sum(V x) {
-  V v = x + dpp_z<0x111, 0xF, 0xF>(x);   // row_shr:1
-  v = v + dpp_z<0x112, 0xF, 0xF>(x);     // row_shr:2 (of x)
-  v = v + dpp_z<0x113, 0xF, 0xF>(x);     // row_shr:3 (of x)
-  v = v + dpp_z<0x114, 0xF, 0xE>(v);     // row_shr:4, banks 1-3
-  v = v + dpp_z<0x118, 0xF, 0xC>(v);     // row_shr:8, banks 2-3
-  v = v + dpp_z<0x142, 0xA, 0xF>(v);     // row_bcast:15, rows 1 and 3
-  v = v + dpp_z<0x143, 0xC, 0xF>(v);     // row_bcast:31, rows 2 and 3
-  return read_lane(v, 63);
-}
-
-// Wave sum of v where only the lanes in `mask` (a ballot, uniform) may be
-// non-zero: none -> 0, up to 8 lanes -> their values added in lane order
-// through scalar reads, else the shuffle tree.  Deterministic: the path
-// depends on the data alone.
-template <typename V>
-__device__ __forceinline__ V wave_sum_sparse(V v, uint64_t mask) {
-  if (mask == 0) return V(0);
-  if (__popcll(mask) <= 8) {
-    V acc = V(0);
-    while (mask) {
-      const int l = __ffsll((long long)mask) - 1;
-      acc += read_lane(v, l);
-      mask &= mask - 1;
-    }
-    return acc;
-  }
-  return wave_sum(v);
-}
-
-// (cost, index) minimum with the lowest index winning ties
-template <typename T>
-__device__ __forceinline__ void argmin_combine(T &v, int &k, T v2, int k2) {
-  if (v2 < v || (v2 == v && k2 < k)) {
-    v = v2;
-    k = k2;
-  }
-}
-
-// Ordering keys of costs (>= 0 or +inf): the bit patterns, in the width of
-// the working precision.
-__device__ __forceinline__ uint32_t key_bits(float v) { return __float_as_uint(v); }
-__device__ __forceinline__ uint64_t key_bits(double v) { return (uint64_t)__double_as_longlong(v); }
-__device__ __forceinline__ int top_bit(uint32_t v) { return 31 - __builtin_clz(v); }
-__device__ __forceinline__ int top_bit(uint64_t v) { return 63 - __builtin_clzll(v); }
-
-// ---------------------------------------------------------------------------
 // Select (elite and best-sample updates): one workgroup per controller.
 // Thread t owns the contiguous samples [t P, (t+1) P), P = max(16,
 // ceil(N / 1024)), the first 16 held in registers (the rest read again from
@@ -905,90 +991,6 @@ constexpr int kSelPer = 16;
 constexpr int kSelCopies = 16;
 constexpr int kHistStride = 257;
 static_assert(kSelBlock == 4 * 256, "the histogram reduction gives each bin one quad of threads");
-
-template <int CTRL, int RM, int BM>
-__device__ __forceinline__ uint32_t dpp_zu(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, BM, true);
-}
-template <int CTRL, int RM, int BM>
-__device__ __forceinline__ uint64_t dpp_zu(uint64_t v) {
-  const uint32_t lo = dpp_zu<CTRL, RM, BM>((uint32_t)v);
-  const uint32_t hi = dpp_zu<CTRL, RM, BM>((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint32_t read_lane_u32(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-
-// Inclusive prefix sum over the 64 lanes: the DPP tree of wave_sum with
-// every lane's partial kept (lane i ends with x[0] + ... + x[i]).
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
-  uint32_t v = x + dpp_zu<0x111, 0xF, 0xF>(x);
-  v += dpp_zu<0x112, 0xF, 0xF>(x);
-  v += dpp_zu<0x113, 0xF, 0xF>(x);
-  v += dpp_zu<0x114, 0xF, 0xE>(v);
-  v += dpp_zu<0x118, 0xF, 0xC>(v);
-  v += dpp_zu<0x142, 0xA, 0xF>(v);
-  v += dpp_zu<0x143, 0xC, 0xF>(v);
-  return v;
-}
-
-// Largest unsigned value over the 64 lanes, in every lane (the same tree;
-// zero, the identity, fills lanes outside a move's reach).
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
-  uint64_t v = umax64(x, dpp_zu<0x111, 0xF, 0xF>(x));
-  v = umax64(v, dpp_zu<0x112, 0xF, 0xF>(x));
-  v = umax64(v, dpp_zu<0x113, 0xF, 0xF>(x));
-  v = umax64(v, dpp_zu<0x114, 0xF, 0xE>(v));
-  v = umax64(v, dpp_zu<0x118, 0xF, 0xC>(v));
-  v = umax64(v, dpp_zu<0x142, 0xA, 0xF>(v));
-  v = umax64(v, dpp_zu<0x143, 0xC, 0xF>(v));
-  const uint32_t lo = read_lane_u32((uint32_t)v, 63), hi = read_lane_u32((uint32_t)(v >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Workgroup maxima of two unsigned values (one barrier; `red` is used by
-// this call alone).
-__device__ __forceinline__ void block_max2_u64(uint64_t a, uint64_t b, uint64_t (*red)[2],
-                                               uint64_t &ra, uint64_t &rb) {
-  a = wave_max_u64(a);
-  b = wave_max_u64(b);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    red[wid][0] = a;
-    red[wid][1] = b;
-  }
-  __syncthreads();
-  ra = 0;
-  rb = 0;
-  for (int i = 0; i < nw; ++i) {
-    ra = umax64(ra, red[i][0]);
-    rb = umax64(rb, red[i][1]);
-  }
-}
-
-// Lowest (cost, index) over the workgroup, lowest index on ties, from each
-// thread's own minimum; costs are >= 0 or +inf, so their bit patterns order
-// like the values.  FP32: key and index packed into one word (one barrier);
-// FP64: the key, then the index among the threads that hold it (two).
-template <typename T>
-__device__ __forceinline__ void block_argmin_packed(T &v, int &k, uint64_t (*red_a)[2],
-                                                    uint64_t (*red_b)[2]) {
-  uint64_t ra, unused;
-  if constexpr (sizeof(T) == 4) {
-    block_max2_u64(~(((uint64_t)key_bits(v) << 32) | (uint32_t)k), 0, red_a, ra, unused);
-    v = __uint_as_float((uint32_t)(~ra >> 32));
-    k = (int)(uint32_t)~ra;
-  } else {
-    block_max2_u64(~key_bits(v), 0, red_a, ra, unused);
-    const uint64_t kmin = ~ra;
-    uint64_t rk;
-    block_max2_u64(key_bits(v) == kmin ? ~(uint64_t)(uint32_t)k : 0, 0, red_b, rk, unused);
-    v = __longlong_as_double((long long)kmin);
-    k = (int)(uint32_t)~rk;
-  }
-}
 
 // Exclusive workgroup prefixes of two counts and their totals (one barrier).
 __device__ __forceinline__ void block_excl_scan2(uint32_t a, uint32_t b, uint2 *red,
@@ -1663,7 +1665,8 @@ static hipError_t launch_rollout(const LaunchTab &tab, const TickDesc &inl, int 
 
 template <bool INL>
 static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int precision,
-                                hipStream_t s, int timing, hipEvent_t *ev) {
+                                hipStream_t s, int timing, hipEvent_t *ev,
+                                const std::function<hipError_t()> *after_rollout) {
   // mean and sigma [max_rows][12]; spline weights [max_h][4] and bases [max_h]
   const size_t ts = precision == 1 ? 8 : 4;
   const size_t roll_lds = (size_t)tab.max_rows * 12 * 2 * ts +
@@ -1678,6 +1681,12 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
   hipError_t e = launch_rollout<INL>(tab, inl, precision, roll_lds, s,
                                      timing == 1 ? ev[0] : nullptr, timing == 1 ? ev[1] : nullptr);
   if (e != hipSuccess) return e;
+  // work for other streams that the host should enqueue while the rollout
+  // runs rather than after the whole iteration (the next tick's noise)
+  if (after_rollout && *after_rollout) {
+    e = (*after_rollout)();
+    if (e != hipSuccess) return e;
+  }
   if (timing == 2) (void)hipEventRecord(ev[2], s);
   // elite / best-sample controllers: selection, then the update; MPPI
   // controllers: the fused update alone (each kernel skips the others' items)
@@ -1709,15 +1718,14 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
 // non-null the launch holds exactly one controller whose descriptor travels
 // in the kernel arguments.
 hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
-                            hipEvent_t *ev, const TickDesc *inl) {
+                            hipEvent_t *ev, const TickDesc *inl,
+                            const std::function<hipError_t()> *after_rollout) {
   if (tab.n == 0) return hipSuccess;
-  if (inl) return launch_stages<true>(tab, *inl, precision, s, timing, ev);
+  if (inl) return launch_stages<true>(tab, *inl, precision, s, timing, ev, after_rollout);
   static const TickDesc none{};
-  return launch_stages<false>(tab, none, precision, s, timing, ev);
+  return launch_stages<false>(tab, none, precision, s, timing, ev, after_rollout);
 }
 
-// The noise stage alone (iterations tab.r .. tab.r + tab.r_count - 1), with
-// the descriptor inline when `inl` is non-null.
 // An empty one-workgroup dispatch carrying start/stop events: the interval
 // it spans is the events' own overhead (the start marker's completion to the
 // dispatch's first wave), which every event-timed launch includes once.
@@ -1728,6 +1736,8 @@ hipError_t launch_empty_timed(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return hipGetLastError();
 }
 
+// The noise stage alone (iterations tab.r .. tab.r + tab.r_count - 1), with
+// the descriptor inline when `inl` is non-null.
 hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl) {
   if (tab.n == 0) return hipSuccess;
   static const TickDesc none{};

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -36,7 +37,8 @@
 
 namespace sbs {
 hipError_t launch_iteration(const LaunchTab &tab, int precision, hipStream_t s, int timing,
-                            hipEvent_t *ev, const TickDesc *inl);
+                            hipEvent_t *ev, const TickDesc *inl,
+                            const std::function<hipError_t()> *after_rollout = nullptr);
 hipError_t launch_noise_only(const LaunchTab &tab, hipStream_t s, const TickDesc *inl);
 hipError_t launch_empty_timed(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 }
@@ -747,6 +749,35 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   }
   const int64_t t_launch = now_ns();
   const int tmode = timing_mode_now(rt);
+  // the next tick's noise goes into the other buffer on the second stream,
+  // after the tick that last read it; the host enqueues it right after this
+  // tick's first rollout, so that it runs beside the rollout (which leaves
+  // SIMDs idle at one controller) and not beside the update
+  std::function<hipError_t()> prefetch_next;
+  if (pc) {
+    prefetch_next = [&, pc, pbuf]() -> hipError_t {
+      hipStream_t s2 = rt->streams[1];
+      const int nb = pbuf ^ 1;
+      TickDesc nd = *inl;
+      nd.tick = ticks[0] + 1u;
+      nd.z = pc->pf_z[nb];
+      LaunchTab nt = tabs[0].first;
+      nt.r = 0;
+      nt.r_count = pc->cfg.iterations;
+      nt.skip_noise = 0;
+      nt.write_q = 0;
+      // fewer, longer noise waves: each thread makes kPrefetchRows rows
+      const int rows = rows_of(pc->cfg), nkb = (pc->cfg.N + kNoiseBlock - 1) / kNoiseBlock;
+      nt.noise_rpt = kPrefetchRows;
+      nt.total_noise = ((rows + kPrefetchRows - 1) / kPrefetchRows) * nkb;
+      hipError_t pe = hipStreamWaitEvent(s2, pc->pf_free[nb], 0);
+      if (pe == hipSuccess) pe = launch_noise_only(nt, s2, &nd);
+      if (pe == hipSuccess) pe = hipEventRecord(pc->pf_ready[nb], s2);
+      if (pe == hipSuccess) pc->pf_tick[nb] = (int64_t)ticks[0] + 1;
+      return pe;
+    };
+  }
+  bool first = true;
   for (auto &tp : tabs) {
     if (e != hipSuccess) break;
     hipEvent_t *ev = nullptr;
@@ -756,33 +787,12 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
       ev = &b->timing[base];
     }
-    e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl);
+    e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl, first ? &prefetch_next : nullptr);
+    first = false;
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
-  if (pc && e == hipSuccess) {
-    // the buffer this tick read is free once the tick is done; the next
-    // tick's noise goes into the other buffer on the second stream, after
-    // the tick that last read it
-    hipStream_t s2 = rt->streams[1];
-    e = hipEventRecord(pc->pf_free[pbuf], s);
-    const int nb = pbuf ^ 1;
-    TickDesc nd = *inl;
-    nd.tick = ticks[0] + 1u;
-    nd.z = pc->pf_z[nb];
-    LaunchTab nt = tabs[0].first;
-    nt.r = 0;
-    nt.r_count = pc->cfg.iterations;
-    nt.skip_noise = 0;
-    nt.write_q = 0;
-    // fewer, longer noise waves: each thread makes kPrefetchRows rows
-    const int rows = rows_of(pc->cfg), nkb = (pc->cfg.N + kNoiseBlock - 1) / kNoiseBlock;
-    nt.noise_rpt = kPrefetchRows;
-    nt.total_noise = ((rows + kPrefetchRows - 1) / kPrefetchRows) * nkb;
-    if (e == hipSuccess) e = hipStreamWaitEvent(s2, pc->pf_free[nb], 0);
-    if (e == hipSuccess) e = launch_noise_only(nt, s2, &nd);
-    if (e == hipSuccess) e = hipEventRecord(pc->pf_ready[nb], s2);
-    if (e == hipSuccess) pc->pf_tick[nb] = (int64_t)ticks[0] + 1;
-  }
+  // the buffer this tick read is free once the whole tick is done
+  if (pc && e == hipSuccess) e = hipEventRecord(pc->pf_free[pbuf], s);
   if (e != hipSuccess) {
     // the stream may still run what was enqueued: wait before freeing
     (void)hipStreamSynchronize(s);
