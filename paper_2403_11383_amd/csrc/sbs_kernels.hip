@@ -992,6 +992,19 @@ constexpr int kSelCopies = 16;
 constexpr int kHistStride = 257;
 static_assert(kSelBlock == 4 * 256, "the histogram reduction gives each bin one quad of threads");
 
+// Index of the wave's lowest (cost, index), lowest index on ties, from each
+// lane's own minimum (every lane gets it; no barrier).  A wave whose lanes
+// hold no sample returns the empty index 0x7fffffff.
+template <typename T>
+__device__ __forceinline__ int wave_argmin_index(T v, int k) {
+  if constexpr (sizeof(T) == 4) {
+    return (int)(uint32_t)~wave_max_u64(~(((uint64_t)key_bits(v) << 32) | (uint32_t)k));
+  } else {
+    const uint64_t kmin = ~wave_max_u64(~key_bits(v));
+    return (int)(uint32_t)~wave_max_u64(key_bits(v) == kmin ? ~(uint64_t)(uint32_t)k : 0);
+  }
+}
+
 // Exclusive workgroup prefixes of two counts and their totals (one barrier).
 __device__ __forceinline__ void block_excl_scan2(uint32_t a, uint32_t b, uint2 *red,
                                                  uint32_t &a_before, uint32_t &b_before,
@@ -1481,6 +1494,33 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
 // iteration, the action.
 constexpr int kMppiPer = 16;
 
+// Sample k's share of the fused MPPI sums: weight w = exp((beta - J) / lambda)
+// in the working precision and, when it does not underflow, the weighted
+// noise row (already requested when k is its wave's lowest cost, kw), the
+// FP64 normaliser and frequency sums and the count of weighted samples.
+template <typename T>
+__device__ __forceinline__ void mppi_visit(const TickDesc &d, const float *zj, int k, T Jk, T bv,
+                                           T il, int kw, float4 pz0, float4 pz1, float4 pz2,
+                                           T (&f1)[12], double &sw,
+                                           double &swf, double &cnt) {
+  const T wk = exp_t((bv - Jk) * il);
+  if (wk == T(0)) return;
+  float4 z0 = pz0, z1 = pz1, z2 = pz2;
+  if (k != kw) {
+    const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)k * 12);
+    z0 = src[0];
+    z1 = src[1];
+    z2 = src[2];
+  }
+  cnt += 1.0;
+  sw += (double)wk;
+  swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+  const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                        z2.x, z2.y, z2.z, z2.w};
+#pragma unroll
+  for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
+}
+
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
   const int b = blockIdx.x;
@@ -1518,34 +1558,33 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
 #pragma unroll
   for (int i = 0; i < kMppiPer; ++i) argmin_combine(bv, bk, Jr[i], tid + i * kMppiBlock);
   for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
+  // The noise row of each wave's lowest-cost sample is requested before the
+  // workgroup's lowest cost is known: when, as usual at small lambda, only
+  // the lowest cost carries weight, its row is then already on its way.
+  const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
+  const int kw = wave_argmin_index(bv, bk);
+  float4 pz0 = make_float4(0.f, 0.f, 0.f, 0.f), pz1 = pz0, pz2 = pz0;
+  if (kw < N) {
+    const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)kw * 12);
+    pz0 = src[0];
+    pz1 = src[1];
+    pz2 = src[2];
+  }
   block_argmin_packed(bv, bk, red_a, red_b);
   const bool skip = !finite_t(bv);
 
-  const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
   T f1[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) f1[c] = T(0);
   double sw = 0.0, swf = 0.0, cnt = 0.0;
   if (!skip) {
     const T il = (T)d.inv_lambda;
-    auto visit = [&](int k, T Jk) {
-      const T wk = exp_t((bv - Jk) * il);
-      if (wk != T(0)) {
-        const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)k * 12);
-        const float4 z0 = src[0], z1 = src[1], z2 = src[2];
-        cnt += 1.0;
-        sw += (double)wk;
-        swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
-        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                              z2.x, z2.y, z2.z, z2.w};
-#pragma unroll
-        for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
-      }
-    };
 #pragma unroll
     for (int i = 0; i < kMppiPer; ++i)
-      if (tid + i * kMppiBlock < N) visit(tid + i * kMppiBlock, Jr[i]);
-    for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) visit(k, Jg[k]);
+      if (tid + i * kMppiBlock < N)
+        mppi_visit(d, zj, tid + i * kMppiBlock, Jr[i], bv, il, kw, pz0, pz1, pz2, f1, sw, swf, cnt);
+    for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock)
+      mppi_visit(d, zj, k, Jg[k], bv, il, kw, pz0, pz1, pz2, f1, sw, swf, cnt);
   }
   // within a wave in the working precision (FP64 for the normaliser), then
   // FP64 across waves

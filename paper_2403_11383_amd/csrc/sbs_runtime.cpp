@@ -750,9 +750,13 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   const int64_t t_launch = now_ns();
   const int tmode = timing_mode_now(rt);
   // the next tick's noise goes into the other buffer on the second stream,
-  // after the tick that last read it; the host enqueues it right after this
-  // tick's first rollout, so that it runs beside the rollout (which leaves
-  // SIMDs idle at one controller) and not beside the update
+  // after the tick that last read it.  With several iterations per tick the
+  // host enqueues it right after the first rollout, so that it runs beside
+  // that rollout rather than beside the later iterations' select and update
+  // stages; with one iteration it is enqueued after the tick, so that the
+  // rollout runs alone and the noise overlaps the short update and the
+  // host's turnaround (both orders measured on the MI355X: each is the
+  // faster one for its case).
   std::function<hipError_t()> prefetch_next;
   if (pc) {
     prefetch_next = [&, pc, pbuf]() -> hipError_t {
@@ -787,12 +791,14 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
       ev = &b->timing[base];
     }
-    e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl, first ? &prefetch_next : nullptr);
+    const bool early = first && pc && pc->cfg.iterations > 1;
+    e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl, early ? &prefetch_next : nullptr);
     first = false;
   }
   if (e == hipSuccess) e = hipEventRecord(b->done, s);
   // the buffer this tick read is free once the whole tick is done
   if (pc && e == hipSuccess) e = hipEventRecord(pc->pf_free[pbuf], s);
+  if (pc && pc->cfg.iterations == 1 && e == hipSuccess) e = prefetch_next();
   if (e != hipSuccess) {
     // the stream may still run what was enqueued: wait before freeing
     (void)hipStreamSynchronize(s);
