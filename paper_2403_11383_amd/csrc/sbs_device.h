@@ -8,14 +8,14 @@
 
 namespace sbs {
 
-constexpr int kRollBlock = 64;     // default rollout workgroup (one wave64)
 constexpr int kNoiseBlock = 256;   // samples per noise workgroup at one step
 constexpr int kUpdBlock = 512;     // threads per update workgroup (elite, best sample)
 constexpr int kMppiBlock = 1024;   // threads per fused MPPI update workgroup
 constexpr int kSelBlock = 1024;    // threads of the per-controller select block
 constexpr int kResultDoubles = 24; // action record
 constexpr int kItScalars = 16;     // per-iteration scalars
-constexpr int kMaxH = 256;         // longest horizon the update stage holds in LDS
+constexpr int kMaxH = 256;         // longest horizon: the rollout stages the mean, std and
+                                   // spline tables in LDS (58 KB at FP64 and H = 256)
 
 // result record layout (doubles)
 enum : int {
