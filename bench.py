@@ -138,9 +138,20 @@ def cpu_baseline(cfg, seconds=10.0):
             break
     dt = time.perf_counter() - t0
     steps = n * cfg["N"] * cfg["H"] * cfg["iterations"]
+    # and on one core, for a few seconds
+    n1, t1 = 0, time.perf_counter()
+    mu1 = np.tile([0.0, 0.0, 0.5 * cfg["mass"] * cfg["gravity"]] * 4, (oracle.rows(cfg), 1))
+    while True:
+        mu1 = oracle.tick(cfg, mu1, cfg["mu_f0"], n1, inp, nthreads=1)["mu_next"]
+        n1 += 1
+        if time.perf_counter() - t1 >= min(3.0, seconds):
+            break
+    dt1 = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} full ticks (N={cfg['N']}, H={cfg['H']}) from the closed loop's "
-                      f"initial state, {dt:.1f} s wall"}
+                      f"initial state, {dt:.1f} s wall",
+            "single_core": {"value": n1 * cfg["N"] * cfg["H"] * cfg["iterations"] / dt1,
+                            "sample": f"{n1} full ticks on one thread, {dt1:.1f} s wall"}}
 
 
 def batched(rt, binding, workloads, steps, warmup, cache_path=None):
@@ -317,6 +328,11 @@ def main():
                      "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
                      "traffic": stored_traffic("k_rollout", workload_key),
                      "flop_per_launch": flop, "duration_us": t_roll * 1e6,
+                     # four lanes per sample: waves in flight against the
+                     # chip's 1024 SIMDs (one wave per SIMD leaves the
+                     # step-to-step dependency chain exposed)
+                     "waves": (N * 4 + 63) // 64 if N <= 32768 else (N + 63) // 64,
+                     "simds": 1024,
                      "event_interval_us": timing["rollout_ns"] * 1e-3,
                      "event_overhead_us": ev_ovh_ns * 1e-3,
                      "event_overhead_taken_us": ev_taken_ns * 1e-3},
