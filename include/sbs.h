@@ -265,6 +265,18 @@ int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st, const sbs
 int sbs_plant_step_wrench(const sbs_controller_cfg *cfg, sbs_plant_state *st,
                           const sbs_action *act, const double ext_wrench[6],
                           const double v_ref[3]);
+/* One closed-loop cycle of a simulated robot in native code (for host-side
+ * simulation loops, where a round trip through an interpreter per call would
+ * dominate the cycle): builds the tick input from the plant state -- x0 =
+ * state, world footholds, gait phase, reference position (x, y of the state,
+ * z_ref), v_ref, yaw_ref -- then sbs_submit_tick, sbs_fetch_action with no
+ * time limit, and sbs_plant_step_wrench under the action and ext_wrench.
+ * cfg gives the plant's model constants (normally the controller's).  The
+ * action is returned in *out; the status is that of the first failing call
+ * (the plant is advanced only when all succeed). */
+int sbs_closed_loop_step(sbs_runtime *rt, int32_t id, const sbs_controller_cfg *cfg,
+                         sbs_plant_state *st, const double ext_wrench[6], const double v_ref[3],
+                         double z_ref, double yaw_ref, sbs_action *out);
 
 const char *sbs_last_error(void);
 int32_t sbs_abi_version(void);

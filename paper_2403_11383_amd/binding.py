@@ -31,7 +31,7 @@ EXPORTED = [
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -126,6 +126,8 @@ def lib():
                                      C.POINTER(Action), vp, vp]
         L.sbs_plant_step_wrench.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
+        L.sbs_closed_loop_step.argtypes = [vp, i32, C.POINTER(ControllerCfg), C.POINTER(PlantState),
+                                           vp, vp, C.c_double, C.c_double, C.POINTER(Action)]
         L.sbs_last_error.restype = C.c_char_p
         L.sbs_abi_version.restype = i32
         for name in EXPORTED:
@@ -447,35 +449,26 @@ class Plant:
 
 
 class ClosedLoop:
-    """One controller driving a Plant with preallocated C structs: each step
-    copies the plant state into the tick input, runs the tick, and applies
-    the returned action to the plant (for closed-loop runs and benchmarks)."""
+    """One controller driving a Plant: each step is one sbs_closed_loop_step
+    call (tick input from the plant state, submit, wait for the action, one
+    plant step under it and the external wrench), with preallocated C
+    structs (for closed-loop runs and benchmarks)."""
 
     def __init__(self, rt: Runtime, cid: int, plant: Plant, v_ref=(0.0, 0.0, 0.0),
                  z_ref: float = 0.35, yaw_ref: float = 0.0):
         self.rt, self.cid, self.plant = rt, cid, plant
-        self.inp = TickInput()
-        self.inp.v_ref[:] = [float(v) for v in v_ref]
-        self.inp.yaw_ref = float(yaw_ref)
         self.z_ref = float(z_ref)
+        self.yaw_ref = float(yaw_ref)
         self.act = Action()
-        self.ticket = C.c_uint64()
         self.ext = np.zeros(6)
         self.vref = np.array([float(v) for v in v_ref])
         self._L = lib()
 
     def step(self, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0)) -> Action:
-        st, inp, L = self.plant.st, self.inp, self._L
-        C.memmove(inp.x0, st.x, 96)
-        C.memmove(inp.foot_pos, st.foot_pos, 96)
-        inp.p_ref0[0] = st.x[0]
-        inp.p_ref0[1] = st.x[1]
-        inp.p_ref0[2] = self.z_ref
-        inp.phase_robot = st.phase
-        _check(L.sbs_submit_tick(self.rt._h, self.cid, C.byref(inp), C.byref(self.ticket)))
-        _check(L.sbs_fetch_action(self.rt._h, self.ticket, C.byref(self.act), -1))
         self.ext[:3] = ext_force
         self.ext[3:] = ext_torque
-        _check(L.sbs_plant_step_wrench(C.byref(self.plant.cfg), C.byref(st), C.byref(self.act),
-                                       self.ext.ctypes.data, self.vref.ctypes.data))
+        _check(self._L.sbs_closed_loop_step(
+            self.rt._h, self.cid, C.byref(self.plant.cfg), C.byref(self.plant.st),
+            self.ext.ctypes.data, self.vref.ctypes.data, self.z_ref, self.yaw_ref,
+            C.byref(self.act)))
         return self.act

@@ -84,3 +84,30 @@ extern "C" int sbs_plant_step(const sbs_controller_cfg *cfg, sbs_plant_state *st
   const double w[6] = {ext_force[0], ext_force[1], ext_force[2], 0.0, 0.0, 0.0};
   return sbs_plant_step_wrench(cfg, st, act, w, v_ref);
 }
+
+// One closed-loop cycle of a simulated robot, all in native code: the tick
+// input from the plant (state estimate, world footholds, gait phase; the
+// reference starts at the robot's horizontal position at height z_ref),
+// submit, wait for the action, one plant step under it.
+extern "C" int sbs_closed_loop_step(sbs_runtime *rt, int32_t id, const sbs_controller_cfg *cfg,
+                                    sbs_plant_state *st, const double ext_wrench[6],
+                                    const double v_ref[3], double z_ref, double yaw_ref,
+                                    sbs_action *out) {
+  if (!rt || !cfg || !st || !ext_wrench || !v_ref || !out) return SBS_EINVAL;
+  sbs_tick_input in;
+  std::memcpy(in.x0, st->x, sizeof in.x0);
+  std::memcpy(in.foot_pos, st->foot_pos, sizeof in.foot_pos);
+  in.p_ref0[0] = st->x[0];
+  in.p_ref0[1] = st->x[1];
+  in.p_ref0[2] = z_ref;
+  for (int c = 0; c < 3; ++c) in.v_ref[c] = v_ref[c];
+  in.yaw_ref = yaw_ref;
+  in.phase_robot = st->phase;
+  in.reserved0 = 0;
+  uint64_t ticket = 0;
+  int rc = sbs_submit_tick(rt, id, &in, &ticket);
+  if (rc != SBS_OK) return rc;
+  rc = sbs_fetch_action(rt, ticket, out, -1);
+  if (rc != SBS_OK) return rc;
+  return sbs_plant_step_wrench(cfg, st, out, ext_wrench, v_ref);
+}

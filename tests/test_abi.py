@@ -49,6 +49,8 @@ def test_null_arguments_are_rejected_without_a_device(built):
     assert b"arena" in L.sbs_last_error()
     assert L.sbs_runtime_destroy(None) == built.EINVAL
     assert L.sbs_fetch_action(None, 1, None, 0) == built.EINVAL
+    assert L.sbs_closed_loop_step(None, 0, None, None, None, None, 0.35, 0.0, None) == built.EINVAL
+    assert L.sbs_timing_overhead(None, 1, None) == built.EINVAL
 
 
 def test_struct_layouts_match_c(built):
