@@ -10,13 +10,15 @@ here; a single-rigid-body quadruped with these constants stands in for them):
 * mass 21.5 kg, diagonal inertia (0.07, 0.26, 0.24) kg m^2, g = 9.81 m/s^2,
   hips at (+-0.24, +-0.13, 0) m in the body frame, feet on flat ground at
   z = 0 (the CoM starts 0.35 m above it), trot (FL/RR in phase, FR/RL half a
-  cycle later), duty factor 0.5, dt = 0.02 s, Q = I, R = 1e-4 I (quadratic
-  cost of Sec. V with positive diagonal weights).
+  cycle later), duty factor 0.5, dt = 0.02 s, Q = I (C1 and the disturbance
+  study: Q_STIFF), R = 1e-4 I (quadratic cost of Sec. V with positive
+  diagonal weights).
 * ``c0``  plain MPPI, FP64, N=256, H=25, fixed trot 1.4 Hz, GRF noise 20 N,
   lambda = 1, no friction clip, reference velocity 0.3 m/s.
 * ``c1``  MPPI with per-sample gait frequency ~ U[1.0, 2.5] Hz, FP32,
-  N=10240, H=50, noise 25 N, friction cone mu = 0.5, 100 receding-horizon
-  ticks, 40 N lateral push from tick 30 (the shape of the paper's push test).
+  N=10240, H=50, noise 10 N, lambda = 30, the stiff weights Q_STIFF,
+  friction cone mu = 0.5, 100 receding-horizon ticks, 40 N lateral push from
+  tick 30 (the shape of the paper's push test).
 * ``c2``  elite (CEM-style) sampler, FP32, N=16384, H=50, 3 iterations per
   tick, top 10 %, Gaussian frequency (mean 1.4 Hz, std 0.4), reference
   velocity ~ U[-0.5, 0.5] m/s, 100 ticks.
@@ -40,6 +42,9 @@ TROT_OFFSETS = (0, 1 << 31, 1 << 31, 0)
 PACE_OFFSETS = (0, 1 << 31, 0, 1 << 31)
 HEIGHT = 0.35
 DT = 0.02
+# state weights [p, Phi, v, omega] that hold the plant up in closed loop:
+# height and attitude stiff (1000) against R = 1e-4 on the GRFs
+Q_STIFF = (10.0, 10.0, 1000.0, 1000.0, 1000.0, 100.0, 10.0, 10.0, 10.0, 1.0, 1.0, 1.0)
 
 
 def base_model() -> dict:
@@ -62,8 +67,12 @@ def config(name: str, **over) -> dict:
         c.update(N=256, H=25, precision="fp64", method="mppi", freq_mode="fixed",
                  sigma_grf=20.0, friction_on=False, rho=0.0, seed=0)
     elif name == "c1":
+        # the closed loop's weights: height and attitude stiff against the GRF
+        # effort, 10 N noise, lambda = 30 (with Q = I and 25 N the plant is not
+        # held up and most benchmark episodes end in a fall)
         c.update(N=10240, H=50, precision="fp32", method="mppi", freq_mode="uniform",
-                 sigma_grf=25.0, friction_on=True, mu_fric=0.5, rho=1.0, seed=1)
+                 sigma_grf=10.0, friction_on=True, mu_fric=0.5, rho=1.0, seed=1,
+                 Q=list(Q_STIFF), **{"lambda": 30.0})
     elif name == "c2":
         c.update(N=16384, H=50, precision="fp32", method="elite", iterations=3,
                  elite_frac=0.1, freq_mode="gaussian", mu_f0=1.4, sigma_f=0.4,
@@ -166,7 +175,7 @@ def c4_arrivals(seed: int = 4, robots: int = 256, rate_hz: float = 50.0,
 # given, so the study weights stiffen height and attitude against the GRF
 # effort (a 5 cm height error then costs as much as a 158 N error in one GRF
 # component).
-STUDY_Q = [10.0, 10.0, 1000.0, 1000.0, 1000.0, 100.0, 10.0, 10.0, 10.0, 1.0, 1.0, 1.0]
+STUDY_Q = list(Q_STIFF)
 STUDY_TICKS = 400
 STUDY_PUSH = (100, 250, 40.0)  # first tick, end tick, lateral force [N]
 STUDY_VREF = (0.0, 0.1, 0.0)
