@@ -163,9 +163,20 @@ int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_t
  * SBS_ETIMEDOUT if not done; on SBS_OK the ticket is consumed. */
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us);
 
+/* sbs_fetch_action for n tickets in order (out[i] for tickets[i]), each
+ * waited for up to timeout_us: one call for a batch's or plan's tickets.
+ * Returns at the first ticket that fails or is not ready with that status;
+ * the tickets before it are consumed and their actions written, the rest
+ * are left as they were.  SBS_EINVAL on a null pointer or n < 0. */
+int sbs_fetch_actions(sbs_runtime *rt, int32_t n, const uint64_t *tickets, sbs_action *out,
+                      int64_t timeout_us);
+
 /* Fixed-membership batch for repeated fused ticks: reserves the workspace of
  * the n controllers once and records the whole tick (all stages and
- * iterations) as a HIP graph that sbs_plan_submit replays with new inputs. */
+ * iterations) as a HIP graph that sbs_plan_submit replays with new inputs.
+ * sbs_plan_submit returns SBS_EAGAIN while the plan's previous replay is
+ * still running (its actions can be fetched before its last kernel ends):
+ * submit again. */
 int sbs_plan_create(sbs_runtime *rt, int32_t n, const int32_t *ids, int32_t use_graph,
                     int32_t *plan);
 int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uint64_t *tickets);

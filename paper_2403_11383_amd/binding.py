@@ -9,6 +9,7 @@ other execution path.
 from __future__ import annotations
 
 import ctypes as C
+import time
 import os
 
 import numpy as np
@@ -27,7 +28,7 @@ OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EDEVICE, ECANCELED, ENOENT = 0, -1, -2, -
 
 EXPORTED = [
     "sbs_runtime_create", "sbs_runtime_destroy", "sbs_init_controller",
-    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action",
+    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions",
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
@@ -106,6 +107,7 @@ def lib():
         L.sbs_submit_tick.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_submit_batch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_fetch_action.argtypes = [vp, u64, C.POINTER(Action), C.c_int64]
+        L.sbs_fetch_actions.argtypes = [vp, i32, vp, C.POINTER(Action), C.c_int64]
         L.sbs_plan_create.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
         L.sbs_plan_submit.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_plan_destroy.argtypes = [vp, i32]
@@ -291,8 +293,27 @@ class Runtime:
         n = len(inputs)
         ins = (TickInput * n)(*[make_input(x) for x in inputs])
         tks = (C.c_uint64 * n)()
-        _check(lib().sbs_plan_submit(self._h, plan, ins, tks))
+        self.plan_submit_raw(plan, ins, tks)
         return list(tks)
+
+    def plan_submit_raw(self, plan: int, ins, tickets):
+        """plan_submit with caller-built ctypes arrays (TickInput * n inputs,
+        c_uint64 * n tickets), for loops that resubmit the same inputs; waits
+        (on the host) while the previous replay is still finishing."""
+        L = lib()
+        while True:
+            rc = L.sbs_plan_submit(self._h, plan, ins, tickets)
+            if rc != EAGAIN:
+                break
+            time.sleep(0)
+        _check(rc)
+
+    def fetch_many(self, tickets, out, timeout_us: int = -1):
+        """Fetch len(tickets) actions in one call into out (Action * n)."""
+        n = len(tickets)
+        rc = lib().sbs_fetch_actions(self._h, n, C.cast(tickets, C.c_void_p), out, timeout_us)
+        _check(rc)
+        return out
 
     def plan_destroy(self, plan: int):
         _check(lib().sbs_plan_destroy(self._h, plan))

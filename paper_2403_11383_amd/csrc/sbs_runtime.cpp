@@ -1183,6 +1183,16 @@ int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t 
   }
 }
 
+int sbs_fetch_actions(sbs_runtime *rt, int32_t n, const uint64_t *tickets, sbs_action *out,
+                      int64_t timeout_us) {
+  if (!rt || n < 0 || (n > 0 && (!tickets || !out))) return fail(SBS_EINVAL, "NULL argument or n < 0");
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = sbs_fetch_action(rt, tickets[i], out + i, timeout_us);
+    if (rc != SBS_OK) return rc;
+  }
+  return SBS_OK;
+}
+
 int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::unique_lock<std::mutex> lk(rt->mu);

@@ -88,3 +88,25 @@ def test_serving_auto_lanes_within_tolerance():
         if np.abs(x["grf"] - y["grf"]).max() > 1e-4 * mg2:
             # only a near-tie of the two best samples may flip the choice
             pytest.skip("near-tie between best samples")
+
+
+def test_fetch_many_equals_one_by_one():
+    """sbs_fetch_actions returns, in ticket order, the actions that
+    sbs_fetch_action returns one ticket at a time (serving mode, so the
+    tickets complete out of submission order inside the runtime)."""
+    from paper_2403_11383_amd import binding
+    cfgs, inps = fleet(8)
+    one, _ = run("serving", cfgs, inps, ticks=2)
+    rt = binding.Runtime(arena_bytes=1 << 30, mode="serving", two_streams=True)
+    rt.set_rollout_lanes(1)
+    ids = [rt.init_controller(c) for c in cfgs]
+    tks = []
+    for t in range(2):
+        for cid, inp in zip(ids, inps):
+            tks.append(rt.submit_tick(cid, inp))
+    arr = (binding.C.c_uint64 * len(tks))(*tks)
+    acts = (binding.Action * len(tks))()
+    rt.fetch_many(arr, acts, timeout_us=30_000_000)
+    rt.close()
+    for a, b in zip(one, acts):
+        same(a, binding.action_dict(b))
