@@ -352,9 +352,8 @@ void give_event(sbs_runtime *rt, hipEvent_t e) {
 }
 
 // Events that only time work: without the system-scope fence, recording one
-// does not write back and invalidate the caches, so the measured interval is
-// the bracketed work's own (with the fence, the write-back of whatever the
-// concurrent noise kernel left dirty lands inside the rollout's interval).
+// does not write back and invalidate the caches, so the measured interval
+// holds the bracketed work and no cache maintenance of its own.
 hipEvent_t take_timing_event(sbs_runtime *rt) {
   if (!rt->timing_pool.empty()) {
     hipEvent_t e = rt->timing_pool.back();
@@ -615,7 +614,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
 
 // Timing mode of the next launch: mode 1 attaches the rollout's dispatch
 // events to one launch in kTimingStride (attaching them costs the tick about
-// as much as the kernel's own launch), mode 2 every launch.
+// as much as the kernel's own launch), mode 3 to every launch; mode 2 puts
+// event commands around every stage of every launch.
 constexpr uint64_t kTimingStride = 16;
 int timing_mode_now(sbs_runtime *rt) {
   if (rt->timing == 3) return 1;  // dispatch events on every launch
