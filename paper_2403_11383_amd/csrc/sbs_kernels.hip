@@ -38,14 +38,24 @@ namespace sbs {
 // fixed sequence of IEEE FP32 operations (no contraction), so the result is
 // reproducible bit for bit on any IEEE machine.
 // ---------------------------------------------------------------------------
+// a ^ b ^ k in one VALU instruction: gfx950's three-input bitwise operation
+// with truth table 0x96 (odd parity).  The key word k is wave-uniform and is
+// read from a scalar register.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// The key (k0, k1) must be uniform across the wave (one controller's seed).
 __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
                                               uint32_t &c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -61,10 +71,9 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t w0, uint32_t w1) {
   const uint32_t i2 = w1 >> 8;          // u2 = i2 2^-24 in [0, 1)
   int e = 31 - __clz((int)i1);
   float m = (float)i1 * __uint_as_float((uint32_t)(127 - e) << 23);  // [1, 2)
-  if (m > 0x1.6a09e6p+0f) {
-    m = m * 0.5f;
-    e = e + 1;
-  }
+  const bool above = m > 0x1.6a09e6p+0f;  // fold onto [sqrt(2)/2, sqrt(2)]
+  m = above ? m * 0.5f : m;
+  e = above ? e + 1 : e;
   const float s = (m - 1.0f) / (m + 1.0f);
   const float t = s * s;
   float p = __builtin_fmaf(t, 0x1.c71c72p-4f, 0x1.24924ap-3f);
@@ -90,9 +99,13 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t w0, uint32_t w1) {
   pc = __builtin_fmaf(a2, pc, 0x1.03c1f0p+6f);
   pc = __builtin_fmaf(a2, pc, -0x1.3bd3ccp+4f);
   const float cs = __builtin_fmaf(a2, pc, 1.0f);
+  // quadrant by rotation: quadrant 1 maps (cos, sin) to (-sin, cos), 2 to
+  // (-cos, -sin), 3 to (sin, -cos); the negations are sign-bit flips
   const uint32_t quad = n & 3u;
-  float c = (quad == 0u) ? cs : (quad == 1u) ? -sn : (quad == 2u) ? -cs : sn;
-  float sv = (quad == 0u) ? sn : (quad == 1u) ? cs : (quad == 2u) ? -sn : -cs;
+  const bool swap = (quad & 1u) != 0u;
+  const float c0 = swap ? sn : cs, s0 = swap ? cs : sn;
+  const float c = __uint_as_float(__float_as_uint(c0) ^ (((quad + 1u) & 2u) << 30));
+  const float sv = __uint_as_float(__float_as_uint(s0) ^ ((quad & 2u) << 30));
   return make_float2(rho * c, rho * sv);
 }
 
@@ -206,8 +219,11 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
   const int k = (local - jb * nkb) * kNoiseBlock + (int)threadIdx.x;
   if (k >= d.N) return;
   const int r = tab.r + rr;
+  // descriptor fields in registers: the noise stores could alias the
+  // descriptor for all the compiler knows, which would reload them per row
   const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
-  const uint32_t rw = (uint32_t)r << 8;
+  const uint32_t rw = (uint32_t)r << 8, tick = d.tick;
+  const int N = d.N;
   float *zr = d.z + (size_t)r * d.z_iter_stride;
   // rows jb * rpt .. jb * rpt + rpt - 1 of sample k (rpt = 1 in batched
   // launches; a single controller's ahead-of-time noise uses fewer, longer
@@ -218,7 +234,7 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
     float z[12];
 #pragma unroll
     for (uint32_t call = 0; call < 3; ++call) {
-      uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = d.tick, c3 = rw | call;
+      uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = tick, c3 = rw | call;
       philox4x32_10(c0, c1, c2, c3, key0, key1);
       const float2 ga = gauss_pair(c0, c1);
       const float2 gb = gauss_pair(c2, c3);
@@ -227,7 +243,7 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
       z[4 * call + 2] = gb.x;
       z[4 * call + 3] = gb.y;
     }
-    float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * d.N + k) * 12);
+    float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * N + k) * 12);
     dst[0] = make_float4(z[0], z[1], z[2], z[3]);
     dst[1] = make_float4(z[4], z[5], z[6], z[7]);
     dst[2] = make_float4(z[8], z[9], z[10], z[11]);
@@ -562,13 +578,17 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   uint32_t ph[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) ph[l] = d.phase_robot + d.phase_offset[l];
-  bool prev[4] = {false, false, false, false};
+  // a leg touches down where it is in stance and was not at the previous
+  // step; starting from "in stance" keeps the first step's feet where the
+  // tick put them
+  bool prev[4] = {true, true, true, true};
   T J = T(0), Jc = T(0), tj = T(0);
 
   const float4 *zp =
       reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
   const size_t zstride = (size_t)N * 3;  // float4 per row
   float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
+  const float4 *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
   // spline: the sample's knots wb .. wb + 3 (theta = mu + sigma z), and the
   // noise of knot wb + 4 loaded ahead
   T win[4][12];
@@ -614,14 +634,14 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
     } else {
       const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                             z2.x, z2.y, z2.z, z2.w};
-      if (j + 1 < H) {  // prefetch the next step's noise
-        const float4 *zn = zp + (size_t)(j + 1) * zstride;
-        z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
-      }
       const T *muj = s_mu + j * 12;
       const T *sgj = s_sig + j * 12;
 #pragma unroll
       for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+      // the next step's noise (the last step reads its own row again), into
+      // the registers this step's noise has just left
+      z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
+      zq += (j + 2 < H) ? zstride : 0;
     }
     // contact schedule
     bool st[4];
@@ -648,7 +668,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
       const T by = x[1] + half_tst * c.vr[1] + cap * (x[7] - c.vr[1]);
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
-        const bool td = (j > 0) && st[l] && !prev[l];
+        const bool td = st[l] && !prev[l];
         const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
         const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
         const T ny = by + R10 * hx + R11 * hy + R12 * hz;
@@ -824,12 +844,13 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   for (int i = 0; i < 12; ++i) x[i] = (float)d.x0[i];
   float pfx = (float)d.foot[3 * l], pfy = (float)d.foot[3 * l + 1], pfz = (float)d.foot[3 * l + 2];
   uint32_t ph = d.phase_robot + d.phase_offset[l];
-  bool prev = false;
+  bool prev = true;  // no touchdown at the first step (tick's footholds)
   float J = 0.f, Jc = 0.f, tj = 0.f;
 
   const float *zp = d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12 + 3 * l;
   const size_t zstride = (size_t)N * 12;
   float za = zp[0], zb = zp[1], zc = zp[2];
+  const float *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
   // spline: this leg's three forces at knots wb .. wb + 3, and the noise of
   // knot wb + 4 loaded ahead
   float win[4][3];
@@ -870,15 +891,13 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
       uy = w0 * win[0][1] + w1 * win[1][1] + w2 * win[2][1] + w3 * win[3][1];
       uz = w0 * win[0][2] + w1 * win[1][2] + w2 * win[2][2] + w3 * win[3][2];
     } else {
-      const float z0 = za, z1 = zb, z2 = zc;
-      if (j + 1 < H) {
-        const float *zn = zp + (size_t)(j + 1) * zstride;
-        za = zn[0]; zb = zn[1]; zc = zn[2];
-      }
       const int o = j * 12 + 3 * l;
-      ux = s_mu[o] + s_sig[o] * z0;
-      uy = s_mu[o + 1] + s_sig[o + 1] * z1;
-      uz = s_mu[o + 2] + s_sig[o + 2] * z2;
+      ux = s_mu[o] + s_sig[o] * za;
+      uy = s_mu[o + 1] + s_sig[o + 1] * zb;
+      uz = s_mu[o + 2] + s_sig[o + 2] * zc;
+      // the next step's noise (the last step reads its own row again)
+      za = zq[0]; zb = zq[1]; zc = zq[2];
+      zq += (j + 2 < H) ? zstride : 0;
     }
     const bool st = duty_full || (ph < duty_q);
     const float nst = quad_sum(st ? 1.f : 0.f);
@@ -897,7 +916,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     {
       const float zcm = x[2] > 0.f ? x[2] : 0.f;
       const float cap = sqrt_t(zcm * inv_g);
-      const bool td = (j > 0) && st && !prev;
+      const bool td = st && !prev;
       const float nx = x[0] + half_tst * vr0 + cap * (x[6] - vr0) + R00 * hx + R01 * hy + R02 * hz;
       const float ny = x[1] + half_tst * vr1 + cap * (x[7] - vr1) + R10 * hx + R11 * hy + R12 * hz;
       pfx = td ? nx : pfx;
