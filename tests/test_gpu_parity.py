@@ -182,6 +182,20 @@ def test_fp32_mppi_small(rt, lanes):
     np.testing.assert_array_equal(out["act"]["contact"], ref["contact"])
 
 
+@pytest.mark.parametrize("H", [1, 2, 3])
+def test_fp32_short_horizons(rt, lanes, H):
+    # the rollouts load the next step's noise one step ahead; at the last
+    # step (the first, for H = 1) they read their own row again
+    cfg = workloads.config("c1", N=333, H=H, seed=40 + H)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(40 + H)))
+    out, ref = run_pair(rt, cfg, inp)
+    np.testing.assert_array_equal(out["q"], ref["q_samples"])
+    check_costs_fp32(out["J"][0], ref["costs"][0], cfg["lambda"])
+    # no rollout tumbles within three steps: every cost agrees, and a wrong
+    # noise row would move it far beyond FP32 rounding
+    np.testing.assert_allclose(out["J"][0], ref["costs"][0], rtol=1e-4)
+
+
 def test_fp32_elite_selection(rt, lanes):
     cfg = workloads.config("c2", N=3000, H=16, seed=12)
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(12)), v_ref=(-0.3, 0, 0))
