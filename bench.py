@@ -356,7 +356,9 @@ def main():
 def main_c3(args):
     from paper_2403_11383_amd import binding, workloads
     rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)))
-    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    # the autotuner's choice for this batch, kept between runs on one machine
+    cache = os.environ.get("SBS_AUTOTUNE_CACHE",
+                           os.path.join(ROOT, ".sbs_cache", "autotune_cache.json"))
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     elapsed, lat, work, tune, cfgs = batched(rt, binding, workloads, args.steps, args.warmup, cache)
     # rollout-kernel timing from a separate pass without the graph: the
