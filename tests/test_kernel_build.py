@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
-def metadata():
+def compiled():
     from paper_2403_11383_amd import build
     src = os.path.join(ROOT, "paper_2403_11383_amd", "csrc", "sbs_kernels.hip")
     with tempfile.TemporaryDirectory() as td:
@@ -33,7 +33,40 @@ def metadata():
                                                "sgpr_spill_count", "vgpr_count")}
         kernels[name]["args"] = [(int(o), int(z)) for o, z in
                                  re.findall(r"\.offset:\s+(\d+)\n\s+\.size:\s+(\d+)", block)][:2]
-    return kernels
+    return {"kernels": kernels, "text": text}
+
+
+@pytest.fixture(scope="module")
+def metadata(compiled):
+    return compiled["kernels"]
+
+
+def kernel_body(text, name_part):
+    """Assembly lines of the first kernel whose symbol contains name_part."""
+    lines = text.split("\n")
+    for i, line in enumerate(lines):
+        if re.match(r"^_Z\S*:", line) and name_part in line.split(":")[0]:
+            body = []
+            for l in lines[i:]:
+                body.append(l)
+                if "s_endpgm" in l:
+                    return body
+    raise AssertionError(f"no kernel matching {name_part}")
+
+
+def largest_loop(body):
+    """Instructions of the kernel's largest loop (header label to its last
+    back-edge)."""
+    best = []
+    for i, line in enumerate(body):
+        m = re.match(r"^(\.LBB\d+_\d+):.*Loop Header", line)
+        if not m:
+            continue
+        ends = [k for k in range(i + 1, len(body))
+                if re.search(r"s_(cbranch_\w+|branch)\s+" + re.escape(m.group(1)) + r"$", body[k])]
+        if ends and ends[-1] - i > len(best):
+            best = body[i:ends[-1] + 1]
+    return [l.split()[0] for l in best if re.match(r"^\s+[a-z]", l)]
 
 
 def test_every_stage_is_built(metadata):
@@ -57,3 +90,25 @@ def test_inline_descriptor_offset(metadata):
             continue
         (o0, z0), (o1, z1) = m["args"]
         assert o0 == 0 and o1 == (z0 + 7) // 8 * 8, (name, m["args"])
+
+
+def test_noise_row_loop(compiled):
+    """The batched noise kernel's per-row loop: no divergent branch, no
+    memory load (the descriptor fields stay in registers), and each Philox
+    round's two three-word XORs as single three-input bit operations."""
+    ins = largest_loop(kernel_body(compiled["text"], "k_noiseILb0E"))
+    assert ins, "row loop not found"
+    assert not [i for i in ins if i.startswith("s_cbranch_exec")], "divergent branch in the row loop"
+    assert not [i for i in ins if i.startswith(("global_load", "s_load", "buffer_load"))]
+    assert sum(i == "v_bitop3_b32" for i in ins) >= 50  # 3 calls x 10 rounds x 2, a few folded
+
+
+@pytest.mark.parametrize("kernel,budget", [("k_rolloutIfLi256ELi1ELb0ELb0E", 480),
+                                           ("k_rollout_quadILi256ELi1ELb1ELb0E", 236)])
+def test_rollout_step_instruction_budget(compiled, kernel, budget):
+    """Instructions per rollout step (the main loop, scalar and memory ones
+    included): 469 for the one-lane form and 233 for the quad form when this
+    was written; the budget catches a change that adds branches or moves to
+    the step."""
+    ins = largest_loop(kernel_body(compiled["text"], kernel))
+    assert ins and len(ins) <= budget, (kernel, len(ins))
