@@ -65,6 +65,23 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
   }
 }
 
+// IEEE round-to-nearest square root for the Box-Muller radius, whose
+// argument is -0, +0 or in [2^-24, 34]: the hardware root (within one ulp)
+// moved to a neighbour where that neighbour's residual says it is closer.
+// No scaling is needed because the argument never comes near the tiny
+// inputs where the hardware root loses accuracy.  For a zero argument the
+// neighbour tests fail (NaN or signed-zero residuals), and the root keeps
+// the argument's sign.
+__device__ __forceinline__ float sqrt_rn_radius(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sd = __uint_as_float(__float_as_uint(s) - 1u);
+  const float su = __uint_as_float(__float_as_uint(s) + 1u);
+  const float rd = __builtin_fmaf(-sd, s, x);
+  const float ru = __builtin_fmaf(-su, s, x);
+  const float r = (rd <= 0.0f) ? sd : s;
+  return (ru > 0.0f) ? su : r;
+}
+
 __device__ __forceinline__ float2 gauss_pair(uint32_t w0, uint32_t w1) {
 #pragma clang fp contract(off)
   const uint32_t i1 = (w0 >> 8) + 1u;   // u1 = i1 2^-24 in (0, 1]
@@ -83,7 +100,7 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t w0, uint32_t w1) {
   const float lnm = __builtin_fmaf(s2 * t, p, s2);
   const float ke = (float)(e - 24);
   const float lnu = __builtin_fmaf(ke, 0x1.62e4p-1f, __builtin_fmaf(ke, 0x1.7f7d1cp-20f, lnm));
-  const float rho = __builtin_sqrtf(-2.0f * lnu);
+  const float rho = sqrt_rn_radius(-2.0f * lnu);
 
   const uint32_t n = (i2 + (1u << 21)) >> 22;
   const int32_t fi = (int32_t)i2 - (int32_t)(n << 22);
