@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   for (int j = 0; j < H; ++j) {
     T u[12];
     if constexpr (SPL) {
-      if (s_spb[j] != wb) {  // uniform: the window moves on by one knot
+      while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
         const int p = wb + 4;
         const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                               z2.x, z2.y, z2.z, z2.w};
@@ -887,7 +887,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   for (int j = 0; j < H; ++j) {
     float ux, uy, uz;
     if constexpr (SPL) {
-      if (s_spb[j] != wb) {  // uniform: the window moves on by one knot
+      while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
         const int p = wb + 4, o = p * 12 + 3 * l;
         const float zn3[3] = {za, zb, zc};
 #pragma unroll

@@ -104,12 +104,15 @@ struct SplineRow {
   double w[4];
 };
 
-SplineRow spline_row(int P, int H, double dt, double t) {
+// seg >= 0 gives the segment of t directly (steps on the grid, below);
+// seg < 0 finds it by comparing t with the knot times.
+SplineRow spline_row(int P, int H, double dt, double t, int seg = -1) {
   const double T = (double)(H - 1) * dt;
   auto tk = [&](int p) { return (double)p * T / (double)(P - 1); };
   t = std::min(std::max(t, 0.0), T);
   int p = 0;
-  while (p < P - 2 && t >= tk(p + 1)) ++p;
+  if (seg >= 0) p = std::min(seg, P - 2);
+  else while (p < P - 2 && t >= tk(p + 1)) ++p;
   const double h = tk(p + 1) - tk(p), s = (t - tk(p)) / h;
   const double h00 = 2 * s * s * s - 3 * s * s + 1, h10 = s * s * s - 2 * s * s + s;
   const double h01 = -2 * s * s * s + 3 * s * s, h11 = s * s * s - s * s;
@@ -831,7 +834,27 @@ int slot_busy(sbs_runtime *rt, int slot) {
   return n;
 }
 
-// Serving scheduler: continuous batching with memory admission.
+// Arena bytes that step workspaces can ever use: everything but the
+// persistent allocations (controller states, debug and prefetch buffers,
+// plan workspaces), i.e. the free bytes plus those of the batches in flight.
+uint64_t workspace_room(const sbs_runtime *rt) {
+  uint64_t transient = 0;
+  for (auto &b : rt->inflight)
+    if (b->owns_memory) transient += align_up(b->ws_bytes);
+  return rt->dev_alloc.size() - (rt->dev_alloc.used() - transient);
+}
+
+// Ends a pending request's ticket with an error status.
+void fail_request(sbs_runtime *rt, size_t i, int status) {
+  rt->tickets[rt->pending[i].ticket].status = status;
+  rt->pending.erase(rt->pending.begin() + i);
+  rt->cv.notify_all();
+}
+
+// Serving scheduler: continuous batching with memory admission.  Progress:
+// with no batch in flight the arena holds only persistent state, so a head
+// request that cannot be placed then can never be; its ticket fails with
+// SBS_ENOMEM instead of blocking every later request.
 void scheduler_loop(sbs_runtime *rt) {
   (void)hipSetDevice(rt->device);
   std::unique_lock<std::mutex> lk(rt->mu);
@@ -880,13 +903,34 @@ void scheduler_loop(sbs_runtime *rt) {
       }
       (void)need;
       if (waited) rt->n_admit_waits += 1;
+      if (ids.empty() && waited && rt->inflight.empty()) {
+        // the first admissible request does not fit beside the persistent
+        // state alone: it never will
+        for (size_t i = 0; i < rt->pending.size(); ++i) {
+          auto cit = rt->ctrls.find(rt->pending[i].id);
+          if (cit == rt->ctrls.end() || cit->second.inflight > 0) continue;
+          (void)fail(SBS_ENOMEM, "controller %d: step workspace does not fit in the arena",
+                     rt->pending[i].id);
+          fail_request(rt, i, SBS_ENOMEM);
+          break;
+        }
+        continue;
+      }
       if (!ids.empty()) {
         int rc = launch(rt, ids, ins, tks, slot);
+        if (rc == SBS_ENOMEM && rt->inflight.empty() && ids.size() > 1) {
+          // fragmented arena with nothing to retire: the head request alone
+          ids.resize(1);
+          ins.resize(1);
+          tks.resize(1);
+          taken.resize(1);
+          rc = launch(rt, ids, ins, tks, slot);
+        }
         if (rc == SBS_OK) {
           for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
           continue;
         }
-        if (rc != SBS_ENOMEM) {
+        if (rc != SBS_ENOMEM || rt->inflight.empty()) {
           for (uint64_t tk : tks) rt->tickets[tk].status = rc;
           for (size_t t = taken.size(); t-- > 0;) rt->pending.erase(rt->pending.begin() + taken[t]);
           rt->cv.notify_all();
@@ -1004,8 +1048,14 @@ int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t 
     double *shw = reinterpret_cast<double *>(hostbuf.data() + sh_off);
     int32_t *spb = reinterpret_cast<int32_t *>(hostbuf.data() + spb_off);
     int32_t *shb = reinterpret_cast<int32_t *>(hostbuf.data() + shb_off);
+    // step j (t_j = j dt) lies on segment floor(j (P - 1) / (H - 1)): exact
+    // in integers, whereas comparing j dt with the rounded knot times can
+    // put a step that sits on a knot into the segment before it.  With
+    // P <= H the segment, and so the window base, moves on by at most one
+    // knot per step.
     for (int j = 0; j < cfg->H; ++j) {
-      const SplineRow r = spline_row(P, cfg->H, cfg->dt, (double)j * cfg->dt);
+      const int seg = cfg->H > 1 ? (int)(((int64_t)j * (P - 1)) / (cfg->H - 1)) : 0;
+      const SplineRow r = spline_row(P, cfg->H, cfg->dt, (double)j * cfg->dt, seg);
       spb[j] = r.base;
       for (int i = 0; i < 4; ++i) spw[4 * j + i] = r.w[i];
     }
@@ -1121,6 +1171,18 @@ int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_t
     tickets[i] = tk;
   }
   if (rt->mode == SBS_MODE_SERVING) {
+    // a controller whose step workspace cannot fit beside the persistent
+    // state would wait forever: refused here
+    const uint64_t room = workspace_room(rt);
+    for (int i = 0; i < n; ++i) {
+      const Layout L = make_layout({&rt->ctrls.at(vid[i])});
+      if (L.total + kAlign > room) {
+        for (uint64_t tk : tks) rt->tickets.erase(tk);
+        return fail(SBS_ENOMEM, "controller %d: step workspace of %llu bytes exceeds the %llu "
+                    "bytes the arena can ever lend to steps", vid[i],
+                    (unsigned long long)L.total, (unsigned long long)room);
+      }
+    }
     for (int i = 0; i < n; ++i) rt->pending.push_back({tks[i], vid[i], in[i], t});
     return SBS_OK;
   }

@@ -77,6 +77,22 @@ def check_costs_fp32(Jg, Jr, lam=1.0, elite_ke=None, well=None):
     return int(rel.sum())
 
 
+def mppi_action_bound(cfg, J, epsJ, mean0, tick=0):
+    """First-order bound on how far an MPPI mean's first step moves when the
+    costs J move by at most epsJ (per sample):
+    |d mean| <= sum_k w_k |theta_k - mean| |dJ_k - sum_i w_i dJ_i| / lambda,
+    with the weights of J, the first-step samples of a hover-mean tick and
+    the mean's first row mean0."""
+    J = np.asarray(J, np.float64)
+    w, *_ = oracle.mppi_weights(J, cfg["lambda"])
+    epsJ = np.where(np.isfinite(epsJ), epsJ, 0.0)
+    z = oracle.noise_block(cfg["seed"], tick, 0, cfg["N"], 1)[:, 0, :].astype(np.float64)
+    th0 = hover(cfg)[0][None] + cfg["sigma_grf"] * z
+    dev = np.abs(th0 - np.asarray(mean0)[None])
+    spread = epsJ + (w * epsJ).sum()
+    return float((w[:, None] * dev * spread[:, None]).sum(0).max() / cfg["lambda"])
+
+
 def hover(cfg):
     """The hover mean, one row per step or spline knot."""
     return np.tile([0.0, 0.0, MG2] * 4, (oracle.rows(cfg), 1))

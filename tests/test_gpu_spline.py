@@ -39,8 +39,11 @@ def test_spline_noise_rows_bit_exact(rt):
 # FP64 at 1e-10: horizons up to 25 steps (longer ones tumble, and a tumbling
 # rollout amplifies the last-bit differences of the two spline evaluations;
 # the FP32 tests and the full-size tests cover H = 40..50)
+# P == H puts a knot on every step: the cases at H = 8 and 25 are ones where
+# comparing j dt with the rounded knot times would skip a segment, so the
+# rollout's knot window must follow the exact segment of every step
 @pytest.mark.parametrize("N,H,P", [(63, 9, 2), (257, 12, 5), (1025, 25, 10), (700, 17, 17),
-                                   (129, 20, 3), (64, 8, 4)])
+                                   (129, 20, 3), (64, 8, 4), (300, 8, 8), (600, 25, 25)])
 def test_spline_fp64_parity(rt, N, H, P):
     cfg = workloads.config("c1", N=N, H=H, knots=P, precision="fp64", seed=N + H + P)
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(P)),
@@ -100,6 +103,20 @@ def test_spline_fp32_mppi(rt, lanes):
     scale = max(np.abs(ref2["grf"]).max(), MG2)
     assert np.abs(out["act"]["grf"] - ref2["grf"]).max() <= 1e-4 * scale
     assert np.abs(out["mean"] - ref2["mean"]).max() <= 1e-4 * max(np.abs(ref2["mean"]).max(), MG2)
+
+
+def test_spline_fp32_knot_on_every_step(rt, lanes):
+    """P == H at H = 25 (a knot on every step) in both rollout forms, whose
+    knot windows advance at run time."""
+    cfg = workloads.config("c1", N=1500, H=25, knots=25, seed=31)
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(31)))
+    out, ref = run_pair(rt, cfg, inp)
+    np.testing.assert_array_equal(out["q"], ref["q_samples"])
+    check_costs_fp32(out["J"][0], ref["costs"][0], cfg["lambda"])
+    ref2 = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, costs_override=out["J"], nthreads=8)
+    scale = max(np.abs(ref2["mean"]).max(), MG2)
+    assert np.abs(out["mean"] - ref2["mean"]).max() <= 1e-4 * scale
+    assert np.abs(out["act"]["grf"] - ref2["grf"]).max() <= 1e-4 * scale
 
 
 def test_spline_fp32_elite(rt, lanes):

@@ -308,3 +308,58 @@ def test_nonfinite_rollout_cost_is_inf(orc):
     assert J == math.inf
     x0 = [0, 0, 0.35, 0, 0, 0, math.nan, 0, 0, 0, 0, 0]
     assert orc.rollout(c, workloads.tick_input(x0), th, 0) == math.inf
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2) by hand: exact numbers chosen so that every term is a short decimal
+# ---------------------------------------------------------------------------
+def _foothold_cfg(**over):
+    # dt = 1/64 s and f = 2 Hz make the phase increment q = 2^27 exact, so the
+    # executed frequency is exactly 2 Hz and the stance time D_f / f = 0.25 s
+    c = cfg0(dt=1.0 / 64.0, duty=0.5)
+    c.update(over)
+    return c
+
+
+Q_2HZ = 1 << 27
+
+
+def test_foothold_steady_gait_is_hip_plus_half_stance_times_vd(orc):
+    """Eq. (2) with v = v^d: the capture term vanishes and the foot lands
+    (T_st / 2) v^d ahead of the hip: 0.125 s x (0.4, -0.2) m/s = (0.05,
+    -0.025) m."""
+    c = _foothold_cfg()
+    x = [1.0, 2.0, 0.35, 0.0, 0.0, 0.0, 0.4, -0.2, 0.0, 0.0, 0.0, 0.0]
+    vd = (0.4, -0.2, 0.0)
+    want = {0: (1.29, 2.105), 1: (1.29, 1.845), 2: (0.81, 2.105), 3: (0.81, 1.845)}
+    for leg, (wx, wy) in want.items():
+        f = orc.foothold(c, x, Q_2HZ, vd, leg)
+        np.testing.assert_allclose(f, [wx, wy, 0.0], rtol=0, atol=1e-15)
+
+
+def test_foothold_capture_term_at_zero_command(orc):
+    """Eq. (2) with v^d = 0: the foot lands sqrt(z / g) v from the hip; with
+    z = 0.4 m and g = 10 m/s^2 the factor is 0.2 s, so v = (0.3, -0.1) m/s
+    moves it by (0.06, -0.02) m."""
+    c = _foothold_cfg(gravity=10.0)
+    x = [0.0, 0.0, 0.4, 0.0, 0.0, 0.0, 0.3, -0.1, 0.7, 0.0, 0.0, 0.0]
+    f = orc.foothold(c, x, Q_2HZ, (0.0, 0.0, 0.0), 0)
+    np.testing.assert_allclose(f, [0.30, 0.11, 0.0], rtol=0, atol=1e-15)
+    # the vertical velocity and the stance time play no part at v^d = 0
+    f2 = orc.foothold(c, x, Q_2HZ >> 1, (0.0, 0.0, 0.0), 0)
+    np.testing.assert_allclose(f2, f, rtol=0, atol=1e-15)
+
+
+def test_foothold_both_terms_and_yawed_hip(orc):
+    """Both terms of Eq. (2) together on a body yawed by 90 degrees: the
+    front-left hip (0.24, 0.13) then sits at (-0.13, 0.24) from the CoM; with
+    v^d = (0.4, 0), v = (0.2, 0.1), z = 0.4, g = 10 and T_st = 0.25 s the
+    foot lands at hip + 0.125 (0.4, 0) + 0.2 (-0.2, 0.1) = hip + (0.01, 0.02)."""
+    c = _foothold_cfg(gravity=10.0)
+    x = [0.0, 0.0, 0.4, 0.0, 0.0, math.pi / 2, 0.2, 0.1, 0.0, 0.0, 0.0, 0.0]
+    f = orc.foothold(c, x, Q_2HZ, (0.4, 0.0, 0.0), 0)
+    np.testing.assert_allclose(f, [-0.12, 0.26, 0.0], rtol=0, atol=1e-15)
+    # a CoM below the ground keeps the foot under the hip term alone
+    x[2] = -0.1
+    f = orc.foothold(c, x, Q_2HZ, (0.4, 0.0, 0.0), 0)
+    np.testing.assert_allclose(f, [-0.13 + 0.05, 0.24, 0.0], rtol=0, atol=1e-15)
