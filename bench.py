@@ -1,16 +1,32 @@
-"""Benchmark of one GPU: closed-loop receding-horizon MPPI with per-sample gait
-frequency (N = 10240 samples, H = 50 steps, dt = 0.02 s, GRF noise 25 N,
-friction cone mu = 0.5, 40 N lateral push from tick 30), FP32 rollouts.
+"""Benchmark of one GPU: the serving workload (256 simulated robots, each
+issuing control ticks at 50 Hz with Poisson jitter; N in {2048, 4096, 8192}
+samples and H in {25, 50} steps per robot; MPPI with per-sample gait
+frequency ~U[1.0, 2.5] Hz, GRF noise 25 N, lambda = 1, Q = I, R = 1e-4 I,
+friction cone mu = 0.5; FP32 rollouts) through continuous batching, against
+the plain single-controller MPPI (each tick its own launch sequence on one
+stream) on the same GPU.  One JSON line is printed.
 
-A step is one control tick: noise, rollouts, selection and mean update on
-the GPU (through the C ABI), then one step of the host plant with the
-returned action.  The value is rollout-steps per second (N x H x iterations
-per tick) over the timed ticks, with the inputs already resident.  One JSON
-line is printed.  Its roofline object rates the rollout kernel: algorithmic
-FP32 FLOP per launch (FLOP_PER_ROLLOUT_STEP x N x H) over the kernel's
-average duration from HIP events on the runtime stream, against the
-non-packed FP32 VALU peak.  Its cpu_baseline object times the FP64 oracle on
-the host cores over a bounded sample of full-size ticks.
+value: rollout-steps per second (N x H per tick, summed over completed
+ticks) that continuous batching sustains with every robot's next tick
+submitted as soon as its previous one completes (saturated), inputs already
+resident.  Beside it: the same for the plain single-controller form
+(vs_baseline = the ratio), and the p50/p99 tick latency from arrival of both
+forms on the 50 Hz Poisson stream.  A step is 0.15 s of the saturated stream
+(and 0.5 s of each 50 Hz arrival stream).
+
+The roofline object rates the rollout kernel of the saturated serving run:
+algorithmic FP32 FLOP of its timed launches (FLOP_PER_ROLLOUT_STEP x the
+rollout-steps each launch covered) over their device time from HIP events
+carried by the launches' own dispatches on the runtime's streams.  An
+untimed serving pass records served ticks of the robots whose index is a
+multiple of 100 (about 1 % of the ticks) with the controller state each
+started from; the cpu_baseline leg reruns them on the FP64 oracle on the
+host cores (timed: cpu_baseline) and compares the actions (shadow_oracle).
+
+Other workloads (--workload): c1 closed-loop MPPI (N = 10240, H = 50), c2
+closed-loop elite sampler (N = 16384, H = 50, 3 iterations), c3 64 uneven
+controllers in one graph-replayed tick, study (push episodes with and
+without gait adaptation), copy (HBM byte-counter reference).
 """
 from __future__ import annotations
 
@@ -38,9 +54,11 @@ FLOP_PER_ROLLOUT_STEP = 326
 # of each sample forms mu + sigma z once (24 per knot).
 FLOP_PER_SPLINE_STEP = FLOP_PER_ROLLOUT_STEP - 24 + 84
 FLOP_PER_SPLINE_KNOT = 24
-# Non-packed FP32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
-PEAK_FP32_VALU_TFLOPS = 78.6
+# MI355X FP32 vector peak as published (it counts packed FMAs: 256 CUs x 4
+# SIMDs x 16 lanes x 2 FLOP x 2 packed x 2.4 GHz) and the non-packed peak the
+# kernels can reach (they are built with packed FP32 off).
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 78.6
 
 
 def pct(a, p):
@@ -76,9 +94,9 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     """Receding-horizon episodes of `episode` ticks (the workload's 100): each
     starts the plant from the seeded initial state (the controller keeps its
     warm start and tick counter); the push acts from tick `push_from` of each
-    episode.  An episode also ends when the robot falls (roll or pitch beyond
-    1.5 rad, CoM height outside [0.05, 1] m, or a non-finite state).  The
-    first `warmup` ticks are untimed."""
+    episode.  An episode also ends when the robot falls (workloads.fallen:
+    roll or pitch beyond 0.8 rad, CoM height outside (0.2, 0.6) m, or a
+    non-finite state).  The first `warmup` ticks are untimed."""
     cid = rt.init_controller(cfg)
     if prefetch:
         rt.set_prefetch(cid, True)
@@ -103,7 +121,7 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
         a = loop.step(push_f if e >= push_from else no_push)
         e += 1
         x = loop.plant.st.x
-        if not (abs(x[3]) < 1.5 and abs(x[4]) < 1.5 and 0.05 < x[2] < 1.0):  # NaN fails too
+        if workloads.fallen(x):
             e = 0
             falls += 1 if t >= warmup else 0
         if t >= warmup:
@@ -189,72 +207,27 @@ def batched(rt, binding, workloads, steps, warmup, cache_path=None):
     return elapsed, lat, work, tune, cfgs
 
 
-def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
-    """C4: Poisson arrivals (50 Hz per robot) of control ticks from simulated
-    robots of different N and H; serving mode batches whatever is admitted,
-    direct mode runs every tick as its own launch sequence ("plain single
-    MPPI").  Latency is measured from the scheduled arrival to completion."""
-    import torch
-    fleet = workloads.c4_fleet(robots=robots)
-    arrivals = workloads.c4_arrivals(robots=robots, duration_s=duration)
-    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
-    ids = [rt.init_controller(c) for c in fleet]
-    rng = np.random.default_rng(5)
-    inputs = [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
-    events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
-    L = binding.lib()
-    import ctypes as C
-    pending = {}
-    lat, done_work = [], 0
-    tk = C.c_uint64()
-    act = binding.Action()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter_ns()
-    i = 0
-    while i < len(events) or pending:
-        now = (time.perf_counter_ns() - t_start) * 1e-9
-        while i < len(events) and events[i][0] <= now:
-            t_arr, r = events[i]
-            rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
-            if rc == binding.ENOMEM:  # arena full: retire finished ticks first
-                break
-            binding._check(rc)
-            pending[tk.value] = (t_arr, r)
-            i += 1
-        for t in list(pending):
-            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
-            if rc == binding.OK:
-                t_arr, r = pending.pop(t)
-                lat.append((act.t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
-                c = fleet[r]
-                done_work += c["N"] * c["H"]
-            elif rc != binding.EAGAIN:
-                binding._check(rc)
-        if mode == "direct" and pending and i < len(events) and events[i][0] > now:
-            time.sleep(0)
-    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
-    stats = rt.stats()
-    rt.close()
-    return {"ticks": len(lat), "elapsed_s": elapsed, "rollout_steps_per_s": done_work / elapsed,
-            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": float(np.max(lat)),
-            "batches": stats["batches"], "admit_waits": stats["admit_waits"]}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000,
-                    help="timed ticks (c1/c2: episodes of 100 ticks from the seeded start)")
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="c4: 0.15 s of the saturated stream and 0.5 s of each 50 Hz stream "
+                         "per step (default 20); c1/c2/c3: timed ticks (default 1000; c1/c2 in "
+                         "episodes of 100 ticks from the seeded start)")
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 the rollout kernel's own dispatch events on "
                          "one tick in 16, 2 event commands around every stage of every tick")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy", "study"],
-                    help="c1 closed-loop single MPPI (default); c2 closed-loop elite "
+    ap.add_argument("--shadow-seconds", type=float, default=6.0,
+                    help="c4: arrival-stream length of the pass that records the served ticks "
+                         "the oracle reruns (cpu_baseline and shadow_oracle)")
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "copy", "study"],
+                    help="c4 serving vs plain single MPPI (default); c1 closed-loop single "
+                         "MPPI; c2 closed-loop elite "
                          "sampler (N=16384, H=50, 3 iterations); c3 batched uneven "
-                         "controllers; c4 serving 256 robots vs plain single MPPI; copy: "
+                         "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
     ap.add_argument("--episodes", type=int, default=20, help="study: seeded episodes per setting")
@@ -265,6 +238,10 @@ def main():
     ap.add_argument("--knots", type=int, default=0,
                     help="c1: GRF spline through this many knots (0: one GRF vector per step)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 20 if args.workload == "c4" else 1000
+    if args.warmup is None:
+        args.warmup = 5 if args.workload == "c4" else 10
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -302,7 +279,6 @@ def main():
     P = args.knots
     flop = N * H * FLOP_PER_ROLLOUT_STEP if P == 0 else \
         N * (H * FLOP_PER_SPLINE_STEP + P * FLOP_PER_SPLINE_KNOT)
-    achieved = flop / t_roll / 1e12 if t_roll > 0 else 0.0
     spline_txt = f", GRF spline through {P} knots" if P else ""
     workload_key = args.workload if P == 0 else f"{args.workload}_knots{P}"
     if c2:
@@ -325,23 +301,16 @@ def main():
                                                         "update_ns") if timing[k] > 0},
         # the automatic lane policy runs one controller of up to 32768
         # samples with four lanes per sample
-        "roofline": {"kernel": "k_rollout_quad" if N <= 32768 else "k_rollout<float>",
-                     "launches_per_tick": R,
-                     "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "peak_published_packed": PEAK_FP32_PUBLISHED_TFLOPS,
-                     "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-                     "traffic": stored_traffic("k_rollout", workload_key),
-                     "flop_per_launch": flop, "duration_us": t_roll * 1e6,
-                     # four lanes per sample: waves in flight against the
-                     # chip's 1024 SIMDs (one wave per SIMD leaves the
-                     # step-to-step dependency chain exposed)
-                     "waves": (N * 4 + 63) // 64 if N <= 32768 else (N + 63) // 64,
-                     "simds": 1024,
-                     "event_interval_us": timing["rollout_ns"] * 1e-3,
-                     "event_overhead_us": ev_ovh_ns * 1e-3,
-                     "event_overhead_taken_us": ev_taken_ns * 1e-3},
+        "roofline": roofline_obj(
+            "k_rollout_quad" if N <= 32768 else "k_rollout<float>", flop, t_roll * 1e9, 1,
+            launches_per_tick=R, traffic=stored_traffic("k_rollout", workload_key),
+            flop_per_launch=flop, duration_us=t_roll * 1e6,
+            # four lanes per sample: waves in flight against the chip's 1024
+            # SIMDs (one wave per SIMD leaves the step-to-step dependency
+            # chain exposed)
+            waves=(N * 4 + 63) // 64 if N <= 32768 else (N + 63) // 64, simds=1024,
+            event_interval_us=timing["rollout_ns"] * 1e-3, event_overhead_us=ev_ovh_ns * 1e-3,
+            event_overhead_taken_us=ev_taken_ns * 1e-3),
         "closed_loop": {"episodes_ended_by_falls": plant[1],
                         "final_x": [round(float(v), 4) for v in plant[0].x],
                         "nonfinite_ticks": int(sum(a[0] & 1 for a in acts)),
@@ -384,7 +353,6 @@ def main_c3(args):
     rt.close()
     roll_ns_total = tm["rollout_ns"] * tm["launches"][1]
     flop = work * FLOP_PER_ROLLOUT_STEP * reps
-    achieved = flop / (roll_ns_total * 1e-9) / 1e12 if roll_ns_total > 0 else 0.0
     line = {
         "metric": METRIC, "value": work * args.steps / elapsed, "unit": "rollout-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -394,15 +362,12 @@ def main_c3(args):
                                "MPPI/elite mix) in one graph-replayed fused tick",
                    "rollout_steps_per_tick": work, "tune": tune},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-        "roofline": {"kernel": "k_rollout (tuned form)", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "peak_published_packed": PEAK_FP32_PUBLISHED_TFLOPS,
-                     "frac_of_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-                     "traffic": stored_traffic("k_rollout", "c3"),
-                     "duration_us": roll_ns_total / max(1, tm["launches"][1]) * 1e-3,
-                     "event_interval_us": tm["rollout_ns"] * 1e-3,
-                     "event_overhead_us": ev_ovh_ns * 1e-3, "event_overhead_taken_us": 0.0},
+        "roofline": roofline_obj(
+            "k_rollout (tuned form)", flop, roll_ns_total / max(1, tm["launches"][1]),
+            tm["launches"][1], traffic=stored_traffic("k_rollout", "c3"),
+            duration_us=roll_ns_total / max(1, tm["launches"][1]) * 1e-3,
+            event_interval_us=tm["rollout_ns"] * 1e-3, event_overhead_us=ev_ovh_ns * 1e-3,
+            event_overhead_taken_us=0.0),
     }
     print(json.dumps(line), flush=True)
 
@@ -440,7 +405,7 @@ def study_episode(rt, binding, workloads, cfg, seed):
         freq.append(a.freq_hz)
         lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
         x = loop.plant.st.x
-        if not (abs(x[3]) < 0.8 and abs(x[4]) < 0.8 and 0.2 < x[2] < 0.6):  # NaN fails too
+        if workloads.fallen(x):
             fell = t
             break
     rt.destroy_controller(cid)
@@ -501,21 +466,114 @@ def main_study(args):
         "wall_s": round(elapsed, 2)}), flush=True)
 
 
-def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256):
+# ---------------------------------------------------------------------------
+# C4: serving 256 robots
+# ---------------------------------------------------------------------------
+STEP_S_ARRIVALS = 0.5    # one step: 0.5 s of each 50 Hz arrival stream
+STEP_S_SATURATED = 0.15  # and 0.15 s of the saturated stream
+SHADOW_EVERY = 100       # robots 0, 100, 200 are shadowed by the oracle
+
+
+def roofline_obj(kernel, flop, dur_ns, launches, **extra):
+    """The roofline object of an ALU-bound rollout: algorithmic FLOP over
+    device time, against the published FP32 vector peak and (beside it) the
+    non-packed peak the kernels can reach."""
+    achieved = flop / (dur_ns * launches * 1e-9) / 1e12 if dur_ns > 0 and launches else 0.0
+    out = {"kernel": kernel, "bound": "alu", "achieved": achieved,
+           "peak": PEAK_FP32_PUBLISHED_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+           "peak_nonpacked": PEAK_FP32_VALU_TFLOPS,
+           "frac_nonpacked": achieved / PEAK_FP32_VALU_TFLOPS,
+           "flop_per_rollout_step": FLOP_PER_ROLLOUT_STEP}
+    out.update(extra)
+    return out
+
+
+def fleet_inputs(binding, workloads, fleet, seed):
+    rng = np.random.default_rng(seed)
+    return [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
+
+
+def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
+    """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
+    ticks; serving mode batches whatever is admitted, direct mode runs every
+    tick as its own launch sequence ("plain single MPPI").  A robot's tick
+    waits for its previous one (the warm start), inside the runtime.
+    Latency is measured from the scheduled arrival to completion."""
+    import ctypes as C
+    import torch
+    fleet = workloads.c4_fleet(robots=robots)
+    arrivals = workloads.c4_arrivals(robots=robots, duration_s=duration)
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
+    ids = [rt.init_controller(c) for c in fleet]
+    inputs = fleet_inputs(binding, workloads, fleet, 5)
+    events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
+    L = binding.lib()
+    pending = {}
+    lat, done_work = [], 0
+    tk = C.c_uint64()
+    act = binding.Action()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter_ns()
+    i = 0
+    while i < len(events) or pending:
+        now = (time.perf_counter_ns() - t_start) * 1e-9
+        while i < len(events) and events[i][0] <= now:
+            t_arr, r = events[i]
+            rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
+            if rc == binding.ENOMEM and mode == "direct":  # retire finished ticks first
+                break
+            binding._check(rc)
+            pending[tk.value] = (t_arr, r)
+            i += 1
+        for t in list(pending):
+            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
+            if rc == binding.OK:
+                t_arr, r = pending.pop(t)
+                lat.append((act.t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
+                c = fleet[r]
+                done_work += c["N"] * c["H"]
+            elif rc != binding.EAGAIN:
+                binding._check(rc)
+        if mode == "direct" and pending and i < len(events) and events[i][0] > now:
+            time.sleep(0)
+    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    stats = rt.stats()
+    rt.close()
+    return {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
+            "rollout_steps_per_s": done_work / elapsed,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": float(np.max(lat)),
+            "batches": stats["batches"], "admit_waits": stats["admit_waits"]}
+
+
+def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
+                  warmup_ticks=0):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
-    mode sustains, and their submit-to-done latency."""
+    form sustains, and their submit-to-done latency.  With timing, the
+    rollout launches carry HIP events (one launch in 16) and the per-form
+    rollout timings of the timed region are returned."""
     import ctypes as C
     import torch
     fleet = workloads.c4_fleet(robots=robots)
     rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
     ids = [rt.init_controller(c) for c in fleet]
-    rng = np.random.default_rng(6)
-    inputs = [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
+    inputs = fleet_inputs(binding, workloads, fleet, 6)
     L = binding.lib()
     tk = C.c_uint64()
     act = binding.Action()
+    # untimed warm-up: every robot's first ticks
+    for _ in range(warmup_ticks):
+        tks = [rt.submit_tick(cid, workloads.tick_input(workloads.initial_state(
+            np.random.default_rng(6)))) for cid in ids]
+        for t in tks:
+            rt.fetch(t)
     torch.cuda.synchronize()
+    if timing:
+        rt.set_timing(timing)
+        rt.timing()
+        for f in range(3):
+            rt.timing_rollout(f)
     pending = {}
     lat, done_work = [], 0
     t_start = time.perf_counter_ns()
@@ -526,7 +584,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256):
             still = []
             for r in idle:
                 rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
-                if rc == binding.ENOMEM:
+                if rc == binding.ENOMEM and mode == "direct":
                     still.append(r)
                     continue
                 binding._check(rc)
@@ -541,34 +599,195 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256):
                 idle.append(r)
             elif rc != binding.EAGAIN:
                 binding._check(rc)
+    torch.cuda.synchronize()
     elapsed = (time.perf_counter_ns() - t_start) * 1e-9
     stats = rt.stats()
+    out = {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
+           "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
+           "p99_ms": pct(lat, 99), "batches": stats["batches"]}
+    if timing:
+        out["rollout_forms"] = [rt.timing_rollout(f) for f in range(3)]
+        out["event_overhead_ns"] = rt.timing_overhead_ns(64)
     rt.close()
-    return {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
-            "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
-            "p99_ms": pct(lat, 99), "batches": stats["batches"]}
+    return out
+
+
+def shadow_pass(binding, workloads, arena_bytes, seconds, robots=256, every=SHADOW_EVERY):
+    """Records served ticks for the shadow oracle (untimed, GPU side only).
+    The fleet runs a Poisson stream through the serving runtime; for the
+    shadowed robots (index a multiple of `every`, about 1 % of the ticks) the
+    bench exports the controller's state before each tick, waits for the
+    tick in the mix and takes its FP32 costs and action."""
+    fleet = workloads.c4_fleet(robots=robots)
+    arrivals = workloads.c4_arrivals(robots=robots, duration_s=seconds, seed=9)
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode="serving", two_streams=True)
+    ids = [rt.init_controller(c) for c in fleet]
+    rng = np.random.default_rng(5)
+    raw = [workloads.tick_input(workloads.initial_state(rng)) for _ in fleet]
+    shadowed = set(range(0, robots, every))
+    for r in shadowed:
+        rt.set_debug(ids[r], True)
+    events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
+    recs, pending, total = [], [], 0
+    t0 = time.perf_counter()
+    for t_arr, r in events:
+        while time.perf_counter() - t0 < t_arr:
+            pass
+        if r in shadowed:
+            mu, mf, tick = rt.export_state(ids[r])  # its previous tick is done
+            a = rt.fetch(rt.submit_tick(ids[r], raw[r]))
+            J, _, _ = rt.debug_costs(ids[r])
+            recs.append({"cfg": fleet[r], "inp": raw[r], "mu": mu, "mf": mf, "tick": tick,
+                         "grf": a["grf"], "J": J})
+        else:
+            pending.append(rt.submit_tick(ids[r], raw[r]))
+        total += 1
+    for t in pending:
+        rt.fetch(t)
+    rt.close()
+    return recs, total
+
+
+def cpu_baseline_c4(workloads, recs, total_ticks):
+    """The FP64 oracle on the host cores, on the served ticks that the shadow
+    pass recorded: each reruns from the controller's exported state and
+    input, timed on all cores (and a few on one core).  The same outputs are
+    the shadow check: the GPU's action against the oracle's (FP32 rollouts
+    and costs vs FP64), and against the oracle's update of the GPU's own
+    costs (selection parity)."""
+    import oracle
+    oracle.build()
+    cores = len(os.sched_getaffinity(0))
+    mg2 = 0.5 * workloads.MASS * workloads.GRAVITY
+    err_own, err_upd, steps = [], [], 0
+    t0 = time.perf_counter()
+    refs = []
+    for rc in recs:
+        refs.append(oracle.tick(rc["cfg"], rc["mu"], rc["mf"], rc["tick"], rc["inp"],
+                                nthreads=cores))
+        steps += rc["cfg"]["N"] * rc["cfg"]["H"]
+    dt = time.perf_counter() - t0
+    over = []
+    for rc, ref in zip(recs, refs):
+        upd = oracle.tick(rc["cfg"], rc["mu"], rc["mf"], rc["tick"], rc["inp"],
+                          costs_override=rc["J"], nthreads=cores)
+        scale = max(np.abs(ref["grf"]).max(), mg2)
+        err_own.append(float(np.abs(rc["grf"] - ref["grf"]).max() / scale))
+        err_upd.append(float(np.abs(rc["grf"] - upd["grf"]).max() / scale))
+        if err_own[-1] > 1e-4:
+            # first-order effect of the measured FP32-vs-FP64 cost differences
+            # on the MPPI mean's first step: sum_k w_k |theta_k - mean|
+            # |dJ_k - sum_i w_i dJ_i| / lambda (the weights of the oracle's
+            # costs; FP32 rollouts of ill-conditioned samples move their costs)
+            c, J = rc["cfg"], ref["costs"][-1]
+            w, *_ = oracle.mppi_weights(J, c["lambda"])
+            with np.errstate(invalid="ignore"):
+                dJ = np.abs(np.asarray(rc["J"][-1], np.float64) - J)
+            dJ = np.where(np.isfinite(dJ), dJ, 0.0)
+            live = np.flatnonzero(w > 0)
+            z = np.array([oracle.noise_step(c["seed"], rc["tick"], 0, int(k), 0) for k in live],
+                         np.float64).reshape(len(live), 12)
+            th = np.asarray(rc["mu"][0])[None] + c["sigma_grf"] * z
+            dev = np.abs(th - ref["mean"][0][None])
+            spread = np.abs(dJ[live] - (w * dJ).sum())
+            bound = float((w[live][:, None] * dev * spread[:, None]).sum(0).max() / c["lambda"])
+            over.append({"err_rel": err_own[-1], "first_order_rel": bound / scale,
+                         "max_cost_diff_rel_of_weighted": float(
+                             (dJ[live] / np.maximum(np.abs(J[live]), 1.0)).max()),
+                         "weighted_samples": int(len(live)), "N": c["N"], "H": c["H"]})
+    n1, steps1, t1 = 0, 0, time.perf_counter()
+    while n1 < len(recs) and (time.perf_counter() - t1 < 3.0 or n1 < 2):
+        rc = recs[n1]
+        oracle.tick(rc["cfg"], rc["mu"], rc["mf"], rc["tick"], rc["inp"], nthreads=1)
+        steps1 += rc["cfg"]["N"] * rc["cfg"]["H"]
+        n1 += 1
+    dt1 = time.perf_counter() - t1
+    base = {"value": steps / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(recs)} served C4 ticks of robots 0, 100, 200 rerun from their "
+                      f"exported states ({steps} rollout-steps), {dt:.1f} s wall",
+            "ticks_per_s": len(recs) / dt,
+            "single_core": {"value": steps1 / dt1,
+                            "sample": f"the first {n1} of those ticks on one thread, "
+                                      f"{dt1:.1f} s wall"}}
+    e = np.asarray(err_own)
+    shadow = {"ticks": len(recs), "of_ticks": total_ticks,
+              "within_tolerance_fraction": float((e <= 1e-4).mean()),
+              "median_action_err_rel": float(np.median(e)), "p99_action_err_rel": pct(e, 99),
+              "max_action_err_rel": float(e.max()), "max_update_err_rel": max(err_upd),
+              "tolerance_rel": 1e-4,
+              "over_tolerance": sorted(over, key=lambda o: -o["err_rel"])[:5],
+              "scale": "max(|grf|, m g / 2) of the oracle's action",
+              "what": "action_err: the GPU's action vs the FP64 oracle's tick from the same "
+                      "controller state and input; update_err: vs the oracle's update of the "
+                      "GPU's own FP32 costs"}
+    return base, shadow
 
 
 def main_c4(args):
     from paper_2403_11383_amd import binding, workloads
     arena = int(args.arena_gb * (1 << 30))
-    serve = serving_run(binding, workloads, args.duration, "serving", arena)
-    plain = serving_run(binding, workloads, args.duration, "direct", arena)
-    sat_serve = saturated_run(binding, workloads, 3.0, "serving", arena)
-    sat_plain = saturated_run(binding, workloads, 3.0, "direct", arena)
+    K = args.steps
+    # warm-up: code objects, first launches, the pinned pools
+    _ = saturated_run(binding, workloads, 0.05 * max(1, args.warmup), "serving", arena,
+                      warmup_ticks=1)
+    serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena)
+    plain = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "direct", arena)
+    sat = saturated_run(binding, workloads, K * STEP_S_SATURATED, "serving", arena,
+                        timing=args.timing)
+    sat_plain = saturated_run(binding, workloads, K * STEP_S_SATURATED, "direct", arena)
+    roof = None
+    if args.timing and "rollout_forms" in sat:
+        forms = sat["rollout_forms"]
+        names = ["k_rollout<float> (one lane per sample)", "k_rollout_quad (four lanes per sample)",
+                 "k_rollout<double>"]
+        f = max(range(3), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
+        fo = forms[f]
+        flop = fo["steps"] * FLOP_PER_ROLLOUT_STEP
+        roof = roofline_obj(
+            names[f], flop, fo["avg_ns"], fo["launches"],
+            traffic=stored_traffic("k_rollout", "c4"),
+            timed_launches=fo["launches"], duration_us=fo["avg_ns"] * 1e-3,
+            rollout_steps_per_launch=fo["steps"] / max(1, fo["launches"]),
+            flop_per_launch=flop / max(1, fo["launches"]),
+            event_overhead_us=sat["event_overhead_ns"] * 1e-3, event_overhead_taken_us=0.0,
+            other_forms={names[i]: {"timed_launches": forms[i]["launches"],
+                                    "duration_us": forms[i]["avg_ns"] * 1e-3,
+                                    "rollout_steps_per_launch":
+                                        forms[i]["steps"] / max(1, forms[i]["launches"])}
+                         for i in range(3) if i != f and forms[i]["launches"]})
+        del sat["rollout_forms"]
+    c = workloads.config("c4")
     line = {
-        "metric": METRIC, "value": serve["rollout_steps_per_s"], "unit": "rollout-steps/s",
-        "n_gpus": 1, "steps": serve["ticks"], "warmup": 0,
-        "ms_per_step": serve["elapsed_s"] / max(1, serve["ticks"]) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "c4: 256 robots, Poisson 50 Hz each, N in {2048,4096,8192}, "
-                               "H in {25,50}, continuous batching vs plain single MPPI",
-                   "duration_s": args.duration, "arena_gb": args.arena_gb},
-        "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"]},
-        "serving": serve, "plain_single_mppi": plain,
-        "saturated": {"serving": sat_serve, "plain_single_mppi": sat_plain},
+        "metric": METRIC, "value": sat["rollout_steps_per_s"], "unit": "rollout-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": sat["elapsed_s"] / K * 1e3,
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": sat["rollout_steps_per_s"] / sat_plain["rollout_steps_per_s"],
+        "vs_baseline_is": "continuous batching / plain single-controller MPPI, saturated "
+                          "rollout-steps/s on the same GPU (the paper prints no number)",
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4: 256 simulated robots, Poisson 50 Hz ticks each, N in "
+                               "{2048,4096,8192}, H in {25,50}, MPPI with gait frequency "
+                               f"~U[1.0,2.5] Hz per sample, GRF noise {c['sigma_grf']:g} N, "
+                               f"lambda {c['lambda']:g}, Q = I, R = 1e-4 I, friction cone "
+                               f"mu {c['mu_fric']:g}, dt {c['dt']:g} s, fixed seeded state "
+                               "per robot, continuous batching vs plain single MPPI",
+                   "robots": 256, "stream_s_50hz": K * STEP_S_ARRIVALS,
+                   "stream_s_saturated": K * STEP_S_SATURATED, "arena_gb": args.arena_gb},
+        "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"],
+                       "what": "arrival to completion, 50 Hz Poisson stream, continuous batching"},
+        "vs_plain": {"throughput_saturated_x": sat["rollout_steps_per_s"] /
+                     sat_plain["rollout_steps_per_s"],
+                     "p99_50hz_x": plain["p99_ms"] / serve["p99_ms"],
+                     "p99_saturated_x": sat_plain["p99_ms"] / sat["p99_ms"]},
+        "serving_50hz": serve, "plain_single_mppi_50hz": plain,
+        "saturated": {"serving": sat, "plain_single_mppi": sat_plain},
     }
+    if roof is not None:
+        line["roofline"] = roof
+    if not args.no_cpu_baseline:
+        recs, total = shadow_pass(binding, workloads, arena, args.shadow_seconds)
+        line["cpu_baseline"], line["shadow_oracle"] = cpu_baseline_c4(workloads, recs, total)
     print(json.dumps(line), flush=True)
 
 

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SBS_ABI_VERSION 3
+#define SBS_ABI_VERSION 4
 
 typedef enum {
   SBS_OK = 0,
@@ -149,7 +149,9 @@ int sbs_runtime_destroy(sbs_runtime *rt);
 int sbs_init_controller(sbs_runtime *rt, const sbs_controller_cfg *cfg, int32_t *id);
 int sbs_destroy_controller(sbs_runtime *rt, int32_t id);
 
-/* Queue one control step of controller id.  Never blocks.  Returns a ticket
+/* Queue one control step of controller id: "given x0" (Alg. 5), sample,
+ * roll out, rank and update as in Alg. 1 (MPPI: Alg. 4; best sample:
+ * Alg. 3) from the controller's warm-started mean (Sec. III-A).  Never blocks.  Returns a ticket
  * for sbs_fetch_action.  SBS_EINVAL for a non-finite state; SBS_ENOMEM
  * (direct mode) if the arena cannot hold the step's workspace now. */
 int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint64_t *ticket);
@@ -159,7 +161,10 @@ int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint6
 int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_tick_input *in,
                      uint64_t *tickets);
 
-/* Wait up to timeout_us (0: poll, <0: forever) for a ticket.  SBS_EAGAIN or
+/* The action of a control step: the first step of the updated mean, the
+ * command handed to the low-level controller (Fig. 2, Sec. IV), with the
+ * contact flags at the robot's phase and the updated gait frequency.
+ * Wait up to timeout_us (0: poll, <0: forever) for a ticket.  SBS_EAGAIN or
  * SBS_ETIMEDOUT if not done; on SBS_OK the ticket is consumed. */
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us);
 
@@ -207,6 +212,11 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
  * following ticks bit for bit (the noise is counter-based). */
 int sbs_get_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick);  /* mu [rows][12] */
 int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick);
+/* The same two calls under their checkpoint names: sbs_export_state is
+ * sbs_get_state, sbs_import_state is sbs_set_state (the warm-started mean of
+ * Sec. III-A is the whole state a controller carries between steps). */
+int sbs_export_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick);
+int sbs_import_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick);
 
 /* Debug taps.  sbs_set_debug(1) makes every later tick of the controller
  * keep its per-iteration costs [iterations][N], sampled phase increments
@@ -216,6 +226,9 @@ int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, ui
  * controller's current frequency mean and returns z [N][rows][12] and q [N]. */
 int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable);
 int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean);
+/* sbs_debug_fetch under the name of the cost tap: the rollout costs of
+ * Alg. 2 that the last completed tick ranked or weighted. */
+int sbs_debug_costs(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean);
 int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q);
 
 /* Noise prefetch for a single controller in direct mode (needs stream2):
@@ -235,6 +248,16 @@ int sbs_stats(sbs_runtime *rt, uint64_t *ticks, uint64_t *batches, uint64_t *adm
  * two forms agree within FP32 rounding, not bit for bit. */
 int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
 
+/* Stance-pair rollouts (default on): for a diagonal trot at duty factor 1/2
+ * (legs 0 and 3 in phase, legs 1 and 2 half a cycle later) exactly one leg
+ * pair is in stance at every step, and the one-lane rollouts form the forces,
+ * footholds, costs and torques of that pair only (the other pair's terms of
+ * Eq. (1) and of the cost are zero).  0 turns this off: every leg is formed
+ * and masked by its contact flag.  Both give the same sums; the switch is
+ * for verification and timing.  Takes effect at the next submission; a plan
+ * keeps the setting it was created with. */
+int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
+
 /* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
  * rollout kernel's own start and end (events carried by its dispatch) on
  * one launch in 16, counted from this call; 2 event commands between every
@@ -245,6 +268,16 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
  * resets it. */
 int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
+/* Rollout timing by form (modes 1 and 3): form 0 FP32 one lane per sample,
+ * 1 FP32 four lanes per sample, 2 FP64.  Returns the average device time
+ * [ns] of that form's timed rollout launches since the last call for the
+ * form, their number and the rollout-steps (sum of N H over the launches'
+ * controllers) they covered, and resets the form's accumulators.  The
+ * algorithmic FLOP rate of the rollout (Alg. 2) is then
+ * flop_per_step * steps / (avg_ns * launches).  SBS_EINVAL for a null
+ * runtime or a form outside 0..2. */
+int sbs_timing_rollout(sbs_runtime *rt, int32_t form, double *avg_ns, uint64_t *launches,
+                       double *steps);
 /* Fixed overhead of dispatch-carried timing events: the average interval [ns]
  * that an empty one-workgroup kernel launched with start/stop events on the
  * runtime's stream spans, over reps launches (1..4096; each waits for its own

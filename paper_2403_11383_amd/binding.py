@@ -31,8 +31,9 @@ EXPORTED = [
     "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions",
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
-    "sbs_set_state", "sbs_set_debug", "sbs_debug_fetch", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_state", "sbs_export_state", "sbs_import_state", "sbs_set_debug", "sbs_debug_fetch",
+    "sbs_debug_costs", "sbs_debug_noise", "sbs_stats",
+    "sbs_set_timing", "sbs_timing", "sbs_timing_rollout", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_rollout_pairs", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -115,7 +116,12 @@ def lib():
         L.sbs_plan_autotune.argtypes = [vp, i32, C.POINTER(TickInput), i32, C.POINTER(Tune)]
         L.sbs_get_state.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.POINTER(u32)]
         L.sbs_set_state.argtypes = [vp, i32, vp, C.c_double, u32]
+        L.sbs_export_state.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.POINTER(u32)]
+        L.sbs_import_state.argtypes = [vp, i32, vp, C.c_double, u32]
         L.sbs_set_debug.argtypes = [vp, i32, i32]
+        L.sbs_debug_costs.argtypes = [vp, i32, vp, vp, vp]
+        L.sbs_timing_rollout.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(u64),
+                                         C.POINTER(C.c_double)]
         L.sbs_debug_fetch.argtypes = [vp, i32, vp, vp, vp]
         L.sbs_debug_noise.argtypes = [vp, i32, u32, u32, vp, vp]
         L.sbs_stats.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
@@ -123,6 +129,7 @@ def lib():
         L.sbs_timing.argtypes = [vp, vp, vp]
         L.sbs_timing_overhead.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.sbs_set_rollout_lanes.argtypes = [vp, i32]
+        L.sbs_set_rollout_pairs.argtypes = [vp, i32]
         L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
@@ -364,17 +371,21 @@ class Runtime:
         return f"{dev}|{h}|" + hashlib.sha256(repr(members).encode()).hexdigest()[:16]
 
     # -- state -----------------------------------------------------------------
-    def get_state(self, cid: int):
+    def export_state(self, cid: int):
         mu = np.zeros((rows(self.cfgs[cid]), 12))
         mf = C.c_double()
         tk = C.c_uint32()
-        _check(lib().sbs_get_state(self._h, cid, mu.ctypes.data, C.byref(mf), C.byref(tk)))
+        _check(lib().sbs_export_state(self._h, cid, mu.ctypes.data, C.byref(mf), C.byref(tk)))
         return mu, mf.value, tk.value
 
-    def set_state(self, cid: int, mu, mu_f: float, tick: int):
+    def import_state(self, cid: int, mu, mu_f: float, tick: int):
         m = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
         assert m.size == 12 * rows(self.cfgs[cid])
-        _check(lib().sbs_set_state(self._h, cid, m.ctypes.data, float(mu_f), int(tick) & 0xFFFFFFFF))
+        _check(lib().sbs_import_state(self._h, cid, m.ctypes.data, float(mu_f),
+                                      int(tick) & 0xFFFFFFFF))
+
+    get_state = export_state   # the C ABI's sbs_get_state / sbs_set_state
+    set_state = import_state
 
     # -- debug taps --------------------------------------------------------------
     def set_debug(self, cid: int, on: bool = True):
@@ -386,8 +397,10 @@ class Runtime:
         J = np.zeros((R, N))
         q = np.zeros((R, N), np.uint32)
         mean = np.zeros((rows(c), 12))
-        _check(lib().sbs_debug_fetch(self._h, cid, J.ctypes.data, q.ctypes.data, mean.ctypes.data))
+        _check(lib().sbs_debug_costs(self._h, cid, J.ctypes.data, q.ctypes.data, mean.ctypes.data))
         return J, q, mean
+
+    debug_costs = debug_fetch
 
     def debug_noise(self, cid: int, tick: int, r: int = 0):
         c = self.cfgs[cid]
@@ -416,12 +429,24 @@ class Runtime:
         """0 automatic, 1 one lane per sample, 4 one lane per leg."""
         _check(lib().sbs_set_rollout_lanes(self._h, int(lanes)))
 
+    def set_rollout_pairs(self, on: bool = True):
+        """Stance-pair one-lane rollouts for the diagonal trot at duty 1/2."""
+        _check(lib().sbs_set_rollout_pairs(self._h, 1 if on else 0))
+
     def timing(self):
         avg = np.zeros(4)
         n = np.zeros(4, np.uint64)
         _check(lib().sbs_timing(self._h, avg.ctypes.data, n.ctypes.data))
         return {"noise_ns": avg[0], "rollout_ns": avg[1], "select_ns": avg[2],
                 "update_ns": avg[3], "launches": n.tolist()}
+
+    def timing_rollout(self, form: int):
+        """Timed rollout launches of one form (0 FP32 one lane, 1 FP32 four
+        lanes, 2 FP64) since the last call: average device time [ns], number
+        of launches and the rollout-steps they covered."""
+        avg, n, st = C.c_double(), C.c_uint64(), C.c_double()
+        _check(lib().sbs_timing_rollout(self._h, int(form), C.byref(avg), C.byref(n), C.byref(st)))
+        return {"avg_ns": avg.value, "launches": n.value, "steps": st.value}
 
     def timing_overhead_ns(self, reps: int = 64) -> float:
         """Interval that the start/stop events of an empty dispatch span [ns]."""

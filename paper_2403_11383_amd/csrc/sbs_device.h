@@ -115,7 +115,9 @@ struct LaunchTab {
   int32_t max_rows;      // most mean rows among the items
   int32_t spline;        // the items use the spline parametrisation
   int32_t noise_rpt;     // noise rows per thread (single-controller launches; 0 = 1)
-  int32_t pad2;
+  int32_t pairs;         // one-lane rollouts in the stance-pair form: every item is a
+                         // diagonal trot at duty 1/2 (one of the leg pairs {0, 3},
+                         // {1, 2} in stance at every step)
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

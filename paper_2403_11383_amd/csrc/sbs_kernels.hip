@@ -26,6 +26,8 @@
 #include <stdint.h>
 
 #include <functional>
+#include <limits>
+#include <type_traits>
 
 #include "sbs_device.h"
 
@@ -465,6 +467,33 @@ __device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 __device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
+
+// The same sine and cosine for |x| <= pi/4 (strictly: |x 2/pi| <= 1/2, where
+// the reduction above picks n = 0 and leaves r = x): the polynomials alone,
+// bit for bit what sincos_t returns there.
+__device__ __forceinline__ bool sincos_small_arg(float x) {
+  return __builtin_fabsf(x * 0x1.45f306p-1f) <= 0.5f;
+}
+__device__ __forceinline__ void sincos_small(float r, float *s, float *c) {
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);
+  ps = __builtin_fmaf(r2, ps, 0x1.111112p-7f);
+  ps = __builtin_fmaf(r2, ps, -0x1.555556p-3f);
+  *s = __builtin_fmaf(r * r2, ps, r);
+  float pc = __builtin_fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);
+  pc = __builtin_fmaf(r2, pc, -0x1.6c16c2p-10f);
+  pc = __builtin_fmaf(r2, pc, 0x1.555556p-5f);
+  pc = __builtin_fmaf(r2, pc, -0.5f);
+  *c = __builtin_fmaf(r2, pc, 1.0f);
+}
+// Attitude sine and cosine of one angle: where every active lane of the wave
+// has a small angle (a wave-uniform branch) the reduction and quadrant steps
+// are skipped.
+__device__ __forceinline__ void sincos_wave(float x, float *s, float *c) {
+  if (__all(sincos_small_arg(x))) sincos_small(x, s, c);
+  else sincos_t(x, s, c);
+}
+__device__ __forceinline__ void sincos_wave(double x, double *s, double *c) { sincos_t(x, s, c); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -525,32 +554,44 @@ __device__ __forceinline__ void friction_clip(T &fx, T &fy, T &fz, T mu) {
 }
 
 // Loop-invariant parameters of one controller in the working precision.
+// The tracking cost sum_i Q_i (x_i - x^r_i)^2 is formed as sum_i e_i^2 with
+// e_i = sqrt(Q_i) x_i - sqrt(Q_i) x^r_i (one FMA per error); the reference
+// position moves with the reference velocity, so its scaled form is
+// sq_pr + t sq_vr.  The Euler update's dt is folded into the constants that
+// scale the accelerations (dt / m, dt / I).
 template <typename T>
 struct RollConst {
-  T dt, inv_m, g, mg, mu_f, rho, f_nom;
-  T I[3], iI[3], hip[12], Q[12], Rw[12], pr[3], vr[3], yaw_ref, inv_g;
+  T dt, g, mg, mu_f, rho, f_nom, dt_m, dt_g;
+  T I[3], dt_iI[3], hip[12], Rw[12], vr[3], inv_g;
+  T sq[12], sq_pr[3], sq_vr[3], sq_yaw;
   T sigma0;
 };
 
 template <typename T>
 __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
-  c.dt = (T)d.dt; c.inv_m = (T)d.inv_mass; c.g = (T)d.gravity; c.mg = (T)(d.mass * d.gravity);
+  c.dt = (T)d.dt; c.g = (T)d.gravity; c.mg = (T)(d.mass * d.gravity);
   c.mu_f = (T)d.mu_fric; c.rho = (T)d.rho; c.f_nom = (T)d.f_nominal; c.inv_g = (T)d.inv_g;
+  c.dt_m = (T)(d.dt * d.inv_mass);
+  c.dt_g = (T)(d.dt * d.gravity);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    c.I[i] = (T)d.inertia[i]; c.iI[i] = (T)d.inv_inertia[i];
-    c.pr[i] = (T)d.p_ref0[i]; c.vr[i] = (T)d.v_ref[i];
+  for (int i = 0; i < 12; ++i) {
+    c.hip[i] = (T)d.hip[i]; c.Rw[i] = (T)d.Rw[i]; c.sq[i] = (T)__builtin_sqrt(d.Q[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 12; ++i) { c.hip[i] = (T)d.hip[i]; c.Q[i] = (T)d.Q[i]; c.Rw[i] = (T)d.Rw[i]; }
-  c.yaw_ref = (T)d.yaw_ref;
+  for (int i = 0; i < 3; ++i) {
+    c.I[i] = (T)d.inertia[i]; c.dt_iI[i] = (T)(d.dt * d.inv_inertia[i]);
+    c.vr[i] = (T)d.v_ref[i];
+    c.sq_pr[i] = (T)(__builtin_sqrt(d.Q[i]) * d.p_ref0[i]);
+    c.sq_vr[i] = (T)(__builtin_sqrt(d.Q[i]) * d.v_ref[i]);
+  }
+  c.sq_yaw = (T)(__builtin_sqrt(d.Q[5]) * d.yaw_ref);
   c.sigma0 = (T)d.sigma0;
 }
 
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
-template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL>
+template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR>
 __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
@@ -562,6 +603,11 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   T *s_spw = s_sig + (size_t)tab.max_rows * 12;                        // SPL: [H][4]
   int *s_spb = reinterpret_cast<int *>(s_spw + (size_t)tab.max_h * 4);  // SPL: [H]
   const bool elite_sigma = (d.method == 1) && (tab.r > 0);
+  // PAIR: per stance slot (pair A = legs 0, 3; pair B = legs 1, 2) the leg's
+  // hip offset and GRF weights, [pair][slot][hx, hy, hz, Rx, Ry, Rz, -, -]; a
+  // lane reads its pair's two rows with one address (selecting between two
+  // uniform constants per lane would take register moves for every value)
+  __shared__ __align__(16) T s_pair[2][2][8];
   {
     const T *mu = mean_in<T>(d, tab.r);
     for (int i = threadIdx.x; i < M * 12; i += BLOCK) {
@@ -571,6 +617,13 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
     if constexpr (SPL) {
       for (int i = threadIdx.x; i < H * 4; i += BLOCK) s_spw[i] = (T)d.sp_w[i];
       for (int i = threadIdx.x; i < H; i += BLOCK) s_spb[i] = d.sp_b[i];
+    }
+    if constexpr (PAIR) {
+      for (int i = threadIdx.x; i < 32; i += BLOCK) {
+        const int pr = i >> 4, sl = (i >> 3) & 1, e = i & 7;
+        const int leg = pr == 0 ? (sl == 0 ? 0 : 3) : (sl == 0 ? 1 : 2);
+        s_pair[pr][sl][e] = e < 3 ? (T)d.hip[3 * leg + e] : e < 6 ? (T)d.Rw[3 * leg + e - 3] : T(0);
+      }
     }
   }
   __syncthreads();
@@ -623,158 +676,240 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
     if (4 < M) { z0 = zp[4 * zstride]; z1 = zp[4 * zstride + 1]; z2 = zp[4 * zstride + 2]; }
   }
 
+  // The step loop, in two forms.  The general one handles every gait: all
+  // four legs' forces are formed, clipped and masked by stance.  The
+  // stance-pair one (PAIR) serves the diagonal trot with duty factor 1/2,
+  // where at every step exactly one pair -- legs {0, 3} while leg 0's phase
+  // is below D_q, legs {1, 2} otherwise -- is in stance: it forms the
+  // forces, footholds, costs and torques of those two legs only.  The swing
+  // legs' terms in the general form are exact zeros added in leg order, so
+  // both forms compute the same sums.
+  auto steps = [&](auto pair_tag) {
+    constexpr bool PAIRS = decltype(pair_tag)::value;
+    // PAIR: world feet of the stance pair's lower- and higher-indexed legs,
+    // starting from the tick's footholds of the pair in stance at step 0
+    const uint32_t phA0 = ph[0];
+    bool sA_prev = duty_full || (phA0 < duty_q);
+    T f0[3], f1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      f0[i] = sA_prev ? pf[i] : pf[3 + i];
+      f1[i] = sA_prev ? pf[9 + i] : pf[6 + i];
+    }
 #pragma unroll UNROLL
-  for (int j = 0; j < H; ++j) {
-    T u[12];
-    if constexpr (SPL) {
-      while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
-        const int p = wb + 4;
-        const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+    for (int j = 0; j < H; ++j) {
+      T u[12];
+      if constexpr (SPL) {
+        while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
+          const int p = wb + 4;
+          const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                                z2.x, z2.y, z2.z, z2.w};
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            win[0][i] = win[1][i];
+            win[1][i] = win[2][i];
+            win[2][i] = win[3][i];
+            win[3][i] = (p < M) ? s_mu[p * 12 + i] + s_sig[p * 12 + i] * (T)zw[i] : T(0);
+          }
+          ++wb;
+          if (wb + 4 < M) {
+            const float4 *zn = zp + (size_t)(wb + 4) * zstride;
+            z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
+          }
+        }
+        const T w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+          u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
+      } else {
+        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                               z2.x, z2.y, z2.z, z2.w};
+        const T *muj = s_mu + j * 12;
+        const T *sgj = s_sig + j * 12;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-          win[0][i] = win[1][i];
-          win[1][i] = win[2][i];
-          win[2][i] = win[3][i];
-          win[3][i] = (p < M) ? s_mu[p * 12 + i] + s_sig[p * 12 + i] * (T)zw[i] : T(0);
-        }
-        ++wb;
-        if (wb + 4 < M) {
-          const float4 *zn = zp + (size_t)(wb + 4) * zstride;
-          z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
-        }
+        for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+        // the next step's noise (the last step reads its own row again), into
+        // the registers this step's noise has just left
+        z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
+        zq += (j + 2 < H) ? zstride : 0;
       }
-      const T w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
-#pragma unroll
-      for (int i = 0; i < 12; ++i)
-        u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
-    } else {
-      const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                            z2.x, z2.y, z2.z, z2.w};
-      const T *muj = s_mu + j * 12;
-      const T *sgj = s_sig + j * 12;
-#pragma unroll
-      for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
-      // the next step's noise (the last step reads its own row again), into
-      // the registers this step's noise has just left
-      z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
-      zq += (j + 2 < H) ? zstride : 0;
-    }
-    // contact schedule
-    bool st[4];
-    int nst = 0;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      st[l] = duty_full || (ph[l] < duty_q);
-      nst += st[l] ? 1 : 0;
-    }
-    // attitude
-    T sr, cr, sp, cp, sy, cy;
-    sincos_t(x[3], &sr, &cr);
-    sincos_t(x[4], &sp, &cp);
-    sincos_t(x[5], &sy, &cy);
-    const T spsr = sp * sr, spcr = sp * cr;
-    const T R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
-    const T R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
-    const T R20 = -sp, R21 = cp * sr, R22 = cp * cr;
-    // footholds of the legs touching down at this step (Eq. (2))
-    {
+      // attitude
+      T sr, cr, sp, cp, sy, cy;
+      sincos_wave(x[3], &sr, &cr);
+      sincos_wave(x[4], &sp, &cp);
+      sincos_wave(x[5], &sy, &cy);
+      const T spsr = sp * sr, spcr = sp * cr;
+      const T R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
+      const T R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
+      const T R20 = -sp, R21 = cp * sr, R22 = cp * cr;
+      // capture-point base of Eq. (2) for legs touching down at this step
       const T zc = x[2] > T(0) ? x[2] : T(0);
       const T cap = sqrt_t(zc * c.inv_g);
       const T bx = x[0] + half_tst * c.vr[0] + cap * (x[6] - c.vr[0]);
       const T by = x[1] + half_tst * c.vr[1] + cap * (x[7] - c.vr[1]);
+      // tracking part of the stage cost (Sec. V); each form adds its legs'
+      // GRF terms to it in leg order
+      auto tracking = [&]() -> T {
+        const T e0 = c.sq[0] * x[0] - (c.sq_pr[0] + tj * c.sq_vr[0]);
+        const T e1 = c.sq[1] * x[1] - (c.sq_pr[1] + tj * c.sq_vr[1]);
+        const T e2 = c.sq[2] * x[2] - (c.sq_pr[2] + tj * c.sq_vr[2]);
+        const T e3 = c.sq[3] * x[3], e4 = c.sq[4] * x[4], e5 = c.sq[5] * x[5] - c.sq_yaw;
+        const T e6 = c.sq[6] * x[6] - c.sq_vr[0], e7 = c.sq[7] * x[7] - c.sq_vr[1];
+        const T e8 = c.sq[8] * x[8] - c.sq_vr[2];
+        const T e9 = c.sq[9] * x[9], e10 = c.sq[10] * x[10], e11 = c.sq[11] * x[11];
+        return e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3 + e4 * e4 + e5 * e5 + e6 * e6 + e7 * e7 +
+               e8 * e8 + e9 * e9 + e10 * e10 + e11 * e11;
+      };
+      T stage;
+      T Fx = T(0), Fy = T(0), Fz = T(0), tx = T(0), ty = T(0), tz = T(0);
+      if constexpr (PAIRS) {
+        const bool sA = duty_full || (ph[0] < duty_q);
+        const bool td = sA != sA_prev;  // the pair in stance has just touched down
+        sA_prev = sA;
+        // the stance legs: 0 and 3 (pair A) or 1 and 2 (pair B), in leg order
+        const T *pc = &s_pair[sA ? 0 : 1][0][0];
+        T v0[3], v1[3], h0[3], h1[3], r0[3], r1[3];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const bool td = st[l] && !prev[l];
-        const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
-        const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
-        const T ny = by + R10 * hx + R11 * hy + R12 * hz;
-        pf[3 * l + 0] = td ? nx : pf[3 * l + 0];
-        pf[3 * l + 1] = td ? ny : pf[3 * l + 1];
-        pf[3 * l + 2] = td ? T(0) : pf[3 * l + 2];
-        prev[l] = st[l];
+        for (int i = 0; i < 3; ++i) {
+          v0[i] = sA ? u[i] : u[3 + i];
+          v1[i] = sA ? u[9 + i] : u[6 + i];
+          h0[i] = pc[i];
+          r0[i] = pc[3 + i];
+          h1[i] = pc[8 + i];
+          r1[i] = pc[11 + i];
+        }
+        {  // footholds of Eq. (2) at touchdown
+          const T n0x = bx + R00 * h0[0] + R01 * h0[1] + R02 * h0[2];
+          const T n0y = by + R10 * h0[0] + R11 * h0[1] + R12 * h0[2];
+          const T n1x = bx + R00 * h1[0] + R01 * h1[1] + R02 * h1[2];
+          const T n1y = by + R10 * h1[0] + R11 * h1[1] + R12 * h1[2];
+          f0[0] = td ? n0x : f0[0];
+          f0[1] = td ? n0y : f0[1];
+          f0[2] = td ? T(0) : f0[2];
+          f1[0] = td ? n1x : f1[0];
+          f1[1] = td ? n1y : f1[1];
+          f1[2] = td ? T(0) : f1[2];
+        }
+        if (friction) {
+          friction_clip<T>(v0[0], v0[1], v0[2], c.mu_f);
+          friction_clip<T>(v1[0], v1[1], v1[2], c.mu_f);
+        }
+        // two legs in stance: each carries half the weight in u^r
+        stage = tracking();
+        {
+          const T ez0 = v0[2] - mg2, ez1 = v1[2] - mg2;
+          stage += r0[0] * v0[0] * v0[0] + r0[1] * v0[1] * v0[1] + r0[2] * ez0 * ez0;
+          stage += r1[0] * v1[0] * v1[0] + r1[1] * v1[1] * v1[1] + r1[2] * ez1 * ez1;
+        }
+        {
+          const T lx = f0[0] - x[0], ly = f0[1] - x[1], lz = f0[2] - x[2];
+          Fx += v0[0]; Fy += v0[1]; Fz += v0[2];
+          tx += ly * v0[2] - lz * v0[1];
+          ty += lz * v0[0] - lx * v0[2];
+          tz += lx * v0[1] - ly * v0[0];
+        }
+        {
+          const T lx = f1[0] - x[0], ly = f1[1] - x[1], lz = f1[2] - x[2];
+          Fx += v1[0]; Fy += v1[1]; Fz += v1[2];
+          tx += ly * v1[2] - lz * v1[1];
+          ty += lz * v1[0] - lx * v1[2];
+          tz += lx * v1[1] - ly * v1[0];
+        }
+      } else {
+        // contact schedule
+        bool st[4];
+        int nst = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          st[l] = duty_full || (ph[l] < duty_q);
+          nst += st[l] ? 1 : 0;
+        }
+        // footholds of the legs touching down at this step (Eq. (2))
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const bool td = st[l] && !prev[l];
+          const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
+          const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
+          const T ny = by + R10 * hx + R11 * hy + R12 * hz;
+          pf[3 * l + 0] = td ? nx : pf[3 * l + 0];
+          pf[3 * l + 1] = td ? ny : pf[3 * l + 1];
+          pf[3 * l + 2] = td ? T(0) : pf[3 * l + 2];
+          prev[l] = st[l];
+        }
+        // policy: theta = mu + sigma z (per step, or the spline of the knots),
+        // clipped to the cone, masked by stance
+        if (friction) {
+#pragma unroll
+          for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          u[3 * l] = st[l] ? u[3 * l] : T(0);
+          u[3 * l + 1] = st[l] ? u[3 * l + 1] : T(0);
+          u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
+        }
+        T share = c.mg;  // m g / n_stance, selected without branches
+        share = (nst >= 2) ? mg2 : share;
+        share = (nst >= 3) ? mg3 : share;
+        share = (nst >= 4) ? mg4 : share;
+        stage = tracking();
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const T ez = u[3 * l + 2] - (st[l] ? share : T(0));
+          stage += c.Rw[3 * l] * u[3 * l] * u[3 * l] + c.Rw[3 * l + 1] * u[3 * l + 1] * u[3 * l + 1] +
+                   c.Rw[3 * l + 2] * ez * ez;
+        }
+        // SRBD derivative, Eq. (1), with world-frame lever arms to the feet
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const T lx = pf[3 * l] - x[0], ly = pf[3 * l + 1] - x[1], lz = pf[3 * l + 2] - x[2];
+          const T ux = u[3 * l], uy = u[3 * l + 1], uz = u[3 * l + 2];
+          Fx += ux; Fy += uy; Fz += uz;
+          tx += ly * uz - lz * uy;
+          ty += lz * ux - lx * uz;
+          tz += lx * uy - ly * ux;
+        }
       }
-    }
-    // policy: theta = mu + sigma z (per step, or the spline of the knots),
-    // clipped to the cone, masked by stance
-    if (friction) {
+      {  // compensated accumulation
+        const T y = stage - Jc;
+        const T t = J + y;
+        Jc = (t - J) - y;
+        J = t;
+      }
+      const T tbx = R00 * tx + R10 * ty + R20 * tz;  // R^T tau_world
+      const T tby = R01 * tx + R11 * ty + R21 * tz;
+      const T tbz = R02 * tx + R12 * ty + R22 * tz;
+      const T wx = x[9], wy = x[10], wz = x[11];
+      const T Iwx = c.I[0] * wx, Iwy = c.I[1] * wy, Iwz = c.I[2] * wz;
+      const T gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
+      const T icp = rcp_t(cp);
+      const T a = sr * wy + cr * wz;
+      const T dphi = wx + a * sp * icp;
+      const T dth = cr * wy - sr * wz;
+      const T dpsi = a * icp;
+      // explicit Euler
+      x[0] += c.dt * x[6];
+      x[1] += c.dt * x[7];
+      x[2] += c.dt * x[8];
+      x[3] += c.dt * dphi;
+      x[4] += c.dt * dth;
+      x[5] += c.dt * dpsi;
+      x[6] += c.dt_m * Fx;
+      x[7] += c.dt_m * Fy;
+      x[8] += c.dt_m * Fz - c.dt_g;
+      x[9] += c.dt_iI[0] * (tbx - gx);
+      x[10] += c.dt_iI[1] * (tby - gy);
+      x[11] += c.dt_iI[2] * (tbz - gz);
+      if constexpr (PAIRS) {
+        ph[0] += q;
+      } else {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
+        for (int l = 0; l < 4; ++l) ph[l] += q;
+      }
+      tj += c.dt;
     }
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      u[3 * l] = st[l] ? u[3 * l] : T(0);
-      u[3 * l + 1] = st[l] ? u[3 * l + 1] : T(0);
-      u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
-    }
-    // stage cost (Sec. V)
-    T share = c.mg;  // m g / n_stance, selected without branches
-    share = (nst >= 2) ? mg2 : share;
-    share = (nst >= 3) ? mg3 : share;
-    share = (nst >= 4) ? mg4 : share;
-    T stage = T(0);
-    {
-      const T e0 = x[0] - (c.pr[0] + tj * c.vr[0]);
-      const T e1 = x[1] - (c.pr[1] + tj * c.vr[1]);
-      const T e2 = x[2] - (c.pr[2] + tj * c.vr[2]);
-      const T e5 = x[5] - c.yaw_ref;
-      const T e6 = x[6] - c.vr[0], e7 = x[7] - c.vr[1], e8 = x[8] - c.vr[2];
-      stage = c.Q[0] * e0 * e0 + c.Q[1] * e1 * e1 + c.Q[2] * e2 * e2 + c.Q[3] * x[3] * x[3] +
-              c.Q[4] * x[4] * x[4] + c.Q[5] * e5 * e5 + c.Q[6] * e6 * e6 + c.Q[7] * e7 * e7 +
-              c.Q[8] * e8 * e8 + c.Q[9] * x[9] * x[9] + c.Q[10] * x[10] * x[10] +
-              c.Q[11] * x[11] * x[11];
-    }
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const T ez = u[3 * l + 2] - (st[l] ? share : T(0));
-      stage += c.Rw[3 * l] * u[3 * l] * u[3 * l] + c.Rw[3 * l + 1] * u[3 * l + 1] * u[3 * l + 1] +
-               c.Rw[3 * l + 2] * ez * ez;
-    }
-    {  // compensated accumulation
-      const T y = stage - Jc;
-      const T t = J + y;
-      Jc = (t - J) - y;
-      J = t;
-    }
-    // SRBD derivative, Eq. (1), with world-frame lever arms to the feet
-    T Fx = T(0), Fy = T(0), Fz = T(0), tx = T(0), ty = T(0), tz = T(0);
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const T lx = pf[3 * l] - x[0], ly = pf[3 * l + 1] - x[1], lz = pf[3 * l + 2] - x[2];
-      const T ux = u[3 * l], uy = u[3 * l + 1], uz = u[3 * l + 2];
-      Fx += ux; Fy += uy; Fz += uz;
-      tx += ly * uz - lz * uy;
-      ty += lz * ux - lx * uz;
-      tz += lx * uy - ly * ux;
-    }
-    const T tbx = R00 * tx + R10 * ty + R20 * tz;  // R^T tau_world
-    const T tby = R01 * tx + R11 * ty + R21 * tz;
-    const T tbz = R02 * tx + R12 * ty + R22 * tz;
-    const T wx = x[9], wy = x[10], wz = x[11];
-    const T Iwx = c.I[0] * wx, Iwy = c.I[1] * wy, Iwz = c.I[2] * wz;
-    const T gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
-    const T icp = rcp_t(cp);
-    const T a = sr * wy + cr * wz;
-    const T dphi = wx + a * sp * icp;
-    const T dth = cr * wy - sr * wz;
-    const T dpsi = a * icp;
-    // explicit Euler
-    x[0] += c.dt * x[6];
-    x[1] += c.dt * x[7];
-    x[2] += c.dt * x[8];
-    x[3] += c.dt * dphi;
-    x[4] += c.dt * dth;
-    x[5] += c.dt * dpsi;
-    x[6] += c.dt * (Fx * c.inv_m);
-    x[7] += c.dt * (Fy * c.inv_m);
-    x[8] += c.dt * (Fz * c.inv_m - c.g);
-    x[9] += c.dt * ((tbx - gx) * c.iI[0]);
-    x[10] += c.dt * ((tby - gy) * c.iI[1]);
-    x[11] += c.dt * ((tbz - gz) * c.iI[2]);
-#pragma unroll
-    for (int l = 0; l < 4; ++l) ph[l] += q;
-    tj += c.dt;
-  }
+  };
+  steps(std::integral_constant<bool, PAIR>{});
   const T df = fk - c.f_nom;
   J += c.rho * df * df;
   if (!(J >= T(0)) || !finite_t(J)) J = inf_t<T>();
@@ -832,22 +967,29 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   const int k = (b - stage_start<INL>(tab.roll_start, it)) * kPerBlock + (int)(threadIdx.x >> 2);
   if (k >= N) return;  // whole quads leave together
 
-  const float dt = (float)d.dt, inv_m = (float)d.inv_mass, g = (float)d.gravity;
+  const float dt = (float)d.dt;
+  const float dt_m = (float)(d.dt * d.inv_mass), dt_g = (float)(d.dt * d.gravity);
   const float mg = (float)(d.mass * d.gravity), mu_f = (float)d.mu_fric, inv_g = (float)d.inv_g;
   const float mg2 = mg * 0.5f, mg3 = mg / 3.f, mg4 = mg * 0.25f;
   const float I0 = (float)d.inertia[0], I1 = (float)d.inertia[1], I2 = (float)d.inertia[2];
-  const float iI0 = (float)d.inv_inertia[0], iI1 = (float)d.inv_inertia[1],
-              iI2 = (float)d.inv_inertia[2];
+  const float dt_iI0 = (float)(d.dt * d.inv_inertia[0]), dt_iI1 = (float)(d.dt * d.inv_inertia[1]),
+              dt_iI2 = (float)(d.dt * d.inv_inertia[2]);
   const float vr0 = (float)d.v_ref[0], vr1 = (float)d.v_ref[1], vr2 = (float)d.v_ref[2];
   const float hx = (float)d.hip[3 * l], hy = (float)d.hip[3 * l + 1], hz = (float)d.hip[3 * l + 2];
   const float Rw0 = (float)d.Rw[3 * l], Rw1 = (float)d.Rw[3 * l + 1], Rw2 = (float)d.Rw[3 * l + 2];
-  const float Qa = (float)d.Q[3 * l], Qb = (float)d.Q[3 * l + 1], Qc = (float)d.Q[3 * l + 2];
-  // reference of state group l: position (moves with v_ref), attitude (0, 0,
+  // tracking errors of state group l scaled by sqrt(Q): e = sq x - sq x^r,
+  // the reference being position (moving with v_ref), attitude (0, 0,
   // yaw_ref), velocity v_ref, angular velocity 0
-  const float ra0 = (l == 0) ? (float)d.p_ref0[0] : (l == 2) ? vr0 : 0.f;
-  const float ra1 = (l == 0) ? (float)d.p_ref0[1] : (l == 2) ? vr1 : 0.f;
-  const float ra2 = (l == 0) ? (float)d.p_ref0[2] : (l == 1) ? (float)d.yaw_ref : (l == 2) ? vr2 : 0.f;
-  const float rv0 = (l == 0) ? vr0 : 0.f, rv1 = (l == 0) ? vr1 : 0.f, rv2 = (l == 0) ? vr2 : 0.f;
+  const double qa = __builtin_sqrt(d.Q[3 * l]), qb = __builtin_sqrt(d.Q[3 * l + 1]),
+               qc = __builtin_sqrt(d.Q[3 * l + 2]);
+  const float sqa = (float)qa, sqb = (float)qb, sqc = (float)qc;
+  const float ra0 = (float)(qa * ((l == 0) ? d.p_ref0[0] : (l == 2) ? d.v_ref[0] : 0.0));
+  const float ra1 = (float)(qb * ((l == 0) ? d.p_ref0[1] : (l == 2) ? d.v_ref[1] : 0.0));
+  const float ra2 = (float)(qc * ((l == 0) ? d.p_ref0[2] : (l == 1) ? d.yaw_ref
+                                                          : (l == 2) ? d.v_ref[2] : 0.0));
+  const float rv0 = (float)(qa * ((l == 0) ? d.v_ref[0] : 0.0));
+  const float rv1 = (float)(qb * ((l == 0) ? d.v_ref[1] : 0.0));
+  const float rv2 = (float)(qc * ((l == 0) ? d.v_ref[2] : 0.0));
   const uint32_t q = draw_q(d, tab.r, k);
   if (l == 0) d.q[k] = q;
   const double fkd = (double)q * d.inv_q_scale;
@@ -921,7 +1063,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     // attitude: lanes 0, 1, 2 take roll, pitch, yaw
     const float ang = (l == 0) ? x[3] : (l == 1) ? x[4] : x[5];
     float sv, cv;
-    sincos_t(ang, &sv, &cv);
+    sincos_wave(ang, &sv, &cv);
     const float sr = dpp<0x00>(sv), cr = dpp<0x00>(cv);
     const float sp = dpp<0x55>(sv), cp = dpp<0x55>(cv);
     const float sy = dpp<0xAA>(sv), cy = dpp<0xAA>(cv);
@@ -955,8 +1097,9 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     const float ga = (l == 0) ? x[0] : (l == 1) ? x[3] : (l == 2) ? x[6] : x[9];
     const float gb = (l == 0) ? x[1] : (l == 1) ? x[4] : (l == 2) ? x[7] : x[10];
     const float gc = (l == 0) ? x[2] : (l == 1) ? x[5] : (l == 2) ? x[8] : x[11];
-    const float e0 = ga - (ra0 + tj * rv0), e1 = gb - (ra1 + tj * rv1), e2 = gc - (ra2 + tj * rv2);
-    const float stage = Qa * e0 * e0 + Qb * e1 * e1 + Qc * e2 * e2 + Rw0 * ux * ux + Rw1 * uy * uy +
+    const float e0 = sqa * ga - (ra0 + tj * rv0), e1 = sqb * gb - (ra1 + tj * rv1);
+    const float e2 = sqc * gc - (ra2 + tj * rv2);
+    const float stage = e0 * e0 + e1 * e1 + e2 * e2 + Rw0 * ux * ux + Rw1 * uy * uy +
                         Rw2 * ez * ez;
     {
       const float y = stage - Jc;
@@ -987,12 +1130,12 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     x[3] += dt * dphi;
     x[4] += dt * dth;
     x[5] += dt * dpsi;
-    x[6] += dt * (Fx * inv_m);
-    x[7] += dt * (Fy * inv_m);
-    x[8] += dt * (Fz * inv_m - g);
-    x[9] += dt * ((tbx - gx) * iI0);
-    x[10] += dt * ((tby - gy) * iI1);
-    x[11] += dt * ((tbz - gz) * iI2);
+    x[6] += dt_m * Fx;
+    x[7] += dt_m * Fy;
+    x[8] += dt_m * Fz - dt_g;
+    x[9] += dt_iI0 * (tbx - gx);
+    x[10] += dt_iI1 * (tby - gy);
+    x[11] += dt_iI2 * (tbz - gz);
     ph += q;
     tj += dt;
   }
@@ -1614,7 +1757,13 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   for (int c = 0; c < 12; ++c) f1[c] = T(0);
   double sw = 0.0, swf = 0.0, cnt = 0.0;
   if (!skip) {
-    const T il = (T)d.inv_lambda;
+    // 1/lambda in the working precision, kept finite: at a lambda whose
+    // reciprocal overflows FP32 the best sample's (beta - J) il stays
+    // 0 * finite = 0 (weight 1) rather than 0 * inf = NaN, and every other
+    // weight underflows to 0 -- the argmin limit of Alg. 4
+    const double ild = d.inv_lambda;
+    const T il = (T)(ild < (double)std::numeric_limits<T>::max() ? ild
+                                                                  : (double)std::numeric_limits<T>::max());
 #pragma unroll
     for (int i = 0; i < kMppiPer; ++i)
       if (tid + i * kMppiBlock < N)
@@ -1697,14 +1846,38 @@ static void launch_timed(K kernel, dim3 g, dim3 b, size_t lds, hipStream_t s, hi
   else hipLaunchKernelGGL(kernel, g, b, lds, s, tab, inl);
 }
 
+template <bool INL, bool SPL, bool PAIR>
+static hipError_t launch_one_lane(const LaunchTab &tab, const TickDesc &inl, int precision,
+                                  size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 rg(tab.total_roll);
+  if (precision == 1) {
+    launch_timed(k_rollout<double, 64, 1, INL, SPL, PAIR>, rg, dim3(64), lds, s, e0, e1, tab, inl);
+    return hipSuccess;
+  }
+  switch (tab.roll_block * 4 + tab.unroll) {
+    case 64 * 4 + 1: launch_timed(k_rollout<float, 64, 1, INL, SPL, PAIR>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
+    case 128 * 4 + 1: launch_timed(k_rollout<float, 128, 1, INL, SPL, PAIR>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
+    case 256 * 4 + 1: launch_timed(k_rollout<float, 256, 1, INL, SPL, PAIR>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
+    case 64 * 4 + 2:
+      if (SPL) return hipErrorInvalidValue;
+      launch_timed(k_rollout<float, 64, 2, INL, false, PAIR>, rg, dim3(64), lds, s, e0, e1, tab, inl);
+      break;
+    case 128 * 4 + 2:
+      if (SPL) return hipErrorInvalidValue;
+      launch_timed(k_rollout<float, 128, 2, INL, false, PAIR>, rg, dim3(128), lds, s, e0, e1, tab, inl);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
 template <bool INL, bool SPL>
 static hipError_t launch_rollout_form(const LaunchTab &tab, const TickDesc &inl, int precision,
                                       size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 rg(tab.total_roll);
-  if (precision == 1) {
-    launch_timed(k_rollout<double, 64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl);
-    return hipSuccess;
-  }
+  if (precision == 1 || tab.lanes != 4)
+    return tab.pairs ? launch_one_lane<INL, SPL, true>(tab, inl, precision, lds, s, e0, e1)
+                     : launch_one_lane<INL, SPL, false>(tab, inl, precision, lds, s, e0, e1);
   if (tab.lanes == 4) {
     switch (tab.roll_block * 4 + tab.unroll) {
       case 64 * 4 + 1: launch_timed(k_rollout_quad<64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
@@ -1714,21 +1887,7 @@ static hipError_t launch_rollout_form(const LaunchTab &tab, const TickDesc &inl,
     }
     return hipSuccess;
   }
-  switch (tab.roll_block * 4 + tab.unroll) {
-    case 64 * 4 + 1: launch_timed(k_rollout<float, 64, 1, INL, SPL>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
-    case 128 * 4 + 1: launch_timed(k_rollout<float, 128, 1, INL, SPL>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
-    case 256 * 4 + 1: launch_timed(k_rollout<float, 256, 1, INL, SPL>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
-    case 64 * 4 + 2:
-      if (SPL) return hipErrorInvalidValue;
-      launch_timed(k_rollout<float, 64, 2, INL, false>, rg, dim3(64), lds, s, e0, e1, tab, inl);
-      break;
-    case 128 * 4 + 2:
-      if (SPL) return hipErrorInvalidValue;
-      launch_timed(k_rollout<float, 128, 2, INL, false>, rg, dim3(128), lds, s, e0, e1, tab, inl);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipSuccess;
+  return hipErrorInvalidValue;
 }
 
 template <bool INL>

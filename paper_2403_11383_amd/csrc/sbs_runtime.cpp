@@ -68,6 +68,7 @@ int64_t now_ns() {
 constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
+
 // noise rows per thread of a single controller's ahead-of-time noise
 constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2, 58.9, 58.1, 71.9 us per tick
 
@@ -77,6 +78,7 @@ struct Tune {
   int lanes = 0;
   int block = 256;  // four waves per workgroup: measured faster than 64 or 128 at C1
   int unroll = 1;
+  bool pairs = true;  // stance-pair one-lane rollouts where the gait allows
 };
 
 bool valid_form(int lanes, int block, int unroll) {
@@ -282,8 +284,18 @@ struct Batch {
   double *host_results = nullptr;
   int plan = -1;
   std::vector<hipEvent_t> timing;  // 5 per launched (iteration, precision)
-  bool owns_memory = true;
+  // modes 1 and 3: per timed rollout launch, its form (RollForm) and
+  // rollout-steps
+  std::vector<std::pair<int, double>> timing_work;
+  bool owns_memory = true;  // device workspace carved from the arena
+  bool owns_host = true;    // pinned staging carved from the runtime's block
 };
+
+// Rollout forms told apart by the per-form timing accumulators.
+enum RollForm { FORM_FP32_ONE_LANE = 0, FORM_FP32_QUAD = 1, FORM_FP64 = 2, kForms = 3 };
+int roll_form(const LaunchTab &t, int precision) {
+  return precision == SBS_FP64 ? FORM_FP64 : (t.lanes == 4 ? FORM_FP32_QUAD : FORM_FP32_ONE_LANE);
+}
 
 struct Plan {
   int id = -1;
@@ -335,6 +347,10 @@ struct sbs_runtime {
   Tune tune;  // default rollout form of direct and serving launches
   double stage_ns[4] = {0, 0, 0, 0};
   uint64_t stage_n[4] = {0, 0, 0, 0};
+  // rollout timing per form (modes 1 and 3): device time, launches and
+  // rollout-steps of the timed launches
+  double form_ns[3] = {0, 0, 0}, form_steps[3] = {0, 0, 0};
+  uint64_t form_n[3] = {0, 0, 0};
 };
 
 namespace {
@@ -414,6 +430,16 @@ int validate_cfg(const sbs_controller_cfg &c) {
   return SBS_OK;
 }
 
+// Diagonal trot at duty 1/2 (leg 3 in phase with leg 0, legs 1 and 2 half a
+// cycle later, stance iff phase < 2^31): exactly one diagonal pair is in
+// stance at every step, which the stance-pair rollouts exploit.
+bool pair_gait(const sbs_controller_cfg &c) {
+  const uint32_t o0 = c.phase_offset[0], half = 0x80000000u;
+  return std::rint(c.duty * 4294967296.0) == 2147483648.0 &&
+         c.phase_offset[3] == o0 && c.phase_offset[1] == o0 + half &&
+         c.phase_offset[2] == o0 + half;
+}
+
 void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char *dev_item,
                double *dev_result, const sbs_tick_input &in, uint32_t tick, int slot,
                TickDesc *d) {
@@ -442,6 +468,8 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   const double dq = std::rint(c.duty * 4294967296.0);
   d->duty_full = dq >= 4294967296.0 ? 1 : 0;
   d->duty_q = d->duty_full ? 0xFFFFFFFFu : (uint32_t)dq;
+  // diagonal trot at duty 1/2: leg 3 in phase with leg 0 and legs 1, 2 half
+  // a cycle later, so exactly one diagonal pair is in stance at every step
   d->slot = slot;
   d->M = rows_of(c);
   d->spline = c.knots > 0 ? 1 : 0;
@@ -503,6 +531,9 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
   (void)rt;
 }
 
+// Launch groups per iteration: precision x parametrisation x stance-pair form.
+constexpr int kGroups = 8;
+
 // Layout of a batch over the given controllers.
 Layout make_layout(const std::vector<const Controller *> &cs) {
   Layout L;
@@ -513,7 +544,7 @@ Layout make_layout(const std::vector<const Controller *> &cs) {
   L.tabs = align_up(n * sizeof(TickDesc));
   // per (iteration, precision, parametrisation): item[n] + 3 x start[n+1]
   const uint64_t tab_bytes = align_up((n + 3 * (n + 1)) * 4);
-  L.hdr_bytes = align_up(L.tabs + (uint64_t)rmax * 4 * tab_bytes);
+  L.hdr_bytes = align_up(L.tabs + (uint64_t)rmax * kGroups * tab_bytes);
   L.results = L.hdr_bytes;
   L.items = align_up(L.results + n * kResultDoubles * 8);
   uint64_t p = L.items;
@@ -533,7 +564,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
                                                    const std::vector<const sbs_tick_input *> &ins,
                                                    const std::vector<uint32_t> &ticks,
                                                    const Layout &L, char *host, char *dev,
-                                                   char *host_dev, const Tune &tn) {
+                                                   char *host_dev, const Tune &tn,
+                                                   std::vector<double> *steps_out = nullptr) {
   const int n = (int)cs.size();
   int rmax = 1;
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
@@ -549,17 +581,17 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
   std::vector<std::pair<LaunchTab, int>> out;
   const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
   for (int r = 0; r < rmax; ++r) {
-    for (int grp = 0; grp < 4; ++grp) {
-      // one launch per (precision, parametrisation) group
-      const int prec = grp >> 1, spl = grp & 1;
-      const uint64_t off = L.tabs + ((uint64_t)r * 4 + grp) * tab_bytes;
+    for (int grp = 0; grp < kGroups; ++grp) {
+      // one launch per (precision, parametrisation, stance-pair form) group
+      const int prec = grp >> 2, spl = (grp >> 1) & 1, pair = grp & 1;
+      const uint64_t off = L.tabs + ((uint64_t)r * kGroups + grp) * tab_bytes;
       int32_t *item = reinterpret_cast<int32_t *>(host + off);
       int32_t *ns = item + n, *rs = ns + (n + 1), *us = rs + (n + 1);
       // longest horizon first: the rollout stage's tail is the longest lanes
       std::vector<int> idx;
       for (int i = 0; i < n; ++i)
         if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec &&
-            (cs[i]->cfg.knots > 0 ? 1 : 0) == spl)
+            (cs[i]->cfg.knots > 0 ? 1 : 0) == spl && ((tn.pairs && pair_gait(cs[i]->cfg)) ? 1 : 0) == pair)
           idx.push_back(i);
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
@@ -600,6 +632,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.max_rows = max_rows;
       tab.spline = spl;
       tab.lanes = lanes;
+      tab.pairs = pair;
       tab.roll_block = block;
       tab.unroll = unroll;
       tab.r_count = 1;
@@ -610,6 +643,11 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.roll_start = tab.noise_start + (n + 1);
       tab.upd_start = tab.roll_start + (n + 1);
       out.push_back({tab, prec});
+      if (steps_out) {  // rollout-steps of this launch (N H per controller)
+        double st = 0.0;
+        for (int t = 0; t < m; ++t) st += (double)cs[idx[t]]->cfg.N * (double)cs[idx[t]]->cfg.H;
+        steps_out->push_back(st);
+      }
     }
   }
   return out;
@@ -637,11 +675,19 @@ void record_timing(sbs_runtime *rt, Batch &b) {
       if (hipEventElapsedTime(&ms, b.timing[o + s], b.timing[o + s + 1]) == hipSuccess) {
         rt->stage_ns[stage] += (double)ms * 1e6;
         rt->stage_n[stage] += 1;
+        const size_t p = o / g;
+        if (g == 2 && p < b.timing_work.size()) {
+          const int f = b.timing_work[p].first;
+          rt->form_ns[f] += (double)ms * 1e6;
+          rt->form_steps[f] += b.timing_work[p].second;
+          rt->form_n[f] += 1;
+        }
       }
     }
   }
   for (auto e : b.timing) give_timing_event(rt, e);
   b.timing.clear();
+  b.timing_work.clear();
 }
 
 // Complete a finished batch: copy the actions into the tickets, free memory.
@@ -664,10 +710,8 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
     for (auto e : b.timing) give_timing_event(rt, e);
     b.timing.clear();
   }
-  if (b.owns_memory) {
-    rt->dev_alloc.release(b.ws_off, b.ws_bytes);
-    rt->host_alloc.release(b.host_off, b.host_bytes);
-  }
+  if (b.owns_memory) rt->dev_alloc.release(b.ws_off, b.ws_bytes);
+  if (b.owns_host) rt->host_alloc.release(b.host_off, b.host_bytes);
   if (b.plan >= 0) {
     auto p = rt->plans.find(b.plan);
     if (p != rt->plans.end()) p->second->busy = false;
@@ -716,7 +760,9 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   char *host = rt->pinned + host_off;
   std::vector<uint32_t> ticks;
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
-  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off, rt->tune);
+  std::vector<double> tab_steps;
+  auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off, rt->tune,
+                          &tab_steps);
   hipStream_t s = rt->streams[slot];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -785,7 +831,8 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
     };
   }
   bool first = true;
-  for (auto &tp : tabs) {
+  for (size_t ti = 0; ti < tabs.size(); ++ti) {
+    auto &tp = tabs[ti];
     if (e != hipSuccess) break;
     hipEvent_t *ev = nullptr;
     if (tmode) {
@@ -793,6 +840,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       const int ne = tmode == 2 ? 5 : 2;
       for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
       ev = &b->timing[base];
+      if (tmode == 1) b->timing_work.push_back({roll_form(tp.first, tp.second), tab_steps[ti]});
     }
     const bool early = first && pc && pc->cfg.iterations > 1;
     e = launch_iteration(tp.first, tp.second, s, tmode, ev, inl, early ? &prefetch_next : nullptr);
@@ -1204,6 +1252,7 @@ int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint6
   return sbs_submit_batch(rt, 1, &id, in, ticket);
 }
 
+
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us) {
   if (!rt || !out) return fail(SBS_EINVAL, "NULL argument");
   const int64_t t0 = now_ns();
@@ -1346,6 +1395,14 @@ int sbs_set_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, ui
   return SBS_OK;
 }
 
+int sbs_export_state(sbs_runtime *rt, int32_t id, double *mu, double *mu_f, uint32_t *tick) {
+  return sbs_get_state(rt, id, mu, mu_f, tick);
+}
+
+int sbs_import_state(sbs_runtime *rt, int32_t id, const double *mu, double mu_f, uint32_t tick) {
+  return sbs_set_state(rt, id, mu, mu_f, tick);
+}
+
 int sbs_set_debug(sbs_runtime *rt, int32_t id, int32_t enable) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
@@ -1405,6 +1462,10 @@ int sbs_debug_fetch(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, dou
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(SBS_EDEVICE, "debug download failed: %s", hipGetErrorString(e));
   return SBS_OK;
+}
+
+int sbs_debug_costs(sbs_runtime *rt, int32_t id, double *costs, uint32_t *q, double *mean) {
+  return sbs_debug_fetch(rt, id, costs, q, mean);
 }
 
 int sbs_debug_noise(sbs_runtime *rt, int32_t id, uint32_t tick, uint32_t r, float *z, uint32_t *q) {
@@ -1531,6 +1592,13 @@ int sbs_set_timing(sbs_runtime *rt, int32_t mode) {
   return SBS_OK;
 }
 
+int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  rt->tune.pairs = enable != 0;
+  return SBS_OK;
+}
+
 int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   if (lanes != 0 && lanes != 1 && lanes != 4) return fail(SBS_EINVAL, "lanes must be 0, 1 or 4");
@@ -1549,6 +1617,21 @@ int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches) {
     rt->stage_ns[s] = 0;
     rt->stage_n[s] = 0;
   }
+  return SBS_OK;
+}
+
+int sbs_timing_rollout(sbs_runtime *rt, int32_t form, double *avg_ns, uint64_t *launches,
+                       double *steps) {
+  if (!rt || form < 0 || form >= kForms) return fail(SBS_EINVAL, "bad runtime or rollout form");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  reap(rt);
+  const uint64_t n = rt->form_n[form];
+  if (avg_ns) *avg_ns = n ? rt->form_ns[form] / (double)n : 0.0;
+  if (launches) *launches = n;
+  if (steps) *steps = rt->form_steps[form];
+  rt->form_ns[form] = 0;
+  rt->form_steps[form] = 0;
+  rt->form_n[form] = 0;
   return SBS_OK;
 }
 
@@ -1832,12 +1915,15 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
     ins.push_back(&in[i]);
     ticks.push_back(c.next_tick);
   }
-  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off, P.tune);
+  std::vector<double> tab_steps;
+  auto tabs = build_batch(rt, cs, ins, ticks, P.lay, P.host, P.dev, rt->pinned_dev + P.host_off,
+                          P.tune, &tab_steps);
   hipStream_t s = rt->streams[0];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
   b->stream_slot = 0;
   b->owns_memory = false;
+  b->owns_host = false;
   b->plan = P.id;
   b->host_results = reinterpret_cast<double *>(P.host + P.lay.results);
   b->ctrls = P.ctrls;
@@ -1849,7 +1935,8 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
   } else {
     e = hipMemcpyAsync(P.dev, P.host, P.lay.hdr_bytes, hipMemcpyHostToDevice, s);
     const int tmode = timing_mode_now(rt);
-    for (auto &tp : tabs) {
+    for (size_t ti = 0; ti < tabs.size(); ++ti) {
+      auto &tp = tabs[ti];
       if (e != hipSuccess) break;
       hipEvent_t *ev = nullptr;
       if (tmode) {
@@ -1857,6 +1944,7 @@ int sbs_plan_submit(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, uin
         const int ne = tmode == 2 ? 5 : 2;
         for (int i = 0; i < ne; ++i) b->timing.push_back(take_timing_event(rt));
         ev = &b->timing[base];
+        if (tmode == 1) b->timing_work.push_back({roll_form(tp.first, tp.second), tab_steps[ti]});
       }
       e = launch_iteration(tp.first, tp.second, s, tmode, ev, nullptr);
     }

@@ -200,6 +200,12 @@ def study_config(method: str = "naive", adapt: bool = True, rho: float = 1.0,
     return c
 
 
+def fallen(x) -> bool:
+    """Fall criterion of every closed-loop run: roll or pitch beyond 0.8 rad,
+    CoM height outside (0.2, 0.6) m, or a non-finite state."""
+    return not (abs(x[3]) < 0.8 and abs(x[4]) < 0.8 and 0.2 < x[2] < 0.6)  # NaN fails too
+
+
 def study_wrench(t: int) -> np.ndarray:
     """External wrench [Fx, Fy, Fz, Tx, Ty, Tz] on the CoM at tick t."""
     w = np.zeros(6)

@@ -18,3 +18,19 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """With SBS_PARITY_LOG set, write the FP32 cost errors the parity checks
+    observed (one record per check) to that file as JSON."""
+    path = os.environ.get("SBS_PARITY_LOG")
+    if not path:
+        return
+    try:
+        import parity_util
+    except ImportError:
+        return
+    import json
+    with open(path, "w") as f:
+        json.dump([{"test": t, "max_rel": a, "max_abs": b, "median_rel": m, "samples": n}
+                   for t, a, b, m, n in parity_util.OBSERVED], f, indent=1)

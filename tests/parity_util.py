@@ -8,14 +8,31 @@ from paper_2403_11383_amd import workloads
 MG2 = 0.5 * workloads.MASS * workloads.GRAVITY
 
 
+# Calibration of the FP32 cost bars on the current kernels (all FP32 parity
+# checks of one GPU run, influential samples only): the worst relative error
+# is 2.1e-5 (served ticks at H = 50 from warm-started means), the worst
+# median over a check with at least 20 influential samples 4.3e-7.  Both
+# bars keep the 4x margin of the tolerance reading: 8.4e-5 relative (plus
+# 1e-4 absolute for costs near zero) and 2e-6.
+COST_REL_TOL = 8.4e-5
+COST_ABS_TOL = 1e-4
+MEDIAN_REL_TOL = 2e-6
+MEDIAN_MIN_SAMPLES = 20
+
+
 def cost_tol(J):
-    """FP32 rollout cost tolerance: 1e-4 relative + 1e-3 absolute.  Calibrated:
-    the worst relative error observed on the influential samples of these
-    seeded workloads is 2.2e-5; the bar keeps a 4x margin."""
-    return 1e-4 * np.abs(J) + 1e-3
+    """FP32 rollout cost tolerance: COST_REL_TOL relative + COST_ABS_TOL
+    absolute (calibrated above)."""
+    return COST_REL_TOL * np.abs(J) + COST_ABS_TOL
 
 
 RELEVANT = 60.0  # weight below exp(-60) relative to the best: no influence
+
+# Observed FP32 cost errors on the influential samples of every check in the
+# session: (test, worst relative error, worst absolute error, median
+# relative error, samples); written out by conftest when SBS_PARITY_LOG names
+# a file, so that the tolerances can be calibrated on the current kernels.
+OBSERVED = []
 
 
 def conditioning(cfg, inp, mu, sigma, tick, r, ks, q, rel=1e-7):
@@ -46,9 +63,10 @@ def check_costs_fp32(Jg, Jr, lam=1.0, elite_ke=None, well=None):
       exp(-RELEVANT) in the oracle, or within twice the oracle's elite
       threshold -- matches within cost_tol;
     * every other sample is also without influence on the GPU side;
-    * the typical influential sample (median) agrees to 1e-5 relative (at
-      H = 50 most rollouts tumble, so the median over all samples says
-      nothing about the arithmetic).
+    * the typical influential sample (median) agrees to MEDIAN_REL_TOL where
+      there are at least MEDIAN_MIN_SAMPLES of them (at H = 50 most rollouts
+      tumble, so the median over all samples says nothing about the
+      arithmetic, and a median of a handful is their maximum).
     `well`, if given, marks the samples whose FP64 cost is well-conditioned
     (see conditioning); the comparisons then skip the others.
     """
@@ -70,24 +88,32 @@ def check_costs_fp32(Jg, Jr, lam=1.0, elite_ke=None, well=None):
     well = np.ones(Jr.shape, bool) if well is None else np.asarray(well, bool)
     assert np.all(far[~rel & well]), np.flatnonzero(~rel & well & ~far)[:10]
     rel = rel & well
+    if rel.any():
+        import os
+        relerr = err[rel] / np.maximum(np.abs(Jr[rel]), 1.0)
+        OBSERVED.append((os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0],
+                         float(relerr.max()), float(err[rel].max()), float(np.median(relerr)),
+                         int(rel.sum())))
     bad = rel & (err > cost_tol(Jr))
     assert not bad.any(), (np.flatnonzero(bad)[:10], err[bad][:10], Jr[bad][:10])
-    if rel.any():
-        assert np.median(err[rel] / np.maximum(np.abs(Jr[rel]), 1.0)) <= 1e-5
+    if rel.sum() >= MEDIAN_MIN_SAMPLES:
+        assert np.median(err[rel] / np.maximum(np.abs(Jr[rel]), 1.0)) <= MEDIAN_REL_TOL
     return int(rel.sum())
 
 
-def mppi_action_bound(cfg, J, epsJ, mean0, tick=0):
+def mppi_action_bound(cfg, J, epsJ, mean0, tick=0, mu_row0=None):
     """First-order bound on how far an MPPI mean's first step moves when the
     costs J move by at most epsJ (per sample):
     |d mean| <= sum_k w_k |theta_k - mean| |dJ_k - sum_i w_i dJ_i| / lambda,
-    with the weights of J, the first-step samples of a hover-mean tick and
-    the mean's first row mean0."""
+    with the weights of J, the first-step samples theta_k = mu_row0 + sigma z
+    of tick `tick` (mu_row0: the sampling mean's first row, hover if None)
+    and the updated mean's first row mean0."""
     J = np.asarray(J, np.float64)
     w, *_ = oracle.mppi_weights(J, cfg["lambda"])
     epsJ = np.where(np.isfinite(epsJ), epsJ, 0.0)
     z = oracle.noise_block(cfg["seed"], tick, 0, cfg["N"], 1)[:, 0, :].astype(np.float64)
-    th0 = hover(cfg)[0][None] + cfg["sigma_grf"] * z
+    row0 = hover(cfg)[0] if mu_row0 is None else np.asarray(mu_row0, np.float64)
+    th0 = row0[None] + cfg["sigma_grf"] * z
     dev = np.abs(th0 - np.asarray(mean0)[None])
     spread = epsJ + (w * epsJ).sum()
     return float((w[:, None] * dev * spread[:, None]).sum(0).max() / cfg["lambda"])

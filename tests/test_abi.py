@@ -34,11 +34,26 @@ def test_every_declared_symbol_is_exported(built):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(built.EXPORTED)
+    # the boundary's three method calls and the checkpoint / debug taps
+    for n in ("sbs_init_controller", "sbs_submit_tick", "sbs_fetch_action", "sbs_export_state",
+              "sbs_import_state", "sbs_debug_costs", "sbs_debug_noise", "sbs_last_error"):
+        assert n in names, n
+
+
+def test_method_calls_cite_their_passage():
+    """The declarations of the three calls the method needs cite the passage
+    that defines them."""
+    text = open(HEADER).read()
+    for fn, cite in (("sbs_init_controller", "Sec. III-A"), ("sbs_submit_tick", "Alg. 5"),
+                     ("sbs_fetch_action", "Fig. 2")):
+        decl = text.index(f"int {fn}(")
+        comment = text[text.rindex("/*", 0, decl):decl]
+        assert cite in comment, (fn, cite)
 
 
 def test_abi_version_and_error_string(built):
     L = built.lib()
-    assert L.sbs_abi_version() == 3
+    assert L.sbs_abi_version() == 4
     assert isinstance(L.sbs_last_error(), bytes)
 
 

