@@ -156,6 +156,22 @@ int sbs_destroy_controller(sbs_runtime *rt, int32_t id);
  * (direct mode) if the arena cannot hold the step's workspace now. */
 int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint64_t *ticket);
 
+/* sbs_submit_tick for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the step workspace (noise, costs, weights, chosen samples, per-iteration
+ * scalars) lives in a static device array of 64 MiB that the library holds
+ * on each GPU it runs on until the process ends, instead of being carved from
+ * the arena; the call takes no arena memory and calls no allocator.  Results
+ * are those of sbs_submit_tick (same kernels); fetch with sbs_fetch_action.
+ * Direct mode only (SBS_EINVAL otherwise); the noise is always made inside
+ * the tick (no prefetch).  SBS_EINVAL if the controller's workspace exceeds
+ * 64 MiB (e.g. N = 16384 per-step samples at H = 80).  Every call on a GPU
+ * shares that GPU's array: calls of one runtime are ordered on its stream,
+ * but calls through runtimes on different streams of one GPU that overlap
+ * in time race on it. */
+int sbs_submit_tick_noalloc(sbs_runtime *rt, int32_t id, const sbs_tick_input *in,
+                            uint64_t *ticket);
+
 /* Queue one control step for each of n distinct controllers as one fused
  * launch sequence (one kernel per stage for all of them). */
 int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_tick_input *in,

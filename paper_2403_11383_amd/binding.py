@@ -28,7 +28,7 @@ OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EDEVICE, ECANCELED, ENOENT = 0, -1, -2, -
 
 EXPORTED = [
     "sbs_runtime_create", "sbs_runtime_destroy", "sbs_init_controller",
-    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions",
+    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_tick_noalloc", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions",
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_export_state", "sbs_import_state", "sbs_set_debug", "sbs_debug_fetch",
@@ -106,6 +106,7 @@ def lib():
         L.sbs_init_controller.argtypes = [vp, C.POINTER(ControllerCfg), C.POINTER(i32)]
         L.sbs_destroy_controller.argtypes = [vp, i32]
         L.sbs_submit_tick.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
+        L.sbs_submit_tick_noalloc.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_submit_batch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_fetch_action.argtypes = [vp, u64, C.POINTER(Action), C.c_int64]
         L.sbs_fetch_actions.argtypes = [vp, i32, vp, C.POINTER(Action), C.c_int64]
@@ -266,6 +267,14 @@ class Runtime:
         t = C.c_uint64()
         i = make_input(inp)
         _check(lib().sbs_submit_tick(self._h, cid, C.byref(i), C.byref(t)))
+        return t.value
+
+    def submit_tick_noalloc(self, cid: int, inp: dict) -> int:
+        """sbs_submit_tick with the step workspace in the library's static
+        device scratch array (no arena memory, no allocation)."""
+        t = C.c_uint64()
+        i = make_input(inp)
+        _check(lib().sbs_submit_tick_noalloc(self._h, cid, C.byref(i), C.byref(t)))
         return t.value
 
     def submit_batch(self, cids, inputs) -> list:

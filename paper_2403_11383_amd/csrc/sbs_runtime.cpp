@@ -69,6 +69,31 @@ constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
 
+// Step workspace of sbs_submit_tick_noalloc: one file-scope device array per
+// GPU, held until the process ends.  Host code never names it directly (its
+// name is a host-side stand-in there): each device's address is taken once,
+// with that device current, when a runtime is created on it.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array (taken on first use per device).
+// Caller has the device current.
+int scratch_address(int device, char **out) {
+  if (device < 0 || device >= kMaxDevices) return fail(SBS_EDEVICE, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SBS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return SBS_OK;
+}
 // noise rows per thread of a single controller's ahead-of-time noise
 constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2, 58.9, 58.1, 71.9 us per tick
 
@@ -345,6 +370,7 @@ struct sbs_runtime {
   int timing = 0;  // 0 off, 1 rollout kernel (sampled launches), 2 all stages
   uint64_t timing_seq = 0;  // launches seen in mode 1
   Tune tune;  // default rollout form of direct and serving launches
+  char *scratch = nullptr;  // this device's scratch array (sbs_submit_tick_noalloc)
   double stage_ns[4] = {0, 0, 0, 0};
   uint64_t stage_n[4] = {0, 0, 0, 0};
   // rollout timing per form (modes 1 and 3): device time, launches and
@@ -742,21 +768,28 @@ int reap(sbs_runtime *rt) {
 
 // Launch one batch of (controller, input) pairs on stream slot `slot`.
 // Caller holds rt->mu; returns SBS_ENOMEM when memory is short.
+// With `scratch_dev` the step workspace is that device buffer (of
+// kScratchBytes) instead of arena memory.
 int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
            const std::vector<const sbs_tick_input *> &ins, const std::vector<uint64_t> &tks,
-           int slot) {
+           int slot, char *scratch_dev = nullptr) {
   std::vector<const Controller *> cs;
   for (int32_t id : ids) cs.push_back(&rt->ctrls.at(id));
   Layout L = make_layout(cs);
   uint64_t ws_off = 0, host_off = 0;
-  if (!rt->dev_alloc.alloc(L.total, &ws_off))
+  if (scratch_dev) {
+    if (L.total > kScratchBytes)
+      return fail(SBS_EINVAL, "step workspace of %llu bytes exceeds the %llu-byte scratch",
+                  (unsigned long long)L.total, (unsigned long long)kScratchBytes);
+  } else if (!rt->dev_alloc.alloc(L.total, &ws_off)) {
     return fail(SBS_ENOMEM, "arena cannot hold %llu bytes of step workspace",
                 (unsigned long long)L.total);
+  }
   if (!rt->host_alloc.alloc(L.host_total, &host_off)) {
-    rt->dev_alloc.release(ws_off, L.total);
+    if (!scratch_dev) rt->dev_alloc.release(ws_off, L.total);
     return fail(SBS_ENOMEM, "pinned staging exhausted");
   }
-  char *dev = rt->arena + ws_off;
+  char *dev = scratch_dev ? scratch_dev : rt->arena + ws_off;
   char *host = rt->pinned + host_off;
   std::vector<uint32_t> ticks;
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
@@ -769,6 +802,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   b->stream_slot = slot;
   b->ws_off = ws_off;
   b->ws_bytes = L.total;
+  b->owns_memory = scratch_dev == nullptr;
   b->host_off = host_off;
   b->host_bytes = L.host_total;
   b->host_results = reinterpret_cast<double *>(host + L.results);
@@ -783,7 +817,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   // from the buffer the previous submission filled ahead of time
   Controller *pc = nullptr;
   int pbuf = 0;
-  if (inl && rt->mode == SBS_MODE_DIRECT && slot == 0 && rt->streams[1]) {
+  if (inl && rt->mode == SBS_MODE_DIRECT && slot == 0 && rt->streams[1] && !scratch_dev) {
     Controller &C0 = rt->ctrls.at(ids[0]);
     if (C0.prefetch) {
       pc = &C0;
@@ -853,7 +887,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   if (e != hipSuccess) {
     // the stream may still run what was enqueued: wait before freeing
     (void)hipStreamSynchronize(s);
-    rt->dev_alloc.release(ws_off, L.total);
+    if (!scratch_dev) rt->dev_alloc.release(ws_off, L.total);
     rt->host_alloc.release(host_off, L.host_total);
     give_event(rt, b->done);
     for (auto ev : b->timing) give_timing_event(rt, ev);
@@ -1016,6 +1050,10 @@ int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *st
   if (hipGetDevice(&rt->device) != hipSuccess) return fail(SBS_EDEVICE, "no HIP device");
   rt->arena = static_cast<char *>(arena);
   rt->dev_alloc.reset(arena_bytes);
+  {
+    const int rc = scratch_address(rt->device, &rt->scratch);
+    if (rc != SBS_OK) return rc;
+  }
   const uint64_t pinned_bytes = 64ull << 20;
   // coherent (fine-grained) so that kernels can write action records into it
   if (hipHostMalloc((void **)&rt->pinned, pinned_bytes,
@@ -1252,6 +1290,35 @@ int sbs_submit_tick(sbs_runtime *rt, int32_t id, const sbs_tick_input *in, uint6
   return sbs_submit_batch(rt, 1, &id, in, ticket);
 }
 
+int sbs_submit_tick_noalloc(sbs_runtime *rt, int32_t id, const sbs_tick_input *in,
+                            uint64_t *ticket) {
+  if (!rt || !ticket) return fail(SBS_EINVAL, "runtime or ticket is NULL");
+  int rc = check_input(in);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(rt->mu);
+  if (rt->mode != SBS_MODE_DIRECT) return fail(SBS_EINVAL, "sbs_submit_tick_noalloc needs direct mode");
+  auto it = rt->ctrls.find(id);
+  if (it == rt->ctrls.end()) return fail(SBS_EINVAL, "unknown controller %d", id);
+  if (!rt->scratch) return fail(SBS_EDEVICE, "no scratch address for device %d", rt->device);
+  const Layout L = make_layout({&it->second});
+  if (L.total > kScratchBytes)
+    return fail(SBS_EINVAL, "controller %d: step workspace of %llu bytes exceeds the %llu-byte "
+                "scratch", id, (unsigned long long)L.total, (unsigned long long)kScratchBytes);
+  const uint64_t tk = rt->next_ticket++;
+  TicketRec rec;
+  rec.controller = id;
+  rec.t_submit = now_ns();
+  rt->tickets[tk] = rec;
+  // every launch of this runtime goes to its first stream, in order, so a
+  // tick reads the scratch only after the previous user of it has finished
+  rc = launch(rt, {id}, {in}, {tk}, 0, rt->scratch);
+  if (rc != SBS_OK) {
+    rt->tickets.erase(tk);
+    return rc;
+  }
+  *ticket = tk;
+  return SBS_OK;
+}
 
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us) {
   if (!rt || !out) return fail(SBS_EINVAL, "NULL argument");
