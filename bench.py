@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 the rollout kernel's own dispatch events on "
                          "one tick in 16, 2 event commands around every stage of every tick")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="c4: streams the serving scheduler alternates batches on")
     ap.add_argument("--shadow-seconds", type=float, default=6.0,
                     help="c4: arrival-stream length of the pass that records the served ticks "
                          "the oracle reruns (cpu_baseline and shadow_oracle)")
@@ -494,7 +496,7 @@ def fleet_inputs(binding, workloads, fleet, seed):
     return [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
 
 
-def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
+def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2):
     """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
     ticks; serving mode batches whatever is admitted, direct mode runs every
     tick as its own launch sequence ("plain single MPPI").  A robot's tick
@@ -504,7 +506,8 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
     import torch
     fleet = workloads.c4_fleet(robots=robots)
     arrivals = workloads.c4_arrivals(robots=robots, duration_s=duration)
-    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode,
+                         two_streams=(mode == "serving" and streams > 1))
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 5)
     events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
@@ -512,7 +515,10 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
     pending = {}
     lat, done_work = [], 0
     tk = C.c_uint64()
-    act = binding.Action()
+    # completed ticks come back in bulk (sbs_fetch_ready): one call per sweep
+    rtk = (C.c_uint64 * 1024)()
+    racts = (binding.Action * 1024)()
+    nready = C.c_int32()
     torch.cuda.synchronize()
     t_start = time.perf_counter_ns()
     i = 0
@@ -526,17 +532,18 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
             binding._check(rc)
             pending[tk.value] = (t_arr, r)
             i += 1
-        for t in list(pending):
-            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
-            if rc == binding.OK:
-                t_arr, r = pending.pop(t)
-                lat.append((act.t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
-                c = fleet[r]
-                done_work += c["N"] * c["H"]
-            elif rc != binding.EAGAIN:
-                binding._check(rc)
-        if mode == "direct" and pending and i < len(events) and events[i][0] > now:
-            time.sleep(0)
+        if not pending:
+            continue
+        # wait for completions at most until the next arrival is due
+        wait_us = 0
+        if i < len(events):
+            wait_us = max(0, min(100, int((events[i][0] - now) * 1e6)))
+        binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), wait_us))
+        for i_ in range(nready.value):
+            t_arr, r = pending.pop(rtk[i_])
+            lat.append((racts[i_].t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
+            c = fleet[r]
+            done_work += c["N"] * c["H"]
     elapsed = (time.perf_counter_ns() - t_start) * 1e-9
     stats = rt.stats()
     rt.close()
@@ -547,7 +554,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256):
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
-                  warmup_ticks=0):
+                  warmup_ticks=0, streams=2):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
     form sustains, and their submit-to-done latency.  With timing, the
@@ -556,12 +563,15 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     import ctypes as C
     import torch
     fleet = workloads.c4_fleet(robots=robots)
-    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode, two_streams=(mode == "serving"))
+    rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode,
+                         two_streams=(mode == "serving" and streams > 1))
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 6)
     L = binding.lib()
     tk = C.c_uint64()
-    act = binding.Action()
+    rtk = (C.c_uint64 * 1024)()
+    racts = (binding.Action * 1024)()
+    nready = C.c_int32()
     # untimed warm-up: every robot's first ticks
     for _ in range(warmup_ticks):
         tks = [rt.submit_tick(cid, workloads.tick_input(workloads.initial_state(
@@ -590,15 +600,12 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
                 binding._check(rc)
                 pending[tk.value] = r
             idle = still
-        for t in list(pending):
-            rc = L.sbs_fetch_action(rt._h, t, C.byref(act), 0)
-            if rc == binding.OK:
-                r = pending.pop(t)
-                lat.append((act.t_done_ns - act.t_submit_ns) * 1e-6)
-                done_work += fleet[r]["N"] * fleet[r]["H"]
-                idle.append(r)
-            elif rc != binding.EAGAIN:
-                binding._check(rc)
+        binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), 0))
+        for i in range(nready.value):
+            r = pending.pop(rtk[i])
+            lat.append((racts[i].t_done_ns - racts[i].t_submit_ns) * 1e-6)
+            done_work += fleet[r]["N"] * fleet[r]["H"]
+            idle.append(r)
     torch.cuda.synchronize()
     elapsed = (time.perf_counter_ns() - t_start) * 1e-9
     stats = rt.stats()
@@ -691,10 +698,26 @@ def cpu_baseline_c4(workloads, recs, total_ticks):
             dev = np.abs(th - ref["mean"][0][None])
             spread = np.abs(dJ[live] - (w * dJ).sum())
             bound = float((w[live][:, None] * dev * spread[:, None]).sum(0).max() / c["lambda"])
+            # the conditioning of the samples the two sides weigh most: the
+            # relative change of the FP64 cost under a 1e-7 relative change
+            # of the decision variable, per unit (FP32 rounds at ~6e-8)
+            rng = np.random.default_rng(12345)
+            amp = {}
+            for name, k in (("gpu_best", int(np.argmin(rc["J"][-1]))),
+                            ("oracle_best", int(np.argmin(J)))):
+                zk = np.array([oracle.noise_step(c["seed"], rc["tick"], 0, k, j)
+                               for j in range(c["H"])], np.float64)
+                thk = np.asarray(rc["mu"]) + c["sigma_grf"] * zk
+                qk = int(ref["q_samples"][-1][k])
+                j0 = oracle.rollout(c, rc["inp"], thk, qk)
+                j1 = oracle.rollout(c, rc["inp"], thk * (1.0 + 1e-7 * rng.normal(size=thk.shape)), qk)
+                amp[name] = float(abs(j1 - j0) / (1e-7 * max(abs(j0), 1.0)))
             over.append({"err_rel": err_own[-1], "first_order_rel": bound / scale,
                          "max_cost_diff_rel_of_weighted": float(
                              (dJ[live] / np.maximum(np.abs(J[live]), 1.0)).max()),
-                         "weighted_samples": int(len(live)), "N": c["N"], "H": c["H"]})
+                         "weighted_samples": int(len(live)), "N": c["N"], "H": c["H"],
+                         "same_best_sample": bool(np.argmin(rc["J"][-1]) == np.argmin(J)),
+                         "cost_amplification": amp})
     n1, steps1, t1 = 0, 0, time.perf_counter()
     while n1 < len(recs) and (time.perf_counter() - t1 < 3.0 or n1 < 2):
         rc = recs[n1]
@@ -723,18 +746,30 @@ def cpu_baseline_c4(workloads, recs, total_ticks):
     return base, shadow
 
 
+def progress(msg):
+    """A line per finished phase on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main_c4(args):
     from paper_2403_11383_amd import binding, workloads
     arena = int(args.arena_gb * (1 << 30))
     K = args.steps
     # warm-up: code objects, first launches, the pinned pools
+    progress("warm-up")
     _ = saturated_run(binding, workloads, 0.05 * max(1, args.warmup), "serving", arena,
                       warmup_ticks=1)
-    serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena)
+    progress("50 Hz stream, continuous batching")
+    serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena,
+                        streams=args.streams)
+    progress(f"done: {serve['ticks']} ticks; 50 Hz stream, plain single MPPI")
     plain = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "direct", arena)
+    progress(f"done: {plain['ticks']} ticks; saturated, continuous batching")
     sat = saturated_run(binding, workloads, K * STEP_S_SATURATED, "serving", arena,
-                        timing=args.timing)
+                        timing=args.timing, streams=args.streams)
+    progress(f"done: {sat['ticks']} ticks; saturated, plain single MPPI")
     sat_plain = saturated_run(binding, workloads, K * STEP_S_SATURATED, "direct", arena)
+    progress(f"done: {sat_plain['ticks']} ticks")
     roof = None
     if args.timing and "rollout_forms" in sat:
         forms = sat["rollout_forms"]
@@ -773,7 +808,8 @@ def main_c4(args):
                                f"mu {c['mu_fric']:g}, dt {c['dt']:g} s, fixed seeded state "
                                "per robot, continuous batching vs plain single MPPI",
                    "robots": 256, "stream_s_50hz": K * STEP_S_ARRIVALS,
-                   "stream_s_saturated": K * STEP_S_SATURATED, "arena_gb": args.arena_gb},
+                   "stream_s_saturated": K * STEP_S_SATURATED, "arena_gb": args.arena_gb,
+                   "serving_streams": args.streams},
         "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"],
                        "what": "arrival to completion, 50 Hz Poisson stream, continuous batching"},
         "vs_plain": {"throughput_saturated_x": sat["rollout_steps_per_s"] /
@@ -786,7 +822,9 @@ def main_c4(args):
     if roof is not None:
         line["roofline"] = roof
     if not args.no_cpu_baseline:
+        progress("shadow pass")
         recs, total = shadow_pass(binding, workloads, arena, args.shadow_seconds)
+        progress(f"done: {len(recs)} shadowed ticks; oracle on the host cores")
         line["cpu_baseline"], line["shadow_oracle"] = cpu_baseline_c4(workloads, recs, total)
     print(json.dumps(line), flush=True)
 

@@ -184,6 +184,17 @@ int sbs_submit_batch(sbs_runtime *rt, int32_t n, const int32_t *ids, const sbs_t
  * SBS_ETIMEDOUT if not done; on SBS_OK the ticket is consumed. */
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us);
 
+/* Every completed control step at once (serving clients polling many
+ * robots): writes up to max completed tickets and their actions into
+ * tickets[] and out[] (consuming them) and their number into *count; ticks
+ * still pending, and failed ones (which sbs_fetch_action reports), are left.
+ * With none ready it waits up to timeout_us (0: return at once, <0: until
+ * one is ready), yielding the CPU between polls.  The order is unspecified:
+ * each action carries its controller and tick.  SBS_EINVAL on a null
+ * pointer or max < 0. */
+int sbs_fetch_ready(sbs_runtime *rt, int32_t max, uint64_t *tickets, sbs_action *out,
+                    int32_t *count, int64_t timeout_us);
+
 /* sbs_fetch_action for n tickets in order (out[i] for tickets[i]), each
  * waited for up to timeout_us: one call for a batch's or plan's tickets.
  * Returns at the first ticket that fails or is not ready with that status;
@@ -273,6 +284,15 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
  * for verification and timing.  Takes effect at the next submission; a plan
  * keeps the setting it was created with. */
 int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
+
+/* Noise made inside the rollout (default on): a one-lane FP32 rollout of
+ * per-step GRFs draws each step's noise row itself (the same counter-based
+ * values, Alg. 1 Sampling) and stores it for the update, instead of a
+ * separate noise launch whose rows it reads back.  0 restores the separate
+ * launch.  Results are the same either way; the switch is for verification
+ * and timing.  Takes effect at the next submission; a plan keeps the
+ * setting it was created with. */
+int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout);
 
 /* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
  * rollout kernel's own start and end (events carried by its dispatch) on

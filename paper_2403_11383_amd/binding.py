@@ -28,12 +28,12 @@ OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EDEVICE, ECANCELED, ENOENT = 0, -1, -2, -
 
 EXPORTED = [
     "sbs_runtime_create", "sbs_runtime_destroy", "sbs_init_controller",
-    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_tick_noalloc", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions",
+    "sbs_destroy_controller", "sbs_submit_tick", "sbs_submit_tick_noalloc", "sbs_submit_batch", "sbs_fetch_action", "sbs_fetch_actions", "sbs_fetch_ready",
     "sbs_plan_create", "sbs_plan_submit", "sbs_plan_destroy", "sbs_plan_set_tune",
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_export_state", "sbs_import_state", "sbs_set_debug", "sbs_debug_fetch",
     "sbs_debug_costs", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_timing_rollout", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_rollout_pairs", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_timing_rollout", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_rollout_pairs", "sbs_set_rollout_noise", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
         L.sbs_submit_batch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_fetch_action.argtypes = [vp, u64, C.POINTER(Action), C.c_int64]
         L.sbs_fetch_actions.argtypes = [vp, i32, vp, C.POINTER(Action), C.c_int64]
+        L.sbs_fetch_ready.argtypes = [vp, i32, vp, C.POINTER(Action), C.POINTER(i32), C.c_int64]
         L.sbs_plan_create.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
         L.sbs_plan_submit.argtypes = [vp, i32, C.POINTER(TickInput), C.POINTER(u64)]
         L.sbs_plan_destroy.argtypes = [vp, i32]
@@ -131,6 +132,7 @@ def lib():
         L.sbs_timing_overhead.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.sbs_set_rollout_lanes.argtypes = [vp, i32]
         L.sbs_set_rollout_pairs.argtypes = [vp, i32]
+        L.sbs_set_rollout_noise.argtypes = [vp, i32]
         L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
@@ -331,6 +333,14 @@ class Runtime:
         _check(rc)
         return out
 
+    def fetch_ready(self, max_n: int = 1024, timeout_us: int = 0):
+        """Every completed tick at once: a list of (ticket, action dict)."""
+        tks = (C.c_uint64 * max_n)()
+        acts = (Action * max_n)()
+        n = C.c_int32()
+        _check(lib().sbs_fetch_ready(self._h, max_n, tks, acts, C.byref(n), int(timeout_us)))
+        return [(int(tks[i]), action_dict(acts[i])) for i in range(n.value)]
+
     def plan_destroy(self, plan: int):
         _check(lib().sbs_plan_destroy(self._h, plan))
 
@@ -441,6 +451,11 @@ class Runtime:
     def set_rollout_pairs(self, on: bool = True):
         """Stance-pair one-lane rollouts for the diagonal trot at duty 1/2."""
         _check(lib().sbs_set_rollout_pairs(self._h, 1 if on else 0))
+
+    def set_rollout_noise(self, in_rollout: bool = True):
+        """One-lane FP32 rollouts make their own noise (True) or read it from
+        a separate noise launch (False)."""
+        _check(lib().sbs_set_rollout_noise(self._h, 1 if in_rollout else 0))
 
     def timing(self):
         avg = np.zeros(4)

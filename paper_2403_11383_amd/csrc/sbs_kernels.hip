@@ -591,7 +591,11 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
-template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR>
+// GEN (FP32, per-step GRFs): the rollout makes its sample's noise itself,
+// row j at step j with the noise kernel's own Philox counter and transform,
+// and stores it for the update instead of reading it: the same values, one
+// launch and a 48-B read per rollout-step fewer.
+template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR, bool GEN = false>
 __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
@@ -654,11 +658,20 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   bool prev[4] = {true, true, true, true};
   T J = T(0), Jc = T(0), tj = T(0);
 
+  static_assert(!GEN || (!SPL && sizeof(T) == 4), "noise made in the rollout: FP32 per-step GRFs");
   const float4 *zp =
       reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
   const size_t zstride = (size_t)N * 3;  // float4 per row
-  float4 z0 = zp[0], z1 = zp[1], z2 = zp[2];
+  float4 z0, z1, z2;
+  if constexpr (!GEN) {
+    z0 = zp[0];
+    z1 = zp[1];
+    z2 = zp[2];
+  }
   const float4 *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
+  // GEN: the noise counter words that do not change along the rollout
+  const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
+  const uint32_t rw = (uint32_t)tab.r << 8, tick = d.tick;
   // spline: the sample's knots wb .. wb + 3 (theta = mu + sigma z), and the
   // noise of knot wb + 4 loaded ahead
   T win[4][12];
@@ -721,6 +734,27 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 #pragma unroll
         for (int i = 0; i < 12; ++i)
           u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
+      } else if constexpr (GEN) {
+        float zz[12];
+#pragma unroll
+        for (uint32_t call = 0; call < 3; ++call) {
+          uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = tick, c3 = rw | call;
+          philox4x32_10(c0, c1, c2, c3, key0, key1);
+          const float2 ga = gauss_pair(c0, c1);
+          const float2 gb = gauss_pair(c2, c3);
+          zz[4 * call + 0] = ga.x;
+          zz[4 * call + 1] = ga.y;
+          zz[4 * call + 2] = gb.x;
+          zz[4 * call + 3] = gb.y;
+        }
+        float4 *dst = const_cast<float4 *>(zp) + (size_t)j * zstride;
+        dst[0] = make_float4(zz[0], zz[1], zz[2], zz[3]);
+        dst[1] = make_float4(zz[4], zz[5], zz[6], zz[7]);
+        dst[2] = make_float4(zz[8], zz[9], zz[10], zz[11]);
+        const T *muj = s_mu + j * 12;
+        const T *sgj = s_sig + j * 12;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
       } else {
         const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                               z2.x, z2.y, z2.z, z2.w};
@@ -1541,7 +1575,10 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
   const int item = stage_item<INL>(tab.upd_start, tab.n, b);
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[item]];
   if (d.method == 0) return;  // MPPI: k_update_mppi
-  const int j = b - stage_start<INL>(tab.upd_start, item);
+  // steps j0 .. j1 - 1, each reduced as a one-step workgroup reduces it
+  const int ch = tab.upd_chunk > 1 ? tab.upd_chunk : 1;
+  const int j0 = (b - stage_start<INL>(tab.upd_start, item)) * ch;
+  const int j1 = j0 + ch < d.M ? j0 + ch : d.M;
   const int N = d.N, tid = threadIdx.x;
   const int r = tab.r;
   const bool elite = (d.method == 1);
@@ -1550,115 +1587,117 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
   __shared__ double lds[kUpdBlock / 64][24];
   __shared__ double s_new[12];
   const bool last_iter = (r == d.R - 1);
-  // What does not depend on the select's output is read first, so that its
-  // latency overlaps the gathers: this step's old mean and std.
-  double m_old = 0.0, sig = 0.0;
-  if (tid < 12) {
-    m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, tid);
-    sig = (elite && r > 0) ? d.sigma[j * 12 + tid] : d.sigma0;
-  }
-  // The chosen samples number at most K_e (elite) or one (best sample): their
-  // indices are read together with the count instead of after it, clamped
-  // into [0, N) so that a stale entry never leaves the noise rows, and the
-  // count (zero on a skipped iteration) masks them afterwards.
-  const int nmax = elite ? d.Ke : 1;
-  const bool skip = d.it[IT_SKIP] != 0.0;
-  const int nact = skip ? 0 : (int)d.it[IT_NACT];
+  for (int j = j0; j < j1; ++j) {
+    // What does not depend on the select's output is read first, so that its
+    // latency overlaps the gathers: this step's old mean and std.
+    double m_old = 0.0, sig = 0.0;
+    if (tid < 12) {
+      m_old = (double)mean_at<T>(d, mean_in<T>(d, r), r, j, tid);
+      sig = (elite && r > 0) ? d.sigma[j * 12 + tid] : d.sigma0;
+    }
+    // The chosen samples number at most K_e (elite) or one (best sample): their
+    // indices are read together with the count instead of after it, clamped
+    // into [0, N) so that a stale entry never leaves the noise rows, and the
+    // count (zero on a skipped iteration) masks them afterwards.
+    const int nmax = elite ? d.Ke : 1;
+    const bool skip = d.it[IT_SKIP] != 0.0;
+    const int nact = skip ? 0 : (int)d.it[IT_NACT];
 
-  double out1[12], out2[12];
-  {
-    const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
-    // four gathers in flight per thread: indices and weights first, then rows
-    double s1[12], s2[12];
-    T f1[12];
+    double out1[12], out2[12];
+    {
+      const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
+      // four gathers in flight per thread: indices and weights first, then rows
+      double s1[12], s2[12];
+      T f1[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
-    for (int a = tid; a < nmax; a += 4 * kUpdBlock) {
-      uint32_t ka[4];
-      T wa[4];
-      bool va[4];
+      for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
+      for (int a = tid; a < nmax; a += 4 * kUpdBlock) {
+        uint32_t ka[4];
+        T wa[4];
+        bool va[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int aa = a + u * kUpdBlock;
-        const int ac = aa < nmax ? aa : nmax - 1;  // always valid: loads issue together
-        const uint32_t kv = act[ac];
-        const T wv = actw[ac];
-        va[u] = aa < nact;
-        ka[u] = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
-        wa[u] = va[u] ? wv : T(0);
-      }
-      float4 zl[4][3];
+        for (int u = 0; u < 4; ++u) {
+          const int aa = a + u * kUpdBlock;
+          const int ac = aa < nmax ? aa : nmax - 1;  // always valid: loads issue together
+          const uint32_t kv = act[ac];
+          const T wv = actw[ac];
+          va[u] = aa < nact;
+          ka[u] = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
+          wa[u] = va[u] ? wv : T(0);
+        }
+        float4 zl[4][3];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
-        zl[u][0] = src[0];
-        zl[u][1] = src[1];
-        zl[u][2] = src[2];
-      }
+        for (int u = 0; u < 4; ++u) {
+          const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
+          zl[u][0] = src[0];
+          zl[u][1] = src[1];
+          zl[u][2] = src[2];
+        }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (!va[u]) continue;
-        const float zz[12] = {zl[u][0].x, zl[u][0].y, zl[u][0].z, zl[u][0].w,
-                              zl[u][1].x, zl[u][1].y, zl[u][1].z, zl[u][1].w,
-                              zl[u][2].x, zl[u][2].y, zl[u][2].z, zl[u][2].w};
-        if (elite) {
+        for (int u = 0; u < 4; ++u) {
+          if (!va[u]) continue;
+          const float zz[12] = {zl[u][0].x, zl[u][0].y, zl[u][0].z, zl[u][0].w,
+                                zl[u][1].x, zl[u][1].y, zl[u][1].z, zl[u][1].w,
+                                zl[u][2].x, zl[u][2].y, zl[u][2].z, zl[u][2].w};
+          if (elite) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            const double zc = (double)zz[c];
-            s1[c] += zc;
-            s2[c] += zc * zc;
+            for (int c = 0; c < 12; ++c) {
+              const double zc = (double)zz[c];
+              s1[c] += zc;
+              s2[c] += zc * zc;
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) f1[c] += wa[u] * (T)zz[c];
           }
-        } else {
-#pragma unroll
-          for (int c = 0; c < 12; ++c) f1[c] += wa[u] * (T)zz[c];
         }
       }
-    }
-    if (elite) {
+      if (elite) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) { out1[c] = wave_sum(s1[c]); out2[c] = wave_sum(s2[c]); }
-    } else {
-      // reduce in the working precision within the wave, FP64 across waves
+        for (int c = 0; c < 12; ++c) { out1[c] = wave_sum(s1[c]); out2[c] = wave_sum(s2[c]); }
+      } else {
+        // reduce in the working precision within the wave, FP64 across waves
 #pragma unroll
-      for (int c = 0; c < 12; ++c) { out1[c] = (double)wave_sum(f1[c]); out2[c] = 0.0; }
-    }
-  }
-  const int lane = tid & 63, wid = tid >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
-  }
-  __syncthreads();
-  if (tid < 12) {
-    const int c = tid, idx = j * 12 + c;
-    double S1 = 0.0, S2 = 0.0;
-    for (int i = 0; i < kUpdBlock / 64; ++i) {
-      S1 += lds[i][c];
-      S2 += lds[i][12 + c];
-    }
-    double m_new = m_old;
-    if (elite) {
-      double sg = sig;
-      if (!skip) {
-        const double omega = d.it[IT_OMEGA];
-        const double mz = S1 / omega;
-        double vz = S2 / omega - mz * mz;
-        vz = vz > 0.0 ? vz : 0.0;
-        m_new = m_old + sig * mz;
-        const double sn = sig * __builtin_sqrt(vz);
-        sg = sn > d.sigma_min_grf ? sn : d.sigma_min_grf;
+        for (int c = 0; c < 12; ++c) { out1[c] = (double)wave_sum(f1[c]); out2[c] = 0.0; }
       }
-      d.sigma[idx] = sg;
-    } else if (!skip) {
-      m_new = m_old + d.sigma0 * (S1 / d.it[IT_OMEGA]);
     }
-    const T stored = (T)m_new;
-    mean_out<T>(d, r)[idx] = stored;
-    s_new[c] = (double)stored;
-    if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
+    const int lane = tid & 63, wid = tid >> 6;
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
+    }
+    __syncthreads();
+    if (tid < 12) {
+      const int c = tid, idx = j * 12 + c;
+      double S1 = 0.0, S2 = 0.0;
+      for (int i = 0; i < kUpdBlock / 64; ++i) {
+        S1 += lds[i][c];
+        S2 += lds[i][12 + c];
+      }
+      double m_new = m_old;
+      if (elite) {
+        double sg = sig;
+        if (!skip) {
+          const double omega = d.it[IT_OMEGA];
+          const double mz = S1 / omega;
+          double vz = S2 / omega - mz * mz;
+          vz = vz > 0.0 ? vz : 0.0;
+          m_new = m_old + sig * mz;
+          const double sn = sig * __builtin_sqrt(vz);
+          sg = sn > d.sigma_min_grf ? sn : d.sigma_min_grf;
+        }
+        d.sigma[idx] = sg;
+      } else if (!skip) {
+        m_new = m_old + d.sigma0 * (S1 / d.it[IT_OMEGA]);
+      }
+      const T stored = (T)m_new;
+      mean_out<T>(d, r)[idx] = stored;
+      if (j == 0) s_new[c] = (double)stored;
+      if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
+    }
+    __syncthreads();  // the next step reuses lds
   }
-  if (!(last_iter && j == 0)) return;
-  __syncthreads();
+  if (!(last_iter && j0 == 0)) return;
   if (tid == 0)
     emit_action(d, s_new, d.it[IT_FNEW], d.it[IT_BETA], d.it[IT_FLAGS], d.it[IT_NACT]);
 }
@@ -1677,57 +1716,50 @@ constexpr int kMppiPer = 16;
 // in the working precision and, when it does not underflow, the weighted
 // noise row (already requested when k is its wave's lowest cost, kw), the
 // FP64 normaliser and frequency sums and the count of weighted samples.
-template <typename T>
-__device__ __forceinline__ void mppi_visit(const TickDesc &d, const float *zj, int k, T Jk, T bv,
-                                           T il, int kw, float4 pz0, float4 pz1, float4 pz2,
-                                           T (&f1)[12], double &sw,
-                                           double &swf, double &cnt) {
-  const T wk = exp_t((bv - Jk) * il);
-  if (wk == T(0)) return;
-  float4 z0 = pz0, z1 = pz1, z2 = pz2;
-  if (k != kw) {
-    const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)k * 12);
-    z0 = src[0];
-    z1 = src[1];
-    z2 = src[2];
-  }
-  cnt += 1.0;
-  sw += (double)wk;
-  swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
-  const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                        z2.x, z2.y, z2.z, z2.w};
-#pragma unroll
-  for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
-}
+
+// MPPI update (Alg. 4), one 1024-thread workgroup per controller: the
+// lowest cost beta, the weights w_k = exp((beta - J_k) / lambda), the FP64
+// normaliser Omega and frequency moment, then every row of the new mean,
+// mu'_j = mu_j + sigma sum_k w_k z_kj / Omega.  Usually few weights do not
+// underflow: their samples are listed in LDS in increasing k and each
+// (row, dimension) output sums its list terms in FP64 in that order.  With
+// more than kListCap of them, or N above the register-held kPer per thread,
+// each row is reduced over all samples instead (per-thread partial sums in
+// the working precision, wave sums, FP64 across waves).  Either way the
+// result depends only on the controller's own data, not on the batch.
+constexpr int kListCap = 2048;
 
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
-  const int b = blockIdx.x;
-  const int item = stage_item<INL>(tab.upd_start, tab.n, b);
-  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[item]];
+  const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[blockIdx.x]];
   if (d.method != 0) return;  // elite / best sample: k_select + k_update
-  const int j = b - stage_start<INL>(tab.upd_start, item);
-  const int N = d.N, tid = threadIdx.x, r = tab.r;
+  const int N = d.N, M = d.M, tid = threadIdx.x, r = tab.r;
   constexpr int kW = kMppiBlock / 64;
+  // the first kPer costs of each thread are held in registers (independent
+  // loads, one memory latency): 16 in FP32, 2 in FP64, which keeps the FP64
+  // form within a 1024-thread workgroup's 128 registers; beyond that (N
+  // above kPer * kMppiBlock) they are read again from memory, in the same
+  // order
+  constexpr int kPer = sizeof(T) == 8 ? 2 : kMppiPer;
   __shared__ double lds[kW][16];
   __shared__ uint64_t red_a[kW][2], red_b[kW][2];
+  __shared__ uint32_t s_pre[kPer][kW];  // list position of each (slot, wave)'s first entry
+  __shared__ uint32_t s_total;
+  __shared__ uint32_t s_k[kListCap];
+  __shared__ T s_w[kListCap];
   __shared__ double s_new[12];
   const T *Jg = reinterpret_cast<const T *>(d.J);
-  // What does not depend on the costs is read first, so that its latency
-  // overlaps the cost loads: this step's old mean and the running
-  // per-iteration scalars.
   const bool last_iter = (r == d.R - 1);
-  const double m_old = (tid < 12) ? (double)mean_at<T>(d, mean_in<T>(d, r), r, j, tid) : 0.0;
   const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
   const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
   const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
+  const T *mu_in = mean_in<T>(d, r);
+  T *mu_out = mean_out<T>(d, r);
+  const float *zr = d.z + (size_t)r * d.z_iter_stride;
 
-  // the first kMppiPer costs of each thread are loaded at once into
-  // registers (independent loads, one memory latency); beyond that (N above
-  // kMppiPer * kMppiBlock) they are read again from memory
-  T Jr[kMppiPer];
+  T Jr[kPer];
 #pragma unroll
-  for (int i = 0; i < kMppiPer; ++i) {
+  for (int i = 0; i < kPer; ++i) {
     const int k = tid + i * kMppiBlock;
     const T jv = Jg[k < N ? k : N - 1];  // always valid: the loads issue together
     Jr[i] = (k < N) ? jv : inf_t<T>();
@@ -1735,73 +1767,157 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   T bv = inf_t<T>();
   int bk = 0x7fffffff;
 #pragma unroll
-  for (int i = 0; i < kMppiPer; ++i) argmin_combine(bv, bk, Jr[i], tid + i * kMppiBlock);
-  for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
-  // The noise row of each wave's lowest-cost sample is requested before the
-  // workgroup's lowest cost is known: when, as usual at small lambda, only
-  // the lowest cost carries weight, its row is then already on its way.
-  const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
-  const int kw = wave_argmin_index(bv, bk);
-  float4 pz0 = make_float4(0.f, 0.f, 0.f, 0.f), pz1 = pz0, pz2 = pz0;
-  if (kw < N) {
-    const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)kw * 12);
-    pz0 = src[0];
-    pz1 = src[1];
-    pz2 = src[2];
-  }
+  for (int i = 0; i < kPer; ++i) argmin_combine(bv, bk, Jr[i], tid + i * kMppiBlock);
+  for (int k = tid + kPer * kMppiBlock; k < N; k += kMppiBlock) argmin_combine(bv, bk, Jg[k], k);
   block_argmin_packed(bv, bk, red_a, red_b);
   const bool skip = !finite_t(bv);
 
-  T f1[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) f1[c] = T(0);
+  // 1/lambda in the working precision, kept finite: at a lambda whose
+  // reciprocal overflows FP32 the best sample's (beta - J) il stays
+  // 0 * finite = 0 (weight 1) rather than 0 * inf = NaN, and every other
+  // weight underflows to 0 -- the argmin limit of Alg. 4
+  const double ild = d.inv_lambda;
+  const T il = (T)(ild < (double)std::numeric_limits<T>::max() ? ild
+                                                                : (double)std::numeric_limits<T>::max());
+  // weights of this thread's samples; a bit per register-held cost marks
+  // those that do not underflow (their weights are formed again where
+  // needed: the same values); FP64 normaliser and frequency moment
+  uint32_t wmask = 0u;
   double sw = 0.0, swf = 0.0, cnt = 0.0;
-  if (!skip) {
-    // 1/lambda in the working precision, kept finite: at a lambda whose
-    // reciprocal overflows FP32 the best sample's (beta - J) il stays
-    // 0 * finite = 0 (weight 1) rather than 0 * inf = NaN, and every other
-    // weight underflows to 0 -- the argmin limit of Alg. 4
-    const double ild = d.inv_lambda;
-    const T il = (T)(ild < (double)std::numeric_limits<T>::max() ? ild
-                                                                  : (double)std::numeric_limits<T>::max());
 #pragma unroll
-    for (int i = 0; i < kMppiPer; ++i)
-      if (tid + i * kMppiBlock < N)
-        mppi_visit(d, zj, tid + i * kMppiBlock, Jr[i], bv, il, kw, pz0, pz1, pz2, f1, sw, swf, cnt);
-    for (int k = tid + kMppiPer * kMppiBlock; k < N; k += kMppiBlock)
-      mppi_visit(d, zj, k, Jg[k], bv, il, kw, pz0, pz1, pz2, f1, sw, swf, cnt);
+  for (int i = 0; i < kPer; ++i) {
+    const int k = tid + i * kMppiBlock;
+    const T wk = (!skip && k < N) ? exp_t((bv - Jr[i]) * il) : T(0);
+    if (wk != T(0)) {
+      wmask |= 1u << i;
+      cnt += 1.0;
+      sw += (double)wk;
+      swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+    }
   }
-  // within a wave in the working precision (FP64 for the normaliser), then
-  // FP64 across waves
-  // (usually a handful of samples carry weight, so most waves have nothing
-  // to add and the rest add a few lanes through scalar reads)
+  if (!skip)
+    for (int k = tid + kPer * kMppiBlock; k < N; k += kMppiBlock) {
+      const T wk = exp_t((bv - Jg[k]) * il);
+      if (wk != T(0)) {
+        cnt += 1.0;
+        sw += (double)wk;
+        swf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
+      }
+    }
   const int lane = tid & 63, wid = tid >> 6;
   const uint64_t live = __ballot(cnt != 0.0);
-  double o[15];
+  {
+    const double o12 = wave_sum_sparse(sw, live);
+    const double o13 = wave_sum_sparse(swf, live);
+    const double o14 = wave_sum_sparse(cnt, live);
+    if (lane == 0) {
+      lds[wid][12] = o12;
+      lds[wid][13] = o13;
+      lds[wid][14] = o14;
+    }
+  }
+  // list positions: samples in increasing k are slot-major (k = tid + i
+  // 1024), so entry (slot i, wave w, lane l) goes after every entry of the
+  // lower slots, of the lower waves of slot i and of the lower lanes
+  const bool regs_only = N <= kPer * kMppiBlock;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) o[c] = (double)wave_sum_sparse(f1[c], live);
-  o[12] = wave_sum_sparse(sw, live);
-  o[13] = wave_sum_sparse(swf, live);
-  o[14] = wave_sum_sparse(cnt, live);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 15; ++c) lds[wid][c] = o[c];
+  for (int i = 0; i < kPer; ++i) {
+    const uint64_t bal = __ballot((wmask >> i) & 1u);
+    if (lane == 0) s_pre[i][wid] = (uint32_t)__popcll(bal);
   }
   __syncthreads();
-  if (tid < 12) {
-    const int c = tid, idx = j * 12 + c;
-    double S1 = 0.0, omega = 0.0;
-    for (int i = 0; i < kW; ++i) {
-      S1 += lds[i][c];
-      omega += lds[i][12];
+  if (wid == 0) {
+    // exclusive scan of the kPer x kW counts, slot-major, by one wave
+    constexpr int kCells = kPer * kW, kPerLane = (kCells + 63) / 64;
+    uint32_t v[kPerLane], sum = 0;
+#pragma unroll
+    for (int e = 0; e < kPerLane; ++e) {
+      const int cell = lane * kPerLane + e;
+      v[e] = cell < kCells ? s_pre[cell / kW][cell % kW] : 0u;
+      sum += v[e];
     }
-    const double m_new = skip ? m_old : m_old + d.sigma0 * (S1 / omega);
-    const T stored = (T)m_new;
-    mean_out<T>(d, r)[idx] = stored;
-    s_new[c] = (double)stored;
-    if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
+    const uint32_t incl = wave_incl_scan_u32(sum);
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int e = 0; e < kPerLane; ++e) {
+      const int cell = lane * kPerLane + e;
+      if (cell < kCells) s_pre[cell / kW][cell % kW] = run;
+      run += v[e];
+    }
+    if (lane == 63) s_total = incl;
   }
-  if (j != 0) return;
+  __syncthreads();
+  const uint32_t total = s_total;
+  const bool listed = regs_only && total <= (uint32_t)kListCap;
+  if (listed) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint64_t bal = __ballot((wmask >> i) & 1u);
+      if ((wmask >> i) & 1u) {
+        const uint32_t pos = s_pre[i][wid] +
+                             (uint32_t)__popcll(bal & ((lane ? ~0ull >> (64 - lane) : 0ull)));
+        s_k[pos] = (uint32_t)(tid + i * kMppiBlock);
+        s_w[pos] = exp_t((bv - Jr[i]) * il);
+      }
+    }
+    __syncthreads();
+    double omega = 0.0;
+    for (int i = 0; i < kW; ++i) omega += lds[i][12];
+    for (int o = tid; o < M * 12; o += kMppiBlock) {
+      const int j = o / 12, c = o - j * 12;
+      const double m_old = (double)mean_at<T>(d, mu_in, r, j, c);
+      const float *zc = zr + (size_t)j * N * 12 + c;
+      double S1 = 0.0;
+      for (uint32_t a = 0; a < total; ++a)
+        S1 = __builtin_fma((double)s_w[a], (double)zc[(size_t)s_k[a] * 12], S1);
+      const double m_new = skip ? m_old : m_old + d.sigma0 * (S1 / omega);
+      const T stored = (T)m_new;
+      mu_out[o] = stored;
+      if (j == 0) s_new[c] = (double)stored;
+      if (last_iter && d.dbg_mean) d.dbg_mean[o] = (double)stored;
+    }
+  } else {
+    for (int j = 0; j < M; ++j) {
+      const float4 *zj = reinterpret_cast<const float4 *>(zr) + (size_t)j * N * 3;
+      T f1[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) f1[c] = T(0);
+      // (the costs are read again from memory here: a rare path, and one
+      // loop over k keeps the register count of the common path)
+      if (!skip)
+        for (int k = tid; k < N; k += kMppiBlock) {
+          const T wk = exp_t((bv - Jg[k]) * il);
+          if (wk == T(0)) continue;
+          const float4 z0 = zj[(size_t)k * 3], z1 = zj[(size_t)k * 3 + 1],
+                       z2 = zj[(size_t)k * 3 + 2];
+          const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                                z2.x, z2.y, z2.z, z2.w};
+#pragma unroll
+          for (int c = 0; c < 12; ++c) f1[c] += wk * (T)zz[c];
+        }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const double o = (double)wave_sum_sparse(f1[c], live);
+        if (lane == 0) lds[wid][c] = o;
+      }
+      __syncthreads();
+      if (tid < 12) {
+        const int c = tid, idx = j * 12 + c;
+        double S1 = 0.0, omega = 0.0;
+        for (int i = 0; i < kW; ++i) {
+          S1 += lds[i][c];
+          omega += lds[i][12];
+        }
+        const double m_old = (double)mean_at<T>(d, mu_in, r, j, c);
+        const double m_new = skip ? m_old : m_old + d.sigma0 * (S1 / omega);
+        const T stored = (T)m_new;
+        mu_out[idx] = stored;
+        if (j == 0) s_new[c] = (double)stored;
+        if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
+      }
+      __syncthreads();  // the next row reuses lds[][0..11]
+    }
+  }
   if (d.dbg_J) {
     for (int k = tid; k < N; k += kMppiBlock) {
       d.dbg_J[(size_t)r * N + k] = (double)Jg[k];
@@ -1853,6 +1969,17 @@ static hipError_t launch_one_lane(const LaunchTab &tab, const TickDesc &inl, int
   if (precision == 1) {
     launch_timed(k_rollout<double, 64, 1, INL, SPL, PAIR>, rg, dim3(64), lds, s, e0, e1, tab, inl);
     return hipSuccess;
+  }
+  if constexpr (!SPL) {
+    if (tab.gen_noise) {  // the rollout makes the noise (one-row loops only)
+      switch (tab.roll_block) {
+        case 64: launch_timed(k_rollout<float, 64, 1, INL, false, PAIR, true>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
+        case 128: launch_timed(k_rollout<float, 128, 1, INL, false, PAIR, true>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
+        case 256: launch_timed(k_rollout<float, 256, 1, INL, false, PAIR, true>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipSuccess;
+    }
   }
   switch (tab.roll_block * 4 + tab.unroll) {
     case 64 * 4 + 1: launch_timed(k_rollout<float, 64, 1, INL, SPL, PAIR>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
@@ -1906,7 +2033,7 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
   const size_t roll_lds = (size_t)tab.max_rows * 12 * 2 * ts +
                           (tab.spline ? (size_t)tab.max_h * (4 * ts + 4) : 0);
   if (timing == 2) (void)hipEventRecord(ev[0], s);
-  if (!tab.skip_noise)
+  if (!tab.skip_noise && !tab.gen_noise)
     hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,
                        tab, inl);
   // mode 1: the rollout kernel's own start and end; mode 2: event commands
@@ -1940,9 +2067,9 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
   }
   if (tab.n_select < tab.n) {
     if (precision == 1)
-      hipLaunchKernelGGL((k_update_mppi<double, INL>), ug, dim3(kMppiBlock), 0, s, tab, inl);
+      hipLaunchKernelGGL((k_update_mppi<double, INL>), dim3(tab.n), dim3(kMppiBlock), 0, s, tab, inl);
     else
-      hipLaunchKernelGGL((k_update_mppi<float, INL>), ug, dim3(kMppiBlock), 0, s, tab, inl);
+      hipLaunchKernelGGL((k_update_mppi<float, INL>), dim3(tab.n), dim3(kMppiBlock), 0, s, tab, inl);
   }
   if (timing == 2) (void)hipEventRecord(ev[4], s);
   return hipGetLastError();

@@ -68,6 +68,10 @@ int64_t now_ns() {
 constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
+// Mean rows per update workgroup in a batch: at most kUpdMaxChunk, and no
+// more than keeps kUpdTargetGroups workgroups (two per compute unit).
+constexpr long long kUpdMaxChunk = 8;
+constexpr long long kUpdTargetGroups = 512;
 
 // Step workspace of sbs_submit_tick_noalloc: one file-scope device array per
 // GPU, held until the process ends.  Host code never names it directly (its
@@ -104,6 +108,7 @@ struct Tune {
   int block = 256;  // four waves per workgroup: measured faster than 64 or 128 at C1
   int unroll = 1;
   bool pairs = true;  // stance-pair one-lane rollouts where the gait allows
+  bool gen = true;    // one-lane FP32 per-step rollouts make their own noise
 };
 
 bool valid_form(int lanes, int block, int unroll) {
@@ -269,6 +274,23 @@ bool complete_from_record(TicketRec &t) {
   t.status = 0;
   t.t_done = now_ns();
   return true;
+}
+
+// A completed ticket's action record as the C ABI returns it.
+void fill_action(const TicketRec &t, sbs_action *out) {
+  std::memset(out, 0, sizeof *out);
+  for (int i = 0; i < 12; ++i) out->grf[i] = t.res[RES_GRF + i];
+  for (int l = 0; l < 4; ++l) out->contact[l] = (int32_t)t.res[RES_CONTACT + l];
+  out->freq_hz = t.res[RES_FREQ];
+  out->q = (uint32_t)t.res[RES_Q];
+  out->best_cost = t.res[RES_BEST];
+  out->flags = (int32_t)t.res[RES_FLAGS];
+  out->tick = t.tick;
+  out->controller = t.controller;
+  out->t_submit_ns = t.t_submit;
+  out->t_launch_ns = t.t_launch;
+  out->t_done_ns = t.t_done;
+  out->n_active = (uint32_t)t.res[RES_NACT];
 }
 
 // Byte layout of one batch (device workspace and host staging share the
@@ -560,6 +582,16 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
 // Launch groups per iteration: precision x parametrisation x stance-pair form.
 constexpr int kGroups = 8;
 
+// Byte offset of the first item workspace in a batch of n controllers with
+// at most rmax iterations: descriptors, then per (iteration, launch group)
+// item[n] + 3 x start[n+1], then the action records.
+uint64_t layout_items_offset(uint64_t n, int rmax) {
+  const uint64_t tabs = align_up(n * sizeof(TickDesc));
+  const uint64_t tab_bytes = align_up((n + 3 * (n + 1)) * 4);
+  const uint64_t hdr = align_up(tabs + (uint64_t)rmax * kGroups * tab_bytes);
+  return align_up(hdr + n * kResultDoubles * 8);
+}
+
 // Layout of a batch over the given controllers.
 Layout make_layout(const std::vector<const Controller *> &cs) {
   Layout L;
@@ -636,6 +668,16 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         }
       }
       const int per_block = block / lanes;
+      // update workgroups cover `chunk` mean rows each: one for a lone
+      // controller (its rows run side by side, the latency path), more in a
+      // batch so that the costs and weights are formed once per chunk while
+      // at least kUpdTargetGroups workgroups remain (results do not depend
+      // on the chunk length)
+      long long rows_all = 0;
+      for (int t = 0; t < m; ++t) rows_all += rows_of(cs[idx[t]]->cfg);
+      const int chunk = m <= 1 ? 1
+                               : (int)std::max<long long>(1, std::min<long long>(kUpdMaxChunk,
+                                                                                 rows_all / kUpdTargetGroups));
       int max_rows = 1;
       ns[0] = rs[0] = us[0] = 0;
       for (int t = 0; t < m; ++t) {
@@ -645,7 +687,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         item[t] = idx[t];
         ns[t + 1] = ns[t] + rows_of(c) * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
         rs[t + 1] = rs[t] + (c.N + per_block - 1) / per_block;
-        us[t + 1] = us[t] + rows_of(c);
+        us[t + 1] = us[t] + (rows_of(c) + chunk - 1) / chunk;
       }
       if (m == 0) continue;
       LaunchTab tab{};
@@ -659,6 +701,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.spline = spl;
       tab.lanes = lanes;
       tab.pairs = pair;
+      tab.upd_chunk = chunk;
+      tab.gen_noise = (tn.gen && prec == SBS_FP32 && lanes == 1 && !spl && unroll == 1) ? 1 : 0;
       tab.roll_block = block;
       tab.unroll = unroll;
       tab.r_count = 1;
@@ -826,7 +870,10 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
       inl->z_iter_stride = (uint64_t)rows_of(C0.cfg) * C0.cfg.N * 12;
       if (C0.pf_tick[pbuf] == (int64_t)ticks[0]) {
         e = hipStreamWaitEvent(s, C0.pf_ready[pbuf], 0);
-        for (auto &tp : tabs) tp.first.skip_noise = 1;
+        for (auto &tp : tabs) {
+          tp.first.skip_noise = 1;
+          tp.first.gen_noise = 0;  // the noise is there already
+        }
       }
     }
   }
@@ -958,11 +1005,13 @@ void scheduler_loop(sbs_runtime *rt) {
       std::vector<const sbs_tick_input *> ins;
       std::vector<uint64_t> tks;
       std::vector<size_t> taken;
-      std::vector<const Controller *> cs;
       std::unordered_map<int32_t, bool> seen;
-      uint64_t need = 0;
       uint64_t avail = rt->dev_alloc.size() - rt->dev_alloc.used();
       bool waited = false;
+      // the batch's workspace grows by one item at a time: header and
+      // records from the count, plus the sum of the item workspaces
+      uint64_t items_bytes = 0;
+      int rmax = 1;
       for (size_t i = 0; i < rt->pending.size() && ids.size() < 1024; ++i) {
         Request &rq = rt->pending[i];
         if (seen.count(rq.id)) continue;
@@ -970,20 +1019,20 @@ void scheduler_loop(sbs_runtime *rt) {
         auto cit = rt->ctrls.find(rq.id);
         if (cit == rt->ctrls.end()) continue;
         if (cit->second.inflight > 0) continue;
-        cs.push_back(&cit->second);
-        Layout L = make_layout(cs);
-        if (L.total + kAlign > avail) {
-          cs.pop_back();
+        const uint64_t ib = align_up(item_ws(cit->second.cfg).bytes);
+        const int rm = std::max(rmax, cit->second.cfg.iterations);
+        const uint64_t total = layout_items_offset(ids.size() + 1, rm) + items_bytes + ib;
+        if (total + kAlign > avail) {
           waited = true;
           break;
         }
-        need = L.total;
+        items_bytes += ib;
+        rmax = rm;
         ids.push_back(rq.id);
         ins.push_back(&rq.in);
         tks.push_back(rq.ticket);
         taken.push_back(i);
       }
-      (void)need;
       if (waited) rt->n_admit_waits += 1;
       if (ids.empty() && waited && rt->inflight.empty()) {
         // the first admissible request does not fit beside the persistent
@@ -1320,6 +1369,40 @@ int sbs_submit_tick_noalloc(sbs_runtime *rt, int32_t id, const sbs_tick_input *i
   return SBS_OK;
 }
 
+int sbs_fetch_ready(sbs_runtime *rt, int32_t max, uint64_t *tickets, sbs_action *out,
+                    int32_t *count, int64_t timeout_us) {
+  if (!rt || !tickets || !out || !count || max < 0)
+    return fail(SBS_EINVAL, "bad sbs_fetch_ready arguments");
+  *count = 0;
+  const int64_t t0 = now_ns();
+  std::unique_lock<std::mutex> lk(rt->mu);
+  for (;;) {
+    if (rt->mode == SBS_MODE_DIRECT) reap(rt);
+    int32_t n = 0;
+    for (auto it = rt->tickets.begin(); it != rt->tickets.end() && n < max;) {
+      TicketRec &t = it->second;
+      if (t.status == 1 && complete_from_record(t)) rt->n_ticks += 1;
+      if (t.status == 0) {
+        tickets[n] = it->first;
+        fill_action(t, &out[n]);
+        ++n;
+        it = rt->tickets.erase(it);
+      } else {
+        ++it;  // pending, or failed: left for sbs_fetch_action to report
+      }
+    }
+    *count = n;
+    if (n > 0 || max == 0) return SBS_OK;
+    // nothing ready: give the lock (and the CPU) to the scheduler before
+    // returning or polling again, so that a client polling in a tight loop
+    // cannot keep it from launching the work it waits for
+    lk.unlock();
+    std::this_thread::yield();
+    if (timeout_us == 0 || (timeout_us > 0 && now_ns() - t0 > timeout_us * 1000)) return SBS_OK;
+    lk.lock();
+  }
+}
+
 int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t timeout_us) {
   if (!rt || !out) return fail(SBS_EINVAL, "NULL argument");
   const int64_t t0 = now_ns();
@@ -1334,29 +1417,15 @@ int sbs_fetch_action(sbs_runtime *rt, uint64_t ticket, sbs_action *out, int64_t 
     }
     if (t.status <= 0) {
       int st = t.status;
-      if (st == 0) {
-        std::memset(out, 0, sizeof *out);
-        for (int i = 0; i < 12; ++i) out->grf[i] = t.res[RES_GRF + i];
-        for (int l = 0; l < 4; ++l) out->contact[l] = (int32_t)t.res[RES_CONTACT + l];
-        out->freq_hz = t.res[RES_FREQ];
-        out->q = (uint32_t)t.res[RES_Q];
-        out->best_cost = t.res[RES_BEST];
-        out->flags = (int32_t)t.res[RES_FLAGS];
-        out->tick = t.tick;
-        out->controller = t.controller;
-        out->t_submit_ns = t.t_submit;
-        out->t_launch_ns = t.t_launch;
-        out->t_done_ns = t.t_done;
-        out->n_active = (uint32_t)t.res[RES_NACT];
-      }
+      if (st == 0) fill_action(t, out);
       rt->tickets.erase(it);
       if (st < 0) return fail(st, "tick failed or was cancelled");
       return SBS_OK;
     }
+    lk.unlock();
+    std::this_thread::yield();  // see sbs_fetch_ready: a polling client yields
     if (timeout_us == 0) return fail(SBS_EAGAIN, "not ready");
     if (timeout_us > 0 && now_ns() - t0 > timeout_us * 1000) return fail(SBS_ETIMEDOUT, "timed out");
-    lk.unlock();
-    std::this_thread::yield();
     lk.lock();
   }
 }
@@ -1663,6 +1732,13 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
   rt->tune.pairs = enable != 0;
+  return SBS_OK;
+}
+
+int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  rt->tune.gen = in_rollout != 0;
   return SBS_OK;
 }
 

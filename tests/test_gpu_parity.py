@@ -269,6 +269,38 @@ def test_batch_equals_alone(rt):
         rt.destroy_controller(cid)
 
 
+def test_chunked_update_equals_one_row_per_workgroup(rt):
+    """A batch of 48 controllers at H = 50 (1200 mean rows per precision)
+    gives each update workgroup two rows; a controller alone gets one.  The
+    costs, weights and normaliser are formed once per workgroup and each row
+    is reduced as a one-row workgroup reduces it, so every action and mean
+    is bit-identical (MPPI, elite and best sample, FP32 and FP64)."""
+    rng = np.random.default_rng(41)
+    cfgs, inps = [], []
+    for i in range(48):
+        method = ["mppi", "elite", "naive", "mppi"][(i // 2) % 4]
+        cfgs.append(workloads.config("c4", N=int(rng.choice([512, 1000, 1500])), H=50,
+                                     method=method, iterations=1 if method == "mppi" else 2,
+                                     precision="fp64" if i % 2 else "fp32", seed=700 + i))
+        inps.append(workloads.tick_input(workloads.initial_state(rng)))
+    rt.set_rollout_lanes(1)  # the same rollout form alone and in the batch
+    try:
+        alone = []
+        for c, inp in zip(cfgs, inps):
+            cid = rt.init_controller(c)
+            alone.append((rt.tick(cid, inp), rt.get_state(cid)[0]))
+            rt.destroy_controller(cid)
+        ids = [rt.init_controller(c) for c in cfgs]
+        batch = [rt.fetch(t) for t in rt.submit_batch(ids, inps)]
+        for cid, (a, mu), b in zip(ids, alone, batch):
+            np.testing.assert_array_equal(a["grf"], b["grf"])
+            assert a["q"] == b["q"] and a["best_cost"] == b["best_cost"]
+            np.testing.assert_array_equal(mu, rt.get_state(cid)[0])
+            rt.destroy_controller(cid)
+    finally:
+        rt.set_rollout_lanes(0)
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_plan_replay_matches_direct(rt, use_graph):
     cfgs = [workloads.config("c1", N=n, H=h, seed=s) for n, h, s in ((900, 10, 1), (2000, 25, 2))]
@@ -320,6 +352,40 @@ def test_stance_pair_form_equals_four_leg_form(rt, precision):
             np.testing.assert_array_equal(m1, m0)
     finally:
         rt.set_rollout_pairs(True)
+        rt.set_rollout_lanes(0)
+
+
+def test_noise_made_in_rollout_equals_noise_launch(rt):
+    """One-lane FP32 rollouts that make their noise rows themselves store
+    exactly the rows the noise kernel writes and compute the same costs:
+    every cost, sampled increment, action and updated mean is bit-equal to
+    the separate noise launch (MPPI, elite with three iterations whose
+    update reads the stored rows, stance-pair and four-leg gaits, a batch)."""
+    cfgs = [workloads.config("c1", N=3000, H=50, seed=81),
+            workloads.config("c2", N=2500, H=30, seed=82),
+            workloads.config("c1", N=1200, H=20, seed=83, duty=0.6)]  # four-leg form
+    rng = np.random.default_rng(84)
+    inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
+    rt.set_rollout_lanes(1)
+    try:
+        res = {}
+        for gen in (True, False):
+            rt.set_rollout_noise(gen)
+            ids = [rt.init_controller(c) for c in cfgs]
+            for cid in ids:
+                rt.set_debug(cid, True)
+            acts = [rt.fetch(t) for t in rt.submit_batch(ids, inps)]
+            res[gen] = [(a, rt.debug_fetch(cid), rt.get_state(cid)[0]) for a, cid in zip(acts, ids)]
+            for cid in ids:
+                rt.destroy_controller(cid)
+        for (a1, (J1, q1, m1), mu1), (a0, (J0, q0, m0), mu0) in zip(res[True], res[False]):
+            np.testing.assert_array_equal(q1, q0)
+            np.testing.assert_array_equal(J1, J0)
+            np.testing.assert_array_equal(a1["grf"], a0["grf"])
+            np.testing.assert_array_equal(m1, m0)
+            np.testing.assert_array_equal(mu1, mu0)
+    finally:
+        rt.set_rollout_noise(True)
         rt.set_rollout_lanes(0)
 
 

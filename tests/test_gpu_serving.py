@@ -213,3 +213,30 @@ def test_shadow_oracle_on_served_ticks():
         assert err <= max(1e-4 * scale, bound), (err, bound, scale)
         worst = max(worst, err / scale)
     print("worst action error against the oracle (relative)", worst, flush=True)
+
+
+def test_fetch_ready_returns_every_tick_once():
+    """sbs_fetch_ready hands back completed ticks in bulk: over repeated
+    calls every submitted ticket comes back exactly once, with the action
+    that fetching it alone gives (serving mode, three ticks per robot)."""
+    import time
+    from paper_2403_11383_amd import binding
+    cfgs, inps = fleet(8)
+    one, _ = run("serving", cfgs, inps, ticks=3)
+    rt = binding.Runtime(arena_bytes=1 << 30, mode="serving", two_streams=True)
+    rt.set_rollout_lanes(1)
+    ids = [rt.init_controller(c) for c in cfgs]
+    tks = []
+    for t in range(3):
+        for cid, inp in zip(ids, inps):
+            tks.append(rt.submit_tick(cid, inp))
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tks) and time.time() - t0 < 30:
+        for tk, a in rt.fetch_ready(5):  # fewer than the ticks: several calls
+            assert tk not in got
+            got[tk] = a
+    rt.close()
+    assert sorted(got) == sorted(tks)
+    for tk, a in zip(tks, one):
+        same(got[tk], a)
