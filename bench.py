@@ -54,6 +54,14 @@ FLOP_PER_ROLLOUT_STEP = 326
 # of each sample forms mu + sigma z once (24 per knot).
 FLOP_PER_SPLINE_STEP = FLOP_PER_ROLLOUT_STEP - 24 + 84
 FLOP_PER_SPLINE_KNOT = 24
+# A rollout that also draws its noise does the FP32 arithmetic of the 12
+# Gaussians of each step too: 45 FLOP per Box-Muller pair (the log's
+# reduction, division and polynomial 18 with the exponent terms, radius 2,
+# the turn's sine and cosine polynomials 21, the two products 2, the
+# mantissa scalings 2), 6 pairs per step; Philox's integer work is not
+# counted.
+FLOP_PER_NOISE_ROW = 270
+FLOP_PER_ROLLOUT_STEP_WITH_NOISE = FLOP_PER_ROLLOUT_STEP + FLOP_PER_NOISE_ROW
 # MI355X FP32 vector peak as published (it counts packed FMAs: 256 CUs x 4
 # SIMDs x 16 lanes x 2 FLOP x 2 packed x 2.4 GHz) and the non-packed peak the
 # kernels can reach (they are built with packed FP32 off).
@@ -232,6 +240,11 @@ def main():
                          "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
+    ap.add_argument("--phase", default="all", choices=["all", "saturated"],
+                    help="c4: 'saturated' runs only the saturated serving stream, with HIP "
+                         "events on every rollout launch and no warm-up, and prints each "
+                         "rollout form's launches, rollout-steps and average duration over "
+                         "the whole process (for kernel traces and HBM byte counters)")
     ap.add_argument("--episodes", type=int, default=20, help="study: seeded episodes per setting")
     ap.add_argument("--duration", type=float, default=10.0, help="c4 stream length [s]")
     ap.add_argument("--arena-gb", type=float, default=4.0)
@@ -487,7 +500,7 @@ def roofline_obj(kernel, flop, dur_ns, launches, **extra):
            "peak_nonpacked": PEAK_FP32_VALU_TFLOPS,
            "frac_nonpacked": achieved / PEAK_FP32_VALU_TFLOPS,
            "flop_per_rollout_step": FLOP_PER_ROLLOUT_STEP}
-    out.update(extra)
+    out.update(extra)  # may restate flop_per_rollout_step for the form
     return out
 
 
@@ -582,7 +595,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     if timing:
         rt.set_timing(timing)
         rt.timing()
-        for f in range(3):
+        for f in range(4):
             rt.timing_rollout(f)
     pending = {}
     lat, done_work = [], 0
@@ -613,7 +626,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
            "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
            "p99_ms": pct(lat, 99), "batches": stats["batches"]}
     if timing:
-        out["rollout_forms"] = [rt.timing_rollout(f) for f in range(3)]
+        out["rollout_forms"] = [rt.timing_rollout(f) for f in range(4)]
         out["event_overhead_ns"] = rt.timing_overhead_ns(64)
     rt.close()
     return out
@@ -751,10 +764,27 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def main_c4_saturated(args, binding, workloads, arena):
+    """Only the saturated serving stream, every rollout launch timed from the
+    runtime's first one: a profiler's per-dispatch figures for the rollout
+    kernels of this process cover exactly the launches counted here."""
+    sat = saturated_run(binding, workloads, args.steps * STEP_S_SATURATED, "serving", arena,
+                        timing=3, streams=args.streams)
+    names = ["fp32_one_lane", "fp32_quad", "fp64", "fp32_one_lane_noise"]
+    forms = {names[i]: {"launches": f["launches"], "rollout_steps": f["steps"],
+                        "avg_us": f["avg_ns"] * 1e-3}
+             for i, f in enumerate(sat.pop("rollout_forms")) if f["launches"]}
+    print(json.dumps({"workload": "c4 saturated serving only", "steps": args.steps,
+                      "serving_streams": args.streams, "rollout_forms": forms,
+                      "saturated": sat}), flush=True)
+
+
 def main_c4(args):
     from paper_2403_11383_amd import binding, workloads
     arena = int(args.arena_gb * (1 << 30))
     K = args.steps
+    if args.phase == "saturated":
+        return main_c4_saturated(args, binding, workloads, arena)
     # warm-up: code objects, first launches, the pinned pools
     progress("warm-up")
     _ = saturated_run(binding, workloads, 0.05 * max(1, args.warmup), "serving", arena,
@@ -774,12 +804,14 @@ def main_c4(args):
     if args.timing and "rollout_forms" in sat:
         forms = sat["rollout_forms"]
         names = ["k_rollout<float> (one lane per sample)", "k_rollout_quad (four lanes per sample)",
-                 "k_rollout<double>"]
-        f = max(range(3), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
+                 "k_rollout<double>", "k_rollout<float> drawing its noise (one lane per sample)"]
+        per_step = [FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP,
+                    FLOP_PER_ROLLOUT_STEP_WITH_NOISE]
+        f = max(range(4), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
         fo = forms[f]
-        flop = fo["steps"] * FLOP_PER_ROLLOUT_STEP
+        flop = fo["steps"] * per_step[f]
         roof = roofline_obj(
-            names[f], flop, fo["avg_ns"], fo["launches"],
+            names[f], flop, fo["avg_ns"], fo["launches"], flop_per_rollout_step=per_step[f],
             traffic=stored_traffic("k_rollout", "c4"),
             timed_launches=fo["launches"], duration_us=fo["avg_ns"] * 1e-3,
             rollout_steps_per_launch=fo["steps"] / max(1, fo["launches"]),
@@ -789,7 +821,7 @@ def main_c4(args):
                                     "duration_us": forms[i]["avg_ns"] * 1e-3,
                                     "rollout_steps_per_launch":
                                         forms[i]["steps"] / max(1, forms[i]["launches"])}
-                         for i in range(3) if i != f and forms[i]["launches"]})
+                         for i in range(4) if i != f and forms[i]["launches"]})
         del sat["rollout_forms"]
     c = workloads.config("c4")
     line = {

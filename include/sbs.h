@@ -305,13 +305,14 @@ int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout);
 int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
 /* Rollout timing by form (modes 1 and 3): form 0 FP32 one lane per sample,
- * 1 FP32 four lanes per sample, 2 FP64.  Returns the average device time
+ * 1 FP32 four lanes per sample, 2 FP64, 3 FP32 one lane per sample making
+ * its own noise (sbs_set_rollout_noise).  Returns the average device time
  * [ns] of that form's timed rollout launches since the last call for the
  * form, their number and the rollout-steps (sum of N H over the launches'
  * controllers) they covered, and resets the form's accumulators.  The
  * algorithmic FLOP rate of the rollout (Alg. 2) is then
  * flop_per_step * steps / (avg_ns * launches).  SBS_EINVAL for a null
- * runtime or a form outside 0..2. */
+ * runtime or a form outside 0..3. */
 int sbs_timing_rollout(sbs_runtime *rt, int32_t form, double *avg_ns, uint64_t *launches,
                        double *steps);
 /* Fixed overhead of dispatch-carried timing events: the average interval [ns]

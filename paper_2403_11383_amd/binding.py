@@ -466,8 +466,9 @@ class Runtime:
 
     def timing_rollout(self, form: int):
         """Timed rollout launches of one form (0 FP32 one lane, 1 FP32 four
-        lanes, 2 FP64) since the last call: average device time [ns], number
-        of launches and the rollout-steps they covered."""
+        lanes, 2 FP64, 3 FP32 one lane drawing its noise) since the last
+        call: average device time [ns], number of launches and the
+        rollout-steps they covered."""
         avg, n, st = C.c_double(), C.c_uint64(), C.c_double()
         _check(lib().sbs_timing_rollout(self._h, int(form), C.byref(avg), C.byref(n), C.byref(st)))
         return {"avg_ns": avg.value, "launches": n.value, "steps": st.value}

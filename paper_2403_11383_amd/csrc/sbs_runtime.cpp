@@ -339,9 +339,14 @@ struct Batch {
 };
 
 // Rollout forms told apart by the per-form timing accumulators.
-enum RollForm { FORM_FP32_ONE_LANE = 0, FORM_FP32_QUAD = 1, FORM_FP64 = 2, kForms = 3 };
+enum RollForm {
+  FORM_FP32_ONE_LANE = 0, FORM_FP32_QUAD = 1, FORM_FP64 = 2, FORM_FP32_ONE_LANE_NOISE = 3,
+  kForms = 4
+};
 int roll_form(const LaunchTab &t, int precision) {
-  return precision == SBS_FP64 ? FORM_FP64 : (t.lanes == 4 ? FORM_FP32_QUAD : FORM_FP32_ONE_LANE);
+  if (precision == SBS_FP64) return FORM_FP64;
+  if (t.lanes == 4) return FORM_FP32_QUAD;
+  return t.gen_noise ? FORM_FP32_ONE_LANE_NOISE : FORM_FP32_ONE_LANE;
 }
 
 struct Plan {
@@ -397,8 +402,8 @@ struct sbs_runtime {
   uint64_t stage_n[4] = {0, 0, 0, 0};
   // rollout timing per form (modes 1 and 3): device time, launches and
   // rollout-steps of the timed launches
-  double form_ns[3] = {0, 0, 0}, form_steps[3] = {0, 0, 0};
-  uint64_t form_n[3] = {0, 0, 0};
+  double form_ns[4] = {0, 0, 0, 0}, form_steps[4] = {0, 0, 0, 0};
+  uint64_t form_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
