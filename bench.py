@@ -81,9 +81,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, workload: str):
+def stored_traffic(kernel: str, workload: str, rollout_steps_per_launch=None):
     """HBM bytes per launch from committed rocprofv3 counter summaries, only
-    while the kernel source is the one the counters were taken on."""
+    while the kernel source is the one the counters were taken on.  Entries
+    of workloads whose launches vary in size (the serving fleet) hold bytes
+    per rollout-step, scaled here by the launches' average rollout-steps."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -91,6 +93,10 @@ def stored_traffic(kernel: str, workload: str):
         doc = json.load(open(path))
         ent = doc.get(f"{kernel}/{workload}")
         if ent and ent.get("kernel_source_hash") == kernel_source_hash():
+            if "bytes_per_rollout_step" in ent:
+                if rollout_steps_per_launch is None:
+                    return None
+                return ent["bytes_per_rollout_step"] * rollout_steps_per_launch
             return ent.get("bytes_per_launch")
     except Exception:
         return None
@@ -570,9 +576,14 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
                   warmup_ticks=0, streams=2):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
-    form sustains, and their submit-to-done latency.  With timing, the
-    rollout launches carry HIP events (one launch in 16) and the per-form
-    rollout timings of the timed region are returned."""
+    form sustains, and their submit-to-done latency.  The serving client
+    works in bulk, as a fleet gateway would: every completed tick that one
+    sbs_fetch_ready call returns is resubmitted in one sbs_submit_batch call
+    (the scheduler still admits and batches them itself).  Plain single MPPI
+    (direct mode) submits tick by tick, each its own launch sequence.  With
+    timing, the rollout launches carry HIP events (one launch in 16; mode 3
+    every launch) and the per-form rollout timings of the timed region are
+    returned."""
     import ctypes as C
     import torch
     fleet = workloads.c4_fleet(robots=robots)
@@ -584,7 +595,20 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     tk = C.c_uint64()
     rtk = (C.c_uint64 * 1024)()
     racts = (binding.Action * 1024)()
+    acts = np.ctypeslib.as_array(racts)
     nready = C.c_int32()
+    ids_np = np.asarray(ids, np.int32)
+    work_np = np.asarray([c["N"] * c["H"] for c in fleet], np.int64)
+    id2robot = np.full(int(ids_np.max()) + 1, -1, np.int64)
+    id2robot[ids_np] = np.arange(robots)
+    # every robot's input once, contiguous; a bulk submission gathers its rows
+    tin = binding.TickInput
+    all_in = (tin * robots)(*inputs)
+    all_np = np.frombuffer(all_in, np.uint8).reshape(robots, C.sizeof(tin))
+    sub_in = (tin * robots)()
+    sub_np = np.frombuffer(sub_in, np.uint8).reshape(robots, C.sizeof(tin))
+    sub_ids = np.zeros(robots, np.int32)
+    sub_tk = np.zeros(robots, np.uint64)
     # untimed warm-up: every robot's first ticks
     for _ in range(warmup_ticks):
         tks = [rt.submit_tick(cid, workloads.tick_input(workloads.initial_state(
@@ -597,32 +621,45 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
         rt.timing()
         for f in range(4):
             rt.timing_rollout(f)
-    pending = {}
-    lat, done_work = [], 0
+    lat, done_work, n_pending = [], 0, 0
     t_start = time.perf_counter_ns()
     t_end = t_start + int(duration * 1e9)
-    idle = list(range(robots))
-    while time.perf_counter_ns() < t_end or pending:
-        if time.perf_counter_ns() < t_end:
-            still = []
-            for r in idle:
-                rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
-                if rc == binding.ENOMEM and mode == "direct":
-                    still.append(r)
-                    continue
-                binding._check(rc)
-                pending[tk.value] = r
-            idle = still
+    idle = np.arange(robots)
+    while time.perf_counter_ns() < t_end or n_pending:
+        if len(idle) and time.perf_counter_ns() < t_end:
+            if mode == "serving":
+                n = len(idle)
+                sub_np[:n] = all_np[idle]
+                sub_ids[:n] = ids_np[idle]
+                binding._check(L.sbs_submit_batch(
+                    rt._h, n, sub_ids.ctypes.data_as(C.POINTER(C.c_int32)), sub_in,
+                    sub_tk.ctypes.data_as(C.POINTER(C.c_uint64))))
+                n_pending += n
+                idle = idle[:0]
+            else:
+                still = []
+                for r in idle:
+                    rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(all_in[r]), C.byref(tk))
+                    if rc == binding.ENOMEM:  # retire finished ticks first
+                        still.append(r)
+                        continue
+                    binding._check(rc)
+                    n_pending += 1
+                idle = np.asarray(still, np.int64)
         binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), 0))
-        for i in range(nready.value):
-            r = pending.pop(rtk[i])
-            lat.append((racts[i].t_done_ns - racts[i].t_submit_ns) * 1e-6)
-            done_work += fleet[r]["N"] * fleet[r]["H"]
-            idle.append(r)
+        n = nready.value
+        if n:
+            a = acts[:n]
+            rob = id2robot[a["controller"]]
+            lat.append((a["t_done_ns"] - a["t_submit_ns"]) * 1e-6)
+            done_work += int(work_np[rob].sum())
+            idle = np.concatenate([idle, rob])
+            n_pending -= n
     torch.cuda.synchronize()
     elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    lat = np.concatenate(lat) if lat else np.zeros(1)
     stats = rt.stats()
-    out = {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
+    out = {"ticks": int(len(lat)), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
            "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
            "p99_ms": pct(lat, 99), "batches": stats["batches"]}
     if timing:
@@ -812,7 +849,8 @@ def main_c4(args):
         flop = fo["steps"] * per_step[f]
         roof = roofline_obj(
             names[f], flop, fo["avg_ns"], fo["launches"], flop_per_rollout_step=per_step[f],
-            traffic=stored_traffic("k_rollout", "c4"),
+            traffic=(stored_traffic("k_rollout", "c4", fo["steps"] / max(1, fo["launches"]))
+                     if f == 3 else None),
             timed_launches=fo["launches"], duration_us=fo["avg_ns"] * 1e-3,
             rollout_steps_per_launch=fo["steps"] / max(1, fo["launches"]),
             flop_per_launch=flop / max(1, fo["launches"]),

@@ -985,6 +985,10 @@ void fail_request(sbs_runtime *rt, size_t i, int status) {
   rt->cv.notify_all();
 }
 
+// Scheduler poll interval when nothing can be launched: the delay between a
+// batch's completion and the launch of the next one on its stream.
+constexpr int kSchedPollUs = 5;
+
 // Serving scheduler: continuous batching with memory admission.  Progress:
 // with no batch in flight the arena holds only persistent state, so a head
 // request that cannot be placed then can never be; its ticket fails with
@@ -1078,7 +1082,7 @@ void scheduler_loop(sbs_runtime *rt) {
     }
     // nothing to launch: poll briefly (completion detection latency)
     lk.unlock();
-    std::this_thread::sleep_for(std::chrono::microseconds(20));
+    std::this_thread::sleep_for(std::chrono::microseconds(kSchedPollUs));
     lk.lock();
   }
 }
