@@ -246,6 +246,8 @@ def main():
                          "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
+    ap.add_argument("--depth", type=int, default=1,
+                    help="c4: serving batches in flight per stream (sbs_set_serving_depth)")
     ap.add_argument("--phase", default="all", choices=["all", "saturated"],
                     help="c4: 'saturated' runs only the saturated serving stream, with HIP "
                          "events on every rollout launch and no warm-up, and prints each "
@@ -515,7 +517,8 @@ def fleet_inputs(binding, workloads, fleet, seed):
     return [binding.make_input(workloads.tick_input(workloads.initial_state(rng))) for _ in fleet]
 
 
-def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2):
+def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2,
+                depth=1):
     """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
     ticks; serving mode batches whatever is admitted, direct mode runs every
     tick as its own launch sequence ("plain single MPPI").  A robot's tick
@@ -527,6 +530,8 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
     arrivals = workloads.c4_arrivals(robots=robots, duration_s=duration)
     rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode,
                          two_streams=(mode == "serving" and streams > 1))
+    if mode == "serving":
+        rt.set_serving_depth(depth)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 5)
     events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
@@ -573,7 +578,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
-                  warmup_ticks=0, streams=2):
+                  warmup_ticks=0, streams=2, depth=1):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
     form sustains, and their submit-to-done latency.  The serving client
@@ -589,6 +594,8 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     fleet = workloads.c4_fleet(robots=robots)
     rt = binding.Runtime(arena_bytes=arena_bytes, mode=mode,
                          two_streams=(mode == "serving" and streams > 1))
+    if mode == "serving":
+        rt.set_serving_depth(depth)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 6)
     L = binding.lib()
@@ -806,13 +813,14 @@ def main_c4_saturated(args, binding, workloads, arena):
     runtime's first one: a profiler's per-dispatch figures for the rollout
     kernels of this process cover exactly the launches counted here."""
     sat = saturated_run(binding, workloads, args.steps * STEP_S_SATURATED, "serving", arena,
-                        timing=3, streams=args.streams)
+                        timing=3, streams=args.streams, depth=args.depth)
     names = ["fp32_one_lane", "fp32_quad", "fp64", "fp32_one_lane_noise"]
     forms = {names[i]: {"launches": f["launches"], "rollout_steps": f["steps"],
                         "avg_us": f["avg_ns"] * 1e-3}
              for i, f in enumerate(sat.pop("rollout_forms")) if f["launches"]}
     print(json.dumps({"workload": "c4 saturated serving only", "steps": args.steps,
-                      "serving_streams": args.streams, "rollout_forms": forms,
+                      "serving_streams": args.streams, "serving_depth": args.depth,
+                      "rollout_forms": forms,
                       "saturated": sat}), flush=True)
 
 
@@ -828,12 +836,12 @@ def main_c4(args):
                       warmup_ticks=1)
     progress("50 Hz stream, continuous batching")
     serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena,
-                        streams=args.streams)
+                        streams=args.streams, depth=args.depth)
     progress(f"done: {serve['ticks']} ticks; 50 Hz stream, plain single MPPI")
     plain = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "direct", arena)
     progress(f"done: {plain['ticks']} ticks; saturated, continuous batching")
     sat = saturated_run(binding, workloads, K * STEP_S_SATURATED, "serving", arena,
-                        timing=args.timing, streams=args.streams)
+                        timing=args.timing, streams=args.streams, depth=args.depth)
     progress(f"done: {sat['ticks']} ticks; saturated, plain single MPPI")
     sat_plain = saturated_run(binding, workloads, K * STEP_S_SATURATED, "direct", arena)
     progress(f"done: {sat_plain['ticks']} ticks")
@@ -879,7 +887,7 @@ def main_c4(args):
                                "per robot, continuous batching vs plain single MPPI",
                    "robots": 256, "stream_s_50hz": K * STEP_S_ARRIVALS,
                    "stream_s_saturated": K * STEP_S_SATURATED, "arena_gb": args.arena_gb,
-                   "serving_streams": args.streams},
+                   "serving_streams": args.streams, "serving_depth": args.depth},
         "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"],
                        "what": "arrival to completion, 50 Hz Poisson stream, continuous batching"},
         "vs_plain": {"throughput_saturated_x": sat["rollout_steps_per_s"] /

@@ -294,6 +294,14 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
  * setting it was created with. */
 int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout);
 
+/* Serving mode: batches the scheduler keeps in flight per stream (1 to 4,
+ * default 1).  With one stream and depth 2 the next batch is formed and
+ * enqueued while the current one runs, so batches run back to back and
+ * each has the device to itself; with two streams and depth 1 consecutive
+ * batches overlap.  Each batch in flight holds its own step workspace in the
+ * arena.  SBS_EINVAL for a null runtime or a depth outside 1..4. */
+int sbs_set_serving_depth(sbs_runtime *rt, int32_t depth);
+
 /* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
  * rollout kernel's own start and end (events carried by its dispatch) on
  * one launch in 16, counted from this call; 2 event commands between every

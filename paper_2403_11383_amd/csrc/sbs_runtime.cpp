@@ -377,6 +377,7 @@ struct sbs_runtime {
   Carver host_alloc;
   hipStream_t streams[2] = {nullptr, nullptr};
   int nstreams = 1;
+  int slot_depth = 1;  // serving: batches in flight per stream
   int mode = SBS_MODE_DIRECT;
   int32_t next_id = 0;
   std::unordered_map<int32_t, Controller> ctrls;
@@ -999,13 +1000,15 @@ void scheduler_loop(sbs_runtime *rt) {
   while (!rt->stop.load()) {
     int retired = reap(rt);
     if (retired) rt->cv.notify_all();
-    // a free stream slot?
+    // a stream with room for another batch (the least busy one)?
     int slot = -1;
-    for (int s = 0; s < rt->nstreams; ++s)
-      if (slot_busy(rt, s) == 0) {
+    for (int s = 0, least = rt->slot_depth; s < rt->nstreams; ++s) {
+      const int busy = slot_busy(rt, s);
+      if (busy < least) {
+        least = busy;
         slot = s;
-        break;
       }
+    }
     if (slot >= 0 && !rt->pending.empty()) {
       // admit in arrival order: one tick per controller per batch, skip
       // controllers with a tick in flight (their next tick needs the warm
@@ -1741,6 +1744,14 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
   rt->tune.pairs = enable != 0;
+  return SBS_OK;
+}
+
+int sbs_set_serving_depth(sbs_runtime *rt, int32_t depth) {
+  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
+  if (depth < 1 || depth > 4) return fail(SBS_EINVAL, "serving depth must be 1 to 4");
+  std::lock_guard<std::mutex> lk(rt->mu);
+  rt->slot_depth = depth;
   return SBS_OK;
 }
 
