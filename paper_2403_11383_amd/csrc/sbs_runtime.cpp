@@ -101,6 +101,15 @@ int scratch_address(int device, char **out) {
 // noise rows per thread of a single controller's ahead-of-time noise
 constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2, 58.9, 58.1, 71.9 us per tick
 
+// With several batches in flight per stream the next batch is formed as late
+// as keeps the stream busy: when the batches ahead of it are estimated to
+// end within kJitMarginNs (the host's batch assembly and launch fit in it),
+// so that it takes every request submitted meanwhile.  The estimate uses
+// the device rate of retired batches of at least kJitMinSteps rollout-steps.
+constexpr int64_t kJitMarginNs = 150000;
+constexpr double kJitMinSteps = 1e6;
+constexpr int64_t kDispatchNs = 20000;  // launch to device start of an idle stream
+
 // Rollout form: lanes per sample (0 = automatic), workgroup size, step-loop
 // unroll.  Only the forms the kernel dispatcher instantiates are valid.
 struct Tune {
@@ -325,6 +334,7 @@ struct Batch {
   int id = 0;
   int stream_slot = 0;
   hipEvent_t done = nullptr;
+  hipEvent_t hdr = nullptr;  // header upload on the copy stream
   std::vector<uint64_t> tickets;
   std::vector<int32_t> ctrls;
   uint64_t ws_off = 0, ws_bytes = 0, host_off = 0, host_bytes = 0;
@@ -336,6 +346,10 @@ struct Batch {
   std::vector<std::pair<int, double>> timing_work;
   bool owns_memory = true;  // device workspace carved from the arena
   bool owns_host = true;    // pinned staging carved from the runtime's block
+  // serving schedule: rollout-steps of all iterations, and the estimated
+  // device start (host clock), re-anchored when the batch ahead retires
+  double steps = 0;
+  int64_t t_start_est = 0;
 };
 
 // Rollout forms told apart by the per-form timing accumulators.
@@ -378,6 +392,10 @@ struct sbs_runtime {
   hipStream_t streams[2] = {nullptr, nullptr};
   int nstreams = 1;
   int slot_depth = 1;  // serving: batches in flight per stream
+  // batch headers go up on their own stream, so that the copy runs while the
+  // batches ahead of it compute
+  hipStream_t copy_stream = nullptr;
+  double jit_rate = 0;  // rollout-steps per ns of retired batches (EMA), 0: none yet
   int mode = SBS_MODE_DIRECT;
   int32_t next_id = 0;
   std::unordered_map<int32_t, Controller> ctrls;
@@ -793,7 +811,9 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
     if (p != rt->plans.end()) p->second->busy = false;
   }
   give_event(rt, b.done);
+  give_event(rt, b.hdr);
   b.done = nullptr;
+  b.hdr = nullptr;
 }
 
 // Retire completed batches in launch order per stream.  Returns the number
@@ -803,7 +823,21 @@ int reap(sbs_runtime *rt) {
   for (auto it = rt->inflight.begin(); it != rt->inflight.end();) {
     hipError_t q = hipEventQuery((*it)->done);
     if (q == hipSuccess) {
-      finish_batch(rt, **it);
+      const int64_t t = now_ns();
+      Batch &b = **it;
+      // the device rate of large batches, and the start of the batch queued
+      // behind this one on its stream
+      const double dur = (double)(t - b.t_start_est);
+      if (b.steps >= kJitMinSteps && dur > 0) {
+        const double r = b.steps / dur;
+        rt->jit_rate = rt->jit_rate > 0 ? 0.8 * rt->jit_rate + 0.2 * r : r;
+      }
+      for (auto nx = std::next(it); nx != rt->inflight.end(); ++nx)
+        if ((*nx)->stream_slot == b.stream_slot) {
+          (*nx)->t_start_est = t;
+          break;
+        }
+      finish_batch(rt, b);
       it = rt->inflight.erase(it);
       ++n;
     } else {
@@ -859,10 +893,28 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   b->tickets = tks;
   b->ctrls = ids;
   b->done = take_event(rt);
+  for (const Controller *c : cs) b->steps += (double)c->cfg.N * c->cfg.H * c->cfg.iterations;
+  {
+    // device start: behind the last batch in flight on this stream, if any
+    int64_t start = now_ns() + kDispatchNs;
+    for (auto &ob : rt->inflight)
+      if (ob->stream_slot == slot && rt->jit_rate > 0)
+        start = std::max(start, ob->t_start_est + (int64_t)(ob->steps / rt->jit_rate));
+    b->t_start_est = start;
+  }
   // a single controller's descriptor travels in the kernel arguments; a
-  // batch's descriptors and block maps go up in one copy
+  // batch's descriptors and block maps go up in one copy, on the copy stream
+  // when there is one (it need not wait for the work ahead on the stream)
   TickDesc *inl = ids.size() == 1 ? reinterpret_cast<TickDesc *>(host + L.desc) : nullptr;
-  hipError_t e = inl ? hipSuccess : hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  hipError_t e = hipSuccess;
+  if (!inl && rt->copy_stream) {
+    b->hdr = take_event(rt);
+    e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, rt->copy_stream);
+    if (e == hipSuccess) e = hipEventRecord(b->hdr, rt->copy_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->hdr, 0);
+  } else if (!inl) {
+    e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, s);
+  }
   // noise prefetch (single controller, direct mode): read this tick's noise
   // from the buffer the previous submission filled ahead of time
   Controller *pc = nullptr;
@@ -938,11 +990,13 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   if (pc && e == hipSuccess) e = hipEventRecord(pc->pf_free[pbuf], s);
   if (pc && pc->cfg.iterations == 1 && e == hipSuccess) e = prefetch_next();
   if (e != hipSuccess) {
-    // the stream may still run what was enqueued: wait before freeing
+    // the streams may still run what was enqueued: wait before freeing
     (void)hipStreamSynchronize(s);
+    if (rt->copy_stream) (void)hipStreamSynchronize(rt->copy_stream);
     if (!scratch_dev) rt->dev_alloc.release(ws_off, L.total);
     rt->host_alloc.release(host_off, L.host_total);
     give_event(rt, b->done);
+    give_event(rt, b->hdr);
     for (auto ev : b->timing) give_timing_event(rt, ev);
     return fail(SBS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   }
@@ -1008,6 +1062,16 @@ void scheduler_loop(sbs_runtime *rt) {
         least = busy;
         slot = s;
       }
+    }
+    if (slot >= 0 && rt->slot_depth > 1 && rt->jit_rate > 0) {
+      // several batches per stream: hold the next one back while the work
+      // ahead of it on the stream keeps the device busy for longer than the
+      // margin
+      int64_t end = 0;
+      for (auto &ob : rt->inflight)
+        if (ob->stream_slot == slot)
+          end = std::max(end, ob->t_start_est + (int64_t)(ob->steps / rt->jit_rate));
+      if (end > 0 && now_ns() < end - kJitMarginNs) slot = -1;
     }
     if (slot >= 0 && !rt->pending.empty()) {
       // admit in arrival order: one tick per controller per batch, skip
@@ -1129,6 +1193,10 @@ int sbs_runtime_create(void *arena, uint64_t arena_bytes, void *stream, void *st
   rt->streams[1] = static_cast<hipStream_t>(stream2);
   rt->nstreams = stream2 ? 2 : 1;
   rt->mode = mode;
+  if (hipStreamCreateWithFlags(&rt->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipHostFree(rt->pinned);
+    return fail(SBS_EDEVICE, "copy stream creation failed");
+  }
   if (mode == SBS_MODE_SERVING) {
     sbs_runtime *raw = rt.get();
     rt->sched = std::thread([raw] { scheduler_loop(raw); });
@@ -1144,6 +1212,7 @@ int sbs_runtime_destroy(sbs_runtime *rt) {
     rt->sched.join();
   }
   for (int s = 0; s < rt->nstreams; ++s) (void)hipStreamSynchronize(rt->streams[s]);
+  if (rt->copy_stream) (void)hipStreamSynchronize(rt->copy_stream);
   {
     std::lock_guard<std::mutex> lk(rt->mu);
     reap(rt);
@@ -1155,6 +1224,7 @@ int sbs_runtime_destroy(sbs_runtime *rt) {
     for (auto e : rt->event_pool) (void)hipEventDestroy(e);
     for (auto e : rt->timing_pool) (void)hipEventDestroy(e);
   }
+  if (rt->copy_stream) (void)hipStreamDestroy(rt->copy_stream);
   (void)hipHostFree(rt->pinned);
   delete rt;
   return SBS_OK;
