@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--timing", type=int, default=1,
                     help="HIP events: 0 none, 1 the rollout kernel's own dispatch events on "
                          "one tick in 16, 2 event commands around every stage of every tick")
-    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
                     help="c4: streams the serving scheduler alternates batches on")
     ap.add_argument("--shadow-seconds", type=float, default=6.0,
                     help="c4: arrival-stream length of the pass that records the served ticks "
@@ -246,7 +246,7 @@ def main():
                          "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
-    ap.add_argument("--depth", type=int, default=1,
+    ap.add_argument("--depth", type=int, default=2,
                     help="c4: serving batches in flight per stream (sbs_set_serving_depth)")
     ap.add_argument("--phase", default="all", choices=["all", "saturated"],
                     help="c4: 'saturated' runs only the saturated serving stream, with HIP "
