@@ -62,6 +62,9 @@ FLOP_PER_SPLINE_KNOT = 24
 # counted.
 FLOP_PER_NOISE_ROW = 270
 FLOP_PER_ROLLOUT_STEP_WITH_NOISE = FLOP_PER_ROLLOUT_STEP + FLOP_PER_NOISE_ROW
+# a stance-pair rollout that draws only its stance legs' noise evaluates four
+# of the six pairs per step
+FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE = FLOP_PER_ROLLOUT_STEP + 4 * 45
 # MI355X FP32 vector peak as published (it counts packed FMAs: 256 CUs x 4
 # SIMDs x 16 lanes x 2 FLOP x 2 packed x 2.4 GHz) and the non-packed peak the
 # kernels can reach (they are built with packed FP32 off).
@@ -246,6 +249,10 @@ def main():
                          "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
+    ap.add_argument("--rollout-noise", type=int, default=2, choices=[0, 1, 2, 3],
+                    help="c4: sbs_set_rollout_noise mode (0 noise launch, 1 rows in the rollout, "
+                         "2 stance legs only where the previous tick weighed few samples, 3 "
+                         "stance legs only wherever the form allows)")
     ap.add_argument("--depth", type=int, default=2,
                     help="c4: serving batches in flight per stream (sbs_set_serving_depth)")
     ap.add_argument("--phase", default="all", choices=["all", "saturated"],
@@ -518,7 +525,7 @@ def fleet_inputs(binding, workloads, fleet, seed):
 
 
 def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2,
-                depth=1):
+                depth=1, noise=2):
     """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
     ticks; serving mode batches whatever is admitted, direct mode runs every
     tick as its own launch sequence ("plain single MPPI").  A robot's tick
@@ -532,6 +539,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
                          two_streams=(mode == "serving" and streams > 1))
     if mode == "serving":
         rt.set_serving_depth(depth)
+    rt.set_rollout_noise(noise)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 5)
     events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
@@ -578,7 +586,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
-                  warmup_ticks=0, streams=2, depth=1):
+                  warmup_ticks=0, streams=2, depth=1, noise=2):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
     form sustains, and their submit-to-done latency.  The serving client
@@ -596,6 +604,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
                          two_streams=(mode == "serving" and streams > 1))
     if mode == "serving":
         rt.set_serving_depth(depth)
+    rt.set_rollout_noise(noise)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 6)
     L = binding.lib()
@@ -626,7 +635,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     if timing:
         rt.set_timing(timing)
         rt.timing()
-        for f in range(4):
+        for f in range(N_FORMS):
             rt.timing_rollout(f)
     lat, done_work, n_pending = [], 0, 0
     t_start = time.perf_counter_ns()
@@ -670,7 +679,7 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
            "rollout_steps_per_s": done_work / elapsed, "p50_ms": pct(lat, 50),
            "p99_ms": pct(lat, 99), "batches": stats["batches"]}
     if timing:
-        out["rollout_forms"] = [rt.timing_rollout(f) for f in range(4)]
+        out["rollout_forms"] = [rt.timing_rollout(f) for f in range(N_FORMS)]
         out["event_overhead_ns"] = rt.timing_overhead_ns(64)
     rt.close()
     return out
@@ -808,18 +817,32 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+# Rollout forms of sbs_timing_rollout: name, algorithmic FLOP per rollout-step,
+# and the key of their stored HBM byte counts at C4
+FORM_NAMES = ["k_rollout<float> (one lane per sample)", "k_rollout_quad (four lanes per sample)",
+              "k_rollout<double>", "k_rollout<float> drawing its noise (one lane per sample)",
+              "k_rollout<float> drawing its stance legs' noise (one lane per sample)"]
+FORM_FLOP_PER_STEP = [FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP,
+                      FLOP_PER_ROLLOUT_STEP_WITH_NOISE, FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE]
+FORM_TRAFFIC_KEY = [None, None, None, "k_rollout", "k_rollout_stance_noise"]
+N_FORMS = len(FORM_NAMES)
+
+
 def main_c4_saturated(args, binding, workloads, arena):
     """Only the saturated serving stream, every rollout launch timed from the
     runtime's first one: a profiler's per-dispatch figures for the rollout
     kernels of this process cover exactly the launches counted here."""
     sat = saturated_run(binding, workloads, args.steps * STEP_S_SATURATED, "serving", arena,
-                        timing=3, streams=args.streams, depth=args.depth)
-    names = ["fp32_one_lane", "fp32_quad", "fp64", "fp32_one_lane_noise"]
+                        timing=3, streams=args.streams, depth=args.depth,
+                        noise=args.rollout_noise)
+    names = ["fp32_one_lane", "fp32_quad", "fp64", "fp32_one_lane_noise",
+             "fp32_one_lane_stance_noise"]
     forms = {names[i]: {"launches": f["launches"], "rollout_steps": f["steps"],
                         "avg_us": f["avg_ns"] * 1e-3}
              for i, f in enumerate(sat.pop("rollout_forms")) if f["launches"]}
     print(json.dumps({"workload": "c4 saturated serving only", "steps": args.steps,
                       "serving_streams": args.streams, "serving_depth": args.depth,
+                      "rollout_noise": args.rollout_noise,
                       "rollout_forms": forms,
                       "saturated": sat}), flush=True)
 
@@ -836,29 +859,28 @@ def main_c4(args):
                       warmup_ticks=1)
     progress("50 Hz stream, continuous batching")
     serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena,
-                        streams=args.streams, depth=args.depth)
+                        streams=args.streams, depth=args.depth, noise=args.rollout_noise)
     progress(f"done: {serve['ticks']} ticks; 50 Hz stream, plain single MPPI")
     plain = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "direct", arena)
     progress(f"done: {plain['ticks']} ticks; saturated, continuous batching")
     sat = saturated_run(binding, workloads, K * STEP_S_SATURATED, "serving", arena,
-                        timing=args.timing, streams=args.streams, depth=args.depth)
+                        timing=args.timing, streams=args.streams, depth=args.depth,
+                        noise=args.rollout_noise)
     progress(f"done: {sat['ticks']} ticks; saturated, plain single MPPI")
     sat_plain = saturated_run(binding, workloads, K * STEP_S_SATURATED, "direct", arena)
     progress(f"done: {sat_plain['ticks']} ticks")
     roof = None
     if args.timing and "rollout_forms" in sat:
         forms = sat["rollout_forms"]
-        names = ["k_rollout<float> (one lane per sample)", "k_rollout_quad (four lanes per sample)",
-                 "k_rollout<double>", "k_rollout<float> drawing its noise (one lane per sample)"]
-        per_step = [FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP,
-                    FLOP_PER_ROLLOUT_STEP_WITH_NOISE]
-        f = max(range(4), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
+        names = FORM_NAMES
+        per_step = FORM_FLOP_PER_STEP
+        f = max(range(N_FORMS), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
         fo = forms[f]
         flop = fo["steps"] * per_step[f]
         roof = roofline_obj(
             names[f], flop, fo["avg_ns"], fo["launches"], flop_per_rollout_step=per_step[f],
-            traffic=(stored_traffic("k_rollout", "c4", fo["steps"] / max(1, fo["launches"]))
-                     if f == 3 else None),
+            traffic=(stored_traffic(FORM_TRAFFIC_KEY[f], "c4", fo["steps"] / max(1, fo["launches"]))
+                     if FORM_TRAFFIC_KEY[f] else None),
             timed_launches=fo["launches"], duration_us=fo["avg_ns"] * 1e-3,
             rollout_steps_per_launch=fo["steps"] / max(1, fo["launches"]),
             flop_per_launch=flop / max(1, fo["launches"]),
@@ -867,7 +889,7 @@ def main_c4(args):
                                     "duration_us": forms[i]["avg_ns"] * 1e-3,
                                     "rollout_steps_per_launch":
                                         forms[i]["steps"] / max(1, forms[i]["launches"])}
-                         for i in range(4) if i != f and forms[i]["launches"]})
+                         for i in range(N_FORMS) if i != f and forms[i]["launches"]})
         del sat["rollout_forms"]
     c = workloads.config("c4")
     line = {
@@ -887,7 +909,8 @@ def main_c4(args):
                                "per robot, continuous batching vs plain single MPPI",
                    "robots": 256, "stream_s_50hz": K * STEP_S_ARRIVALS,
                    "stream_s_saturated": K * STEP_S_SATURATED, "arena_gb": args.arena_gb,
-                   "serving_streams": args.streams, "serving_depth": args.depth},
+                   "serving_streams": args.streams, "serving_depth": args.depth,
+                   "rollout_noise": args.rollout_noise},
         "latency_ms": {"p50": serve["p50_ms"], "p99": serve["p99_ms"],
                        "what": "arrival to completion, 50 Hz Poisson stream, continuous batching"},
         "vs_plain": {"throughput_saturated_x": sat["rollout_steps_per_s"] /

@@ -285,14 +285,21 @@ int sbs_set_rollout_lanes(sbs_runtime *rt, int32_t lanes);
  * keeps the setting it was created with. */
 int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
 
-/* Noise made inside the rollout (default on): a one-lane FP32 rollout of
- * per-step GRFs draws each step's noise row itself (the same counter-based
- * values, Alg. 1 Sampling) and stores it for the update, instead of a
- * separate noise launch whose rows it reads back.  0 restores the separate
- * launch.  Results are the same either way; the switch is for verification
- * and timing.  Takes effect at the next submission; a plan keeps the
- * setting it was created with. */
-int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout);
+/* Noise made inside the rollout (Alg. 1 Sampling; the same counter-based
+ * values in every mode).  mode 0: a separate noise launch writes every row
+ * and the rollout reads it back.  1: a one-lane FP32 rollout of per-step
+ * GRFs draws each step's row itself and stores it for the update.  2
+ * (default): as 1, except that an MPPI controller in the stance-pair form
+ * (diagonal trot at duty 1/2, N at most 16384) whose previous tick weighed
+ * at most 32 samples draws only its two stance legs' GRF components -- the
+ * only ones the rollout uses -- and stores nothing; the MPPI update then
+ * draws the rows of the samples it weighs (a tick that weighs many more
+ * samples still gives the same result, more slowly).  Plans take mode 1 in
+ * place of 2.  3: as 2 whatever the previous tick weighed, plans included
+ * (for verification).  Results are the same in every mode.  Takes effect
+ * at the next submission; a plan keeps the setting it was created with.
+ * SBS_EINVAL for a null runtime or a mode outside 0..3. */
+int sbs_set_rollout_noise(sbs_runtime *rt, int32_t mode);
 
 /* Serving mode: batches the scheduler keeps in flight per stream (1 to 4,
  * default 1).  With one stream and depth 2 the next batch is formed and
@@ -314,13 +321,14 @@ int sbs_set_timing(sbs_runtime *rt, int32_t mode);
 int sbs_timing(sbs_runtime *rt, double *avg_ns, uint64_t *launches);
 /* Rollout timing by form (modes 1 and 3): form 0 FP32 one lane per sample,
  * 1 FP32 four lanes per sample, 2 FP64, 3 FP32 one lane per sample making
- * its own noise (sbs_set_rollout_noise).  Returns the average device time
+ * its own noise rows, 4 FP32 one lane per sample making its stance legs'
+ * noise only (sbs_set_rollout_noise).  Returns the average device time
  * [ns] of that form's timed rollout launches since the last call for the
  * form, their number and the rollout-steps (sum of N H over the launches'
  * controllers) they covered, and resets the form's accumulators.  The
  * algorithmic FLOP rate of the rollout (Alg. 2) is then
  * flop_per_step * steps / (avg_ns * launches).  SBS_EINVAL for a null
- * runtime or a form outside 0..3. */
+ * runtime or a form outside 0..4. */
 int sbs_timing_rollout(sbs_runtime *rt, int32_t form, double *avg_ns, uint64_t *launches,
                        double *steps);
 /* Fixed overhead of dispatch-carried timing events: the average interval [ns]

@@ -453,10 +453,16 @@ class Runtime:
         """Stance-pair one-lane rollouts for the diagonal trot at duty 1/2."""
         _check(lib().sbs_set_rollout_pairs(self._h, 1 if on else 0))
 
-    def set_rollout_noise(self, in_rollout: bool = True):
-        """One-lane FP32 rollouts make their own noise (True) or read it from
-        a separate noise launch (False)."""
-        _check(lib().sbs_set_rollout_noise(self._h, 1 if in_rollout else 0))
+    def set_rollout_noise(self, mode=2):
+        """Where the noise is made (sbs_set_rollout_noise): 0 (or False) a
+        separate noise launch, 1 every row in the rollout, 2 (or True, the
+        default) the stance legs' only where the previous tick weighed few
+        samples, 3 the stance legs' only wherever the form allows."""
+        if mode is True:
+            mode = 2
+        elif mode is False:
+            mode = 0
+        _check(lib().sbs_set_rollout_noise(self._h, int(mode)))
 
     def set_serving_depth(self, depth: int):
         """Serving: batches in flight per stream (1 to 4)."""
@@ -471,9 +477,10 @@ class Runtime:
 
     def timing_rollout(self, form: int):
         """Timed rollout launches of one form (0 FP32 one lane, 1 FP32 four
-        lanes, 2 FP64, 3 FP32 one lane drawing its noise) since the last
-        call: average device time [ns], number of launches and the
-        rollout-steps they covered."""
+        lanes, 2 FP64, 3 FP32 one lane drawing its noise rows, 4 FP32 one
+        lane drawing its stance legs' noise) since the last call: average
+        device time [ns], number of launches and the rollout-steps they
+        covered."""
         avg, n, st = C.c_double(), C.c_uint64(), C.c_double()
         _check(lib().sbs_timing_rollout(self._h, int(form), C.byref(avg), C.byref(n), C.byref(st)))
         return {"avg_ns": avg.value, "launches": n.value, "steps": st.value}

@@ -116,8 +116,11 @@ struct LaunchTab {
   int32_t spline;        // the items use the spline parametrisation
   int32_t noise_rpt;     // noise rows per thread (single-controller launches; 0 = 1)
   int32_t upd_chunk;     // mean rows per update workgroup (0 or 1: one)
-  int32_t gen_noise;     // the one-lane FP32 rollout makes and stores the noise itself
-                         // (no noise launch; per-step GRFs only)
+  int32_t gen_noise;     // the one-lane FP32 rollout makes the noise itself (no noise
+                         // launch; per-step GRFs only): 1 every row, stored for the
+                         // update; 2 (stance-pair form, MPPI items) only the stance
+                         // legs' Gaussians, nothing stored: the MPPI update makes the
+                         // rows it reads
   int32_t pairs;         // one-lane rollouts in the stance-pair form: every item is a
                          // diagonal trot at duty 1/2 (one of the leg pairs {0, 3},
                          // {1, 2} in stance at every step)

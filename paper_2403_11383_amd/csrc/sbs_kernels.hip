@@ -220,6 +220,24 @@ __device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
   return freq_gaussian(mf, sf, gauss_pair(c0, c1).x, d.f_min, d.f_max, d.dt);
 }
 
+// Noise row j of sample k in iteration r: the 12 Gaussians of the GRF
+// dimensions, from Philox calls 0..2 of the counter (k, j, tick, (r << 8) |
+// call), dimensions 4 call .. 4 call + 3 from its four words.
+__device__ __forceinline__ void noise_row(uint32_t key0, uint32_t key1, uint32_t rw,
+                                          uint32_t tick, uint32_t k, uint32_t j, float z[12]) {
+#pragma unroll
+  for (uint32_t call = 0; call < 3; ++call) {
+    uint32_t c0 = k, c1 = j, c2 = tick, c3 = rw | call;
+    philox4x32_10(c0, c1, c2, c3, key0, key1);
+    const float2 ga = gauss_pair(c0, c1);
+    const float2 gb = gauss_pair(c2, c3);
+    z[4 * call + 0] = ga.x;
+    z[4 * call + 1] = ga.y;
+    z[4 * call + 2] = gb.x;
+    z[4 * call + 3] = gb.y;
+  }
+}
+
 // GRF noise of iterations tab.r .. tab.r + tab.r_count - 1: one thread per
 // (iteration, row j, sample k), a row being a step or a spline knot;
 // iteration r lands at z + r * z_iter_stride.  The noise depends only on
@@ -251,17 +269,7 @@ __global__ void __launch_bounds__(kNoiseBlock) k_noise(LaunchTab tab, TickDesc i
   const int j0 = jb * rpt, j1 = j0 + rpt < d.M ? j0 + rpt : d.M;
   for (int j = j0; j < j1; ++j) {
     float z[12];
-#pragma unroll
-    for (uint32_t call = 0; call < 3; ++call) {
-      uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = tick, c3 = rw | call;
-      philox4x32_10(c0, c1, c2, c3, key0, key1);
-      const float2 ga = gauss_pair(c0, c1);
-      const float2 gb = gauss_pair(c2, c3);
-      z[4 * call + 0] = ga.x;
-      z[4 * call + 1] = ga.y;
-      z[4 * call + 2] = gb.x;
-      z[4 * call + 3] = gb.y;
-    }
+    noise_row(key0, key1, rw, tick, (uint32_t)k, (uint32_t)j, z);
     float4 *dst = reinterpret_cast<float4 *>(zr + ((size_t)j * N + k) * 12);
     dst[0] = make_float4(z[0], z[1], z[2], z[3]);
     dst[1] = make_float4(z[4], z[5], z[6], z[7]);
@@ -592,10 +600,14 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
 // GEN (FP32, per-step GRFs): the rollout makes its sample's noise itself,
-// row j at step j with the noise kernel's own Philox counter and transform,
-// and stores it for the update instead of reading it: the same values, one
-// launch and a 48-B read per rollout-step fewer.
-template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR, bool GEN = false>
+// with the noise kernel's own Philox counter and transform.  GEN 1: all of
+// row j at step j, stored for the update instead of read: the same values,
+// one launch and a 48-B read per rollout-step fewer.  GEN 2 (stance-pair
+// form, MPPI): only the Gaussians of the two stance legs' six GRF
+// components -- four of the row's six Box-Muller pairs, from two or three
+// of its Philox calls -- and nothing stored; the MPPI update makes the rows
+// of the samples it weighs (noise_row, the same values).
+template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR, int GEN = 0>
 __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
   const int b = blockIdx.x;
@@ -659,6 +671,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   T J = T(0), Jc = T(0), tj = T(0);
 
   static_assert(!GEN || (!SPL && sizeof(T) == 4), "noise made in the rollout: FP32 per-step GRFs");
+  static_assert(GEN != 2 || PAIR, "stance legs' noise only: stance-pair form");
   const float4 *zp =
       reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
   const size_t zstride = (size_t)N * 3;  // float4 per row
@@ -712,6 +725,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 #pragma unroll UNROLL
     for (int j = 0; j < H; ++j) {
       T u[12];
+      T ulo[3], uhi[3];  // GEN 2: the stance legs' GRFs (lower-, higher-indexed leg)
       if constexpr (SPL) {
         while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
           const int p = wb + 4;
@@ -734,19 +748,38 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
 #pragma unroll
         for (int i = 0; i < 12; ++i)
           u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
-      } else if constexpr (GEN) {
-        float zz[12];
-#pragma unroll
-        for (uint32_t call = 0; call < 3; ++call) {
-          uint32_t c0 = (uint32_t)k, c1 = (uint32_t)j, c2 = tick, c3 = rw | call;
-          philox4x32_10(c0, c1, c2, c3, key0, key1);
-          const float2 ga = gauss_pair(c0, c1);
-          const float2 gb = gauss_pair(c2, c3);
-          zz[4 * call + 0] = ga.x;
-          zz[4 * call + 1] = ga.y;
-          zz[4 * call + 2] = gb.x;
-          zz[4 * call + 3] = gb.y;
+      } else if constexpr (GEN == 2) {
+        // the stance pair's GRF dimensions: pair A (legs 0, 3) dims 0-2 and
+        // 9-11 from calls 0 and 2; pair B (legs 1, 2) dims 3-8 from calls
+        // 0, 1 and 2.  Four Box-Muller slots per lane, fed the words of the
+        // pairs its stance legs need (the pair of dims 2, 3 serves dim 2 of
+        // leg 0 or dim 3 of leg 1, that of dims 8, 9 dim 9 or dim 8); call 1
+        // runs only where a lane of the wave has pair B in stance.
+        const bool sA = duty_full || (ph[0] < duty_q);
+        uint32_t a0 = (uint32_t)k, a1 = (uint32_t)j, a2 = tick, a3 = rw;
+        philox4x32_10(a0, a1, a2, a3, key0, key1);
+        uint32_t b0 = (uint32_t)k, b1 = (uint32_t)j, b2 = tick, b3 = rw | 2u;
+        philox4x32_10(b0, b1, b2, b3, key0, key1);
+        uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+        if (__any(!sA)) {
+          m0 = (uint32_t)k; m1 = (uint32_t)j; m2 = tick; m3 = rw | 1u;
+          philox4x32_10(m0, m1, m2, m3, key0, key1);
         }
+        const float2 g0 = gauss_pair(sA ? a0 : a2, sA ? a1 : a3);  // dims 0,1 | 2,3
+        const float2 g1 = gauss_pair(sA ? a2 : m0, sA ? a3 : m1);  // dims 2,3 | 4,5
+        const float2 g2 = gauss_pair(sA ? b0 : m2, sA ? b1 : m3);  // dims 8,9 | 6,7
+        const float2 g3 = gauss_pair(sA ? b2 : b0, sA ? b3 : b1);  // dims 10,11 | 8,9
+        const float zl[3] = {sA ? g0.x : g0.y, sA ? g0.y : g1.x, sA ? g1.x : g1.y};
+        const float zh[3] = {sA ? g2.y : g2.x, sA ? g3.x : g2.y, sA ? g3.y : g3.x};
+        const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          ulo[i] = s_mu[bl + i] + s_sig[bl + i] * (T)zl[i];
+          uhi[i] = s_mu[bh + i] + s_sig[bh + i] * (T)zh[i];
+        }
+      } else if constexpr (GEN == 1) {
+        float zz[12];
+        noise_row(key0, key1, rw, tick, (uint32_t)k, (uint32_t)j, zz);
         float4 *dst = const_cast<float4 *>(zp) + (size_t)j * zstride;
         dst[0] = make_float4(zz[0], zz[1], zz[2], zz[3]);
         dst[1] = make_float4(zz[4], zz[5], zz[6], zz[7]);
@@ -805,8 +838,13 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
         T v0[3], v1[3], h0[3], h1[3], r0[3], r1[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          v0[i] = sA ? u[i] : u[3 + i];
-          v1[i] = sA ? u[9 + i] : u[6 + i];
+          if constexpr (GEN == 2) {
+            v0[i] = ulo[i];
+            v1[i] = uhi[i];
+          } else {
+            v0[i] = sA ? u[i] : u[3 + i];
+            v1[i] = sA ? u[9 + i] : u[6 + i];
+          }
           h0[i] = pc[i];
           r0[i] = pc[3 + i];
           h1[i] = pc[8 + i];
@@ -1729,6 +1767,18 @@ constexpr int kMppiPer = 16;
 // result depends only on the controller's own data, not on the batch.
 constexpr int kListCap = 2048;
 
+// Noise row j of sample k made again and stored where the rollout would have
+// stored it (z of iteration r: [M][N][12]).
+__device__ __forceinline__ void make_noise_row(const TickDesc &d, int r, uint32_t k, uint32_t j,
+                                               const float *zr) {
+  float z[12];
+  noise_row((uint32_t)d.seed, (uint32_t)(d.seed >> 32), (uint32_t)r << 8, d.tick, k, j, z);
+  float4 *dst = reinterpret_cast<float4 *>(const_cast<float *>(zr) + ((size_t)j * d.N + k) * 12);
+  dst[0] = make_float4(z[0], z[1], z[2], z[3]);
+  dst[1] = make_float4(z[4], z[5], z[6], z[7]);
+  dst[2] = make_float4(z[8], z[9], z[10], z[11]);
+}
+
 template <typename T, bool INL>
 __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[blockIdx.x]];
@@ -1861,6 +1911,14 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
       }
     }
     __syncthreads();
+    if (tab.gen_noise == 2) {
+      // the rollout stored no noise: the rows of the listed samples
+      for (uint32_t e = tid; e < total * (uint32_t)M; e += kMppiBlock) {
+        const uint32_t a = e / (uint32_t)M, j = e - a * (uint32_t)M;
+        make_noise_row(d, r, s_k[a], j, zr);
+      }
+      __syncthreads();
+    }
     double omega = 0.0;
     for (int i = 0; i < kW; ++i) omega += lds[i][12];
     for (int o = tid; o < M * 12; o += kMppiBlock) {
@@ -1877,6 +1935,15 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
       if (last_iter && d.dbg_mean) d.dbg_mean[o] = (double)stored;
     }
   } else {
+    if (tab.gen_noise == 2) {
+      // the rollout stored no noise and too many samples weigh for the
+      // list: every row (slow, and rare where the previous tick weighed few)
+      for (uint32_t e = tid; e < (uint32_t)N * (uint32_t)M; e += kMppiBlock) {
+        const uint32_t j = e / (uint32_t)N, k = e - j * (uint32_t)N;
+        make_noise_row(d, r, k, j, zr);
+      }
+      __syncthreads();
+    }
     for (int j = 0; j < M; ++j) {
       const float4 *zj = reinterpret_cast<const float4 *>(zr) + (size_t)j * N * 3;
       T f1[12];
@@ -1971,11 +2038,19 @@ static hipError_t launch_one_lane(const LaunchTab &tab, const TickDesc &inl, int
     return hipSuccess;
   }
   if constexpr (!SPL) {
+    if (tab.gen_noise == 2) {  // stance legs' noise only: stance-pair form, 256 lanes
+      if constexpr (PAIR) {
+        if (tab.roll_block != 256) return hipErrorInvalidValue;
+        launch_timed(k_rollout<float, 256, 1, INL, false, true, 2>, rg, dim3(256), lds, s, e0, e1, tab, inl);
+        return hipSuccess;
+      }
+      return hipErrorInvalidValue;
+    }
     if (tab.gen_noise) {  // the rollout makes the noise (one-row loops only)
       switch (tab.roll_block) {
-        case 64: launch_timed(k_rollout<float, 64, 1, INL, false, PAIR, true>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
-        case 128: launch_timed(k_rollout<float, 128, 1, INL, false, PAIR, true>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
-        case 256: launch_timed(k_rollout<float, 256, 1, INL, false, PAIR, true>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
+        case 64: launch_timed(k_rollout<float, 64, 1, INL, false, PAIR, 1>, rg, dim3(64), lds, s, e0, e1, tab, inl); break;
+        case 128: launch_timed(k_rollout<float, 128, 1, INL, false, PAIR, 1>, rg, dim3(128), lds, s, e0, e1, tab, inl); break;
+        case 256: launch_timed(k_rollout<float, 256, 1, INL, false, PAIR, 1>, rg, dim3(256), lds, s, e0, e1, tab, inl); break;
         default: return hipErrorInvalidValue;
       }
       return hipSuccess;

@@ -109,6 +109,14 @@ constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2,
 constexpr int64_t kJitMarginNs = 150000;
 constexpr double kJitMinSteps = 1e6;
 constexpr int64_t kDispatchNs = 20000;  // launch to device start of an idle stream
+// A rollout that makes only the stance legs' noise leaves the MPPI update to
+// make the rows of the samples it weighs: cheap for a few samples (each row
+// is three Philox calls and six Box-Muller pairs in one workgroup); the form
+// is chosen where the controller's previous tick weighed at most this many.
+constexpr uint32_t kStanceMaxActive = 32;
+// MPPI costs the update holds in registers (16 per thread of 1024): the
+// list of weighed samples needs all of them there.
+constexpr int kMppiRegN = 16 * 1024;
 
 // Rollout form: lanes per sample (0 = automatic), workgroup size, step-loop
 // unroll.  Only the forms the kernel dispatcher instantiates are valid.
@@ -117,7 +125,12 @@ struct Tune {
   int block = 256;  // four waves per workgroup: measured faster than 64 or 128 at C1
   int unroll = 1;
   bool pairs = true;  // stance-pair one-lane rollouts where the gait allows
-  bool gen = true;    // one-lane FP32 per-step rollouts make their own noise
+  // one-lane FP32 per-step rollouts make their own noise: 0 no (a noise
+  // launch), 1 every row, 2 only the stance legs' Gaussians for MPPI
+  // controllers in the stance-pair form whose previous tick weighed at most
+  // kStanceMaxActive samples (every row otherwise), 3 as 2 whatever the
+  // previous tick weighed
+  int gen = 2;
 };
 
 bool valid_form(int lanes, int block, int unroll) {
@@ -245,6 +258,7 @@ struct Controller {
   double *dbg_mean = nullptr;
   int inflight = 0;
   int plan = -1;
+  uint32_t last_active = 0xFFFFFFFFu;  // samples weighed in the last tick (unknown: max)
   // noise prefetch: two buffers of iterations x H x N x 12 floats; the next
   // tick's noise is written into the idle one on the second stream
   bool prefetch = false;
@@ -355,11 +369,12 @@ struct Batch {
 // Rollout forms told apart by the per-form timing accumulators.
 enum RollForm {
   FORM_FP32_ONE_LANE = 0, FORM_FP32_QUAD = 1, FORM_FP64 = 2, FORM_FP32_ONE_LANE_NOISE = 3,
-  kForms = 4
+  FORM_FP32_ONE_LANE_STANCE_NOISE = 4, kForms = 5
 };
 int roll_form(const LaunchTab &t, int precision) {
   if (precision == SBS_FP64) return FORM_FP64;
   if (t.lanes == 4) return FORM_FP32_QUAD;
+  if (t.gen_noise == 2) return FORM_FP32_ONE_LANE_STANCE_NOISE;
   return t.gen_noise ? FORM_FP32_ONE_LANE_NOISE : FORM_FP32_ONE_LANE;
 }
 
@@ -421,8 +436,8 @@ struct sbs_runtime {
   uint64_t stage_n[4] = {0, 0, 0, 0};
   // rollout timing per form (modes 1 and 3): device time, launches and
   // rollout-steps of the timed launches
-  double form_ns[4] = {0, 0, 0, 0}, form_steps[4] = {0, 0, 0, 0};
-  uint64_t form_n[4] = {0, 0, 0, 0};
+  double form_ns[5] = {0, 0, 0, 0, 0}, form_steps[5] = {0, 0, 0, 0, 0};
+  uint64_t form_n[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -510,6 +525,18 @@ bool pair_gait(const sbs_controller_cfg &c) {
   return std::rint(c.duty * 4294967296.0) == 2147483648.0 &&
          c.phase_offset[3] == o0 && c.phase_offset[1] == o0 + half &&
          c.phase_offset[2] == o0 + half;
+}
+
+// Whether a controller's one-lane FP32 rollout may make only its stance
+// legs' noise (the MPPI update then makes the rows it weighs).  `adaptive`:
+// the launch is built for this tick alone (not captured in a plan), so the
+// previous tick's count of weighed samples may decide.
+bool stance_noise(const Controller &C, const Tune &tn, bool adaptive) {
+  const sbs_controller_cfg &c = C.cfg;
+  if (tn.gen < 2 || !tn.pairs || c.precision != SBS_FP32 || c.knots > 0 ||
+      c.method != SBS_MPPI || c.N > kMppiRegN || !pair_gait(c))
+    return false;
+  return tn.gen == 3 || (adaptive && C.last_active <= kStanceMaxActive);
 }
 
 void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char *dev_item,
@@ -604,7 +631,7 @@ void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char
 }
 
 // Launch groups per iteration: precision x parametrisation x stance-pair form.
-constexpr int kGroups = 8;
+constexpr int kGroups = 16;
 
 // Byte offset of the first item workspace in a batch of n controllers with
 // at most rmax iterations: descriptors, then per (iteration, launch group)
@@ -647,7 +674,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
                                                    const std::vector<uint32_t> &ticks,
                                                    const Layout &L, char *host, char *dev,
                                                    char *host_dev, const Tune &tn,
-                                                   std::vector<double> *steps_out = nullptr) {
+                                                   std::vector<double> *steps_out = nullptr,
+                                                   bool adaptive = false) {
   const int n = (int)cs.size();
   int rmax = 1;
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
@@ -664,8 +692,9 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
   const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
   for (int r = 0; r < rmax; ++r) {
     for (int grp = 0; grp < kGroups; ++grp) {
-      // one launch per (precision, parametrisation, stance-pair form) group
-      const int prec = grp >> 2, spl = (grp >> 1) & 1, pair = grp & 1;
+      // one launch per (precision, parametrisation, stance-pair form, noise
+      // of the stance legs only) group
+      const int prec = (grp >> 3) & 1, spl = (grp >> 2) & 1, pair = (grp >> 1) & 1, sto = grp & 1;
       const uint64_t off = L.tabs + ((uint64_t)r * kGroups + grp) * tab_bytes;
       int32_t *item = reinterpret_cast<int32_t *>(host + off);
       int32_t *ns = item + n, *rs = ns + (n + 1), *us = rs + (n + 1);
@@ -673,7 +702,8 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       std::vector<int> idx;
       for (int i = 0; i < n; ++i)
         if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec &&
-            (cs[i]->cfg.knots > 0 ? 1 : 0) == spl && ((tn.pairs && pair_gait(cs[i]->cfg)) ? 1 : 0) == pair)
+            (cs[i]->cfg.knots > 0 ? 1 : 0) == spl && ((tn.pairs && pair_gait(cs[i]->cfg)) ? 1 : 0) == pair &&
+            (stance_noise(*cs[i], tn, adaptive) ? 1 : 0) == sto)
           idx.push_back(i);
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
@@ -727,6 +757,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.pairs = pair;
       tab.upd_chunk = chunk;
       tab.gen_noise = (tn.gen && prec == SBS_FP32 && lanes == 1 && !spl && unroll == 1) ? 1 : 0;
+      if (tab.gen_noise && sto && pair && block == 256) tab.gen_noise = 2;
       tab.roll_block = block;
       tab.unroll = unroll;
       tab.r_count = 1;
@@ -797,7 +828,11 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
     }
     if (it != rt->tickets.end()) it->second.rec = nullptr;  // the record is released below
     auto c = rt->ctrls.find(b.ctrls[i]);
-    if (c != rt->ctrls.end()) c->second.inflight -= 1;
+    if (c != rt->ctrls.end()) {
+      c->second.inflight -= 1;
+      const double na = b.host_results[i * kResultDoubles + RES_NACT];
+      c->second.last_active = (na >= 0 && na < 4e9) ? (uint32_t)na : 0xFFFFFFFFu;
+    }
   }
   if (rt->timing) record_timing(rt, b);
   else {
@@ -879,7 +914,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
   std::vector<double> tab_steps;
   auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off, rt->tune,
-                          &tab_steps);
+                          &tab_steps, true);
   hipStream_t s = rt->streams[slot];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -1828,7 +1863,8 @@ int sbs_set_serving_depth(sbs_runtime *rt, int32_t depth) {
 int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
-  rt->tune.gen = in_rollout != 0;
+  if (in_rollout < 0 || in_rollout > 3) return fail(SBS_EINVAL, "rollout noise mode must be 0 to 3");
+  rt->tune.gen = in_rollout;
   return SBS_OK;
 }
 

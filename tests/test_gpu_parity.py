@@ -356,36 +356,56 @@ def test_stance_pair_form_equals_four_leg_form(rt, precision):
 
 
 def test_noise_made_in_rollout_equals_noise_launch(rt):
-    """One-lane FP32 rollouts that make their noise rows themselves store
-    exactly the rows the noise kernel writes and compute the same costs:
-    every cost, sampled increment, action and updated mean is bit-equal to
-    the separate noise launch (MPPI, elite with three iterations whose
-    update reads the stored rows, stance-pair and four-leg gaits, a batch)."""
+    """One-lane FP32 rollouts that make their noise themselves compute exactly
+    what the separate noise launch gives: every cost, sampled increment,
+    action and updated mean is bit-equal, over two consecutive ticks (the
+    second one warm-started), in every mode of sbs_set_rollout_noise -- every
+    row stored by the rollout (1); only the stance legs' Gaussians drawn in
+    the rollout and the rows of the weighed samples drawn by the MPPI update
+    (3 everywhere the form allows, 2 where the previous tick weighed few
+    samples).  Cases: MPPI with few and with all samples weighed (lambda 1e9:
+    more than the update's list holds, so it draws every row), an elite
+    controller with three iterations whose update reads the stored rows, a
+    four-leg gait and a batch of them all."""
     cfgs = [workloads.config("c1", N=3000, H=50, seed=81),
             workloads.config("c2", N=2500, H=30, seed=82),
-            workloads.config("c1", N=1200, H=20, seed=83, duty=0.6)]  # four-leg form
+            workloads.config("c1", N=1200, H=20, seed=83, duty=0.6),  # four-leg form
+            workloads.config("c4", N=2600, H=12, seed=85, **{"lambda": 1e9}),
+            workloads.config("c4", N=2048, H=25, seed=86)]
     rng = np.random.default_rng(84)
     inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
     rt.set_rollout_lanes(1)
     try:
         res = {}
-        for gen in (True, False):
-            rt.set_rollout_noise(gen)
+        for mode in (0, 1, 2, 3):
+            rt.set_rollout_noise(mode)
             ids = [rt.init_controller(c) for c in cfgs]
             for cid in ids:
                 rt.set_debug(cid, True)
-            acts = [rt.fetch(t) for t in rt.submit_batch(ids, inps)]
-            res[gen] = [(a, rt.debug_fetch(cid), rt.get_state(cid)[0]) for a, cid in zip(acts, ids)]
+            out = []
+            for _ in range(2):
+                acts = [rt.fetch(t) for t in rt.submit_batch(ids, inps)]
+                out.append([(a, rt.debug_fetch(cid), rt.get_state(cid)[0])
+                            for a, cid in zip(acts, ids)])
+            res[mode] = out
             for cid in ids:
                 rt.destroy_controller(cid)
-        for (a1, (J1, q1, m1), mu1), (a0, (J0, q0, m0), mu0) in zip(res[True], res[False]):
-            np.testing.assert_array_equal(q1, q0)
-            np.testing.assert_array_equal(J1, J0)
-            np.testing.assert_array_equal(a1["grf"], a0["grf"])
-            np.testing.assert_array_equal(m1, m0)
-            np.testing.assert_array_equal(mu1, mu0)
+        for mode in (1, 2, 3):
+            for tick in range(2):
+                for c, ((a1, (J1, q1, m1), mu1), (a0, (J0, q0, m0), mu0)) in enumerate(
+                        zip(res[mode][tick], res[0][tick])):
+                    where = (mode, tick, c)
+                    np.testing.assert_array_equal(q1, q0, err_msg=str(where))
+                    np.testing.assert_array_equal(J1, J0, err_msg=str(where))
+                    np.testing.assert_array_equal(a1["grf"], a0["grf"], err_msg=str(where))
+                    assert a1["n_active"] == a0["n_active"], where
+                    np.testing.assert_array_equal(m1, m0, err_msg=str(where))
+                    np.testing.assert_array_equal(mu1, mu0, err_msg=str(where))
+        # the lambda 1e9 controller weighs every sample, the last one few
+        assert res[3][0][3][0]["n_active"] > 2048
+        assert res[3][0][4][0]["n_active"] <= 32
     finally:
-        rt.set_rollout_noise(True)
+        rt.set_rollout_noise(2)
         rt.set_rollout_lanes(0)
 
 

@@ -74,10 +74,12 @@ def test_every_stage_is_built(metadata):
     for k in ("k_noise", "k_rollout", "k_rollout_quad", "k_select", "k_update", "k_update_mppi"):
         assert k in names, k
     # both one-lane forms: four legs masked by contact, and the stance pair
-    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb0ELb0E" in names
-    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb1ELb0E" in names
-    # and the stance-pair one-lane form that makes its own noise
-    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb1ELb1E" in names
+    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb0ELi0EE" in names
+    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi0EE" in names
+    # and the stance-pair one-lane forms that make their own noise: every
+    # row, and the stance legs' Gaussians only
+    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi1EE" in names
+    assert "k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi2EE" in names
 
 
 def test_no_scratch_and_no_vector_spills(metadata):
@@ -108,9 +110,10 @@ def test_noise_row_loop(compiled):
     assert sum(i == "v_bitop3_b32" for i in ins) >= 50  # 3 calls x 10 rounds x 2, a few folded
 
 
-@pytest.mark.parametrize("kernel,budget", [("k_rolloutIfLi256ELi1ELb0ELb0ELb0ELb0E", 535),
-                                           ("k_rolloutIfLi256ELi1ELb0ELb0ELb1ELb0E", 410),
-                                           ("k_rolloutIfLi256ELi1ELb0ELb0ELb1ELb1E", 980),
+@pytest.mark.parametrize("kernel,budget", [("k_rolloutIfLi256ELi1ELb0ELb0ELb0ELi0EE", 535),
+                                           ("k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi0EE", 410),
+                                           ("k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi1EE", 980),
+                                           ("k_rolloutIfLi256ELi1ELb0ELb0ELb1ELi2EE", 830),
                                            ("k_rollout_quadILi256ELi1ELb1ELb0E", 250)])
 def test_rollout_step_instruction_budget(compiled, kernel, budget):
     """Instructions in the step loop (scalar and memory ones included, both
@@ -118,8 +121,9 @@ def test_rollout_step_instruction_budget(compiled, kernel, budget):
     when any lane of the wave has a large angle, and the polynomial alone):
     526 for the one-lane four-leg form, 403 for the one-lane stance-pair
     form, 969 for the stance-pair form that also makes the step's noise
-    (three Philox calls, six Box-Muller pairs) and 245 for the quad form
-    when this was written; the budget catches a change that adds branches
+    (three Philox calls, six Box-Muller pairs), 821 for the stance-pair form
+    that makes only its stance legs' Gaussians (two or three Philox calls,
+    four pairs) and 245 for the quad form when this was written; the budget catches a change that adds branches
     or moves to the step."""
     ins = largest_loop(kernel_body(compiled["text"], kernel))
     assert ins and len(ins) <= budget, (kernel, len(ins))
