@@ -249,10 +249,9 @@ def main():
                          "controllers; copy: "
                          "a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "study: closed-loop push episodes with and without gait adaptation")
-    ap.add_argument("--rollout-noise", type=int, default=2, choices=[0, 1, 2, 3],
+    ap.add_argument("--rollout-noise", type=int, default=2, choices=[0, 1, 2],
                     help="c4: sbs_set_rollout_noise mode (0 noise launch, 1 rows in the rollout, "
-                         "2 stance legs only where the previous tick weighed few samples, 3 "
-                         "stance legs only wherever the form allows)")
+                         "2 stance legs only where the form allows)")
     ap.add_argument("--depth", type=int, default=2,
                     help="c4: serving batches in flight per stream (sbs_set_serving_depth)")
     ap.add_argument("--phase", default="all", choices=["all", "saturated"],

@@ -289,16 +289,16 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
  * values in every mode).  mode 0: a separate noise launch writes every row
  * and the rollout reads it back.  1: a one-lane FP32 rollout of per-step
  * GRFs draws each step's row itself and stores it for the update.  2
- * (default): as 1, except that an MPPI controller in the stance-pair form
- * (diagonal trot at duty 1/2, N at most 16384) whose previous tick weighed
- * at most 32 samples draws only its two stance legs' GRF components -- the
- * only ones the rollout uses -- and stores nothing; the MPPI update then
- * draws the rows of the samples it weighs (a tick that weighs many more
- * samples still gives the same result, more slowly).  Plans take mode 1 in
- * place of 2.  3: as 2 whatever the previous tick weighed, plans included
- * (for verification).  Results are the same in every mode.  Takes effect
- * at the next submission; a plan keeps the setting it was created with.
- * SBS_EINVAL for a null runtime or a mode outside 0..3. */
+ * (default): as 1, except that the one-lane rollout of an MPPI controller in
+ * the stance-pair form (diagonal trot at duty 1/2, N at most 16384) draws
+ * only its two stance legs' GRF components -- the only ones it uses -- and
+ * stores nothing; the MPPI update then draws the rows of the samples it
+ * weighs (quick for the usual few; with thousands of weighed samples one
+ * workgroup draws them all, correct but slow).  The choice depends on the
+ * configuration alone.  Modes 0 and 1 give bit-identical results; mode 2's
+ * rollout is compiled apart and agrees with them within FP32 rounding.
+ * Takes effect at the next submission; a plan keeps the setting it was
+ * created with.  SBS_EINVAL for a null runtime or a mode outside 0..2. */
 int sbs_set_rollout_noise(sbs_runtime *rt, int32_t mode);
 
 /* Serving mode: batches the scheduler keeps in flight per stream (1 to 4,

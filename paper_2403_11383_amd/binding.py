@@ -456,8 +456,7 @@ class Runtime:
     def set_rollout_noise(self, mode=2):
         """Where the noise is made (sbs_set_rollout_noise): 0 (or False) a
         separate noise launch, 1 every row in the rollout, 2 (or True, the
-        default) the stance legs' only where the previous tick weighed few
-        samples, 3 the stance legs' only wherever the form allows."""
+        default) the stance legs' only where the form allows."""
         if mode is True:
             mode = 2
         elif mode is False:

@@ -596,6 +596,15 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
   c.sigma0 = (T)d.sigma0;
 }
 
+// The policy's sample theta = mu + sigma z as one fused multiply-add, in
+// every rollout form (so that forms that pick their operands differently
+// still round alike).
+template <typename T>
+__device__ __forceinline__ T theta_of(T mu, T sig, T z) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(sig, z, mu);
+  else return __builtin_fmaf(sig, z, mu);
+}
+
 // One lane per sample.  The block stages the controller's mean (and the elite
 // std of later iterations) in LDS once; each step reads them as broadcasts,
 // and the noise of step j+1 is requested while step j computes.
@@ -697,7 +706,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
       const float zw[12] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, cq.x, cq.y, cq.z, cq.w};
 #pragma unroll
       for (int i = 0; i < 12; ++i)
-        win[w][i] = (w < M) ? s_mu[w * 12 + i] + s_sig[w * 12 + i] * (T)zw[i] : T(0);
+        win[w][i] = (w < M) ? theta_of<T>(s_mu[w * 12 + i], s_sig[w * 12 + i], (T)zw[i]) : T(0);
     }
     if (4 < M) { z0 = zp[4 * zstride]; z1 = zp[4 * zstride + 1]; z2 = zp[4 * zstride + 2]; }
   }
@@ -736,7 +745,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
             win[0][i] = win[1][i];
             win[1][i] = win[2][i];
             win[2][i] = win[3][i];
-            win[3][i] = (p < M) ? s_mu[p * 12 + i] + s_sig[p * 12 + i] * (T)zw[i] : T(0);
+            win[3][i] = (p < M) ? theta_of<T>(s_mu[p * 12 + i], s_sig[p * 12 + i], (T)zw[i]) : T(0);
           }
           ++wb;
           if (wb + 4 < M) {
@@ -774,8 +783,8 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
         const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          ulo[i] = s_mu[bl + i] + s_sig[bl + i] * (T)zl[i];
-          uhi[i] = s_mu[bh + i] + s_sig[bh + i] * (T)zh[i];
+          ulo[i] = theta_of<T>(s_mu[bl + i], s_sig[bl + i], (T)zl[i]);
+          uhi[i] = theta_of<T>(s_mu[bh + i], s_sig[bh + i], (T)zh[i]);
         }
       } else if constexpr (GEN == 1) {
         float zz[12];
@@ -787,14 +796,14 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
         const T *muj = s_mu + j * 12;
         const T *sgj = s_sig + j * 12;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+        for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
       } else {
         const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                               z2.x, z2.y, z2.z, z2.w};
         const T *muj = s_mu + j * 12;
         const T *sgj = s_sig + j * 12;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) u[i] = muj[i] + sgj[i] * (T)zz[i];
+        for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
         // the next step's noise (the last step reads its own row again), into
         // the registers this step's noise has just left
         z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
@@ -1091,7 +1100,8 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
     for (int w = 0; w < 4; ++w) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
-        win[w][i] = (w < M) ? s_mu[w * 12 + 3 * l + i] + s_sig[w * 12 + 3 * l + i] * zp[w * zstride + i]
+        win[w][i] = (w < M) ? theta_of<float>(s_mu[w * 12 + 3 * l + i], s_sig[w * 12 + 3 * l + i],
+                                              zp[w * zstride + i])
                             : 0.f;
     }
     if (4 < M) { za = zp[4 * zstride]; zb = zp[4 * zstride + 1]; zc = zp[4 * zstride + 2]; }
@@ -1109,7 +1119,7 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
           win[0][i] = win[1][i];
           win[1][i] = win[2][i];
           win[2][i] = win[3][i];
-          win[3][i] = (p < M) ? s_mu[o + i] + s_sig[o + i] * zn3[i] : 0.f;
+          win[3][i] = (p < M) ? theta_of<float>(s_mu[o + i], s_sig[o + i], zn3[i]) : 0.f;
         }
         ++wb;
         if (wb + 4 < M) {
@@ -1123,9 +1133,9 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
       uz = w0 * win[0][2] + w1 * win[1][2] + w2 * win[2][2] + w3 * win[3][2];
     } else {
       const int o = j * 12 + 3 * l;
-      ux = s_mu[o] + s_sig[o] * za;
-      uy = s_mu[o + 1] + s_sig[o + 1] * zb;
-      uz = s_mu[o + 2] + s_sig[o + 2] * zc;
+      ux = theta_of<float>(s_mu[o], s_sig[o], za);
+      uy = theta_of<float>(s_mu[o + 1], s_sig[o + 1], zb);
+      uz = theta_of<float>(s_mu[o + 2], s_sig[o + 2], zc);
       // the next step's noise (the last step reads its own row again)
       za = zq[0]; zb = zq[1]; zc = zq[2];
       zq += (j + 2 < H) ? zstride : 0;

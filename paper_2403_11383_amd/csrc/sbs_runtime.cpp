@@ -109,13 +109,9 @@ constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2,
 constexpr int64_t kJitMarginNs = 150000;
 constexpr double kJitMinSteps = 1e6;
 constexpr int64_t kDispatchNs = 20000;  // launch to device start of an idle stream
-// A rollout that makes only the stance legs' noise leaves the MPPI update to
-// make the rows of the samples it weighs: cheap for a few samples (each row
-// is three Philox calls and six Box-Muller pairs in one workgroup); the form
-// is chosen where the controller's previous tick weighed at most this many.
-constexpr uint32_t kStanceMaxActive = 32;
-// MPPI costs the update holds in registers (16 per thread of 1024): the
-// list of weighed samples needs all of them there.
+// MPPI costs the update holds in registers (16 per thread of 1024): a
+// rollout may leave the noise rows to the update (which lists the samples it
+// weighs from those registers) only up to this many samples.
 constexpr int kMppiRegN = 16 * 1024;
 
 // Rollout form: lanes per sample (0 = automatic), workgroup size, step-loop
@@ -127,9 +123,7 @@ struct Tune {
   bool pairs = true;  // stance-pair one-lane rollouts where the gait allows
   // one-lane FP32 per-step rollouts make their own noise: 0 no (a noise
   // launch), 1 every row, 2 only the stance legs' Gaussians for MPPI
-  // controllers in the stance-pair form whose previous tick weighed at most
-  // kStanceMaxActive samples (every row otherwise), 3 as 2 whatever the
-  // previous tick weighed
+  // controllers in the stance-pair form (every row for the others)
   int gen = 2;
 };
 
@@ -258,7 +252,6 @@ struct Controller {
   double *dbg_mean = nullptr;
   int inflight = 0;
   int plan = -1;
-  uint32_t last_active = 0xFFFFFFFFu;  // samples weighed in the last tick (unknown: max)
   // noise prefetch: two buffers of iterations x H x N x 12 floats; the next
   // tick's noise is written into the idle one on the second stream
   bool prefetch = false;
@@ -528,15 +521,15 @@ bool pair_gait(const sbs_controller_cfg &c) {
 }
 
 // Whether a controller's one-lane FP32 rollout may make only its stance
-// legs' noise (the MPPI update then makes the rows it weighs).  `adaptive`:
-// the launch is built for this tick alone (not captured in a plan), so the
-// previous tick's count of weighed samples may decide.
-bool stance_noise(const Controller &C, const Tune &tn, bool adaptive) {
+// legs' noise (the MPPI update then makes the rows of the samples it
+// weighs).  It depends on the configuration alone, so a controller takes the
+// same form in every tick, alone, in a batch, in a plan and after a resume;
+// a controller whose noise is produced ahead of its ticks keeps reading
+// stored rows in every tick.
+bool stance_noise(const Controller &C, const Tune &tn) {
   const sbs_controller_cfg &c = C.cfg;
-  if (tn.gen < 2 || !tn.pairs || c.precision != SBS_FP32 || c.knots > 0 ||
-      c.method != SBS_MPPI || c.N > kMppiRegN || !pair_gait(c))
-    return false;
-  return tn.gen == 3 || (adaptive && C.last_active <= kStanceMaxActive);
+  return tn.gen == 2 && tn.pairs && !C.prefetch && c.precision == SBS_FP32 && c.knots == 0 &&
+         c.method == SBS_MPPI && c.N <= kMppiRegN && pair_gait(c);
 }
 
 void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char *dev_item,
@@ -674,8 +667,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
                                                    const std::vector<uint32_t> &ticks,
                                                    const Layout &L, char *host, char *dev,
                                                    char *host_dev, const Tune &tn,
-                                                   std::vector<double> *steps_out = nullptr,
-                                                   bool adaptive = false) {
+                                                   std::vector<double> *steps_out = nullptr) {
   const int n = (int)cs.size();
   int rmax = 1;
   for (auto *c : cs) rmax = std::max(rmax, c->cfg.iterations);
@@ -703,7 +695,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       for (int i = 0; i < n; ++i)
         if (cs[i]->cfg.iterations > r && cs[i]->cfg.precision == prec &&
             (cs[i]->cfg.knots > 0 ? 1 : 0) == spl && ((tn.pairs && pair_gait(cs[i]->cfg)) ? 1 : 0) == pair &&
-            (stance_noise(*cs[i], tn, adaptive) ? 1 : 0) == sto)
+            (stance_noise(*cs[i], tn) ? 1 : 0) == sto)
           idx.push_back(i);
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int a, int b) { return cs[a]->cfg.H > cs[b]->cfg.H; });
@@ -828,11 +820,7 @@ void finish_batch(sbs_runtime *rt, Batch &b) {
     }
     if (it != rt->tickets.end()) it->second.rec = nullptr;  // the record is released below
     auto c = rt->ctrls.find(b.ctrls[i]);
-    if (c != rt->ctrls.end()) {
-      c->second.inflight -= 1;
-      const double na = b.host_results[i * kResultDoubles + RES_NACT];
-      c->second.last_active = (na >= 0 && na < 4e9) ? (uint32_t)na : 0xFFFFFFFFu;
-    }
+    if (c != rt->ctrls.end()) c->second.inflight -= 1;
   }
   if (rt->timing) record_timing(rt, b);
   else {
@@ -914,7 +902,7 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   for (int32_t id : ids) ticks.push_back(rt->ctrls.at(id).next_tick);
   std::vector<double> tab_steps;
   auto tabs = build_batch(rt, cs, ins, ticks, L, host, dev, rt->pinned_dev + host_off, rt->tune,
-                          &tab_steps, true);
+                          &tab_steps);
   hipStream_t s = rt->streams[slot];
   auto b = std::make_unique<Batch>();
   b->id = rt->next_batch++;
@@ -1863,7 +1851,7 @@ int sbs_set_serving_depth(sbs_runtime *rt, int32_t depth) {
 int sbs_set_rollout_noise(sbs_runtime *rt, int32_t in_rollout) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
-  if (in_rollout < 0 || in_rollout > 3) return fail(SBS_EINVAL, "rollout noise mode must be 0 to 3");
+  if (in_rollout < 0 || in_rollout > 2) return fail(SBS_EINVAL, "rollout noise mode must be 0 to 2");
   rt->tune.gen = in_rollout;
   return SBS_OK;
 }

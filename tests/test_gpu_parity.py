@@ -332,6 +332,7 @@ def test_stance_pair_form_equals_four_leg_form(rt, precision):
             workloads.config("c2", N=2500, H=30, seed=62, precision=precision),
             workloads.config("c1", N=1500, H=40, knots=8, seed=63, precision=precision)]
     rt.set_rollout_lanes(1)
+    rt.set_rollout_noise(1)  # both forms store every noise row
     try:
         for cfg in cfgs:
             inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(cfg["seed"])))
@@ -352,32 +353,28 @@ def test_stance_pair_form_equals_four_leg_form(rt, precision):
             np.testing.assert_array_equal(m1, m0)
     finally:
         rt.set_rollout_pairs(True)
+        rt.set_rollout_noise(2)
         rt.set_rollout_lanes(0)
 
 
 def test_noise_made_in_rollout_equals_noise_launch(rt):
-    """One-lane FP32 rollouts that make their noise themselves compute exactly
-    what the separate noise launch gives: every cost, sampled increment,
-    action and updated mean is bit-equal, over two consecutive ticks (the
-    second one warm-started), in every mode of sbs_set_rollout_noise -- every
-    row stored by the rollout (1); only the stance legs' Gaussians drawn in
-    the rollout and the rows of the weighed samples drawn by the MPPI update
-    (3 everywhere the form allows, 2 where the previous tick weighed few
-    samples).  Cases: MPPI with few and with all samples weighed (lambda 1e9:
-    more than the update's list holds, so it draws every row), an elite
+    """One-lane FP32 rollouts that make their noise rows themselves and store
+    them (sbs_set_rollout_noise 1) compute exactly what the separate noise
+    launch (0) gives: every cost, sampled increment, action and updated mean
+    is bit-equal, over two consecutive ticks (the second warm-started).
+    Cases: MPPI with few and with all samples weighed (lambda 1e9), an elite
     controller with three iterations whose update reads the stored rows, a
     four-leg gait and a batch of them all."""
     cfgs = [workloads.config("c1", N=3000, H=50, seed=81),
             workloads.config("c2", N=2500, H=30, seed=82),
             workloads.config("c1", N=1200, H=20, seed=83, duty=0.6),  # four-leg form
-            workloads.config("c4", N=2600, H=12, seed=85, **{"lambda": 1e9}),
-            workloads.config("c4", N=2048, H=25, seed=86)]
+            workloads.config("c4", N=2600, H=12, seed=85, **{"lambda": 1e9})]
     rng = np.random.default_rng(84)
     inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
     rt.set_rollout_lanes(1)
     try:
         res = {}
-        for mode in (0, 1, 2, 3):
+        for mode in (0, 1):
             rt.set_rollout_noise(mode)
             ids = [rt.init_controller(c) for c in cfgs]
             for cid in ids:
@@ -390,21 +387,60 @@ def test_noise_made_in_rollout_equals_noise_launch(rt):
             res[mode] = out
             for cid in ids:
                 rt.destroy_controller(cid)
-        for mode in (1, 2, 3):
-            for tick in range(2):
-                for c, ((a1, (J1, q1, m1), mu1), (a0, (J0, q0, m0), mu0)) in enumerate(
-                        zip(res[mode][tick], res[0][tick])):
-                    where = (mode, tick, c)
-                    np.testing.assert_array_equal(q1, q0, err_msg=str(where))
-                    np.testing.assert_array_equal(J1, J0, err_msg=str(where))
-                    np.testing.assert_array_equal(a1["grf"], a0["grf"], err_msg=str(where))
-                    assert a1["n_active"] == a0["n_active"], where
-                    np.testing.assert_array_equal(m1, m0, err_msg=str(where))
-                    np.testing.assert_array_equal(mu1, mu0, err_msg=str(where))
-        # the lambda 1e9 controller weighs every sample, the last one few
-        assert res[3][0][3][0]["n_active"] > 2048
-        assert res[3][0][4][0]["n_active"] <= 32
+        for tick in range(2):
+            for c, ((a1, (J1, q1, m1), mu1), (a0, (J0, q0, m0), mu0)) in enumerate(
+                    zip(res[1][tick], res[0][tick])):
+                where = str((tick, c))
+                np.testing.assert_array_equal(q1, q0, err_msg=where)
+                np.testing.assert_array_equal(J1, J0, err_msg=where)
+                np.testing.assert_array_equal(a1["grf"], a0["grf"], err_msg=where)
+                np.testing.assert_array_equal(m1, m0, err_msg=where)
+                np.testing.assert_array_equal(mu1, mu0, err_msg=where)
     finally:
+        rt.set_rollout_noise(2)
+        rt.set_rollout_lanes(0)
+
+
+def test_stance_noise_rollouts_against_oracle(rt):
+    """MPPI controllers in the stance-pair form whose rollouts draw only the
+    stance legs' Gaussians and store no noise (sbs_set_rollout_noise 2), the
+    update drawing the rows of the samples it weighs.  This form is compiled apart
+    from the others, so its costs agree with theirs within FP32 rounding,
+    not bit for bit.  Against the FP64 oracle from the state each controller
+    holds before each of three consecutive ticks: every sampled increment
+    is equal, the influential costs meet the FP32 bars, and the update
+    reproduces the oracle's update of the GPU's own costs (selection parity)
+    -- with few weighed samples (the list) and with all of them weighed
+    (lambda 1e9: the update draws every row).  A four-leg controller in the
+    same batch keeps the stored-row form."""
+    cfgs = [workloads.config("c1", N=3000, H=50, seed=81),
+            workloads.config("c4", N=2600, H=12, seed=85, **{"lambda": 1e9}),
+            workloads.config("c4", N=2048, H=25, seed=86),
+            workloads.config("c1", N=1200, H=20, seed=83, duty=0.6)]
+    rng = np.random.default_rng(84)
+    inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
+    rt.set_rollout_lanes(1)
+    rt.set_rollout_noise(2)
+    ids = [rt.init_controller(c) for c in cfgs]
+    try:
+        for cid in ids:
+            rt.set_debug(cid, True)
+        for tick in range(3):
+            before = [rt.get_state(cid) for cid in ids]
+            acts = [rt.fetch(t) for t in rt.submit_batch(ids, inps)]
+            for c, (cfg, inp, cid, a, (mu, mf, tk)) in enumerate(zip(cfgs, inps, ids, acts, before)):
+                J, q, mean = rt.debug_fetch(cid)
+                own = oracle.tick(cfg, mu, mf, tk, inp, nthreads=8)
+                np.testing.assert_array_equal(q, own["q_samples"], err_msg=str((tick, c)))
+                check_costs_fp32(J[0], own["costs"][0], cfg["lambda"])
+                sel = oracle.tick(cfg, mu, mf, tk, inp, costs_override=J, nthreads=8)
+                scale = max(np.abs(sel["mean"]).max(), MG2)
+                assert np.abs(mean - sel["mean"]).max() <= 1e-4 * scale, (tick, c)
+                assert np.abs(a["grf"] - sel["grf"]).max() <= 1e-4 * scale, (tick, c)
+        assert acts[1]["n_active"] > 2048 and acts[2]["n_active"] <= 32
+    finally:
+        for cid in ids:
+            rt.destroy_controller(cid)
         rt.set_rollout_noise(2)
         rt.set_rollout_lanes(0)
 
