@@ -2099,7 +2099,7 @@ int sbs_plan_autotune(sbs_runtime *rt, int32_t plan, const sbs_tick_input *in, i
   std::vector<const sbs_tick_input *> ins;
   for (int i = 0; i < n; ++i) ins.push_back(&in[i]);
   for (int f = 0; f < nforms && e == hipSuccess; ++f) {
-    Tune tn;
+    Tune tn = P.tune;  // the plan's stance-pair and noise settings stay
     tn.lanes = forms[f][0];
     tn.block = forms[f][1];
     tn.unroll = forms[f][2];

@@ -468,16 +468,19 @@ def test_fp32_lane_forms_agree(rt):
 
 def test_plan_forms_and_autotune(rt):
     """Every rollout form of a plan gives bit-identical results within one
-    lane form (workgroup size and unroll do not change any sample's
-    arithmetic); the autotuner restores the controllers' state and leaves a
-    working plan."""
+    lane form and one noise form (workgroup size and unroll do not change
+    any sample's arithmetic; the noise rows are stored, sbs_set_rollout_noise
+    1); the autotuner restores the controllers' state and leaves a working
+    plan."""
     cfgs = [workloads.config("c1", N=n, H=h, seed=s, method=m, iterations=it)
             for n, h, s, m, it in ((1500, 22, 1, "mppi", 1), (3000, 40, 2, "elite", 3),
                                    (700, 31, 3, "mppi", 1))]
     rng = np.random.default_rng(12)
     inps = [workloads.tick_input(workloads.initial_state(rng)) for _ in cfgs]
     ids = [rt.init_controller(c) for c in cfgs]
+    rt.set_rollout_noise(1)
     plan = rt.plan_create(ids, use_graph=True)
+    rt.set_rollout_noise(2)
     state0 = [rt.get_state(c) for c in ids]
 
     def run(form):
