@@ -370,18 +370,22 @@ def main_c3(args):
         for t in rt.plan_submit(plan, inps):
             rt.fetch(t)
     rt.timing()
+    for f in range(N_FORMS):
+        rt.timing_rollout(f)
     reps = 5
     for _ in range(reps):
         for t in rt.plan_submit(plan, inps):
             rt.fetch(t)
-    tm = rt.timing()
-    # every rollout here queues behind its iteration's noise stage, so its
-    # events span the kernel alone (the overhead of an idle-stream launch is
-    # reported, not taken off)
+    rt.timing()
+    forms = [rt.timing_rollout(f) for f in range(N_FORMS)]
+    # the events of a rollout queued behind other work span the kernel alone
+    # (the overhead of an idle-stream launch is reported, not taken off)
     ev_ovh_ns = rt.timing_overhead_ns(64)
     rt.close()
-    roll_ns_total = tm["rollout_ns"] * tm["launches"][1]
-    flop = work * FLOP_PER_ROLLOUT_STEP * reps
+    # dominant rollout form by device time, rated with its own FLOP count
+    f = max(range(N_FORMS), key=lambda i: forms[i]["avg_ns"] * forms[i]["launches"])
+    fo = forms[f]
+    flop = fo["steps"] * FORM_FLOP_PER_STEP[f]
     line = {
         "metric": METRIC, "value": work * args.steps / elapsed, "unit": "rollout-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -392,11 +396,18 @@ def main_c3(args):
                    "rollout_steps_per_tick": work, "tune": tune},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "roofline": roofline_obj(
-            "k_rollout (tuned form)", flop, roll_ns_total / max(1, tm["launches"][1]),
-            tm["launches"][1], traffic=stored_traffic("k_rollout", "c3"),
-            duration_us=roll_ns_total / max(1, tm["launches"][1]) * 1e-3,
-            event_interval_us=tm["rollout_ns"] * 1e-3, event_overhead_us=ev_ovh_ns * 1e-3,
-            event_overhead_taken_us=0.0),
+            FORM_NAMES[f], flop, fo["avg_ns"], fo["launches"],
+            flop_per_rollout_step=FORM_FLOP_PER_STEP[f],
+            traffic=(stored_traffic(FORM_TRAFFIC_KEY[f], "c3", fo["steps"] / max(1, fo["launches"]))
+                     if FORM_TRAFFIC_KEY[f] else None),
+            timed_launches=fo["launches"], duration_us=fo["avg_ns"] * 1e-3,
+            rollout_steps_per_launch=fo["steps"] / max(1, fo["launches"]),
+            event_overhead_us=ev_ovh_ns * 1e-3, event_overhead_taken_us=0.0,
+            other_forms={FORM_NAMES[i]: {"timed_launches": forms[i]["launches"],
+                                         "duration_us": forms[i]["avg_ns"] * 1e-3,
+                                         "rollout_steps_per_launch":
+                                             forms[i]["steps"] / max(1, forms[i]["launches"])}
+                         for i in range(N_FORMS) if i != f and forms[i]["launches"]}),
     }
     print(json.dumps(line), flush=True)
 
