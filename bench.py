@@ -62,9 +62,9 @@ FLOP_PER_SPLINE_KNOT = 24
 # counted.
 FLOP_PER_NOISE_ROW = 270
 FLOP_PER_ROLLOUT_STEP_WITH_NOISE = FLOP_PER_ROLLOUT_STEP + FLOP_PER_NOISE_ROW
-# a stance-pair rollout that draws only its stance legs' noise evaluates four
-# of the six pairs per step
-FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE = FLOP_PER_ROLLOUT_STEP + 4 * 45
+# a stance-pair rollout that draws only its stance diagonal's noise evaluates
+# three of the six pairs per step
+FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE = FLOP_PER_ROLLOUT_STEP + 3 * 45
 # MI355X FP32 vector peak as published (it counts packed FMAs: 256 CUs x 4
 # SIMDs x 16 lanes x 2 FLOP x 2 packed x 2.4 GHz) and the non-packed peak the
 # kernels can reach (they are built with packed FP32 off).
@@ -831,7 +831,7 @@ def progress(msg):
 # and the key of their stored HBM byte counts at C4
 FORM_NAMES = ["k_rollout<float> (one lane per sample)", "k_rollout_quad (four lanes per sample)",
               "k_rollout<double>", "k_rollout<float> drawing its noise (one lane per sample)",
-              "k_rollout<float> drawing its stance legs' noise (one lane per sample)"]
+              "k_rollout<float> drawing its stance diagonal's noise (one lane per sample)"]
 FORM_FLOP_PER_STEP = [FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP, FLOP_PER_ROLLOUT_STEP,
                       FLOP_PER_ROLLOUT_STEP_WITH_NOISE, FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE]
 FORM_TRAFFIC_KEY = [None, None, None, "k_rollout", "k_rollout_stance_noise"]

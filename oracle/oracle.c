@@ -101,8 +101,12 @@ void orc_gauss_pair(uint32_t w0, uint32_t w1, float out[2]) {
 }
 
 /* Counter map of the noise stream: key = seed, counter = (k, j, tick,      */
-/* (r << 8) | call).  Calls 0..2 give GRF dims 4c..4c+3 of step j; call 3 at */
-/* j = 0 gives the frequency draw of sample k.                              */
+/* (r << 8) | call).  Calls 0..2 give the six Box-Muller pairs of row j:     */
+/* pair p uses words 2(p mod 2), 2(p mod 2) + 1 of call p / 2.  Each pair    */
+/* serves one force component of the two legs of a diagonal: pairs 0..2 the  */
+/* x, y, z components of legs 0 and 3 (dims 0..2 and 9..11), pairs 3..5      */
+/* those of legs 1 and 2 (dims 3..5 and 6..8).  Call 3 at j = 0 gives the    */
+/* frequency draw of sample k.                                              */
 static void philox_call(uint64_t seed, uint32_t k, uint32_t j, uint32_t tick, uint32_t r,
                         uint32_t call, uint32_t w[4]) {
   uint32_t ctr[4] = {k, j, tick, (r << 8) | call};
@@ -110,13 +114,21 @@ static void philox_call(uint64_t seed, uint32_t k, uint32_t j, uint32_t tick, ui
   orc_philox4x32_10(ctr, key, w);
 }
 
+/* GRF dimensions of Box-Muller pair p: (first value, second value). */
+static const int kPairDims[6][2] = {{0, 9}, {1, 10}, {2, 11}, {3, 6}, {4, 7}, {5, 8}};
+
 void orc_noise_step(uint64_t seed, uint32_t tick, uint32_t r, uint32_t k, uint32_t j,
                     float z[12]) {
   for (uint32_t c = 0; c < 3; ++c) {
     uint32_t w[4];
     philox_call(seed, k, j, tick, r, c, w);
-    orc_gauss_pair(w[0], w[1], &z[4 * c]);
-    orc_gauss_pair(w[2], w[3], &z[4 * c + 2]);
+    for (int h = 0; h < 2; ++h) {
+      float g[2];
+      orc_gauss_pair(w[2 * h], w[2 * h + 1], g);
+      const int p = 2 * (int)c + h;
+      z[kPairDims[p][0]] = g[0];
+      z[kPairDims[p][1]] = g[1];
+    }
   }
 }
 

@@ -35,8 +35,11 @@ namespace sbs {
 
 // ---------------------------------------------------------------------------
 // Noise contract: Philox4x32-10 keyed by the seed, counter (k, j, tick,
-// (r << 8) | call); calls 0..2 feed GRF dims 4c..4c+3 of step j, call 3 at
-// j = 0 the frequency.  Gaussians by Box-Muller on 24-bit uniforms with a
+// (r << 8) | call); calls 0..2 give the six Box-Muller pairs of row j (pair
+// p from words 2 (p mod 2), +1 of call p / 2), pair p serving one force
+// component of the two legs of a diagonal: pairs 0..2 the x, y, z forces of
+// legs 0 and 3 (dims 0..2, 9..11), pairs 3..5 those of legs 1 and 2 (dims
+// 3..5, 6..8); call 3 at j = 0 the frequency.  Gaussians by Box-Muller on 24-bit uniforms with a
 // fixed sequence of IEEE FP32 operations (no contraction), so the result is
 // reproducible bit for bit on any IEEE machine.
 // ---------------------------------------------------------------------------
@@ -222,19 +225,21 @@ __device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
 
 // Noise row j of sample k in iteration r: the 12 Gaussians of the GRF
 // dimensions, from Philox calls 0..2 of the counter (k, j, tick, (r << 8) |
-// call), dimensions 4 call .. 4 call + 3 from its four words.
+// call): pair p of words 2 (p mod 2), +1 of call p / 2 goes to dims
+// kPairDim[p] (the same force component of the two legs of a diagonal).
 __device__ __forceinline__ void noise_row(uint32_t key0, uint32_t key1, uint32_t rw,
                                           uint32_t tick, uint32_t k, uint32_t j, float z[12]) {
+  constexpr int kPairDim[6][2] = {{0, 9}, {1, 10}, {2, 11}, {3, 6}, {4, 7}, {5, 8}};
 #pragma unroll
   for (uint32_t call = 0; call < 3; ++call) {
     uint32_t c0 = k, c1 = j, c2 = tick, c3 = rw | call;
     philox4x32_10(c0, c1, c2, c3, key0, key1);
     const float2 ga = gauss_pair(c0, c1);
     const float2 gb = gauss_pair(c2, c3);
-    z[4 * call + 0] = ga.x;
-    z[4 * call + 1] = ga.y;
-    z[4 * call + 2] = gb.x;
-    z[4 * call + 3] = gb.y;
+    z[kPairDim[2 * call][0]] = ga.x;
+    z[kPairDim[2 * call][1]] = ga.y;
+    z[kPairDim[2 * call + 1][0]] = gb.x;
+    z[kPairDim[2 * call + 1][1]] = gb.y;
   }
 }
 
@@ -612,8 +617,8 @@ __device__ __forceinline__ T theta_of(T mu, T sig, T z) {
 // with the noise kernel's own Philox counter and transform.  GEN 1: all of
 // row j at step j, stored for the update instead of read: the same values,
 // one launch and a 48-B read per rollout-step fewer.  GEN 2 (stance-pair
-// form, MPPI): only the Gaussians of the two stance legs' six GRF
-// components -- four of the row's six Box-Muller pairs, from two or three
+// form, MPPI): only the Gaussians of the stance diagonal's six GRF
+// components -- three of the row's six Box-Muller pairs, from two or three
 // of its Philox calls -- and nothing stored; the MPPI update makes the rows
 // of the samples it weighs (noise_row, the same values).
 template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR, int GEN = 0>
@@ -758,28 +763,28 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
         for (int i = 0; i < 12; ++i)
           u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
       } else if constexpr (GEN == 2) {
-        // the stance pair's GRF dimensions: pair A (legs 0, 3) dims 0-2 and
-        // 9-11 from calls 0 and 2; pair B (legs 1, 2) dims 3-8 from calls
-        // 0, 1 and 2.  Four Box-Muller slots per lane, fed the words of the
-        // pairs its stance legs need (the pair of dims 2, 3 serves dim 2 of
-        // leg 0 or dim 3 of leg 1, that of dims 8, 9 dim 9 or dim 8); call 1
-        // runs only where a lane of the wave has pair B in stance.
+        // the stance diagonal's three Box-Muller pairs: pair A (legs 0, 3)
+        // pairs 0, 1 (call 0) and 2 (words 0, 1 of call 1); pair B (legs 1,
+        // 2) pairs 3 (words 2, 3 of call 1), 4 and 5 (call 2).  Slot s gives
+        // the lower-indexed stance leg's component s and the other leg's;
+        // calls 0 and 2 run only where a lane of the wave needs them.
         const bool sA = duty_full || (ph[0] < duty_q);
-        uint32_t a0 = (uint32_t)k, a1 = (uint32_t)j, a2 = tick, a3 = rw;
-        philox4x32_10(a0, a1, a2, a3, key0, key1);
-        uint32_t b0 = (uint32_t)k, b1 = (uint32_t)j, b2 = tick, b3 = rw | 2u;
-        philox4x32_10(b0, b1, b2, b3, key0, key1);
-        uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
-        if (__any(!sA)) {
-          m0 = (uint32_t)k; m1 = (uint32_t)j; m2 = tick; m3 = rw | 1u;
-          philox4x32_10(m0, m1, m2, m3, key0, key1);
+        uint32_t m0 = (uint32_t)k, m1 = (uint32_t)j, m2 = tick, m3 = rw | 1u;
+        philox4x32_10(m0, m1, m2, m3, key0, key1);
+        uint32_t a0 = 0u, a1 = 0u, a2 = 0u, a3 = 0u, b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
+        if (__any(sA)) {
+          a0 = (uint32_t)k; a1 = (uint32_t)j; a2 = tick; a3 = rw;
+          philox4x32_10(a0, a1, a2, a3, key0, key1);
         }
-        const float2 g0 = gauss_pair(sA ? a0 : a2, sA ? a1 : a3);  // dims 0,1 | 2,3
-        const float2 g1 = gauss_pair(sA ? a2 : m0, sA ? a3 : m1);  // dims 2,3 | 4,5
-        const float2 g2 = gauss_pair(sA ? b0 : m2, sA ? b1 : m3);  // dims 8,9 | 6,7
-        const float2 g3 = gauss_pair(sA ? b2 : b0, sA ? b3 : b1);  // dims 10,11 | 8,9
-        const float zl[3] = {sA ? g0.x : g0.y, sA ? g0.y : g1.x, sA ? g1.x : g1.y};
-        const float zh[3] = {sA ? g2.y : g2.x, sA ? g3.x : g2.y, sA ? g3.y : g3.x};
+        if (__any(!sA)) {
+          b0 = (uint32_t)k; b1 = (uint32_t)j; b2 = tick; b3 = rw | 2u;
+          philox4x32_10(b0, b1, b2, b3, key0, key1);
+        }
+        const float2 g0 = gauss_pair(sA ? a0 : m2, sA ? a1 : m3);  // pair 0 | 3: x forces
+        const float2 g1 = gauss_pair(sA ? a2 : b0, sA ? a3 : b1);  // pair 1 | 4: y forces
+        const float2 g2 = gauss_pair(sA ? m0 : b2, sA ? m1 : b3);  // pair 2 | 5: z forces
+        const float zl[3] = {g0.x, g1.x, g2.x};
+        const float zh[3] = {g0.y, g1.y, g2.y};
         const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {

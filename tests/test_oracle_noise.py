@@ -101,13 +101,22 @@ def test_noise_is_standard_normal(orc):
 
 
 def test_noise_counter_map(orc):
+    # pair p = words 2 (p mod 2), +1 of Philox call p // 2; pairs 0..2 give the
+    # x, y, z forces of legs 0 and 3 (FL, RR), pairs 3..5 those of legs 1 and
+    # 2 (FR, RL): [first value, second value] -> dims written out by hand
+    dims = {0: (0, 9), 1: (1, 10), 2: (2, 11), 3: (3, 6), 4: (4, 7), 5: (5, 8)}
     seed, tick, r, k, j = 0x123456789ABCDEF0, 17, 2, 333, 41
     z = orc.noise_step(seed, tick, r, k, j)
     key = [seed & 0xFFFFFFFF, seed >> 32]
+    seen = set()
     for c in range(3):
         w = orc.philox([k, j, tick, (r << 8) | c], key)
-        np.testing.assert_array_equal(z[4 * c:4 * c + 2], orc.gauss_pair(int(w[0]), int(w[1])))
-        np.testing.assert_array_equal(z[4 * c + 2:4 * c + 4], orc.gauss_pair(int(w[2]), int(w[3])))
+        for h in range(2):
+            g = orc.gauss_pair(int(w[2 * h]), int(w[2 * h + 1]))
+            a, b = dims[2 * c + h]
+            assert z[a] == g[0] and z[b] == g[1]
+            seen.update((a, b))
+    assert seen == set(range(12))
 
 
 def test_noise_streams_are_distinct(orc):

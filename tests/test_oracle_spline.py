@@ -75,8 +75,9 @@ def hover(cfg, rows):
 def test_spline_tick_mppi_limit_and_warm_start(orc):
     """lambda -> infinity: the new knots are the sample mean of the knot
     samples; the warm start re-samples that spline one step later, hover at
-    the last knot."""
-    cfg = scfg(4, 10, **{"lambda": 1e13})
+    the last knot.  (The weights differ from uniform by about (J - beta) /
+    lambda, costs here span ~1e4: lambda = 1e16 keeps that below 1e-11.)"""
+    cfg = scfg(4, 10, **{"lambda": 1e16})
     mu = hover(cfg, 4) + np.random.default_rng(4).normal(size=(4, 12)) * 10
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(5)))
     out = orc.tick(cfg, mu, 1.4, 3, inp)
