@@ -141,7 +141,7 @@ def run_pair(rt, cfg, inp, tick=None, mu=None, mu_f=None, nthreads=8):
     ref = oracle.tick(cfg, mu_gpu_in, mu_f, t, inp, nthreads=nthreads)
     rt.destroy_controller(cid)
     return {"act": act, "J": J, "q": q, "mean": mean, "mu_next": mu_next, "mf_next": mf_next,
-            "tick_next": tk}, ref
+            "tick_next": tk, "ctx": (inp, mu_gpu_in, t)}, ref
 
 
 def check_fp64(out, ref, cfg, rel=1e-10, influential_only=False):
@@ -153,15 +153,35 @@ def check_fp64(out, ref, cfg, rel=1e-10, influential_only=False):
     R, N = ref["costs"].shape
     np.testing.assert_array_equal(out["q"], ref["q_samples"])
     Jr = ref["costs"]
+
+    def influential(r):
+        if cfg.get("method", "mppi") == "mppi":
+            return Jr[r] <= Jr[r].min() + RELEVANT * cfg.get("lambda", 1.0)
+        return Jr[r] <= 2.0 * np.sort(Jr[r])[oracle.elite_count(N, cfg.get("elite_frac", 0.1)) - 1]
+
     if influential_only:
         for r in range(R):
-            if cfg.get("method", "mppi") == "mppi":
-                m = Jr[r] <= Jr[r].min() + RELEVANT * cfg.get("lambda", 1.0)
-            else:
-                m = Jr[r] <= 2.0 * np.sort(Jr[r])[oracle.elite_count(N, cfg.get("elite_frac", 0.1)) - 1]
+            m = influential(r)
             np.testing.assert_allclose(out["J"][r][m], Jr[r][m], rtol=rel, atol=0)
     else:
-        np.testing.assert_allclose(out["J"], Jr, rtol=rel, atol=0)
+        # every cost within rel, except a sample without influence whose
+        # rollout is ill-conditioned: FP64 rounding (the GPU fuses
+        # multiply-adds, the oracle does not) moves its cost by up to about
+        # H A eps, A its amplification of relative input perturbations
+        Jg = np.asarray(out["J"], np.float64)
+        bad = np.abs(Jg - Jr) > rel * np.abs(Jr)
+        if bad.any() and R == 1 and "ctx" in out:
+            ks = np.flatnonzero(bad[0])
+            assert not influential(0)[ks].any(), ks
+            inp, mu, t = out["ctx"]
+            amp = conditioning(cfg, inp, mu, cfg["sigma_grf"], t, 0, ks, ref["q_samples"][0],
+                               rel=1e-9)
+            err = np.abs(Jg[0, ks] - Jr[0, ks]) / np.abs(Jr[0, ks])
+            assert np.all(err <= 10.0 * cfg["H"] * np.maximum(amp, 1.0) * 2.2e-16), (ks, err, amp)
+            print("FP64 costs beyond", rel, "on ill-conditioned samples", ks.tolist(),
+                  "amplification", amp.tolist(), flush=True)
+            bad[0, ks] = False
+        assert not bad.any(), np.argwhere(bad)[:8]
     scale = max(np.abs(ref["mean"]).max(), MG2)
     assert np.abs(out["mean"] - ref["mean"]).max() <= rel * scale
     assert np.abs(out["act"]["grf"] - ref["grf"]).max() <= rel * scale
