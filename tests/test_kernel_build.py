@@ -42,15 +42,17 @@ def metadata(compiled):
 
 
 def kernel_body(text, name_part):
-    """Assembly lines of the first kernel whose symbol contains name_part."""
+    """Assembly lines of the first kernel whose symbol contains name_part (up
+    to the function's end label: a kernel may end its waves in several
+    places)."""
     lines = text.split("\n")
     for i, line in enumerate(lines):
         if re.match(r"^_Z\S*:", line) and name_part in line.split(":")[0]:
             body = []
             for l in lines[i:]:
-                body.append(l)
-                if "s_endpgm" in l:
+                if l.startswith(".Lfunc_end"):
                     return body
+                body.append(l)
     raise AssertionError(f"no kernel matching {name_part}")
 
 
