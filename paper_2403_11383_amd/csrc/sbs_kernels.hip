@@ -2132,20 +2132,40 @@ __device__ __forceinline__ void mppi_update_wg(const TickDesc &d, int r, unsigne
   const float *zr = d.z + (size_t)r * d.z_iter_stride;
   __syncthreads();  // the rollout's staging area becomes this update's LDS
 
+  // costs are read kBatch slots at a time: independent loads, one latency
+  constexpr int kBatch = 8;
+  auto load_costs = [&](int s0, float (&v)[kBatch]) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int k = (s0 + u) * B + tid;
+      const float jv = Jg[k < N ? k : N - 1];
+      v[u] = k < N ? jv : inf_t<float>();
+    }
+  };
   float bv = inf_t<float>();
   int bk = 0x7fffffff;
-  for (int k = tid; k < N; k += B) argmin_combine(bv, bk, Jg[k], k);
+  for (int s0 = 0; s0 < NS; s0 += kBatch) {
+    float v[kBatch];
+    load_costs(s0, v);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) argmin_combine(bv, bk, v[u], (s0 + u) * B + tid);
+  }
   block_argmin_packed(bv, bk, red_a, red_b);
   const bool skip = !finite_t(bv);
   const double ild = d.inv_lambda;
   const float il = (float)(ild < (double)std::numeric_limits<float>::max()
                                ? ild : (double)std::numeric_limits<float>::max());
   // per (slot, wave): how many weights do not underflow
-  for (int sl = 0; sl < NS; ++sl) {
-    const int k = sl * B + tid;
-    const float wk = (!skip && k < N) ? exp_t((bv - Jg[k]) * il) : 0.f;
-    const uint64_t bal = __ballot(wk != 0.f);
-    if (lane == 0) s_cnt[sl * kW + wid] = (uint32_t)__popcll(bal);
+  for (int s0 = 0; s0 < NS; s0 += kBatch) {
+    float v[kBatch];
+    load_costs(s0, v);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int sl = s0 + u;
+      const float wk = (!skip && sl < NS) ? exp_t((bv - v[u]) * il) : 0.f;
+      const uint64_t bal = __ballot(wk != 0.f);
+      if (lane == 0 && sl < NS) s_cnt[sl * kW + wid] = (uint32_t)__popcll(bal);
+    }
   }
   __syncthreads();
   const int cells = NS * kW;
@@ -2173,15 +2193,20 @@ __device__ __forceinline__ void mppi_update_wg(const TickDesc &d, int r, unsigne
   const bool listed = total <= (uint32_t)kListCap;
   double omega = 0.0, sf = 0.0;
   if (listed) {
-    for (int sl = 0; sl < NS; ++sl) {
-      const int k = sl * B + tid;
-      const float wk = (!skip && k < N) ? exp_t((bv - Jg[k]) * il) : 0.f;
-      const uint64_t bal = __ballot(wk != 0.f);
-      if (wk != 0.f) {
-        const uint32_t pos = s_cnt[sl * kW + wid] +
-                             (uint32_t)__popcll(bal & (lane ? ~0ull >> (64 - lane) : 0ull));
-        s_k[pos] = (uint32_t)k;
-        s_w[pos] = wk;
+    for (int s0 = 0; s0 < NS; s0 += kBatch) {
+      float v[kBatch];
+      load_costs(s0, v);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int sl = s0 + u, k = sl * B + tid;
+        const float wk = (!skip && sl < NS) ? exp_t((bv - v[u]) * il) : 0.f;
+        const uint64_t bal = __ballot(wk != 0.f);
+        if (wk != 0.f) {
+          const uint32_t pos = s_cnt[sl * kW + wid] +
+                               (uint32_t)__popcll(bal & (lane ? ~0ull >> (64 - lane) : 0ull));
+          s_k[pos] = (uint32_t)k;
+          s_w[pos] = wk;
+        }
       }
     }
     __syncthreads();
