@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--rollout-noise", type=int, default=2, choices=[0, 1, 2],
                     help="c4: sbs_set_rollout_noise mode (0 noise launch, 1 rows in the rollout, "
                          "2 stance legs only where the form allows)")
-    ap.add_argument("--fused-update", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--fused-update", type=int, default=0, choices=[0, 1],
                     help="sbs_set_fused_update: FP32 MPPI updates formed by the last rollout "
                          "workgroup (1) or by a separate update launch (0)")
     ap.add_argument("--depth", type=int, default=2,
@@ -539,7 +539,7 @@ def fleet_inputs(binding, workloads, fleet, seed):
 
 
 def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2,
-                depth=1, noise=2, fused=True):
+                depth=1, noise=2, fused=False):
     """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
     ticks; serving mode batches whatever is admitted, direct mode runs every
     tick as its own launch sequence ("plain single MPPI").  A robot's tick
@@ -601,7 +601,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
-                  warmup_ticks=0, streams=2, depth=1, noise=2, fused=True):
+                  warmup_ticks=0, streams=2, depth=1, noise=2, fused=False):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
     form sustains, and their submit-to-done latency.  The serving client

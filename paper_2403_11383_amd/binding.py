@@ -470,7 +470,7 @@ class Runtime:
 
     def set_fused_update(self, on: bool = True):
         """FP32 MPPI updates formed by the last rollout workgroup (True) or by
-        a separate update launch (False)."""
+        a separate update launch (False, the default)."""
         _check(lib().sbs_set_fused_update(self._h, 1 if on else 0))
 
     def timing(self):

@@ -126,8 +126,9 @@ struct Tune {
   // controllers in the stance-pair form (every row for the others)
   int gen = 2;
   // FP32 MPPI controllers (N <= kTailMaxN): the last rollout workgroup of a
-  // controller forms its update, instead of a separate update launch
-  bool fused = true;
+  // controller forms its update, instead of a separate update launch (off:
+  // measured slower, see sbs_set_fused_update)
+  bool fused = false;
 };
 
 bool valid_form(int lanes, int block, int unroll) {

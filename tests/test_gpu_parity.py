@@ -448,7 +448,7 @@ def test_stance_noise_rollouts_against_oracle(rt):
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_update_in_rollout_tail_equals_update_launch(rt, lanes):
     """The MPPI update formed by the last rollout workgroup of each FP32
-    controller (sbs_set_fused_update, default) equals the separate update
+    controller (sbs_set_fused_update(1)) equals the separate update
     launch bit for bit where at most 2048 samples weigh (both sum the listed
     samples in increasing order): costs, increments, actions, means and the
     next tick's warm start over two ticks, for a batch of per-step, spline,
@@ -479,7 +479,7 @@ def test_update_in_rollout_tail_equals_update_launch(rt, lanes):
             for cid in ids:
                 rt.destroy_controller(cid)
     finally:
-        rt.set_fused_update(True)
+        rt.set_fused_update(False)
         rt.set_rollout_lanes(0)
     listed = [True] * len(cfgs)  # every tick so far weighed at most 2048 samples
     for tick in range(2):
