@@ -252,9 +252,6 @@ def main():
     ap.add_argument("--rollout-noise", type=int, default=2, choices=[0, 1, 2],
                     help="c4: sbs_set_rollout_noise mode (0 noise launch, 1 rows in the rollout, "
                          "2 stance legs only where the form allows)")
-    ap.add_argument("--fused-update", type=int, default=0, choices=[0, 1],
-                    help="sbs_set_fused_update: FP32 MPPI updates formed by the last rollout "
-                         "workgroup (1) or by a separate update launch (0)")
     ap.add_argument("--depth", type=int, default=2,
                     help="c4: serving batches in flight per stream (sbs_set_serving_depth)")
     ap.add_argument("--phase", default="all", choices=["all", "saturated"],
@@ -291,7 +288,6 @@ def main():
     c2 = args.workload == "c2"
     cfg = workloads.config(args.workload, knots=args.knots)
     rt = binding.Runtime(arena_bytes=int(args.arena_gb * (1 << 30)), two_streams=True)
-    rt.set_fused_update(bool(args.fused_update))
     rt.set_timing(args.timing)
     elapsed, lat, acts, timing, plant = closed_loop(
         rt, binding, workloads, cfg, args.steps, args.warmup, prefetch=not args.no_prefetch,
@@ -539,7 +535,7 @@ def fleet_inputs(binding, workloads, fleet, seed):
 
 
 def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, streams=2,
-                depth=1, noise=2, fused=False):
+                depth=1, noise=2):
     """The C4 arrival stream: Poisson arrivals (50 Hz per robot) of control
     ticks; serving mode batches whatever is admitted, direct mode runs every
     tick as its own launch sequence ("plain single MPPI").  A robot's tick
@@ -554,7 +550,6 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
     if mode == "serving":
         rt.set_serving_depth(depth)
     rt.set_rollout_noise(noise)
-    rt.set_fused_update(fused)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 5)
     events = sorted((t, r) for r, ts in enumerate(arrivals) for t in ts)
@@ -601,7 +596,7 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
 
 
 def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, timing=0,
-                  warmup_ticks=0, streams=2, depth=1, noise=2, fused=False):
+                  warmup_ticks=0, streams=2, depth=1, noise=2):
     """The C4 fleet with every robot's next tick submitted as soon as its
     previous one completes (no arrival gaps): the most ticks per second each
     form sustains, and their submit-to-done latency.  The serving client
@@ -620,7 +615,6 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
     if mode == "serving":
         rt.set_serving_depth(depth)
     rt.set_rollout_noise(noise)
-    rt.set_fused_update(fused)
     ids = [rt.init_controller(c) for c in fleet]
     inputs = fleet_inputs(binding, workloads, fleet, 6)
     L = binding.lib()
@@ -850,8 +844,7 @@ def main_c4_saturated(args, binding, workloads, arena):
     kernels of this process cover exactly the launches counted here."""
     sat = saturated_run(binding, workloads, args.steps * STEP_S_SATURATED, "serving", arena,
                         timing=3, streams=args.streams, depth=args.depth,
-                        noise=args.rollout_noise,
-                        fused=bool(args.fused_update))
+                        noise=args.rollout_noise)
     names = ["fp32_one_lane", "fp32_quad", "fp64", "fp32_one_lane_noise",
              "fp32_one_lane_stance_noise"]
     forms = {names[i]: {"launches": f["launches"], "rollout_steps": f["steps"],
@@ -876,15 +869,13 @@ def main_c4(args):
                       warmup_ticks=1)
     progress("50 Hz stream, continuous batching")
     serve = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "serving", arena,
-                        streams=args.streams, depth=args.depth, noise=args.rollout_noise,
-                        fused=bool(args.fused_update))
+                        streams=args.streams, depth=args.depth, noise=args.rollout_noise)
     progress(f"done: {serve['ticks']} ticks; 50 Hz stream, plain single MPPI")
     plain = serving_run(binding, workloads, K * STEP_S_ARRIVALS, "direct", arena)
     progress(f"done: {plain['ticks']} ticks; saturated, continuous batching")
     sat = saturated_run(binding, workloads, K * STEP_S_SATURATED, "serving", arena,
                         timing=args.timing, streams=args.streams, depth=args.depth,
-                        noise=args.rollout_noise,
-                        fused=bool(args.fused_update))
+                        noise=args.rollout_noise)
     progress(f"done: {sat['ticks']} ticks; saturated, plain single MPPI")
     sat_plain = saturated_run(binding, workloads, K * STEP_S_SATURATED, "direct", arena)
     progress(f"done: {sat_plain['ticks']} ticks")

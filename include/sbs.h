@@ -309,20 +309,6 @@ int sbs_set_rollout_noise(sbs_runtime *rt, int32_t mode);
  * arena.  SBS_EINVAL for a null runtime or a depth outside 1..4. */
 int sbs_set_serving_depth(sbs_runtime *rt, int32_t depth);
 
-/* MPPI update in the rollout (Alg. 4 after Alg. 2; default off): for FP32
- * MPPI controllers with N <= 16384 in batched launches every rollout
- * workgroup counts itself done on a per-controller counter, and the last one
- * forms the controller's update (weights, mean, action) itself, so no
- * separate update launch runs and no workgroup waits for another.  The
- * update sums the weighed samples in increasing sample order either way, so
- * both give the same results while at most 2048 samples weigh.  Off by
- * default: every rollout workgroup must then publish its costs at device
- * scope, which on a multi-die GPU writes back its die's L2 cache, and the
- * rollouts run slower than the separate update costs.  Takes effect at the
- * next submission; a plan keeps the setting it was created with.
- * SBS_EINVAL for a null runtime. */
-int sbs_set_fused_update(sbs_runtime *rt, int32_t on);
-
 /* Kernel timing with HIP events on the runtime stream: mode 0 off; 1 the
  * rollout kernel's own start and end (events carried by its dispatch) on
  * one launch in 16, counted from this call; 2 event commands between every

@@ -33,7 +33,7 @@ EXPORTED = [
     "sbs_plan_autotune", "sbs_get_state",
     "sbs_set_state", "sbs_export_state", "sbs_import_state", "sbs_set_debug", "sbs_debug_fetch",
     "sbs_debug_costs", "sbs_debug_noise", "sbs_stats",
-    "sbs_set_timing", "sbs_timing", "sbs_timing_rollout", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_rollout_pairs", "sbs_set_rollout_noise", "sbs_set_serving_depth", "sbs_set_fused_update", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
+    "sbs_set_timing", "sbs_timing", "sbs_timing_rollout", "sbs_timing_overhead", "sbs_set_rollout_lanes", "sbs_set_rollout_pairs", "sbs_set_rollout_noise", "sbs_set_serving_depth", "sbs_set_prefetch", "sbs_plant_step", "sbs_plant_step_wrench", "sbs_closed_loop_step", "sbs_last_error", "sbs_abi_version",
 ]
 
 
@@ -134,7 +134,6 @@ def lib():
         L.sbs_set_rollout_pairs.argtypes = [vp, i32]
         L.sbs_set_rollout_noise.argtypes = [vp, i32]
         L.sbs_set_serving_depth.argtypes = [vp, i32]
-        L.sbs_set_fused_update.argtypes = [vp, i32]
         L.sbs_set_prefetch.argtypes = [vp, i32, i32]
         L.sbs_plant_step.argtypes = [C.POINTER(ControllerCfg), C.POINTER(PlantState),
                                      C.POINTER(Action), vp, vp]
@@ -467,11 +466,6 @@ class Runtime:
     def set_serving_depth(self, depth: int):
         """Serving: batches in flight per stream (1 to 4)."""
         _check(lib().sbs_set_serving_depth(self._h, int(depth)))
-
-    def set_fused_update(self, on: bool = True):
-        """FP32 MPPI updates formed by the last rollout workgroup (True) or by
-        a separate update launch (False, the default)."""
-        _check(lib().sbs_set_fused_update(self._h, 1 if on else 0))
 
     def timing(self):
         avg = np.zeros(4)

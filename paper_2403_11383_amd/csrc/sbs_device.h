@@ -16,12 +16,6 @@ constexpr int kResultDoubles = 24; // action record
 constexpr int kItScalars = 16;     // per-iteration scalars
 constexpr int kMaxH = 256;         // longest horizon: the rollout stages the mean, std and
                                    // spline tables in LDS (58 KB at FP64 and H = 256)
-constexpr int kListCap = 2048;     // MPPI update: most weighed samples listed in LDS
-constexpr int kTailMaxN = 16384;   // MPPI update in the rollout's last workgroup: most samples
-// LDS of that update (dynamic, reusing the rollout's staging area): wave sums
-// [4][16] FP64, two argmin exchanges [4][2] u64, per-(slot, wave) counts
-// [272] u32, scalars [16] FP64, the list [kListCap] u32 + FP32 weights
-constexpr int kTailLds = 4 * 16 * 8 + 2 * 4 * 2 * 8 + 272 * 4 + 16 * 8 + kListCap * 8;
 
 // result record layout (doubles)
 enum : int {
@@ -58,8 +52,7 @@ struct TickDesc {
   uint32_t q_fixed, q_lo, q_hi;
   uint32_t q_set[4];     // frequency-set mode: phase increments of the members
   int32_t n_fset;
-  int32_t fused_update;  // 1: MPPI, FP32, N <= kTailMaxN: the last rollout workgroup of
-                         // the controller forms the update (k_update_mppi skips it)
+  int32_t pad1;
   uint32_t phase_offset[4];
   uint32_t duty_q;       // stance iff phase < duty_q (duty_full: always)
   int32_t duty_full;
@@ -131,7 +124,6 @@ struct LaunchTab {
   int32_t pairs;         // one-lane rollouts in the stance-pair form: every item is a
                          // diagonal trot at duty 1/2 (one of the leg pairs {0, 3},
                          // {1, 2} in stance at every step)
-  int32_t n_fused;       // items whose MPPI update the rollout's last workgroup forms
   const TickDesc *desc;  // descriptor array of the batch
   const int32_t *item;   // [n] descriptor index
   const int32_t *noise_start;  // [n+1]

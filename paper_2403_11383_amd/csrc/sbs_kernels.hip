@@ -225,24 +225,21 @@ __device__ __forceinline__ uint32_t draw_q(const TickDesc &d, int r, int k) {
 
 // Noise row j of sample k in iteration r: the 12 Gaussians of the GRF
 // dimensions, from Philox calls 0..2 of the counter (k, j, tick, (r << 8) |
-// call): pair p of words 2 (p mod 2), +1 of call p / 2 goes to dims p and
-// pair_dim_second(p) (the same force component of the two legs of a
-// diagonal: 0-2 with 9-11, 3-5 with 6-8).
-__device__ __forceinline__ int pair_dim_second(int p) { return p < 3 ? p + 9 : p + 3; }
-
+// call): pair p of words 2 (p mod 2), +1 of call p / 2 goes to dims
+// kPairDim[p] (the same force component of the two legs of a diagonal).
 __device__ __forceinline__ void noise_row(uint32_t key0, uint32_t key1, uint32_t rw,
                                           uint32_t tick, uint32_t k, uint32_t j, float z[12]) {
+  constexpr int kPairDim[6][2] = {{0, 9}, {1, 10}, {2, 11}, {3, 6}, {4, 7}, {5, 8}};
 #pragma unroll
   for (uint32_t call = 0; call < 3; ++call) {
     uint32_t c0 = k, c1 = j, c2 = tick, c3 = rw | call;
     philox4x32_10(c0, c1, c2, c3, key0, key1);
     const float2 ga = gauss_pair(c0, c1);
     const float2 gb = gauss_pair(c2, c3);
-    const int p = 2 * (int)call;  // pairs p, p + 1: dims (p, second(p)), (p + 1, second(p + 1))
-    z[p] = ga.x;
-    z[pair_dim_second(p)] = ga.y;
-    z[p + 1] = gb.x;
-    z[pair_dim_second(p + 1)] = gb.y;
+    z[kPairDim[2 * call][0]] = ga.x;
+    z[kPairDim[2 * call][1]] = ga.y;
+    z[kPairDim[2 * call + 1][0]] = gb.x;
+    z[kPairDim[2 * call + 1][1]] = gb.y;
   }
 }
 
@@ -604,13 +601,6 @@ __device__ __forceinline__ void load_const(const TickDesc &d, RollConst<T> &c) {
   c.sigma0 = (T)d.sigma0;
 }
 
-// MPPI update in the rollout's tail (defined with the update kernels): every
-// workgroup of a controller counts itself done; the last one forms the
-// controller's update (Alg. 4) with its B threads.
-template <int B, bool GEN2>
-__device__ __forceinline__ void mppi_tail_after_rollout(const TickDesc &d, int r, int nblocks,
-                                                        unsigned char *lds);
-
 // The policy's sample theta = mu + sigma z as one fused multiply-add, in
 // every rollout form (so that forms that pick their operands differently
 // still round alike).
@@ -668,361 +658,348 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
   }
   __syncthreads();
   const int k = (b - stage_start<INL>(tab.roll_start, it)) * BLOCK + (int)threadIdx.x;
-  if (k < N) {  // lanes past the last sample skip to the update tail
-    RollConst<T> c;
-    load_const<T>(d, c);
-    const T mg2 = c.mg * T(0.5), mg3 = c.mg / T(3), mg4 = c.mg * T(0.25);
-    const uint32_t q = draw_q(d, tab.r, k);
-    d.q[k] = q;
-    const double fkd = (double)q * d.inv_q_scale;
-    const T fk = (T)fkd;
-    const T half_tst = (q > 0u) ? (T)(d.half_duty / fkd) : T(0);
-    const uint32_t duty_q = d.duty_q;
-    const bool duty_full = d.duty_full != 0;
-    const bool friction = d.friction_on != 0;
+  if (k >= N) return;
 
-    T x[12], pf[12];
-  #pragma unroll
-    for (int i = 0; i < 12; ++i) { x[i] = (T)d.x0[i]; pf[i] = (T)d.foot[i]; }
-    uint32_t ph[4];
-  #pragma unroll
-    for (int l = 0; l < 4; ++l) ph[l] = d.phase_robot + d.phase_offset[l];
-    // a leg touches down where it is in stance and was not at the previous
-    // step; starting from "in stance" keeps the first step's feet where the
-    // tick put them
-    bool prev[4] = {true, true, true, true};
-    T J = T(0), Jc = T(0), tj = T(0);
+  RollConst<T> c;
+  load_const<T>(d, c);
+  const T mg2 = c.mg * T(0.5), mg3 = c.mg / T(3), mg4 = c.mg * T(0.25);
+  const uint32_t q = draw_q(d, tab.r, k);
+  d.q[k] = q;
+  const double fkd = (double)q * d.inv_q_scale;
+  const T fk = (T)fkd;
+  const T half_tst = (q > 0u) ? (T)(d.half_duty / fkd) : T(0);
+  const uint32_t duty_q = d.duty_q;
+  const bool duty_full = d.duty_full != 0;
+  const bool friction = d.friction_on != 0;
 
-    static_assert(!GEN || (!SPL && sizeof(T) == 4), "noise made in the rollout: FP32 per-step GRFs");
-    static_assert(GEN != 2 || PAIR, "stance legs' noise only: stance-pair form");
-    const float4 *zp =
-        reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
-    const size_t zstride = (size_t)N * 3;  // float4 per row
-    float4 z0, z1, z2;
-    if constexpr (!GEN) {
-      z0 = zp[0];
-      z1 = zp[1];
-      z2 = zp[2];
+  T x[12], pf[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) { x[i] = (T)d.x0[i]; pf[i] = (T)d.foot[i]; }
+  uint32_t ph[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) ph[l] = d.phase_robot + d.phase_offset[l];
+  // a leg touches down where it is in stance and was not at the previous
+  // step; starting from "in stance" keeps the first step's feet where the
+  // tick put them
+  bool prev[4] = {true, true, true, true};
+  T J = T(0), Jc = T(0), tj = T(0);
+
+  static_assert(!GEN || (!SPL && sizeof(T) == 4), "noise made in the rollout: FP32 per-step GRFs");
+  static_assert(GEN != 2 || PAIR, "stance legs' noise only: stance-pair form");
+  const float4 *zp =
+      reinterpret_cast<const float4 *>(d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12);
+  const size_t zstride = (size_t)N * 3;  // float4 per row
+  float4 z0, z1, z2;
+  if constexpr (!GEN) {
+    z0 = zp[0];
+    z1 = zp[1];
+    z2 = zp[2];
+  }
+  const float4 *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
+  // GEN: the noise counter words that do not change along the rollout
+  const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
+  const uint32_t rw = (uint32_t)tab.r << 8, tick = d.tick;
+  // spline: the sample's knots wb .. wb + 3 (theta = mu + sigma z), and the
+  // noise of knot wb + 4 loaded ahead
+  T win[4][12];
+  int wb = 0;
+  if constexpr (SPL) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), bq = a, cq = a;
+      if (w < M) { a = zp[w * zstride]; bq = zp[w * zstride + 1]; cq = zp[w * zstride + 2]; }
+      const float zw[12] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, cq.x, cq.y, cq.z, cq.w};
+#pragma unroll
+      for (int i = 0; i < 12; ++i)
+        win[w][i] = (w < M) ? theta_of<T>(s_mu[w * 12 + i], s_sig[w * 12 + i], (T)zw[i]) : T(0);
     }
-    const float4 *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
-    // GEN: the noise counter words that do not change along the rollout
-    const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
-    const uint32_t rw = (uint32_t)tab.r << 8, tick = d.tick;
-    // spline: the sample's knots wb .. wb + 3 (theta = mu + sigma z), and the
-    // noise of knot wb + 4 loaded ahead
-    T win[4][12];
-    int wb = 0;
-    if constexpr (SPL) {
-  #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), bq = a, cq = a;
-        if (w < M) { a = zp[w * zstride]; bq = zp[w * zstride + 1]; cq = zp[w * zstride + 2]; }
-        const float zw[12] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, cq.x, cq.y, cq.z, cq.w};
-  #pragma unroll
-        for (int i = 0; i < 12; ++i)
-          win[w][i] = (w < M) ? theta_of<T>(s_mu[w * 12 + i], s_sig[w * 12 + i], (T)zw[i]) : T(0);
-      }
-      if (4 < M) { z0 = zp[4 * zstride]; z1 = zp[4 * zstride + 1]; z2 = zp[4 * zstride + 2]; }
-    }
+    if (4 < M) { z0 = zp[4 * zstride]; z1 = zp[4 * zstride + 1]; z2 = zp[4 * zstride + 2]; }
+  }
 
-    // The step loop, in two forms.  The general one handles every gait: all
-    // four legs' forces are formed, clipped and masked by stance.  The
-    // stance-pair one (PAIR) serves the diagonal trot with duty factor 1/2,
-    // where at every step exactly one pair -- legs {0, 3} while leg 0's phase
-    // is below D_q, legs {1, 2} otherwise -- is in stance: it forms the
-    // forces, footholds, costs and torques of those two legs only.  The swing
-    // legs' terms in the general form are exact zeros added in leg order, so
-    // both forms compute the same sums.
-    auto steps = [&](auto pair_tag) {
-      constexpr bool PAIRS = decltype(pair_tag)::value;
-      // PAIR: world feet of the stance pair's lower- and higher-indexed legs,
-      // starting from the tick's footholds of the pair in stance at step 0
-      const uint32_t phA0 = ph[0];
-      bool sA_prev = duty_full || (phA0 < duty_q);
-      T f0[3], f1[3];
-  #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        f0[i] = sA_prev ? pf[i] : pf[3 + i];
-        f1[i] = sA_prev ? pf[9 + i] : pf[6 + i];
-      }
-  #pragma unroll UNROLL
-      for (int j = 0; j < H; ++j) {
-        T u[12];
-        T ulo[3], uhi[3];  // GEN 2: the stance legs' GRFs (lower-, higher-indexed leg)
-        if constexpr (SPL) {
-          while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
-            const int p = wb + 4;
-            const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                                  z2.x, z2.y, z2.z, z2.w};
-  #pragma unroll
-            for (int i = 0; i < 12; ++i) {
-              win[0][i] = win[1][i];
-              win[1][i] = win[2][i];
-              win[2][i] = win[3][i];
-              win[3][i] = (p < M) ? theta_of<T>(s_mu[p * 12 + i], s_sig[p * 12 + i], (T)zw[i]) : T(0);
-            }
-            ++wb;
-            if (wb + 4 < M) {
-              const float4 *zn = zp + (size_t)(wb + 4) * zstride;
-              z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
-            }
-          }
-          const T w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
-  #pragma unroll
-          for (int i = 0; i < 12; ++i)
-            u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
-        } else if constexpr (GEN == 2) {
-          // the stance diagonal's three Box-Muller pairs: pair A (legs 0, 3)
-          // pairs 0, 1 (call 0) and 2 (words 0, 1 of call 1); pair B (legs 1,
-          // 2) pairs 3 (words 2, 3 of call 1), 4 and 5 (call 2).  Slot s gives
-          // the lower-indexed stance leg's component s and the other leg's;
-          // calls 0 and 2 run only where a lane of the wave needs them.
-          const bool sA = duty_full || (ph[0] < duty_q);
-          uint32_t m0 = (uint32_t)k, m1 = (uint32_t)j, m2 = tick, m3 = rw | 1u;
-          philox4x32_10(m0, m1, m2, m3, key0, key1);
-          uint32_t a0 = 0u, a1 = 0u, a2 = 0u, a3 = 0u, b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
-          if (__any(sA)) {
-            a0 = (uint32_t)k; a1 = (uint32_t)j; a2 = tick; a3 = rw;
-            philox4x32_10(a0, a1, a2, a3, key0, key1);
-          }
-          if (__any(!sA)) {
-            b0 = (uint32_t)k; b1 = (uint32_t)j; b2 = tick; b3 = rw | 2u;
-            philox4x32_10(b0, b1, b2, b3, key0, key1);
-          }
-          const float2 g0 = gauss_pair(sA ? a0 : m2, sA ? a1 : m3);  // pair 0 | 3: x forces
-          const float2 g1 = gauss_pair(sA ? a2 : b0, sA ? a3 : b1);  // pair 1 | 4: y forces
-          const float2 g2 = gauss_pair(sA ? m0 : b2, sA ? m1 : b3);  // pair 2 | 5: z forces
-          const float zl[3] = {g0.x, g1.x, g2.x};
-          const float zh[3] = {g0.y, g1.y, g2.y};
-          const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
-  #pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            ulo[i] = theta_of<T>(s_mu[bl + i], s_sig[bl + i], (T)zl[i]);
-            uhi[i] = theta_of<T>(s_mu[bh + i], s_sig[bh + i], (T)zh[i]);
-          }
-        } else if constexpr (GEN == 1) {
-          float zz[12];
-          noise_row(key0, key1, rw, tick, (uint32_t)k, (uint32_t)j, zz);
-          float4 *dst = const_cast<float4 *>(zp) + (size_t)j * zstride;
-          dst[0] = make_float4(zz[0], zz[1], zz[2], zz[3]);
-          dst[1] = make_float4(zz[4], zz[5], zz[6], zz[7]);
-          dst[2] = make_float4(zz[8], zz[9], zz[10], zz[11]);
-          const T *muj = s_mu + j * 12;
-          const T *sgj = s_sig + j * 12;
-  #pragma unroll
-          for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
-        } else {
-          const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+  // The step loop, in two forms.  The general one handles every gait: all
+  // four legs' forces are formed, clipped and masked by stance.  The
+  // stance-pair one (PAIR) serves the diagonal trot with duty factor 1/2,
+  // where at every step exactly one pair -- legs {0, 3} while leg 0's phase
+  // is below D_q, legs {1, 2} otherwise -- is in stance: it forms the
+  // forces, footholds, costs and torques of those two legs only.  The swing
+  // legs' terms in the general form are exact zeros added in leg order, so
+  // both forms compute the same sums.
+  auto steps = [&](auto pair_tag) {
+    constexpr bool PAIRS = decltype(pair_tag)::value;
+    // PAIR: world feet of the stance pair's lower- and higher-indexed legs,
+    // starting from the tick's footholds of the pair in stance at step 0
+    const uint32_t phA0 = ph[0];
+    bool sA_prev = duty_full || (phA0 < duty_q);
+    T f0[3], f1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      f0[i] = sA_prev ? pf[i] : pf[3 + i];
+      f1[i] = sA_prev ? pf[9 + i] : pf[6 + i];
+    }
+#pragma unroll UNROLL
+    for (int j = 0; j < H; ++j) {
+      T u[12];
+      T ulo[3], uhi[3];  // GEN 2: the stance legs' GRFs (lower-, higher-indexed leg)
+      if constexpr (SPL) {
+        while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
+          const int p = wb + 4;
+          const float zw[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
                                 z2.x, z2.y, z2.z, z2.w};
-          const T *muj = s_mu + j * 12;
-          const T *sgj = s_sig + j * 12;
-  #pragma unroll
-          for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
-          // the next step's noise (the last step reads its own row again), into
-          // the registers this step's noise has just left
-          z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
-          zq += (j + 2 < H) ? zstride : 0;
-        }
-        // attitude
-        T sr, cr, sp, cp, sy, cy;
-        sincos_wave(x[3], &sr, &cr);
-        sincos_wave(x[4], &sp, &cp);
-        sincos_wave(x[5], &sy, &cy);
-        const T spsr = sp * sr, spcr = sp * cr;
-        const T R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
-        const T R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
-        const T R20 = -sp, R21 = cp * sr, R22 = cp * cr;
-        // capture-point base of Eq. (2) for legs touching down at this step
-        const T zc = x[2] > T(0) ? x[2] : T(0);
-        const T cap = sqrt_t(zc * c.inv_g);
-        const T bx = x[0] + half_tst * c.vr[0] + cap * (x[6] - c.vr[0]);
-        const T by = x[1] + half_tst * c.vr[1] + cap * (x[7] - c.vr[1]);
-        // tracking part of the stage cost (Sec. V); each form adds its legs'
-        // GRF terms to it in leg order
-        auto tracking = [&]() -> T {
-          const T e0 = c.sq[0] * x[0] - (c.sq_pr[0] + tj * c.sq_vr[0]);
-          const T e1 = c.sq[1] * x[1] - (c.sq_pr[1] + tj * c.sq_vr[1]);
-          const T e2 = c.sq[2] * x[2] - (c.sq_pr[2] + tj * c.sq_vr[2]);
-          const T e3 = c.sq[3] * x[3], e4 = c.sq[4] * x[4], e5 = c.sq[5] * x[5] - c.sq_yaw;
-          const T e6 = c.sq[6] * x[6] - c.sq_vr[0], e7 = c.sq[7] * x[7] - c.sq_vr[1];
-          const T e8 = c.sq[8] * x[8] - c.sq_vr[2];
-          const T e9 = c.sq[9] * x[9], e10 = c.sq[10] * x[10], e11 = c.sq[11] * x[11];
-          return e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3 + e4 * e4 + e5 * e5 + e6 * e6 + e7 * e7 +
-                 e8 * e8 + e9 * e9 + e10 * e10 + e11 * e11;
-        };
-        T stage;
-        T Fx = T(0), Fy = T(0), Fz = T(0), tx = T(0), ty = T(0), tz = T(0);
-        if constexpr (PAIRS) {
-          const bool sA = duty_full || (ph[0] < duty_q);
-          const bool td = sA != sA_prev;  // the pair in stance has just touched down
-          sA_prev = sA;
-          // the stance legs: 0 and 3 (pair A) or 1 and 2 (pair B), in leg order
-          const T *pc = &s_pair[sA ? 0 : 1][0][0];
-          T v0[3], v1[3], h0[3], h1[3], r0[3], r1[3];
-  #pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            if constexpr (GEN == 2) {
-              v0[i] = ulo[i];
-              v1[i] = uhi[i];
-            } else {
-              v0[i] = sA ? u[i] : u[3 + i];
-              v1[i] = sA ? u[9 + i] : u[6 + i];
-            }
-            h0[i] = pc[i];
-            r0[i] = pc[3 + i];
-            h1[i] = pc[8 + i];
-            r1[i] = pc[11 + i];
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            win[0][i] = win[1][i];
+            win[1][i] = win[2][i];
+            win[2][i] = win[3][i];
+            win[3][i] = (p < M) ? theta_of<T>(s_mu[p * 12 + i], s_sig[p * 12 + i], (T)zw[i]) : T(0);
           }
-          {  // footholds of Eq. (2) at touchdown
-            const T n0x = bx + R00 * h0[0] + R01 * h0[1] + R02 * h0[2];
-            const T n0y = by + R10 * h0[0] + R11 * h0[1] + R12 * h0[2];
-            const T n1x = bx + R00 * h1[0] + R01 * h1[1] + R02 * h1[2];
-            const T n1y = by + R10 * h1[0] + R11 * h1[1] + R12 * h1[2];
-            f0[0] = td ? n0x : f0[0];
-            f0[1] = td ? n0y : f0[1];
-            f0[2] = td ? T(0) : f0[2];
-            f1[0] = td ? n1x : f1[0];
-            f1[1] = td ? n1y : f1[1];
-            f1[2] = td ? T(0) : f1[2];
-          }
-          if (friction) {
-            friction_clip<T>(v0[0], v0[1], v0[2], c.mu_f);
-            friction_clip<T>(v1[0], v1[1], v1[2], c.mu_f);
-          }
-          // two legs in stance: each carries half the weight in u^r
-          stage = tracking();
-          {
-            const T ez0 = v0[2] - mg2, ez1 = v1[2] - mg2;
-            stage += r0[0] * v0[0] * v0[0] + r0[1] * v0[1] * v0[1] + r0[2] * ez0 * ez0;
-            stage += r1[0] * v1[0] * v1[0] + r1[1] * v1[1] * v1[1] + r1[2] * ez1 * ez1;
-          }
-          {
-            const T lx = f0[0] - x[0], ly = f0[1] - x[1], lz = f0[2] - x[2];
-            Fx += v0[0]; Fy += v0[1]; Fz += v0[2];
-            tx += ly * v0[2] - lz * v0[1];
-            ty += lz * v0[0] - lx * v0[2];
-            tz += lx * v0[1] - ly * v0[0];
-          }
-          {
-            const T lx = f1[0] - x[0], ly = f1[1] - x[1], lz = f1[2] - x[2];
-            Fx += v1[0]; Fy += v1[1]; Fz += v1[2];
-            tx += ly * v1[2] - lz * v1[1];
-            ty += lz * v1[0] - lx * v1[2];
-            tz += lx * v1[1] - ly * v1[0];
-          }
-        } else {
-          // contact schedule
-          bool st[4];
-          int nst = 0;
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            st[l] = duty_full || (ph[l] < duty_q);
-            nst += st[l] ? 1 : 0;
-          }
-          // footholds of the legs touching down at this step (Eq. (2))
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const bool td = st[l] && !prev[l];
-            const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
-            const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
-            const T ny = by + R10 * hx + R11 * hy + R12 * hz;
-            pf[3 * l + 0] = td ? nx : pf[3 * l + 0];
-            pf[3 * l + 1] = td ? ny : pf[3 * l + 1];
-            pf[3 * l + 2] = td ? T(0) : pf[3 * l + 2];
-            prev[l] = st[l];
-          }
-          // policy: theta = mu + sigma z (per step, or the spline of the knots),
-          // clipped to the cone, masked by stance
-          if (friction) {
-  #pragma unroll
-            for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
-          }
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            u[3 * l] = st[l] ? u[3 * l] : T(0);
-            u[3 * l + 1] = st[l] ? u[3 * l + 1] : T(0);
-            u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
-          }
-          T share = c.mg;  // m g / n_stance, selected without branches
-          share = (nst >= 2) ? mg2 : share;
-          share = (nst >= 3) ? mg3 : share;
-          share = (nst >= 4) ? mg4 : share;
-          stage = tracking();
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const T ez = u[3 * l + 2] - (st[l] ? share : T(0));
-            stage += c.Rw[3 * l] * u[3 * l] * u[3 * l] + c.Rw[3 * l + 1] * u[3 * l + 1] * u[3 * l + 1] +
-                     c.Rw[3 * l + 2] * ez * ez;
-          }
-          // SRBD derivative, Eq. (1), with world-frame lever arms to the feet
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const T lx = pf[3 * l] - x[0], ly = pf[3 * l + 1] - x[1], lz = pf[3 * l + 2] - x[2];
-            const T ux = u[3 * l], uy = u[3 * l + 1], uz = u[3 * l + 2];
-            Fx += ux; Fy += uy; Fz += uz;
-            tx += ly * uz - lz * uy;
-            ty += lz * ux - lx * uz;
-            tz += lx * uy - ly * ux;
+          ++wb;
+          if (wb + 4 < M) {
+            const float4 *zn = zp + (size_t)(wb + 4) * zstride;
+            z0 = zn[0]; z1 = zn[1]; z2 = zn[2];
           }
         }
-        {  // compensated accumulation
-          const T y = stage - Jc;
-          const T t = J + y;
-          Jc = (t - J) - y;
-          J = t;
+        const T w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+          u[i] = w0 * win[0][i] + w1 * win[1][i] + w2 * win[2][i] + w3 * win[3][i];
+      } else if constexpr (GEN == 2) {
+        // the stance diagonal's three Box-Muller pairs: pair A (legs 0, 3)
+        // pairs 0, 1 (call 0) and 2 (words 0, 1 of call 1); pair B (legs 1,
+        // 2) pairs 3 (words 2, 3 of call 1), 4 and 5 (call 2).  Slot s gives
+        // the lower-indexed stance leg's component s and the other leg's;
+        // calls 0 and 2 run only where a lane of the wave needs them.
+        const bool sA = duty_full || (ph[0] < duty_q);
+        uint32_t m0 = (uint32_t)k, m1 = (uint32_t)j, m2 = tick, m3 = rw | 1u;
+        philox4x32_10(m0, m1, m2, m3, key0, key1);
+        uint32_t a0 = 0u, a1 = 0u, a2 = 0u, a3 = 0u, b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
+        if (__any(sA)) {
+          a0 = (uint32_t)k; a1 = (uint32_t)j; a2 = tick; a3 = rw;
+          philox4x32_10(a0, a1, a2, a3, key0, key1);
         }
-        const T tbx = R00 * tx + R10 * ty + R20 * tz;  // R^T tau_world
-        const T tby = R01 * tx + R11 * ty + R21 * tz;
-        const T tbz = R02 * tx + R12 * ty + R22 * tz;
-        const T wx = x[9], wy = x[10], wz = x[11];
-        const T Iwx = c.I[0] * wx, Iwy = c.I[1] * wy, Iwz = c.I[2] * wz;
-        const T gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
-        const T icp = rcp_t(cp);
-        const T a = sr * wy + cr * wz;
-        const T dphi = wx + a * sp * icp;
-        const T dth = cr * wy - sr * wz;
-        const T dpsi = a * icp;
-        // explicit Euler
-        x[0] += c.dt * x[6];
-        x[1] += c.dt * x[7];
-        x[2] += c.dt * x[8];
-        x[3] += c.dt * dphi;
-        x[4] += c.dt * dth;
-        x[5] += c.dt * dpsi;
-        x[6] += c.dt_m * Fx;
-        x[7] += c.dt_m * Fy;
-        x[8] += c.dt_m * Fz - c.dt_g;
-        x[9] += c.dt_iI[0] * (tbx - gx);
-        x[10] += c.dt_iI[1] * (tby - gy);
-        x[11] += c.dt_iI[2] * (tbz - gz);
-        if constexpr (PAIRS) {
-          ph[0] += q;
-        } else {
-  #pragma unroll
-          for (int l = 0; l < 4; ++l) ph[l] += q;
+        if (__any(!sA)) {
+          b0 = (uint32_t)k; b1 = (uint32_t)j; b2 = tick; b3 = rw | 2u;
+          philox4x32_10(b0, b1, b2, b3, key0, key1);
         }
-        tj += c.dt;
+        const float2 g0 = gauss_pair(sA ? a0 : m2, sA ? a1 : m3);  // pair 0 | 3: x forces
+        const float2 g1 = gauss_pair(sA ? a2 : b0, sA ? a3 : b1);  // pair 1 | 4: y forces
+        const float2 g2 = gauss_pair(sA ? m0 : b2, sA ? m1 : b3);  // pair 2 | 5: z forces
+        const float zl[3] = {g0.x, g1.x, g2.x};
+        const float zh[3] = {g0.y, g1.y, g2.y};
+        const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          ulo[i] = theta_of<T>(s_mu[bl + i], s_sig[bl + i], (T)zl[i]);
+          uhi[i] = theta_of<T>(s_mu[bh + i], s_sig[bh + i], (T)zh[i]);
+        }
+      } else if constexpr (GEN == 1) {
+        float zz[12];
+        noise_row(key0, key1, rw, tick, (uint32_t)k, (uint32_t)j, zz);
+        float4 *dst = const_cast<float4 *>(zp) + (size_t)j * zstride;
+        dst[0] = make_float4(zz[0], zz[1], zz[2], zz[3]);
+        dst[1] = make_float4(zz[4], zz[5], zz[6], zz[7]);
+        dst[2] = make_float4(zz[8], zz[9], zz[10], zz[11]);
+        const T *muj = s_mu + j * 12;
+        const T *sgj = s_sig + j * 12;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
+      } else {
+        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
+                              z2.x, z2.y, z2.z, z2.w};
+        const T *muj = s_mu + j * 12;
+        const T *sgj = s_sig + j * 12;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) u[i] = theta_of<T>(muj[i], sgj[i], (T)zz[i]);
+        // the next step's noise (the last step reads its own row again), into
+        // the registers this step's noise has just left
+        z0 = zq[0]; z1 = zq[1]; z2 = zq[2];
+        zq += (j + 2 < H) ? zstride : 0;
       }
-    };
-    steps(std::integral_constant<bool, PAIR>{});
-    const T df = fk - c.f_nom;
-    J += c.rho * df * df;
-    if (!(J >= T(0)) || !finite_t(J)) J = inf_t<T>();
-    reinterpret_cast<T *>(d.J)[k] = J;
-    // every lane's cost and increment (and noise rows) stored at device scope
-    // before the workgroup counts itself done
-    if (d.fused_update && tab.n_fused > 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  }
-  // (a lone controller's one-lane rollout keeps the update launch: the
-  // descriptor in the kernel arguments leaves no scalar registers to spare
-  // for the tail, and a lone controller takes this form only above the
-  // samples the tail serves, or when the form is forced)
-  if constexpr (sizeof(T) == 4 && !INL) {
-    if (d.fused_update && tab.n_fused > 0) {
-      const int nb = INL ? tab.total_roll : tab.roll_start[it + 1] - tab.roll_start[it];
-      mppi_tail_after_rollout<BLOCK, GEN == 2>(d, tab.r, nb, roll_lds);
+      // attitude
+      T sr, cr, sp, cp, sy, cy;
+      sincos_wave(x[3], &sr, &cr);
+      sincos_wave(x[4], &sp, &cp);
+      sincos_wave(x[5], &sy, &cy);
+      const T spsr = sp * sr, spcr = sp * cr;
+      const T R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
+      const T R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
+      const T R20 = -sp, R21 = cp * sr, R22 = cp * cr;
+      // capture-point base of Eq. (2) for legs touching down at this step
+      const T zc = x[2] > T(0) ? x[2] : T(0);
+      const T cap = sqrt_t(zc * c.inv_g);
+      const T bx = x[0] + half_tst * c.vr[0] + cap * (x[6] - c.vr[0]);
+      const T by = x[1] + half_tst * c.vr[1] + cap * (x[7] - c.vr[1]);
+      // tracking part of the stage cost (Sec. V); each form adds its legs'
+      // GRF terms to it in leg order
+      auto tracking = [&]() -> T {
+        const T e0 = c.sq[0] * x[0] - (c.sq_pr[0] + tj * c.sq_vr[0]);
+        const T e1 = c.sq[1] * x[1] - (c.sq_pr[1] + tj * c.sq_vr[1]);
+        const T e2 = c.sq[2] * x[2] - (c.sq_pr[2] + tj * c.sq_vr[2]);
+        const T e3 = c.sq[3] * x[3], e4 = c.sq[4] * x[4], e5 = c.sq[5] * x[5] - c.sq_yaw;
+        const T e6 = c.sq[6] * x[6] - c.sq_vr[0], e7 = c.sq[7] * x[7] - c.sq_vr[1];
+        const T e8 = c.sq[8] * x[8] - c.sq_vr[2];
+        const T e9 = c.sq[9] * x[9], e10 = c.sq[10] * x[10], e11 = c.sq[11] * x[11];
+        return e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3 + e4 * e4 + e5 * e5 + e6 * e6 + e7 * e7 +
+               e8 * e8 + e9 * e9 + e10 * e10 + e11 * e11;
+      };
+      T stage;
+      T Fx = T(0), Fy = T(0), Fz = T(0), tx = T(0), ty = T(0), tz = T(0);
+      if constexpr (PAIRS) {
+        const bool sA = duty_full || (ph[0] < duty_q);
+        const bool td = sA != sA_prev;  // the pair in stance has just touched down
+        sA_prev = sA;
+        // the stance legs: 0 and 3 (pair A) or 1 and 2 (pair B), in leg order
+        const T *pc = &s_pair[sA ? 0 : 1][0][0];
+        T v0[3], v1[3], h0[3], h1[3], r0[3], r1[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if constexpr (GEN == 2) {
+            v0[i] = ulo[i];
+            v1[i] = uhi[i];
+          } else {
+            v0[i] = sA ? u[i] : u[3 + i];
+            v1[i] = sA ? u[9 + i] : u[6 + i];
+          }
+          h0[i] = pc[i];
+          r0[i] = pc[3 + i];
+          h1[i] = pc[8 + i];
+          r1[i] = pc[11 + i];
+        }
+        {  // footholds of Eq. (2) at touchdown
+          const T n0x = bx + R00 * h0[0] + R01 * h0[1] + R02 * h0[2];
+          const T n0y = by + R10 * h0[0] + R11 * h0[1] + R12 * h0[2];
+          const T n1x = bx + R00 * h1[0] + R01 * h1[1] + R02 * h1[2];
+          const T n1y = by + R10 * h1[0] + R11 * h1[1] + R12 * h1[2];
+          f0[0] = td ? n0x : f0[0];
+          f0[1] = td ? n0y : f0[1];
+          f0[2] = td ? T(0) : f0[2];
+          f1[0] = td ? n1x : f1[0];
+          f1[1] = td ? n1y : f1[1];
+          f1[2] = td ? T(0) : f1[2];
+        }
+        if (friction) {
+          friction_clip<T>(v0[0], v0[1], v0[2], c.mu_f);
+          friction_clip<T>(v1[0], v1[1], v1[2], c.mu_f);
+        }
+        // two legs in stance: each carries half the weight in u^r
+        stage = tracking();
+        {
+          const T ez0 = v0[2] - mg2, ez1 = v1[2] - mg2;
+          stage += r0[0] * v0[0] * v0[0] + r0[1] * v0[1] * v0[1] + r0[2] * ez0 * ez0;
+          stage += r1[0] * v1[0] * v1[0] + r1[1] * v1[1] * v1[1] + r1[2] * ez1 * ez1;
+        }
+        {
+          const T lx = f0[0] - x[0], ly = f0[1] - x[1], lz = f0[2] - x[2];
+          Fx += v0[0]; Fy += v0[1]; Fz += v0[2];
+          tx += ly * v0[2] - lz * v0[1];
+          ty += lz * v0[0] - lx * v0[2];
+          tz += lx * v0[1] - ly * v0[0];
+        }
+        {
+          const T lx = f1[0] - x[0], ly = f1[1] - x[1], lz = f1[2] - x[2];
+          Fx += v1[0]; Fy += v1[1]; Fz += v1[2];
+          tx += ly * v1[2] - lz * v1[1];
+          ty += lz * v1[0] - lx * v1[2];
+          tz += lx * v1[1] - ly * v1[0];
+        }
+      } else {
+        // contact schedule
+        bool st[4];
+        int nst = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          st[l] = duty_full || (ph[l] < duty_q);
+          nst += st[l] ? 1 : 0;
+        }
+        // footholds of the legs touching down at this step (Eq. (2))
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const bool td = st[l] && !prev[l];
+          const T hx = c.hip[3 * l], hy = c.hip[3 * l + 1], hz = c.hip[3 * l + 2];
+          const T nx = bx + R00 * hx + R01 * hy + R02 * hz;
+          const T ny = by + R10 * hx + R11 * hy + R12 * hz;
+          pf[3 * l + 0] = td ? nx : pf[3 * l + 0];
+          pf[3 * l + 1] = td ? ny : pf[3 * l + 1];
+          pf[3 * l + 2] = td ? T(0) : pf[3 * l + 2];
+          prev[l] = st[l];
+        }
+        // policy: theta = mu + sigma z (per step, or the spline of the knots),
+        // clipped to the cone, masked by stance
+        if (friction) {
+#pragma unroll
+          for (int l = 0; l < 4; ++l) friction_clip<T>(u[3 * l], u[3 * l + 1], u[3 * l + 2], c.mu_f);
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          u[3 * l] = st[l] ? u[3 * l] : T(0);
+          u[3 * l + 1] = st[l] ? u[3 * l + 1] : T(0);
+          u[3 * l + 2] = st[l] ? u[3 * l + 2] : T(0);
+        }
+        T share = c.mg;  // m g / n_stance, selected without branches
+        share = (nst >= 2) ? mg2 : share;
+        share = (nst >= 3) ? mg3 : share;
+        share = (nst >= 4) ? mg4 : share;
+        stage = tracking();
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const T ez = u[3 * l + 2] - (st[l] ? share : T(0));
+          stage += c.Rw[3 * l] * u[3 * l] * u[3 * l] + c.Rw[3 * l + 1] * u[3 * l + 1] * u[3 * l + 1] +
+                   c.Rw[3 * l + 2] * ez * ez;
+        }
+        // SRBD derivative, Eq. (1), with world-frame lever arms to the feet
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const T lx = pf[3 * l] - x[0], ly = pf[3 * l + 1] - x[1], lz = pf[3 * l + 2] - x[2];
+          const T ux = u[3 * l], uy = u[3 * l + 1], uz = u[3 * l + 2];
+          Fx += ux; Fy += uy; Fz += uz;
+          tx += ly * uz - lz * uy;
+          ty += lz * ux - lx * uz;
+          tz += lx * uy - ly * ux;
+        }
+      }
+      {  // compensated accumulation
+        const T y = stage - Jc;
+        const T t = J + y;
+        Jc = (t - J) - y;
+        J = t;
+      }
+      const T tbx = R00 * tx + R10 * ty + R20 * tz;  // R^T tau_world
+      const T tby = R01 * tx + R11 * ty + R21 * tz;
+      const T tbz = R02 * tx + R12 * ty + R22 * tz;
+      const T wx = x[9], wy = x[10], wz = x[11];
+      const T Iwx = c.I[0] * wx, Iwy = c.I[1] * wy, Iwz = c.I[2] * wz;
+      const T gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
+      const T icp = rcp_t(cp);
+      const T a = sr * wy + cr * wz;
+      const T dphi = wx + a * sp * icp;
+      const T dth = cr * wy - sr * wz;
+      const T dpsi = a * icp;
+      // explicit Euler
+      x[0] += c.dt * x[6];
+      x[1] += c.dt * x[7];
+      x[2] += c.dt * x[8];
+      x[3] += c.dt * dphi;
+      x[4] += c.dt * dth;
+      x[5] += c.dt * dpsi;
+      x[6] += c.dt_m * Fx;
+      x[7] += c.dt_m * Fy;
+      x[8] += c.dt_m * Fz - c.dt_g;
+      x[9] += c.dt_iI[0] * (tbx - gx);
+      x[10] += c.dt_iI[1] * (tby - gy);
+      x[11] += c.dt_iI[2] * (tbz - gz);
+      if constexpr (PAIRS) {
+        ph[0] += q;
+      } else {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) ph[l] += q;
+      }
+      tj += c.dt;
     }
-  }
+  };
+  steps(std::integral_constant<bool, PAIR>{});
+  const T df = fk - c.f_nom;
+  J += c.rho * df * df;
+  if (!(J >= T(0)) || !finite_t(J)) J = inf_t<T>();
+  reinterpret_cast<T *>(d.J)[k] = J;
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,191 +1051,186 @@ __global__ void __launch_bounds__(BLOCK) k_rollout_quad(LaunchTab tab, TickDesc 
   __syncthreads();
   const int l = threadIdx.x & 3;
   const int k = (b - stage_start<INL>(tab.roll_start, it)) * kPerBlock + (int)(threadIdx.x >> 2);
-  if (k < N) {  // quads past the last sample skip to the update tail
-    const float dt = (float)d.dt;
-    const float dt_m = (float)(d.dt * d.inv_mass), dt_g = (float)(d.dt * d.gravity);
-    const float mg = (float)(d.mass * d.gravity), mu_f = (float)d.mu_fric, inv_g = (float)d.inv_g;
-    const float mg2 = mg * 0.5f, mg3 = mg / 3.f, mg4 = mg * 0.25f;
-    const float I0 = (float)d.inertia[0], I1 = (float)d.inertia[1], I2 = (float)d.inertia[2];
-    const float dt_iI0 = (float)(d.dt * d.inv_inertia[0]), dt_iI1 = (float)(d.dt * d.inv_inertia[1]),
-                dt_iI2 = (float)(d.dt * d.inv_inertia[2]);
-    const float vr0 = (float)d.v_ref[0], vr1 = (float)d.v_ref[1], vr2 = (float)d.v_ref[2];
-    const float hx = (float)d.hip[3 * l], hy = (float)d.hip[3 * l + 1], hz = (float)d.hip[3 * l + 2];
-    const float Rw0 = (float)d.Rw[3 * l], Rw1 = (float)d.Rw[3 * l + 1], Rw2 = (float)d.Rw[3 * l + 2];
-    // tracking errors of state group l scaled by sqrt(Q): e = sq x - sq x^r,
-    // the reference being position (moving with v_ref), attitude (0, 0,
-    // yaw_ref), velocity v_ref, angular velocity 0
-    const double qa = __builtin_sqrt(d.Q[3 * l]), qb = __builtin_sqrt(d.Q[3 * l + 1]),
-                 qc = __builtin_sqrt(d.Q[3 * l + 2]);
-    const float sqa = (float)qa, sqb = (float)qb, sqc = (float)qc;
-    const float ra0 = (float)(qa * ((l == 0) ? d.p_ref0[0] : (l == 2) ? d.v_ref[0] : 0.0));
-    const float ra1 = (float)(qb * ((l == 0) ? d.p_ref0[1] : (l == 2) ? d.v_ref[1] : 0.0));
-    const float ra2 = (float)(qc * ((l == 0) ? d.p_ref0[2] : (l == 1) ? d.yaw_ref
-                                                            : (l == 2) ? d.v_ref[2] : 0.0));
-    const float rv0 = (float)(qa * ((l == 0) ? d.v_ref[0] : 0.0));
-    const float rv1 = (float)(qb * ((l == 0) ? d.v_ref[1] : 0.0));
-    const float rv2 = (float)(qc * ((l == 0) ? d.v_ref[2] : 0.0));
-    const uint32_t q = draw_q(d, tab.r, k);
-    if (l == 0) d.q[k] = q;
-    const double fkd = (double)q * d.inv_q_scale;
-    const float half_tst = (q > 0u) ? (float)(d.half_duty / fkd) : 0.f;
-    const uint32_t duty_q = d.duty_q;
-    const bool duty_full = d.duty_full != 0;
-    const bool friction = d.friction_on != 0;
+  if (k >= N) return;  // whole quads leave together
 
-    float x[12];
-  #pragma unroll
-    for (int i = 0; i < 12; ++i) x[i] = (float)d.x0[i];
-    float pfx = (float)d.foot[3 * l], pfy = (float)d.foot[3 * l + 1], pfz = (float)d.foot[3 * l + 2];
-    uint32_t ph = d.phase_robot + d.phase_offset[l];
-    bool prev = true;  // no touchdown at the first step (tick's footholds)
-    float J = 0.f, Jc = 0.f, tj = 0.f;
+  const float dt = (float)d.dt;
+  const float dt_m = (float)(d.dt * d.inv_mass), dt_g = (float)(d.dt * d.gravity);
+  const float mg = (float)(d.mass * d.gravity), mu_f = (float)d.mu_fric, inv_g = (float)d.inv_g;
+  const float mg2 = mg * 0.5f, mg3 = mg / 3.f, mg4 = mg * 0.25f;
+  const float I0 = (float)d.inertia[0], I1 = (float)d.inertia[1], I2 = (float)d.inertia[2];
+  const float dt_iI0 = (float)(d.dt * d.inv_inertia[0]), dt_iI1 = (float)(d.dt * d.inv_inertia[1]),
+              dt_iI2 = (float)(d.dt * d.inv_inertia[2]);
+  const float vr0 = (float)d.v_ref[0], vr1 = (float)d.v_ref[1], vr2 = (float)d.v_ref[2];
+  const float hx = (float)d.hip[3 * l], hy = (float)d.hip[3 * l + 1], hz = (float)d.hip[3 * l + 2];
+  const float Rw0 = (float)d.Rw[3 * l], Rw1 = (float)d.Rw[3 * l + 1], Rw2 = (float)d.Rw[3 * l + 2];
+  // tracking errors of state group l scaled by sqrt(Q): e = sq x - sq x^r,
+  // the reference being position (moving with v_ref), attitude (0, 0,
+  // yaw_ref), velocity v_ref, angular velocity 0
+  const double qa = __builtin_sqrt(d.Q[3 * l]), qb = __builtin_sqrt(d.Q[3 * l + 1]),
+               qc = __builtin_sqrt(d.Q[3 * l + 2]);
+  const float sqa = (float)qa, sqb = (float)qb, sqc = (float)qc;
+  const float ra0 = (float)(qa * ((l == 0) ? d.p_ref0[0] : (l == 2) ? d.v_ref[0] : 0.0));
+  const float ra1 = (float)(qb * ((l == 0) ? d.p_ref0[1] : (l == 2) ? d.v_ref[1] : 0.0));
+  const float ra2 = (float)(qc * ((l == 0) ? d.p_ref0[2] : (l == 1) ? d.yaw_ref
+                                                          : (l == 2) ? d.v_ref[2] : 0.0));
+  const float rv0 = (float)(qa * ((l == 0) ? d.v_ref[0] : 0.0));
+  const float rv1 = (float)(qb * ((l == 0) ? d.v_ref[1] : 0.0));
+  const float rv2 = (float)(qc * ((l == 0) ? d.v_ref[2] : 0.0));
+  const uint32_t q = draw_q(d, tab.r, k);
+  if (l == 0) d.q[k] = q;
+  const double fkd = (double)q * d.inv_q_scale;
+  const float half_tst = (q > 0u) ? (float)(d.half_duty / fkd) : 0.f;
+  const uint32_t duty_q = d.duty_q;
+  const bool duty_full = d.duty_full != 0;
+  const bool friction = d.friction_on != 0;
 
-    const float *zp = d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12 + 3 * l;
-    const size_t zstride = (size_t)N * 12;
-    float za = zp[0], zb = zp[1], zc = zp[2];
-    const float *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
-    // spline: this leg's three forces at knots wb .. wb + 3, and the noise of
-    // knot wb + 4 loaded ahead
-    float win[4][3];
-    int wb = 0;
+  float x[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) x[i] = (float)d.x0[i];
+  float pfx = (float)d.foot[3 * l], pfy = (float)d.foot[3 * l + 1], pfz = (float)d.foot[3 * l + 2];
+  uint32_t ph = d.phase_robot + d.phase_offset[l];
+  bool prev = true;  // no touchdown at the first step (tick's footholds)
+  float J = 0.f, Jc = 0.f, tj = 0.f;
+
+  const float *zp = d.z + (size_t)tab.r * d.z_iter_stride + (size_t)k * 12 + 3 * l;
+  const size_t zstride = (size_t)N * 12;
+  float za = zp[0], zb = zp[1], zc = zp[2];
+  const float *zq = zp + (H > 1 ? zstride : 0);  // row min(j + 1, H - 1)
+  // spline: this leg's three forces at knots wb .. wb + 3, and the noise of
+  // knot wb + 4 loaded ahead
+  float win[4][3];
+  int wb = 0;
+  if constexpr (SPL) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        win[w][i] = (w < M) ? theta_of<float>(s_mu[w * 12 + 3 * l + i], s_sig[w * 12 + 3 * l + i],
+                                              zp[w * zstride + i])
+                            : 0.f;
+    }
+    if (4 < M) { za = zp[4 * zstride]; zb = zp[4 * zstride + 1]; zc = zp[4 * zstride + 2]; }
+  }
+
+#pragma unroll UNROLL
+  for (int j = 0; j < H; ++j) {
+    float ux, uy, uz;
     if constexpr (SPL) {
-  #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-  #pragma unroll
-        for (int i = 0; i < 3; ++i)
-          win[w][i] = (w < M) ? theta_of<float>(s_mu[w * 12 + 3 * l + i], s_sig[w * 12 + 3 * l + i],
-                                                zp[w * zstride + i])
-                              : 0.f;
-      }
-      if (4 < M) { za = zp[4 * zstride]; zb = zp[4 * zstride + 1]; zc = zp[4 * zstride + 2]; }
-    }
-
-  #pragma unroll UNROLL
-    for (int j = 0; j < H; ++j) {
-      float ux, uy, uz;
-      if constexpr (SPL) {
-        while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
-          const int p = wb + 4, o = p * 12 + 3 * l;
-          const float zn3[3] = {za, zb, zc};
-  #pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            win[0][i] = win[1][i];
-            win[1][i] = win[2][i];
-            win[2][i] = win[3][i];
-            win[3][i] = (p < M) ? theta_of<float>(s_mu[o + i], s_sig[o + i], zn3[i]) : 0.f;
-          }
-          ++wb;
-          if (wb + 4 < M) {
-            const float *zn = zp + (size_t)(wb + 4) * zstride;
-            za = zn[0]; zb = zn[1]; zc = zn[2];
-          }
+      while (s_spb[j] != wb) {  // uniform: the window moves on knot by knot
+        const int p = wb + 4, o = p * 12 + 3 * l;
+        const float zn3[3] = {za, zb, zc};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          win[0][i] = win[1][i];
+          win[1][i] = win[2][i];
+          win[2][i] = win[3][i];
+          win[3][i] = (p < M) ? theta_of<float>(s_mu[o + i], s_sig[o + i], zn3[i]) : 0.f;
         }
-        const float w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
-        ux = w0 * win[0][0] + w1 * win[1][0] + w2 * win[2][0] + w3 * win[3][0];
-        uy = w0 * win[0][1] + w1 * win[1][1] + w2 * win[2][1] + w3 * win[3][1];
-        uz = w0 * win[0][2] + w1 * win[1][2] + w2 * win[2][2] + w3 * win[3][2];
-      } else {
-        const int o = j * 12 + 3 * l;
-        ux = theta_of<float>(s_mu[o], s_sig[o], za);
-        uy = theta_of<float>(s_mu[o + 1], s_sig[o + 1], zb);
-        uz = theta_of<float>(s_mu[o + 2], s_sig[o + 2], zc);
-        // the next step's noise (the last step reads its own row again)
-        za = zq[0]; zb = zq[1]; zc = zq[2];
-        zq += (j + 2 < H) ? zstride : 0;
+        ++wb;
+        if (wb + 4 < M) {
+          const float *zn = zp + (size_t)(wb + 4) * zstride;
+          za = zn[0]; zb = zn[1]; zc = zn[2];
+        }
       }
-      const bool st = duty_full || (ph < duty_q);
-      const float nst = quad_sum(st ? 1.f : 0.f);
-      // attitude: lanes 0, 1, 2 take roll, pitch, yaw
-      const float ang = (l == 0) ? x[3] : (l == 1) ? x[4] : x[5];
-      float sv, cv;
-      sincos_wave(ang, &sv, &cv);
-      const float sr = dpp<0x00>(sv), cr = dpp<0x00>(cv);
-      const float sp = dpp<0x55>(sv), cp = dpp<0x55>(cv);
-      const float sy = dpp<0xAA>(sv), cy = dpp<0xAA>(cv);
-      const float spsr = sp * sr, spcr = sp * cr;
-      const float R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
-      const float R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
-      const float R20 = -sp, R21 = cp * sr, R22 = cp * cr;
-      // foothold of this leg when it touches down (Eq. (2))
-      {
-        const float zcm = x[2] > 0.f ? x[2] : 0.f;
-        const float cap = sqrt_t(zcm * inv_g);
-        const bool td = st && !prev;
-        const float nx = x[0] + half_tst * vr0 + cap * (x[6] - vr0) + R00 * hx + R01 * hy + R02 * hz;
-        const float ny = x[1] + half_tst * vr1 + cap * (x[7] - vr1) + R10 * hx + R11 * hy + R12 * hz;
-        pfx = td ? nx : pfx;
-        pfy = td ? ny : pfy;
-        pfz = td ? 0.f : pfz;
-        prev = st;
-      }
-      // policy of this leg
-      if (friction) friction_clip<float>(ux, uy, uz, mu_f);
-      ux = st ? ux : 0.f;
-      uy = st ? uy : 0.f;
-      uz = st ? uz : 0.f;
-      // stage cost: this leg's GRF error and state group l's tracking error
-      float share = mg;  // m g / n_stance, selected without branches
-      share = (nst > 1.5f) ? mg2 : share;
-      share = (nst > 2.5f) ? mg3 : share;
-      share = (nst > 3.5f) ? mg4 : share;
-      const float ez = uz - (st ? share : 0.f);
-      const float ga = (l == 0) ? x[0] : (l == 1) ? x[3] : (l == 2) ? x[6] : x[9];
-      const float gb = (l == 0) ? x[1] : (l == 1) ? x[4] : (l == 2) ? x[7] : x[10];
-      const float gc = (l == 0) ? x[2] : (l == 1) ? x[5] : (l == 2) ? x[8] : x[11];
-      const float e0 = sqa * ga - (ra0 + tj * rv0), e1 = sqb * gb - (ra1 + tj * rv1);
-      const float e2 = sqc * gc - (ra2 + tj * rv2);
-      const float stage = e0 * e0 + e1 * e1 + e2 * e2 + Rw0 * ux * ux + Rw1 * uy * uy +
-                          Rw2 * ez * ez;
-      {
-        const float y = stage - Jc;
-        const float t = J + y;
-        Jc = (t - J) - y;
-        J = t;
-      }
-      // net force and torque about the CoM (world frame)
-      const float lx = pfx - x[0], ly = pfy - x[1], lz = pfz - x[2];
-      const float Fx = quad_sum(ux), Fy = quad_sum(uy), Fz = quad_sum(uz);
-      const float tx = quad_sum(ly * uz - lz * uy);
-      const float ty = quad_sum(lz * ux - lx * uz);
-      const float tz = quad_sum(lx * uy - ly * ux);
-      const float tbx = R00 * tx + R10 * ty + R20 * tz;
-      const float tby = R01 * tx + R11 * ty + R21 * tz;
-      const float tbz = R02 * tx + R12 * ty + R22 * tz;
-      const float wx = x[9], wy = x[10], wz = x[11];
-      const float Iwx = I0 * wx, Iwy = I1 * wy, Iwz = I2 * wz;
-      const float gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
-      const float icp = rcp_t(cp);
-      const float a = sr * wy + cr * wz;
-      const float dphi = wx + a * sp * icp;
-      const float dth = cr * wy - sr * wz;
-      const float dpsi = a * icp;
-      x[0] += dt * x[6];
-      x[1] += dt * x[7];
-      x[2] += dt * x[8];
-      x[3] += dt * dphi;
-      x[4] += dt * dth;
-      x[5] += dt * dpsi;
-      x[6] += dt_m * Fx;
-      x[7] += dt_m * Fy;
-      x[8] += dt_m * Fz - dt_g;
-      x[9] += dt_iI0 * (tbx - gx);
-      x[10] += dt_iI1 * (tby - gy);
-      x[11] += dt_iI2 * (tbz - gz);
-      ph += q;
-      tj += dt;
+      const float w0 = s_spw[4 * j], w1 = s_spw[4 * j + 1], w2 = s_spw[4 * j + 2], w3 = s_spw[4 * j + 3];
+      ux = w0 * win[0][0] + w1 * win[1][0] + w2 * win[2][0] + w3 * win[3][0];
+      uy = w0 * win[0][1] + w1 * win[1][1] + w2 * win[2][1] + w3 * win[3][1];
+      uz = w0 * win[0][2] + w1 * win[1][2] + w2 * win[2][2] + w3 * win[3][2];
+    } else {
+      const int o = j * 12 + 3 * l;
+      ux = theta_of<float>(s_mu[o], s_sig[o], za);
+      uy = theta_of<float>(s_mu[o + 1], s_sig[o + 1], zb);
+      uz = theta_of<float>(s_mu[o + 2], s_sig[o + 2], zc);
+      // the next step's noise (the last step reads its own row again)
+      za = zq[0]; zb = zq[1]; zc = zq[2];
+      zq += (j + 2 < H) ? zstride : 0;
     }
-    float Jt = quad_sum(J);
-    const float df = (float)fkd - (float)d.f_nominal;
-    Jt += (float)d.rho * df * df;
-    if (!(Jt >= 0.f) || !finite_t(Jt)) Jt = inf_t<float>();
-    if (l == 0) reinterpret_cast<float *>(d.J)[k] = Jt;
-    if (d.fused_update && tab.n_fused > 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const bool st = duty_full || (ph < duty_q);
+    const float nst = quad_sum(st ? 1.f : 0.f);
+    // attitude: lanes 0, 1, 2 take roll, pitch, yaw
+    const float ang = (l == 0) ? x[3] : (l == 1) ? x[4] : x[5];
+    float sv, cv;
+    sincos_wave(ang, &sv, &cv);
+    const float sr = dpp<0x00>(sv), cr = dpp<0x00>(cv);
+    const float sp = dpp<0x55>(sv), cp = dpp<0x55>(cv);
+    const float sy = dpp<0xAA>(sv), cy = dpp<0xAA>(cv);
+    const float spsr = sp * sr, spcr = sp * cr;
+    const float R00 = cy * cp, R01 = cy * spsr - sy * cr, R02 = cy * spcr + sy * sr;
+    const float R10 = sy * cp, R11 = sy * spsr + cy * cr, R12 = sy * spcr - cy * sr;
+    const float R20 = -sp, R21 = cp * sr, R22 = cp * cr;
+    // foothold of this leg when it touches down (Eq. (2))
+    {
+      const float zcm = x[2] > 0.f ? x[2] : 0.f;
+      const float cap = sqrt_t(zcm * inv_g);
+      const bool td = st && !prev;
+      const float nx = x[0] + half_tst * vr0 + cap * (x[6] - vr0) + R00 * hx + R01 * hy + R02 * hz;
+      const float ny = x[1] + half_tst * vr1 + cap * (x[7] - vr1) + R10 * hx + R11 * hy + R12 * hz;
+      pfx = td ? nx : pfx;
+      pfy = td ? ny : pfy;
+      pfz = td ? 0.f : pfz;
+      prev = st;
+    }
+    // policy of this leg
+    if (friction) friction_clip<float>(ux, uy, uz, mu_f);
+    ux = st ? ux : 0.f;
+    uy = st ? uy : 0.f;
+    uz = st ? uz : 0.f;
+    // stage cost: this leg's GRF error and state group l's tracking error
+    float share = mg;  // m g / n_stance, selected without branches
+    share = (nst > 1.5f) ? mg2 : share;
+    share = (nst > 2.5f) ? mg3 : share;
+    share = (nst > 3.5f) ? mg4 : share;
+    const float ez = uz - (st ? share : 0.f);
+    const float ga = (l == 0) ? x[0] : (l == 1) ? x[3] : (l == 2) ? x[6] : x[9];
+    const float gb = (l == 0) ? x[1] : (l == 1) ? x[4] : (l == 2) ? x[7] : x[10];
+    const float gc = (l == 0) ? x[2] : (l == 1) ? x[5] : (l == 2) ? x[8] : x[11];
+    const float e0 = sqa * ga - (ra0 + tj * rv0), e1 = sqb * gb - (ra1 + tj * rv1);
+    const float e2 = sqc * gc - (ra2 + tj * rv2);
+    const float stage = e0 * e0 + e1 * e1 + e2 * e2 + Rw0 * ux * ux + Rw1 * uy * uy +
+                        Rw2 * ez * ez;
+    {
+      const float y = stage - Jc;
+      const float t = J + y;
+      Jc = (t - J) - y;
+      J = t;
+    }
+    // net force and torque about the CoM (world frame)
+    const float lx = pfx - x[0], ly = pfy - x[1], lz = pfz - x[2];
+    const float Fx = quad_sum(ux), Fy = quad_sum(uy), Fz = quad_sum(uz);
+    const float tx = quad_sum(ly * uz - lz * uy);
+    const float ty = quad_sum(lz * ux - lx * uz);
+    const float tz = quad_sum(lx * uy - ly * ux);
+    const float tbx = R00 * tx + R10 * ty + R20 * tz;
+    const float tby = R01 * tx + R11 * ty + R21 * tz;
+    const float tbz = R02 * tx + R12 * ty + R22 * tz;
+    const float wx = x[9], wy = x[10], wz = x[11];
+    const float Iwx = I0 * wx, Iwy = I1 * wy, Iwz = I2 * wz;
+    const float gx = wy * Iwz - wz * Iwy, gy = wz * Iwx - wx * Iwz, gz = wx * Iwy - wy * Iwx;
+    const float icp = rcp_t(cp);
+    const float a = sr * wy + cr * wz;
+    const float dphi = wx + a * sp * icp;
+    const float dth = cr * wy - sr * wz;
+    const float dpsi = a * icp;
+    x[0] += dt * x[6];
+    x[1] += dt * x[7];
+    x[2] += dt * x[8];
+    x[3] += dt * dphi;
+    x[4] += dt * dth;
+    x[5] += dt * dpsi;
+    x[6] += dt_m * Fx;
+    x[7] += dt_m * Fy;
+    x[8] += dt_m * Fz - dt_g;
+    x[9] += dt_iI0 * (tbx - gx);
+    x[10] += dt_iI1 * (tby - gy);
+    x[11] += dt_iI2 * (tbz - gz);
+    ph += q;
+    tj += dt;
   }
-  if (d.fused_update && tab.n_fused > 0) {
-    const int nb = INL ? tab.total_roll : tab.roll_start[it + 1] - tab.roll_start[it];
-    mppi_tail_after_rollout<BLOCK, false>(d, tab.r, nb, roll_lds);
-  }
+  float Jt = quad_sum(J);
+  const float df = (float)fkd - (float)d.f_nominal;
+  Jt += (float)d.rho * df * df;
+  if (!(Jt >= 0.f) || !finite_t(Jt)) Jt = inf_t<float>();
+  if (l == 0) reinterpret_cast<float *>(d.J)[k] = Jt;
 }
 
 // ---------------------------------------------------------------------------
@@ -1808,41 +1780,7 @@ constexpr int kMppiPer = 16;
 // each row is reduced over all samples instead (per-thread partial sums in
 // the working precision, wave sums, FP64 across waves).  Either way the
 // result depends only on the controller's own data, not on the batch.
-// make_noise_row with one Philox call and two Box-Muller pairs in flight at a
-// time, each value stored as it is made (the same values): for the update in
-// the rollout's tail, whose kernel's register budget is the rollout's.
-__device__ __forceinline__ void make_noise_row_lean(const TickDesc &d, int r, uint32_t k,
-                                                    uint32_t j, const float *zr) {
-  float *dst = const_cast<float *>(zr) + ((size_t)j * d.N + k) * 12;
-  const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
-#pragma unroll 1
-  for (uint32_t call = 0; call < 3; ++call) {
-    uint32_t c0 = k, c1 = j, c2 = d.tick, c3 = ((uint32_t)r << 8) | call;
-    philox4x32_10(c0, c1, c2, c3, key0, key1);
-    const float2 ga = gauss_pair(c0, c1);
-    const float2 gb = gauss_pair(c2, c3);
-    const int p = 2 * (int)call;
-    dst[p] = ga.x;
-    dst[pair_dim_second(p)] = ga.y;
-    dst[p + 1] = gb.x;
-    dst[pair_dim_second(p + 1)] = gb.y;
-  }
-}
-
-// Omega = sum of the listed weights and the weighted frequency sum, in FP64,
-// over the list in its (increasing k) order, by one thread: out[0], out[1].
-template <typename T>
-__device__ __forceinline__ void list_sums(const TickDesc &d, uint32_t total, const uint32_t *s_k,
-                                          const T *s_w, double *out) {
-  double om = 0.0, sf = 0.0;
-  for (uint32_t a = 0; a < total; ++a) {
-    const double w = (double)s_w[a];
-    om += w;
-    sf += w * ((double)d.q[s_k[a]] * d.inv_q_scale);
-  }
-  out[0] = om;
-  out[1] = sf;
-}
+constexpr int kListCap = 2048;
 
 // Noise row j of sample k made again and stored where the rollout would have
 // stored it (z of iteration r: [M][N][12]).
@@ -1860,7 +1798,6 @@ template <typename T, bool INL>
 __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickDesc inl) {
   const TickDesc &d = INL ? inline_desc() : tab.desc[tab.item[blockIdx.x]];
   if (d.method != 0) return;  // elite / best sample: k_select + k_update
-  if (d.fused_update && tab.n_fused > 0) return;  // formed by the rollout's last workgroup
   const int N = d.N, M = d.M, tid = threadIdx.x, r = tab.r;
   constexpr int kW = kMppiBlock / 64;
   // the first kPer costs of each thread are held in registers (independent
@@ -1876,7 +1813,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
   __shared__ uint32_t s_k[kListCap];
   __shared__ T s_w[kListCap];
   __shared__ double s_new[12];
-  __shared__ double s_list_sums[2];  // listed path: Omega, frequency moment
   const T *Jg = reinterpret_cast<const T *>(d.J);
   const bool last_iter = (r == d.R - 1);
   const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
@@ -1996,12 +1932,10 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
         const uint32_t a = e / (uint32_t)M, j = e - a * (uint32_t)M;
         make_noise_row(d, r, s_k[a], j, zr);
       }
+      __syncthreads();
     }
-    // Omega and the frequency moment over the list in increasing k (the
-    // order does not depend on the workgroup size)
-    if (tid == 0) list_sums(d, total, s_k, s_w, s_list_sums);
-    __syncthreads();
-    const double omega = s_list_sums[0];
+    double omega = 0.0;
+    for (int i = 0; i < kW; ++i) omega += lds[i][12];
     for (int o = tid; o < M * 12; o += kMppiBlock) {
       const int j = o / 12, c = o - j * 12;
       const double m_old = (double)mean_at<T>(d, mu_in, r, j, c);
@@ -2080,10 +2014,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
       sf += lds[i][13];
       nact += lds[i][14];
     }
-    if (listed) {
-      omega = s_list_sums[0];
-      sf = s_list_sums[1];
-    }
     const double fnew = skip ? cur_mf : sf / omega;
     const double flags = (double)((int)prev_flags | (skip ? 1 : 0));
     d.it[IT_BETA] = (double)bv;
@@ -2097,243 +2027,6 @@ __global__ void __launch_bounds__(kMppiBlock) k_update_mppi(LaunchTab tab, TickD
     d.it[IT_NACT] = nact;
     if (last_iter) emit_action(d, s_new, fnew, (double)bv, flags, nact);
   }
-}
-
-// MPPI update (Alg. 4) of one FP32 controller by one workgroup of B threads,
-// run by the controller's last rollout workgroup: beta = min J (lowest index
-// on ties), w_k = exp((beta - J_k) / lambda) in FP32, the samples whose
-// weight does not underflow listed in LDS in increasing k, then Omega, the
-// frequency moment and every output mu'_j = mu_j + sigma sum_k w_k z_kj /
-// Omega summed in FP64 over the list in that order -- the same sums, in the
-// same order, as k_update_mppi's list, whatever B.  With more than kListCap
-// weighed samples each row is reduced over all samples instead.  GEN2: the
-// rollout stored no noise; the rows read here are drawn first.
-template <int B, bool GEN2>
-__device__ __forceinline__ void mppi_update_wg(const TickDesc &d, int r, unsigned char *lds) {
-  static_assert(B % 64 == 0 && B <= 256, "one to four waves");
-  constexpr int kW = B / 64;
-  constexpr int kCells = 272;  // (slot, wave) counts: ceil(kTailMaxN / B) * kW <= 260
-  double (*red)[16] = reinterpret_cast<double (*)[16]>(lds);
-  uint64_t (*red_a)[2] = reinterpret_cast<uint64_t (*)[2]>(lds + 4 * 16 * 8);
-  uint64_t (*red_b)[2] = red_a + 4;
-  uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lds + 4 * 16 * 8 + 2 * 4 * 2 * 8);
-  double *s_sc = reinterpret_cast<double *>(s_cnt + kCells);  // [0] Omega [1] moment [4..15] row 0
-  uint32_t *s_k = reinterpret_cast<uint32_t *>(s_sc + 16);
-  float *s_w = reinterpret_cast<float *>(s_k + kListCap);
-  const int N = d.N, M = d.M, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int NS = (N + B - 1) / B;  // slots of B samples: sample k = slot * B + tid
-  const float *Jg = reinterpret_cast<const float *>(d.J);
-  const bool last_iter = (r == d.R - 1);
-  const double cur_mf = (r == 0) ? d.ctl[0] : d.it[IT_MUF];
-  const double cur_sf = (r == 0) ? d.sigma_f0 : d.it[IT_SIGF];
-  const double prev_flags = (r == 0) ? 0.0 : d.it[IT_FLAGS];
-  const float *mu_in = mean_in<float>(d, r);
-  float *mu_out = mean_out<float>(d, r);
-  const float *zr = d.z + (size_t)r * d.z_iter_stride;
-  __syncthreads();  // the rollout's staging area becomes this update's LDS
-
-  // costs are read kBatch slots at a time: independent loads, one latency
-  constexpr int kBatch = 8;
-  auto load_costs = [&](int s0, float (&v)[kBatch]) {
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int k = (s0 + u) * B + tid;
-      const float jv = Jg[k < N ? k : N - 1];
-      v[u] = k < N ? jv : inf_t<float>();
-    }
-  };
-  float bv = inf_t<float>();
-  int bk = 0x7fffffff;
-  for (int s0 = 0; s0 < NS; s0 += kBatch) {
-    float v[kBatch];
-    load_costs(s0, v);
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) argmin_combine(bv, bk, v[u], (s0 + u) * B + tid);
-  }
-  block_argmin_packed(bv, bk, red_a, red_b);
-  const bool skip = !finite_t(bv);
-  const double ild = d.inv_lambda;
-  const float il = (float)(ild < (double)std::numeric_limits<float>::max()
-                               ? ild : (double)std::numeric_limits<float>::max());
-  // per (slot, wave): how many weights do not underflow
-  for (int s0 = 0; s0 < NS; s0 += kBatch) {
-    float v[kBatch];
-    load_costs(s0, v);
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int sl = s0 + u;
-      const float wk = (!skip && sl < NS) ? exp_t((bv - v[u]) * il) : 0.f;
-      const uint64_t bal = __ballot(wk != 0.f);
-      if (lane == 0 && sl < NS) s_cnt[sl * kW + wid] = (uint32_t)__popcll(bal);
-    }
-  }
-  __syncthreads();
-  const int cells = NS * kW;
-  if (wid == 0) {  // exclusive scan of the counts, slot-major, by one wave
-    constexpr int kPerLane = (kCells + 63) / 64;
-    uint32_t v[kPerLane], sum = 0;
-#pragma unroll
-    for (int e = 0; e < kPerLane; ++e) {
-      const int cell = lane * kPerLane + e;
-      v[e] = cell < cells ? s_cnt[cell] : 0u;
-      sum += v[e];
-    }
-    const uint32_t incl = wave_incl_scan_u32(sum);
-    uint32_t run = incl - sum;
-#pragma unroll
-    for (int e = 0; e < kPerLane; ++e) {
-      const int cell = lane * kPerLane + e;
-      if (cell < cells) s_cnt[cell] = run;
-      run += v[e];
-    }
-    if (lane == 63) s_cnt[kCells - 1] = incl;
-  }
-  __syncthreads();
-  const uint32_t total = s_cnt[kCells - 1];
-  const bool listed = total <= (uint32_t)kListCap;
-  double omega = 0.0, sf = 0.0;
-  if (listed) {
-    for (int s0 = 0; s0 < NS; s0 += kBatch) {
-      float v[kBatch];
-      load_costs(s0, v);
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int sl = s0 + u, k = sl * B + tid;
-        const float wk = (!skip && sl < NS) ? exp_t((bv - v[u]) * il) : 0.f;
-        const uint64_t bal = __ballot(wk != 0.f);
-        if (wk != 0.f) {
-          const uint32_t pos = s_cnt[sl * kW + wid] +
-                               (uint32_t)__popcll(bal & (lane ? ~0ull >> (64 - lane) : 0ull));
-          s_k[pos] = (uint32_t)k;
-          s_w[pos] = wk;
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (GEN2)
-      for (uint32_t e = tid; e < total * (uint32_t)M; e += B) {
-        const uint32_t a = e / (uint32_t)M, j = e - a * (uint32_t)M;
-        make_noise_row_lean(d, r, s_k[a], j, zr);
-      }
-    if (tid == 0) list_sums(d, total, s_k, s_w, s_sc);
-    __syncthreads();
-    omega = s_sc[0];
-    sf = s_sc[1];
-    for (int o = tid; o < M * 12; o += B) {
-      const int j = o / 12, c = o - j * 12;
-      const double m_old = (double)mean_at<float>(d, mu_in, r, j, c);
-      const float *zc = zr + (size_t)j * N * 12 + c;
-      double S1 = 0.0;
-      for (uint32_t a = 0; a < total; ++a)
-        S1 = __builtin_fma((double)s_w[a], (double)zc[(size_t)s_k[a] * 12], S1);
-      const float stored = (float)(skip ? m_old : m_old + d.sigma0 * (S1 / omega));
-      mu_out[o] = stored;
-      if (j == 0) s_sc[4 + c] = (double)stored;
-      if (last_iter && d.dbg_mean) d.dbg_mean[o] = (double)stored;
-    }
-  } else {
-    if constexpr (GEN2) {
-      for (uint32_t e = tid; e < (uint32_t)N * (uint32_t)M; e += B) {
-        const uint32_t j = e / (uint32_t)N, k = e - j * (uint32_t)N;
-        make_noise_row_lean(d, r, k, j, zr);
-      }
-      __syncthreads();
-    }
-    // Omega and the moment: per-thread partials, wave sums, waves in order
-    double pw = 0.0, pf = 0.0;
-    if (!skip)
-      for (int k = tid; k < N; k += B) {
-        const float wk = exp_t((bv - Jg[k]) * il);
-        pw += (double)wk;
-        pf += (double)wk * ((double)d.q[k] * d.inv_q_scale);
-      }
-    {
-      const double a = wave_sum(pw), b2 = wave_sum(pf);
-      if (lane == 0) {
-        red[wid][12] = a;
-        red[wid][13] = b2;
-      }
-    }
-    __syncthreads();
-    for (int i = 0; i < kW; ++i) {
-      omega += red[i][12];
-      sf += red[i][13];
-    }
-    for (int j = 0; j < M; ++j) {
-      const float4 *zj = reinterpret_cast<const float4 *>(zr) + (size_t)j * N * 3;
-      float f1[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) f1[c] = 0.f;
-      if (!skip)
-        for (int k = tid; k < N; k += B) {
-          const float wk = exp_t((bv - Jg[k]) * il);
-          if (wk == 0.f) continue;
-          const float4 z0 = zj[(size_t)k * 3], z1 = zj[(size_t)k * 3 + 1], z2 = zj[(size_t)k * 3 + 2];
-          const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w,
-                                z2.x, z2.y, z2.z, z2.w};
-#pragma unroll
-          for (int c = 0; c < 12; ++c) f1[c] += wk * zz[c];
-        }
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const double o = (double)wave_sum(f1[c]);
-        if (lane == 0) red[wid][c] = o;
-      }
-      __syncthreads();
-      if (tid < 12) {
-        const int c = tid, idx = j * 12 + c;
-        double S1 = 0.0;
-        for (int i = 0; i < kW; ++i) S1 += red[i][c];
-        const double m_old = (double)mean_at<float>(d, mu_in, r, j, c);
-        const float stored = (float)(skip ? m_old : m_old + d.sigma0 * (S1 / omega));
-        mu_out[idx] = stored;
-        if (j == 0) s_sc[4 + c] = (double)stored;
-        if (last_iter && d.dbg_mean) d.dbg_mean[idx] = (double)stored;
-      }
-      __syncthreads();  // the next row reuses red[][0..11]
-    }
-  }
-  if (d.dbg_J)
-    for (int k = tid; k < N; k += B) {
-      d.dbg_J[(size_t)r * N + k] = (double)Jg[k];
-      d.dbg_q[(size_t)r * N + k] = d.q[k];
-    }
-  __syncthreads();
-  if (tid == 0) {
-    const double fnew = skip ? cur_mf : sf / omega;
-    const double flags = (double)((int)prev_flags | (skip ? 1 : 0));
-    d.it[IT_BETA] = (double)bv;
-    d.it[IT_OMEGA] = omega;
-    d.it[IT_BEST] = (double)bk;
-    d.it[IT_FNEW] = fnew;
-    d.it[IT_MUF] = fnew;
-    d.it[IT_SIGF] = cur_sf;
-    d.it[IT_SKIP] = skip ? 1.0 : 0.0;
-    d.it[IT_FLAGS] = flags;
-    d.it[IT_NACT] = (double)total;
-    if (last_iter) emit_action(d, s_sc + 4, fnew, (double)bv, flags, (double)total);
-  }
-}
-
-template <int B, bool GEN2>
-__device__ __forceinline__ void mppi_tail_after_rollout(const TickDesc &d, int r, int nblocks,
-                                                        unsigned char *lds) {
-  __shared__ uint32_t s_last;
-  __syncthreads();  // every lane of this workgroup has released its stores
-  if (threadIdx.x == 0) {
-    // the controller's count of finished rollout workgroups lives beside its
-    // frequency mean; the last one resets it for the next launch
-    uint32_t *ctr = reinterpret_cast<uint32_t *>(d.ctl + 1);
-    const uint32_t before =
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    const bool last = before + 1u == (uint32_t)nblocks;
-    if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = last ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other workgroups' costs
-  mppi_update_wg<B, GEN2>(d, r, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -2427,10 +2120,8 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
                                 const std::function<hipError_t()> *after_rollout) {
   // mean and sigma [max_rows][12]; spline weights [max_h][4] and bases [max_h]
   const size_t ts = precision == 1 ? 8 : 4;
-  size_t roll_lds = (size_t)tab.max_rows * 12 * 2 * ts +
-                    (tab.spline ? (size_t)tab.max_h * (4 * ts + 4) : 0);
-  // the MPPI update in the rollout's tail reuses that area
-  if (tab.n_fused > 0 && roll_lds < (size_t)kTailLds) roll_lds = kTailLds;
+  const size_t roll_lds = (size_t)tab.max_rows * 12 * 2 * ts +
+                          (tab.spline ? (size_t)tab.max_h * (4 * ts + 4) : 0);
   if (timing == 2) (void)hipEventRecord(ev[0], s);
   if (!tab.skip_noise && !tab.gen_noise)
     hipLaunchKernelGGL((k_noise<INL>), dim3(tab.total_noise * tab.r_count), dim3(kNoiseBlock), 0, s,
@@ -2464,7 +2155,7 @@ static hipError_t launch_stages(const LaunchTab &tab, const TickDesc &inl, int p
     else
       hipLaunchKernelGGL((k_update<float, INL>), ug, dim3(kUpdBlock), 0, s, tab, inl);
   }
-  if (tab.n_select + tab.n_fused < tab.n) {
+  if (tab.n_select < tab.n) {
     if (precision == 1)
       hipLaunchKernelGGL((k_update_mppi<double, INL>), dim3(tab.n), dim3(kMppiBlock), 0, s, tab, inl);
     else

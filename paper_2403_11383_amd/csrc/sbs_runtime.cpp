@@ -125,10 +125,6 @@ struct Tune {
   // launch), 1 every row, 2 only the stance legs' Gaussians for MPPI
   // controllers in the stance-pair form (every row for the others)
   int gen = 2;
-  // FP32 MPPI controllers (N <= kTailMaxN): the last rollout workgroup of a
-  // controller forms its update, instead of a separate update launch (off:
-  // measured slower, see sbs_set_fused_update)
-  bool fused = false;
 };
 
 bool valid_form(int lanes, int block, int unroll) {
@@ -683,9 +679,6 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
     fill_desc(rt, *cs[i], item_ws(cs[i]->cfg), dev + L.item_off[i],
               reinterpret_cast<double *>(host_dev + L.results) + (size_t)i * kResultDoubles,
               *ins[i], ticks[i], i, &hd[i]);
-    const sbs_controller_cfg &c = cs[i]->cfg;
-    hd[i].fused_update = (tn.fused && c.method == SBS_MPPI && c.precision == SBS_FP32 &&
-                          c.N <= kTailMaxN) ? 1 : 0;
   }
   std::vector<std::pair<LaunchTab, int>> out;
   const uint64_t tab_bytes = align_up(((uint64_t)n + 3 * ((uint64_t)n + 1)) * 4);
@@ -760,10 +753,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
       tab.roll_block = block;
       tab.unroll = unroll;
       tab.r_count = 1;
-      for (int t = 0; t < m; ++t) {
-        tab.n_select += cs[idx[t]]->cfg.method != SBS_MPPI ? 1 : 0;
-        tab.n_fused += hd[idx[t]].fused_update;
-      }
+      for (int t = 0; t < m; ++t) tab.n_select += cs[idx[t]]->cfg.method != SBS_MPPI ? 1 : 0;
       tab.desc = reinterpret_cast<const TickDesc *>(dev + L.desc);
       tab.item = reinterpret_cast<const int32_t *>(dev + off);
       tab.noise_start = tab.item + n;
@@ -935,11 +925,6 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
         start = std::max(start, ob->t_start_est + (int64_t)(ob->steps / rt->jit_rate));
     b->t_start_est = start;
   }
-  // a lone controller's one-lane rollout keeps the separate MPPI update (that
-  // kernel form has no update tail)
-  if (ids.size() == 1)
-    for (auto &tp : tabs)
-      if (tp.first.lanes == 1) tp.first.n_fused = 0;
   // a single controller's descriptor travels in the kernel arguments; a
   // batch's descriptors and block maps go up in one copy, on the copy stream
   // when there is one (it need not wait for the work ahead on the stream)
@@ -1852,13 +1837,6 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable) {
   if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
   std::lock_guard<std::mutex> lk(rt->mu);
   rt->tune.pairs = enable != 0;
-  return SBS_OK;
-}
-
-int sbs_set_fused_update(sbs_runtime *rt, int32_t on) {
-  if (!rt) return fail(SBS_EINVAL, "runtime is NULL");
-  std::lock_guard<std::mutex> lk(rt->mu);
-  rt->tune.fused = on != 0;
   return SBS_OK;
 }
 
