@@ -289,12 +289,13 @@ int sbs_set_rollout_pairs(sbs_runtime *rt, int32_t enable);
  * values in every mode).  mode 0: a separate noise launch writes every row
  * and the rollout reads it back.  1: a one-lane FP32 rollout of per-step
  * GRFs draws each step's row itself and stores it for the update.  2
- * (default): as 1, except that the one-lane rollout of an MPPI controller in
- * the stance-pair form (diagonal trot at duty 1/2, N at most 16384) draws
- * only its two stance legs' GRF components -- the only ones it uses -- and
- * stores nothing; the MPPI update then draws the rows of the samples it
- * weighs (quick for the usual few; with thousands of weighed samples one
- * workgroup draws them all, correct but slow).  The choice depends on the
+ * (default): as 1, except that the one-lane rollout of a controller in the
+ * stance-pair form (diagonal trot at duty 1/2, N at most 16384) draws only
+ * its two stance legs' GRF components -- the only ones it uses -- and stores
+ * nothing; the update then draws the rows of the samples it needs: the
+ * weighed ones of MPPI (quick for the usual few; with thousands of weighed
+ * samples one workgroup draws them all, correct but slow), the K_e chosen
+ * ones of an elite or best-sample update.  The choice depends on the
  * configuration alone.  Modes 0 and 1 give bit-identical results; mode 2's
  * rollout is compiled apart and agrees with them within FP32 rounding.
  * Takes effect at the next submission; a plan keeps the setting it was

@@ -617,10 +617,11 @@ __device__ __forceinline__ T theta_of(T mu, T sig, T z) {
 // with the noise kernel's own Philox counter and transform.  GEN 1: all of
 // row j at step j, stored for the update instead of read: the same values,
 // one launch and a 48-B read per rollout-step fewer.  GEN 2 (stance-pair
-// form, MPPI): only the Gaussians of the stance diagonal's six GRF
-// components -- three of the row's six Box-Muller pairs, from two or three
-// of its Philox calls -- and nothing stored; the MPPI update makes the rows
-// of the samples it weighs (noise_row, the same values).
+// form): only the Gaussians of the stance diagonal's six GRF components --
+// three of the row's six Box-Muller pairs, from two or three of its Philox
+// calls -- and nothing stored; the update makes the rows of the samples it
+// weighs (MPPI) or chooses (elite, best sample) itself (noise_row, the same
+// values).
 template <typename T, int BLOCK, int UNROLL, bool INL, bool SPL, bool PAIR, int GEN = 0>
 __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) {
   extern __shared__ __align__(16) unsigned char roll_lds[];
@@ -1679,12 +1680,25 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
           wa[u] = va[u] ? wv : T(0);
         }
         float4 zl[4][3];
+        if (tab.gen_noise == 2) {
+          // the rollout stored no noise: the chosen samples' rows, drawn again
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
-          zl[u][0] = src[0];
-          zl[u][1] = src[1];
-          zl[u][2] = src[2];
+          for (int u = 0; u < 4; ++u) {
+            float z[12];
+            noise_row((uint32_t)d.seed, (uint32_t)(d.seed >> 32), (uint32_t)r << 8, d.tick,
+                      ka[u], (uint32_t)j, z);
+            zl[u][0] = make_float4(z[0], z[1], z[2], z[3]);
+            zl[u][1] = make_float4(z[4], z[5], z[6], z[7]);
+            zl[u][2] = make_float4(z[8], z[9], z[10], z[11]);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
+            zl[u][0] = src[0];
+            zl[u][1] = src[1];
+            zl[u][2] = src[2];
+          }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {

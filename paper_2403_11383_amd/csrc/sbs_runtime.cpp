@@ -521,15 +521,15 @@ bool pair_gait(const sbs_controller_cfg &c) {
 }
 
 // Whether a controller's one-lane FP32 rollout may make only its stance
-// legs' noise (the MPPI update then makes the rows of the samples it
-// weighs).  It depends on the configuration alone, so a controller takes the
-// same form in every tick, alone, in a batch, in a plan and after a resume;
-// a controller whose noise is produced ahead of its ticks keeps reading
-// stored rows in every tick.
+// legs' noise (the update then makes the rows of the samples it weighs or
+// chooses).  It depends on the configuration alone, so a controller takes
+// the same form in every tick, alone, in a batch, in a plan and after a
+// resume; a controller whose noise is produced ahead of its ticks keeps
+// reading stored rows in every tick.
 bool stance_noise(const Controller &C, const Tune &tn) {
   const sbs_controller_cfg &c = C.cfg;
   return tn.gen == 2 && tn.pairs && !C.prefetch && c.precision == SBS_FP32 && c.knots == 0 &&
-         c.method == SBS_MPPI && c.N <= kMppiRegN && pair_gait(c);
+         c.N <= kMppiRegN && pair_gait(c);
 }
 
 void fill_desc(const sbs_runtime *rt, const Controller &C, const ItemWs &w, char *dev_item,
