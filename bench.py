@@ -31,6 +31,8 @@ without gait adaptation), copy (HBM byte-counter reference).
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import hashlib
 import json
 import os
@@ -74,6 +76,21 @@ PEAK_FP32_VALU_TFLOPS = 78.6
 
 def pct(a, p):
     return float(np.percentile(np.asarray(a, np.float64), p))
+
+
+@contextlib.contextmanager
+def gc_paused():
+    """Python's cyclic garbage collector paused over a timed region (after one
+    full collection): a full pass over torch's object graph takes tens of
+    milliseconds and would otherwise land inside the timing at random."""
+    gc.collect()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
 
 
 def kernel_source_hash():
@@ -125,28 +142,29 @@ def closed_loop(rt, binding, workloads, cfg, ticks, warmup, push_from=30, push=4
     no_push, push_f = (0.0, 0.0, 0.0), (0.0, push, 0.0)
     loop = None
     e, falls = 0, 0
-    for t in range(warmup + ticks):
-        if t == warmup or e == episode:
-            e = 0
-        if e == 0:
-            plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
-            loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
-        if t == warmup:
-            torch.cuda.synchronize()
-            rt.timing()  # reset the stage-timing accumulators
-            t_start = time.perf_counter()
-        a = loop.step(push_f if e >= push_from else no_push)
-        e += 1
-        x = loop.plant.st.x
-        if workloads.fallen(x):
-            e = 0
-            falls += 1 if t >= warmup else 0
-        if t >= warmup:
-            # submit-to-visible latency as recorded by the runtime
-            lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
-            acts.append((a.flags, a.freq_hz, a.n_active))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    with gc_paused():
+        for t in range(warmup + ticks):
+            if t == warmup or e == episode:
+                e = 0
+            if e == 0:
+                plant = binding.Plant(cfg, x0, workloads.feet_under_hips(x0), phase=0)
+                loop = binding.ClosedLoop(rt, cid, plant, v_ref=v_ref, z_ref=workloads.HEIGHT)
+            if t == warmup:
+                torch.cuda.synchronize()
+                rt.timing()  # reset the stage-timing accumulators
+                t_start = time.perf_counter()
+            a = loop.step(push_f if e >= push_from else no_push)
+            e += 1
+            x = loop.plant.st.x
+            if workloads.fallen(x):
+                e = 0
+                falls += 1 if t >= warmup else 0
+            if t >= warmup:
+                # submit-to-visible latency as recorded by the runtime
+                lat.append((a.t_done_ns - a.t_submit_ns) * 1e-6)
+                acts.append((a.flags, a.freq_hz, a.n_active))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
     timing = rt.timing()
     rt.destroy_controller(cid)
     return elapsed, lat, acts, timing, (loop.plant, falls)
@@ -209,14 +227,15 @@ def batched(rt, binding, workloads, steps, warmup, cache_path=None):
         rt.fetch_many(tks, acts)
     torch.cuda.synchronize()
     lat = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        a = time.perf_counter_ns()
-        rt.plan_submit_raw(plan, ins, tks)
-        rt.fetch_many(tks, acts)
-        lat.append((time.perf_counter_ns() - a) * 1e-6)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter_ns()
+            rt.plan_submit_raw(plan, ins, tks)
+            rt.fetch_many(tks, acts)
+            lat.append((time.perf_counter_ns() - a) * 1e-6)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     work = sum(c["N"] * c["H"] * c.get("iterations", 1) for c in cfgs)
     rt.plan_destroy(plan)
     for c in ids:
@@ -562,31 +581,32 @@ def serving_run(binding, workloads, duration, mode, arena_bytes, robots=256, str
     racts = (binding.Action * 1024)()
     nready = C.c_int32()
     torch.cuda.synchronize()
-    t_start = time.perf_counter_ns()
-    i = 0
-    while i < len(events) or pending:
-        now = (time.perf_counter_ns() - t_start) * 1e-9
-        while i < len(events) and events[i][0] <= now:
-            t_arr, r = events[i]
-            rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
-            if rc == binding.ENOMEM and mode == "direct":  # retire finished ticks first
-                break
-            binding._check(rc)
-            pending[tk.value] = (t_arr, r)
-            i += 1
-        if not pending:
-            continue
-        # wait for completions at most until the next arrival is due
-        wait_us = 0
-        if i < len(events):
-            wait_us = max(0, min(100, int((events[i][0] - now) * 1e6)))
-        binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), wait_us))
-        for i_ in range(nready.value):
-            t_arr, r = pending.pop(rtk[i_])
-            lat.append((racts[i_].t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
-            c = fleet[r]
-            done_work += c["N"] * c["H"]
-    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    with gc_paused():
+        t_start = time.perf_counter_ns()
+        i = 0
+        while i < len(events) or pending:
+            now = (time.perf_counter_ns() - t_start) * 1e-9
+            while i < len(events) and events[i][0] <= now:
+                t_arr, r = events[i]
+                rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(inputs[r]), C.byref(tk))
+                if rc == binding.ENOMEM and mode == "direct":  # retire finished ticks first
+                    break
+                binding._check(rc)
+                pending[tk.value] = (t_arr, r)
+                i += 1
+            if not pending:
+                continue
+            # wait for completions at most until the next arrival is due
+            wait_us = 0
+            if i < len(events):
+                wait_us = max(0, min(100, int((events[i][0] - now) * 1e6)))
+            binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), wait_us))
+            for i_ in range(nready.value):
+                t_arr, r = pending.pop(rtk[i_])
+                lat.append((racts[i_].t_done_ns - t_start) * 1e-6 - t_arr * 1e3)
+                c = fleet[r]
+                done_work += c["N"] * c["H"]
+        elapsed = (time.perf_counter_ns() - t_start) * 1e-9
     stats = rt.stats()
     rt.close()
     return {"ticks": len(lat), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,
@@ -648,41 +668,42 @@ def saturated_run(binding, workloads, duration, mode, arena_bytes, robots=256, t
         for f in range(N_FORMS):
             rt.timing_rollout(f)
     lat, done_work, n_pending = [], 0, 0
-    t_start = time.perf_counter_ns()
-    t_end = t_start + int(duration * 1e9)
-    idle = np.arange(robots)
-    while time.perf_counter_ns() < t_end or n_pending:
-        if len(idle) and time.perf_counter_ns() < t_end:
-            if mode == "serving":
-                n = len(idle)
-                sub_np[:n] = all_np[idle]
-                sub_ids[:n] = ids_np[idle]
-                binding._check(L.sbs_submit_batch(
-                    rt._h, n, sub_ids.ctypes.data_as(C.POINTER(C.c_int32)), sub_in,
-                    sub_tk.ctypes.data_as(C.POINTER(C.c_uint64))))
-                n_pending += n
-                idle = idle[:0]
-            else:
-                still = []
-                for r in idle:
-                    rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(all_in[r]), C.byref(tk))
-                    if rc == binding.ENOMEM:  # retire finished ticks first
-                        still.append(r)
-                        continue
-                    binding._check(rc)
-                    n_pending += 1
-                idle = np.asarray(still, np.int64)
-        binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), 0))
-        n = nready.value
-        if n:
-            a = acts[:n]
-            rob = id2robot[a["controller"]]
-            lat.append((a["t_done_ns"] - a["t_submit_ns"]) * 1e-6)
-            done_work += int(work_np[rob].sum())
-            idle = np.concatenate([idle, rob])
-            n_pending -= n
-    torch.cuda.synchronize()
-    elapsed = (time.perf_counter_ns() - t_start) * 1e-9
+    with gc_paused():
+        t_start = time.perf_counter_ns()
+        t_end = t_start + int(duration * 1e9)
+        idle = np.arange(robots)
+        while time.perf_counter_ns() < t_end or n_pending:
+            if len(idle) and time.perf_counter_ns() < t_end:
+                if mode == "serving":
+                    n = len(idle)
+                    sub_np[:n] = all_np[idle]
+                    sub_ids[:n] = ids_np[idle]
+                    binding._check(L.sbs_submit_batch(
+                        rt._h, n, sub_ids.ctypes.data_as(C.POINTER(C.c_int32)), sub_in,
+                        sub_tk.ctypes.data_as(C.POINTER(C.c_uint64))))
+                    n_pending += n
+                    idle = idle[:0]
+                else:
+                    still = []
+                    for r in idle:
+                        rc = L.sbs_submit_tick(rt._h, ids[r], C.byref(all_in[r]), C.byref(tk))
+                        if rc == binding.ENOMEM:  # retire finished ticks first
+                            still.append(r)
+                            continue
+                        binding._check(rc)
+                        n_pending += 1
+                    idle = np.asarray(still, np.int64)
+            binding._check(L.sbs_fetch_ready(rt._h, len(rtk), rtk, racts, C.byref(nready), 0))
+            n = nready.value
+            if n:
+                a = acts[:n]
+                rob = id2robot[a["controller"]]
+                lat.append((a["t_done_ns"] - a["t_submit_ns"]) * 1e-6)
+                done_work += int(work_np[rob].sum())
+                idle = np.concatenate([idle, rob])
+                n_pending -= n
+        torch.cuda.synchronize()
+        elapsed = (time.perf_counter_ns() - t_start) * 1e-9
     lat = np.concatenate(lat) if lat else np.zeros(1)
     stats = rt.stats()
     out = {"ticks": int(len(lat)), "elapsed_s": elapsed, "ticks_per_s": len(lat) / elapsed,

@@ -766,24 +766,19 @@ __global__ void __launch_bounds__(BLOCK) k_rollout(LaunchTab tab, TickDesc inl) 
       } else if constexpr (GEN == 2) {
         // the stance diagonal's three Box-Muller pairs: pair A (legs 0, 3)
         // pairs 0, 1 (call 0) and 2 (words 0, 1 of call 1); pair B (legs 1,
-        // 2) pairs 3 (words 2, 3 of call 1), 4 and 5 (call 2).  Slot s gives
-        // the lower-indexed stance leg's component s and the other leg's;
-        // calls 0 and 2 run only where a lane of the wave needs them.
+        // 2) pairs 3 (words 2, 3 of call 1), 4 and 5 (call 2).  Every lane
+        // makes call 1 and one more call, 0 or 2 by its pair (the counter is
+        // per lane, so a wave that mixes the pairs still makes two calls);
+        // slot s gives the lower-indexed stance leg's component s and the
+        // other leg's.
         const bool sA = duty_full || (ph[0] < duty_q);
         uint32_t m0 = (uint32_t)k, m1 = (uint32_t)j, m2 = tick, m3 = rw | 1u;
         philox4x32_10(m0, m1, m2, m3, key0, key1);
-        uint32_t a0 = 0u, a1 = 0u, a2 = 0u, a3 = 0u, b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
-        if (__any(sA)) {
-          a0 = (uint32_t)k; a1 = (uint32_t)j; a2 = tick; a3 = rw;
-          philox4x32_10(a0, a1, a2, a3, key0, key1);
-        }
-        if (__any(!sA)) {
-          b0 = (uint32_t)k; b1 = (uint32_t)j; b2 = tick; b3 = rw | 2u;
-          philox4x32_10(b0, b1, b2, b3, key0, key1);
-        }
-        const float2 g0 = gauss_pair(sA ? a0 : m2, sA ? a1 : m3);  // pair 0 | 3: x forces
-        const float2 g1 = gauss_pair(sA ? a2 : b0, sA ? a3 : b1);  // pair 1 | 4: y forces
-        const float2 g2 = gauss_pair(sA ? m0 : b2, sA ? m1 : b3);  // pair 2 | 5: z forces
+        uint32_t o0 = (uint32_t)k, o1 = (uint32_t)j, o2 = tick, o3 = rw | (sA ? 0u : 2u);
+        philox4x32_10(o0, o1, o2, o3, key0, key1);
+        const float2 g0 = gauss_pair(sA ? o0 : m2, sA ? o1 : m3);  // pair 0 | 3: x forces
+        const float2 g1 = gauss_pair(sA ? o2 : o0, sA ? o3 : o1);  // pair 1 | 4: y forces
+        const float2 g2 = gauss_pair(sA ? m0 : o2, sA ? m1 : o3);  // pair 2 | 5: z forces
         const float zl[3] = {g0.x, g1.x, g2.x};
         const float zh[3] = {g0.y, g1.y, g2.y};
         const int bl = j * 12 + (sA ? 0 : 3), bh = j * 12 + (sA ? 9 : 6);
