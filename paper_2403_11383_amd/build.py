@@ -17,7 +17,9 @@ HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # scalar FP32 only: the packed forms are kept off in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # IEEE-rounded division and square root (the noise transform relies on it)
+    # IEEE-rounded FP32 division and square root wherever the source writes
+    # them; the kernels call the hardware's approximate forms by name where
+    # those suffice
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-result",
 ]

@@ -91,18 +91,26 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t w0, uint32_t w1) {
 #pragma clang fp contract(off)
   const uint32_t i1 = (w0 >> 8) + 1u;   // u1 = i1 2^-24 in (0, 1]
   const uint32_t i2 = w1 >> 8;          // u2 = i2 2^-24 in [0, 1)
-  int e = 31 - __clz((int)i1);
-  float m = (float)i1 * __uint_as_float((uint32_t)(127 - e) << 23);  // [1, 2)
+  // i1 = 2^e m, m in [1, 2): the exponent and fraction fields of i1
+  // converted to FP32 (exact: i1 <= 2^24)
+  const uint32_t fb = __float_as_uint((float)i1);
+  int e = (int)(fb >> 23) - 127;
+  float m = __uint_as_float((fb & 0x7FFFFFu) | 0x3F800000u);
   const bool above = m > 0x1.6a09e6p+0f;  // fold onto [sqrt(2)/2, sqrt(2)]
   m = above ? m * 0.5f : m;
   e = above ? e + 1 : e;
-  const float s = (m - 1.0f) / (m + 1.0f);
-  const float t = s * s;
-  float p = __builtin_fmaf(t, 0x1.c71c72p-4f, 0x1.24924ap-3f);
-  p = __builtin_fmaf(t, p, 0x1.99999ap-3f);
-  p = __builtin_fmaf(t, p, 0x1.555556p-2f);
-  const float s2 = s + s;
-  const float lnm = __builtin_fmaf(s2 * t, p, s2);
+  // ln m = f + f^2 (f P(f) - 1/2), f = m - 1 (exact), P of degree 7 fitted
+  // to (ln(1 + f) - f + f^2 / 2) / f^3 on the folded range: no division
+  const float f = m - 1.0f;
+  const float h = f * f;
+  float p = __builtin_fmaf(f, -0x1.38b4e6p-4f, 0x1.055b58p-3f);
+  p = __builtin_fmaf(f, p, -0x1.0d8556p-3f);
+  p = __builtin_fmaf(f, p, 0x1.22da20p-3f);
+  p = __builtin_fmaf(f, p, -0x1.547242p-3f);
+  p = __builtin_fmaf(f, p, 0x1.99a008p-3f);
+  p = __builtin_fmaf(f, p, -0x1.000228p-2f);
+  p = __builtin_fmaf(f, p, 0x1.555554p-2f);
+  const float lnm = __builtin_fmaf(h, __builtin_fmaf(f, p, -0.5f), f);
   const float ke = (float)(e - 24);
   const float lnu = __builtin_fmaf(ke, 0x1.62e4p-1f, __builtin_fmaf(ke, 0x1.7f7d1cp-20f, lnm));
   const float rho = sqrt_rn_radius(-2.0f * lnu);

