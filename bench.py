@@ -57,16 +57,17 @@ FLOP_PER_ROLLOUT_STEP = 326
 FLOP_PER_SPLINE_STEP = FLOP_PER_ROLLOUT_STEP - 24 + 84
 FLOP_PER_SPLINE_KNOT = 24
 # A rollout that also draws its noise does the FP32 arithmetic of the 12
-# Gaussians of each step too: 45 FLOP per Box-Muller pair (the log's
-# reduction, division and polynomial 18 with the exponent terms, radius 2,
-# the turn's sine and cosine polynomials 21, the two products 2, the
-# mantissa scalings 2), 6 pairs per step; Philox's integer work is not
-# counted.
-FLOP_PER_NOISE_ROW = 270
+# Gaussians of each step too: 50 FLOP per Box-Muller pair (the logarithm
+# 24: f = m - 1, f^2, the degree-7 polynomial P and the two FMAs around it
+# 20, the exponent terms 4; radius 2; the turn's sine and cosine polynomials
+# 21; the two products 2; the fold's halving 1), 6 pairs per step; Philox's
+# integer work is not counted.
+FLOP_PER_GAUSS_PAIR = 50
+FLOP_PER_NOISE_ROW = 6 * FLOP_PER_GAUSS_PAIR
 FLOP_PER_ROLLOUT_STEP_WITH_NOISE = FLOP_PER_ROLLOUT_STEP + FLOP_PER_NOISE_ROW
 # a stance-pair rollout that draws only its stance diagonal's noise evaluates
 # three of the six pairs per step
-FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE = FLOP_PER_ROLLOUT_STEP + 3 * 45
+FLOP_PER_ROLLOUT_STEP_WITH_STANCE_NOISE = FLOP_PER_ROLLOUT_STEP + 3 * FLOP_PER_GAUSS_PAIR
 # MI355X FP32 vector peak as published (it counts packed FMAs: 256 CUs x 4
 # SIMDs x 16 lanes x 2 FLOP x 2 packed x 2.4 GHz) and the non-packed peak the
 # kernels can reach (they are built with packed FP32 off).

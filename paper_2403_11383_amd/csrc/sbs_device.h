@@ -115,12 +115,13 @@ struct LaunchTab {
   int32_t max_rows;      // most mean rows among the items
   int32_t spline;        // the items use the spline parametrisation
   int32_t noise_rpt;     // noise rows per thread (single-controller launches; 0 = 1)
-  int32_t upd_chunk;     // mean rows per update workgroup (0 or 1: one)
+  int32_t upd_chunk;     // mean rows per elite / best-sample update workgroup (0 or
+                         // 1: one); MPPI items have no blocks in upd_start
   int32_t gen_noise;     // the one-lane FP32 rollout makes the noise itself (no noise
                          // launch; per-step GRFs only): 1 every row, stored for the
-                         // update; 2 (stance-pair form, MPPI items) only the stance
-                         // legs' Gaussians, nothing stored: the MPPI update makes the
-                         // rows it reads
+                         // update; 2 (stance-pair form) only the stance legs'
+                         // Gaussians, nothing stored: the updates make the rows they
+                         // read
   int32_t pairs;         // one-lane rollouts in the stance-pair form: every item is a
                          // diagonal trot at duty 1/2 (one of the leg pairs {0, 3},
                          // {1, 2} in stance at every step)

@@ -1663,52 +1663,20 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
     double out1[12], out2[12];
     {
       const float *zj = d.z + (size_t)r * d.z_iter_stride + (size_t)j * N * 12;
-      // four gathers in flight per thread: indices and weights first, then rows
       double s1[12], s2[12];
       T f1[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) { s1[c] = 0.0; s2[c] = 0.0; f1[c] = T(0); }
-      for (int a = tid; a < nmax; a += 4 * kUpdBlock) {
-        uint32_t ka[4];
-        T wa[4];
-        bool va[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int aa = a + u * kUpdBlock;
-          const int ac = aa < nmax ? aa : nmax - 1;  // always valid: loads issue together
-          const uint32_t kv = act[ac];
-          const T wv = actw[ac];
-          va[u] = aa < nact;
-          ka[u] = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
-          wa[u] = va[u] ? wv : T(0);
-        }
-        float4 zl[4][3];
-        if (tab.gen_noise == 2) {
-          // the rollout stored no noise: the chosen samples' rows, drawn again
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            float z[12];
-            noise_row((uint32_t)d.seed, (uint32_t)(d.seed >> 32), (uint32_t)r << 8, d.tick,
-                      ka[u], (uint32_t)j, z);
-            zl[u][0] = make_float4(z[0], z[1], z[2], z[3]);
-            zl[u][1] = make_float4(z[4], z[5], z[6], z[7]);
-            zl[u][2] = make_float4(z[8], z[9], z[10], z[11]);
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
-            zl[u][0] = src[0];
-            zl[u][1] = src[1];
-            zl[u][2] = src[2];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!va[u]) continue;
-          const float zz[12] = {zl[u][0].x, zl[u][0].y, zl[u][0].z, zl[u][0].w,
-                                zl[u][1].x, zl[u][1].y, zl[u][1].z, zl[u][1].w,
-                                zl[u][2].x, zl[u][2].y, zl[u][2].z, zl[u][2].w};
+      if (tab.gen_noise == 2) {
+        // the rollout stored no noise: each chosen sample's row drawn again,
+        // one row per thread and pass (sample a on thread a mod the block:
+        // the order of the sums the gathers below keep)
+        for (int a = tid; a < nact; a += kUpdBlock) {
+          const uint32_t kv = act[a];
+          const uint32_t k = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
+          float zz[12];
+          noise_row((uint32_t)d.seed, (uint32_t)(d.seed >> 32), (uint32_t)r << 8, d.tick, k,
+                    (uint32_t)j, zz);
           if (elite) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -1717,8 +1685,52 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
               s2[c] += zc * zc;
             }
           } else {
+            const T wv = actw[a];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) f1[c] += wa[u] * (T)zz[c];
+            for (int c = 0; c < 12; ++c) f1[c] += wv * (T)zz[c];
+          }
+        }
+      } else {
+        // four gathers in flight per thread: indices and weights first, then rows
+        for (int a = tid; a < nmax; a += 4 * kUpdBlock) {
+          uint32_t ka[4];
+          T wa[4];
+          bool va[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int aa = a + u * kUpdBlock;
+            const int ac = aa < nmax ? aa : nmax - 1;  // always valid: loads issue together
+            const uint32_t kv = act[ac];
+            const T wv = actw[ac];
+            va[u] = aa < nact;
+            ka[u] = kv < (uint32_t)N ? kv : (uint32_t)(N - 1);
+            wa[u] = va[u] ? wv : T(0);
+          }
+          float4 zl[4][3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 *src = reinterpret_cast<const float4 *>(zj + (size_t)ka[u] * 12);
+            zl[u][0] = src[0];
+            zl[u][1] = src[1];
+            zl[u][2] = src[2];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (!va[u]) continue;
+            const float zz[12] = {zl[u][0].x, zl[u][0].y, zl[u][0].z, zl[u][0].w,
+                                  zl[u][1].x, zl[u][1].y, zl[u][1].z, zl[u][1].w,
+                                  zl[u][2].x, zl[u][2].y, zl[u][2].z, zl[u][2].w};
+            if (elite) {
+#pragma unroll
+              for (int c = 0; c < 12; ++c) {
+                const double zc = (double)zz[c];
+                s1[c] += zc;
+                s2[c] += zc * zc;
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < 12; ++c) f1[c] += wa[u] * (T)zz[c];
+            }
           }
         }
       }

@@ -68,10 +68,12 @@ int64_t now_ns() {
 constexpr uint64_t kAlign = 256;
 // auto policy: four lanes per sample up to this many samples in one launch
 constexpr long long kQuadMaxSamples = 32768;
-// Mean rows per update workgroup in a batch: at most kUpdMaxChunk, and no
-// more than keeps kUpdTargetGroups workgroups (two per compute unit).
+// Mean rows per elite / best-sample update workgroup in a batch: at most
+// kUpdMaxChunk, and no more than keeps kUpdTargetGroups workgroups (eight
+// per compute unit).  A workgroup reduces its rows one after the other, so
+// rows run in parallel until the device is several times full.
 constexpr long long kUpdMaxChunk = 8;
-constexpr long long kUpdTargetGroups = 512;
+constexpr long long kUpdTargetGroups = 2048;
 
 // Step workspace of sbs_submit_tick_noalloc: one file-scope device array per
 // GPU, held until the process ends.  Host code never names it directly (its
@@ -122,8 +124,8 @@ struct Tune {
   int unroll = 1;
   bool pairs = true;  // stance-pair one-lane rollouts where the gait allows
   // one-lane FP32 per-step rollouts make their own noise: 0 no (a noise
-  // launch), 1 every row, 2 only the stance legs' Gaussians for MPPI
-  // controllers in the stance-pair form (every row for the others)
+  // launch), 1 every row, 2 only the stance legs' Gaussians for controllers
+  // in the stance-pair form (every row for the others)
   int gen = 2;
 };
 
@@ -714,16 +716,18 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         }
       }
       const int per_block = block / lanes;
-      // update workgroups cover `chunk` mean rows each: one for a lone
-      // controller (its rows run side by side, the latency path), more in a
-      // batch so that the costs and weights are formed once per chunk while
-      // at least kUpdTargetGroups workgroups remain (results do not depend
-      // on the chunk length)
-      long long rows_all = 0;
-      for (int t = 0; t < m; ++t) rows_all += rows_of(cs[idx[t]]->cfg);
+      // elite / best-sample update workgroups cover `chunk` mean rows each
+      // (MPPI items get none: their update is k_update_mppi, one workgroup
+      // per controller): one row for a lone controller (its rows run side by
+      // side, the latency path), more in a large batch while at least
+      // kUpdTargetGroups workgroups remain (results do not depend on the
+      // chunk length)
+      long long rows_sel = 0;
+      for (int t = 0; t < m; ++t)
+        if (cs[idx[t]]->cfg.method != SBS_MPPI) rows_sel += rows_of(cs[idx[t]]->cfg);
       const int chunk = m <= 1 ? 1
                                : (int)std::max<long long>(1, std::min<long long>(kUpdMaxChunk,
-                                                                                 rows_all / kUpdTargetGroups));
+                                                                                 rows_sel / kUpdTargetGroups));
       int max_rows = 1;
       ns[0] = rs[0] = us[0] = 0;
       for (int t = 0; t < m; ++t) {
@@ -733,7 +737,7 @@ std::vector<std::pair<LaunchTab, int>> build_batch(sbs_runtime *rt,
         item[t] = idx[t];
         ns[t + 1] = ns[t] + rows_of(c) * ((c.N + kNoiseBlock - 1) / kNoiseBlock);
         rs[t + 1] = rs[t] + (c.N + per_block - 1) / per_block;
-        us[t + 1] = us[t] + (rows_of(c) + chunk - 1) / chunk;
+        us[t + 1] = us[t] + (c.method != SBS_MPPI ? (rows_of(c) + chunk - 1) / chunk : 0);
       }
       if (m == 0) continue;
       LaunchTab tab{};

@@ -270,16 +270,16 @@ def test_batch_equals_alone(rt):
 
 
 def test_chunked_update_equals_one_row_per_workgroup(rt):
-    """A batch of 48 controllers at H = 50 (1200 mean rows per precision)
-    gives each update workgroup two rows; a controller alone gets one.  The
-    costs, weights and normaliser are formed once per workgroup and each row
-    is reduced as a one-row workgroup reduces it, so every action and mean
-    is bit-identical (MPPI, elite and best sample, FP32 and FP64)."""
+    """A batch of 192 controllers at H = 60, 80 elite or best-sample ones per
+    precision (4800 mean rows per launch), gives each elite / best-sample
+    update workgroup two rows; a controller alone gets one.  Each row is
+    reduced as a one-row workgroup reduces it, so every action and mean is
+    bit-identical (MPPI, elite and best sample, FP32 and FP64)."""
     rng = np.random.default_rng(41)
     cfgs, inps = [], []
-    for i in range(48):
-        method = ["mppi", "elite", "naive", "mppi"][(i // 2) % 4]
-        cfgs.append(workloads.config("c4", N=int(rng.choice([512, 1000, 1500])), H=50,
+    for i in range(192):
+        method = ["elite", "naive", "elite", "naive", "elite", "mppi"][(i // 2) % 6]
+        cfgs.append(workloads.config("c4", N=int(rng.choice([256, 400, 600])), H=60,
                                      method=method, iterations=1 if method == "mppi" else 2,
                                      precision="fp64" if i % 2 else "fp32", seed=700 + i))
         inps.append(workloads.tick_input(workloads.initial_state(rng)))
