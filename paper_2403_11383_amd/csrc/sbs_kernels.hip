@@ -356,6 +356,57 @@ __device__ __forceinline__ V wave_sum_sparse(V v, uint64_t mask) {
   return wave_sum(v);
 }
 
+// v of lane (this lane XOR m), through the LDS crossbar (no LDS storage).
+__device__ __forceinline__ double lane_xor(double v, int m) {
+  const int addr = (((int)threadIdx.x & 63) ^ m) << 2;
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Wave sums of 24 values at once, written to out[0..23] (by the lanes
+// whose index is a multiple of 8).  Three halving exchanges first: across
+// lanes l and l ^ m (m = 32, 16, 8) the lane whose bit m is clear keeps the
+// lower half of its values and adds its partner's lower half, the other the
+// upper half -- so each exchange adds half the values and moves each once --
+// leaving lane l three partial sums of values 12 b5 + 6 b4 + 3 b3 + {0, 1,
+// 2} (b the bits of l) over its group of 8 lanes; then three plain XOR
+// steps complete them.  A fixed order, so the result is deterministic.
+__device__ __forceinline__ void wave_sum24(const double (&v)[24], double *out) {
+  const int lane = threadIdx.x & 63;
+  double a[12], b[6], c[3];
+  const bool u32 = (lane & 32) != 0;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const double keep = u32 ? v[12 + i] : v[i], send = u32 ? v[i] : v[12 + i];
+    a[i] = keep + lane_xor(send, 32);
+  }
+  const bool u16 = (lane & 16) != 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double keep = u16 ? a[6 + i] : a[i], send = u16 ? a[i] : a[6 + i];
+    b[i] = keep + lane_xor(send, 16);
+  }
+  const bool u8 = (lane & 8) != 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double keep = u8 ? b[3 + i] : b[i], send = u8 ? b[i] : b[3 + i];
+    c[i] = keep + lane_xor(send, 8);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c[i] += lane_xor(c[i], 4);
+    c[i] += lane_xor(c[i], 2);
+    c[i] += lane_xor(c[i], 1);
+  }
+  if ((lane & 7) == 0) {
+    const int base = (u32 ? 12 : 0) + (u16 ? 6 : 0) + (u8 ? 3 : 0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[base + i] = c[i];
+  }
+}
+
 // (cost, index) minimum with the lowest index winning ties
 template <typename T>
 __device__ __forceinline__ void argmin_combine(T &v, int &k, T v2, int k2) {
@@ -1735,8 +1786,11 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
         }
       }
       if (elite) {
+        // the wave's 12 first and 12 second moments, into this wave's row
+        double v[24];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) { out1[c] = wave_sum(s1[c]); out2[c] = wave_sum(s2[c]); }
+        for (int c = 0; c < 12; ++c) { v[c] = s1[c]; v[12 + c] = s2[c]; }
+        wave_sum24(v, lds[tid >> 6]);
       } else {
         // reduce in the working precision within the wave, FP64 across waves
 #pragma unroll
@@ -1744,7 +1798,7 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(LaunchTab tab, TickDesc in
       }
     }
     const int lane = tid & 63, wid = tid >> 6;
-    if (lane == 0) {
+    if (!elite && lane == 0) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) { lds[wid][c] = out1[c]; lds[wid][12 + c] = out2[c]; }
     }
