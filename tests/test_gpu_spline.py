@@ -123,7 +123,7 @@ def test_spline_fp32_elite(rt, lanes):
     cfg = workloads.config("c2", N=3000, H=30, knots=5, seed=14)
     inp = workloads.tick_input(workloads.initial_state(np.random.default_rng(14)), v_ref=(-0.3, 0, 0))
     out, ref = run_pair(rt, cfg, inp)
-    # elite influence reaches up to the K_e-th cost, so judge conditioning
+    # elite influence reaches up to the K_e-th cost, so check conditioning
     ks = np.arange(cfg["N"])
     amp = conditioning(cfg, inp, hover(cfg), cfg["sigma_grf"], 0, 0, ks, ref["q_samples"][0])
     # FP32 rounds every step's arithmetic (~6e-8): a sample whose cost
