@@ -111,6 +111,10 @@ constexpr int kPrefetchRows = 10;  // measured at C1: 1, 4, 10, 25 rows -> 60.2,
 constexpr int64_t kJitMarginNs = 150000;
 constexpr double kJitMinSteps = 1e6;
 constexpr int64_t kDispatchNs = 20000;  // launch to device start of an idle stream
+// A batch header goes up on the copy stream when the work ahead of the
+// batch on its stream is estimated to run for longer than this (measured at C4:
+// 30 us against always or never).
+constexpr int64_t kHdrAheadNs = 30000;
 // MPPI costs the update holds in registers (16 per thread of 1024): a
 // rollout may leave the noise rows to the update (which lists the samples it
 // weighs from those registers) only up to this many samples.
@@ -934,7 +938,16 @@ int launch(sbs_runtime *rt, const std::vector<int32_t> &ids,
   // when there is one (it need not wait for the work ahead on the stream)
   TickDesc *inl = ids.size() == 1 ? reinterpret_cast<TickDesc *>(host + L.desc) : nullptr;
   hipError_t e = hipSuccess;
-  if (!inl && rt->copy_stream) {
+  // the copy stream pays off only while the work ahead on this stream runs
+  // for a while yet; behind an idle or nearly done stream the copy goes on
+  // the stream itself, which saves the wait across queues
+  bool ahead = false;
+  for (auto &ob : rt->inflight)
+    if (!ahead && ob->stream_slot == slot && hipEventQuery(ob->done) != hipSuccess)
+      ahead = rt->jit_rate <= 0 ||
+              ob->t_start_est + (int64_t)(ob->steps / rt->jit_rate) > now_ns() + kHdrAheadNs;
+  (void)hipGetLastError();  // the queries' not-ready status
+  if (!inl && rt->copy_stream && ahead) {
     b->hdr = take_event(rt);
     e = hipMemcpyAsync(dev, host, L.hdr_bytes, hipMemcpyHostToDevice, rt->copy_stream);
     if (e == hipSuccess) e = hipEventRecord(b->hdr, rt->copy_stream);
