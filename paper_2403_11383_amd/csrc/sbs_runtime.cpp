@@ -32,6 +32,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <sys/prctl.h>
+
 #include "../../include/sbs.h"
 #include "sbs_device.h"
 
@@ -1090,6 +1092,9 @@ constexpr int kSchedPollUs = 5;
 // SBS_ENOMEM instead of blocking every later request.
 void scheduler_loop(sbs_runtime *rt) {
   (void)hipSetDevice(rt->device);
+  // Linux lengthens a thread's sleeps by its timer slack (50 us by default),
+  // ten times the poll interval: 1 us keeps the polls close to kSchedPollUs
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(rt->mu);
   while (!rt->stop.load()) {
     int retired = reap(rt);
